@@ -1,0 +1,210 @@
+/*
+ * tcw.h -- C ABI of the deterministic-walk T-count synthesis library for MI355X (gfx950).
+ *
+ * Method: Di Matteo & Mosca, "Parallelizing quantum circuit synthesis" (arXiv:1606.07413).
+ * Problem (Sec. 4.1, the T-count decomposition): given the channel representation U_hat of an
+ * n-qubit Clifford+T unitary U, find Paulis P_1..P_t and a Clifford D with
+ *     U = e^{i phi} D R(P_t) ... R(P_1),   R(P) = (1 + w)/2 I + (1 - w)/2 P,  w = e^{i pi/4},
+ * t (the T-count) as small as the depth order allows.  (The paper writes the Clifford on the right;
+ * the left form used here is equivalent: conjugating D through R(P) gives R(+-P') and
+ * R(-Q) = (Clifford commuting with R(Q)) R(Q).)
+ * The search is the parallel claw search of Sec. 3: meet-in-the-middle halves of floor(k/2)
+ * rotations, a walk function f(x, b) = z_b(x), distinguished points with fraction
+ * theta = 2^-delta, a shared table of trail end points and backtracking of merged trails.
+ *
+ * Conventions shared by every call
+ *  - Pauli code q in [0, 4^n): x = q mod 2^n, z = q >> n, qubit j carries bit j of x and z, qubit 0
+ *    is the leftmost Kronecker factor.  Channel-rep rows and columns are indexed by this code
+ *    (U_hat_ij = 2^-n Tr(P_i U P_j U^dag), Sec. 4.1).
+ *  - Exact matrices: M = (A + B sqrt2) / sqrt2^e, A and B int32 row-major 4^n x 4^n, e >= 0.
+ *  - Walk points (uint64): x in bits 0..31 (x < xi^h, xi = 4^n - 1, h = floor(k/2)), side b in bit 32
+ *    (0: half-circuits from the identity, the paper's V side; 1: from the target, the W side).
+ *  - Every pointer named *_dev is device memory (e.g. a torch CUDA tensor's data_ptr) borrowed for
+ *    the call; work is enqueued on the context's stream and is asynchronous unless stated.  Host
+ *    pointers are read or written before the call returns.
+ *  - Return codes: TCW_OK or a negative TCW_E*; tcw_last_error() then describes the failure.  No
+ *    C++ exception crosses this boundary.  One context per host thread.
+ */
+#ifndef TCW_H
+#define TCW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TCW_OK 0
+#define TCW_EINVAL (-1)    /* bad argument: n, k, chunk, sizes, a matrix that is not orthogonal */
+#define TCW_ENOMEM (-2)    /* device or host allocation failed */
+#define TCW_EDEVICE (-3)   /* a HIP runtime error (message in tcw_last_error) */
+#define TCW_EOVERFLOW (-4) /* an exact value outside the proven int32/int8 range of the kernels */
+#define TCW_ESTATE (-5)    /* call out of order (e.g. a finished walk session) */
+
+#define TCW_MAX_T 64
+#define TCW_MAX_R 256
+
+typedef struct tcw_ctx tcw_ctx;
+typedef struct tcw_target tcw_target;
+typedef struct tcw_walk tcw_walk;
+
+/* ---- context ------------------------------------------------------------------------------
+ * tcw_create: bind to HIP device `device`; `hip_stream` (a hipStream_t, may be NULL for the null
+ * stream) is borrowed, e.g. torch.cuda.current_stream().cuda_stream.  The context owns the device
+ * buffers it allocates.  tcw_last_error's string is owned by the context and valid until the next
+ * call on it. */
+int tcw_create(tcw_ctx** out, int device, void* hip_stream);
+int tcw_destroy(tcw_ctx* ctx);
+const char* tcw_last_error(const tcw_ctx* ctx);
+int tcw_set_stream(tcw_ctx* ctx, void* hip_stream);
+
+/* ---- targets (Sec. 4.1, channel representation) ------------------------------------------
+ * tcw_target_from_words: U_hat = D_hat R_hat(P_k) ... R_hat(P_1) with D_hat = prod_j R_hat(C_j)^2,
+ * built exactly on the GPU.  paulis = [P_1..P_k] (host, each in 1..4^n-1), clifford = [C_1..C_m].
+ * tcw_target_from_channel: A, B host arrays (R x R, R = 4^n) and e; validated on the GPU
+ * (X X^T = 2^e I exactly with X = A + B sqrt2), TCW_EINVAL if not orthogonal.
+ * The target owns a device copy; it must be freed with tcw_target_free before its context. */
+int tcw_target_from_words(tcw_ctx* ctx, int n, const uint16_t* paulis, int k, const uint16_t* clifford,
+                          int m, tcw_target** out);
+int tcw_target_from_channel(tcw_ctx* ctx, int n, const int32_t* a, const int32_t* b, int32_t e,
+                            tcw_target** out);
+int tcw_target_free(tcw_target* t);
+/* Copy the reduced exact channel rep to host arrays a, b (R*R each) and *e.  Blocking. */
+int tcw_target_channel(tcw_ctx* ctx, const tcw_target* t, int32_t* a, int32_t* b, int32_t* e);
+int tcw_target_n(const tcw_target* t);
+
+/* ---- one search space: target x depth k x chunk (Sec. 3) ---------------------------------
+ * k >= 1; chunk = 0 for even k, 1..xi for odd k (S_c = U_hat R_hat(c)^T fixes P_1 = c).
+ * seed: search seed (hash keys, salts, trail starts); version: function version (re-salting);
+ * delta: theta = 2^-delta (0 marks every point distinguished). */
+typedef struct tcw_space {
+    int32_t k;
+    int32_t chunk;
+    uint64_t seed;
+    uint32_t version;
+    int32_t delta;
+} tcw_space;
+
+/* tcw_step (parity): pts_out[i] = f(pts_in[i]) and, if hash_out_dev != NULL, the matrix hash H of
+ * pts_in[i] (Sec. 3, f(x, b) = z_b(x); Sec. 2, h o nu o mu).  Device arrays of `count` entries. */
+int tcw_step(tcw_ctx* ctx, const tcw_target* t, const tcw_space* sp, const uint64_t* pts_in_dev,
+             uint64_t* pts_out_dev, uint64_t* hash_out_dev, int64_t count);
+
+/* tcw_trails (parity): from each start, apply f until the next point is distinguished (Sec. 3).
+ * dp_out_dev[i] = that point, len_out_dev[i] = steps taken (>= 1); len 0 = no distinguished point
+ * within `cap` steps (trail abandoned; dp_out undefined). */
+int tcw_trails(tcw_ctx* ctx, const tcw_target* t, const tcw_space* sp, const uint64_t* starts_dev,
+               int64_t count, uint32_t cap, uint64_t* dp_out_dev, uint32_t* len_out_dev);
+
+/* tcw_start_points: start of trail j for walk w (Sec. 3, random starting pairs), for
+ * w = w0 .. w0+count-1 at fixed j, into pts_out_dev. */
+int tcw_start_points(tcw_ctx* ctx, const tcw_target* t, const tcw_space* sp, int64_t w0, uint32_t j,
+                     int64_t count, uint64_t* pts_out_dev);
+
+/* tcw_canon_hash (parity): matrix hash H of `count` exact matrices (the nu + h part of the walk
+ * step): a_dev, b_dev are count x R x R int32, e_dev count int32; keys from (n, sp).  Values must
+ * fit int8 (|a|, |b| <= 127) else TCW_EOVERFLOW. */
+int tcw_canon_hash(tcw_ctx* ctx, int n, const tcw_space* sp, const int32_t* a_dev, const int32_t* b_dev,
+                   const int32_t* e_dev, int64_t count, uint64_t* h_out_dev);
+
+/* tcw_claw_check (exact, Sec. 3 last merge case): for point pairs (u0, u1) on opposite sides,
+ * D = W V^T computed exactly; ok_out_dev[i] = 1 iff D is a signed permutation (a Clifford), and
+ * then perm_out_dev[i*R + q], sign_out_dev[i*R + q] give D P_q D^dag = sign P_perm. */
+int tcw_claw_check(tcw_ctx* ctx, const tcw_target* t, const tcw_space* sp, const uint64_t* u0_dev,
+                   const uint64_t* u1_dev, int64_t count, int32_t* ok_out_dev, int32_t* perm_out_dev,
+                   int8_t* sign_out_dev);
+
+/* ---- walk sessions: many concurrent walks with a device distinguished-point table ----------
+ * A session owns `walks` walk states (64 B each) and a table of 2^log2_table slots (16 B each).
+ * tcw_walk_run enqueues one launch in which every walk performs `iters` evaluations of f
+ * (walking, inserting distinguished points, backtracking merged trails).  Claw candidates (equal
+ * matrix hash, opposite sides) are queued on the device.  enumerate != 0 is the exhaustive mode for
+ * small spaces: walk w takes the points w, w + walks, w + 2 walks, ... of the space once each and the
+ * table is keyed by each point's full 64-bit matrix hash, so every pair of opposite-side points with
+ * equal hash is reported (the first point of each hash class against every later one). */
+typedef struct tcw_walk_stats {
+    int64_t steps;          /* f evaluations, including backtracking */
+    int64_t dps;            /* distinguished points reached */
+    int64_t inserts;        /* new table entries */
+    int64_t abandoned;      /* trails that hit the cap */
+    int64_t robin_hood;     /* merges where one trail started on the other */
+    int64_t same_side;      /* collisions of f within one side */
+    int64_t reduction;      /* cross-side collisions of f with different matrix hashes */
+    int64_t claws;          /* cross-side collisions with equal matrix hash (candidates) */
+    int64_t table_full;     /* inserts dropped for lack of a free slot */
+    int64_t spin_timeouts;  /* table readers that gave up waiting for a slot's value */
+    int64_t active_walks;   /* walks not yet finished (enumeration mode) */
+} tcw_walk_stats;
+
+int tcw_walk_begin(tcw_ctx* ctx, const tcw_target* t, const tcw_space* sp, int64_t walks, int log2_table,
+                   uint32_t cap, int enumerate, tcw_walk** out);
+int tcw_walk_run(tcw_walk* w, int iters);
+/* Blocking: synchronise the stream and read counters. */
+int tcw_walk_stats_get(tcw_walk* w, tcw_walk_stats* out);
+/* Blocking: copy up to max_pairs claw candidates (u0, u1) to host arrays; returns the count found
+ * so far in *total. */
+int tcw_walk_claws(tcw_walk* w, uint64_t* u0, uint64_t* u1, int64_t max_pairs, int64_t* total);
+/* Re-salt: switch to function version `version`, clear the table, restart every walk. */
+int tcw_walk_reset(tcw_walk* w, uint32_t version);
+/* Time of the last tcw_walk_run launch in milliseconds, from HIP events on the context stream
+ * (blocking). */
+int tcw_walk_last_ms(tcw_walk* w, float* ms);
+/* Checkpoint / inspection: copy walk states [first, first + count) (64-byte records: start, cur,
+ * pa, pb, na, ha as uint64; len, trail, mode, rem as uint32) to or from host memory, and the
+ * table (2^log2_table slots of (key, value) uint64 pairs; key ~0 = empty; value = start |
+ * len << 33 | 1 << 63).  A session resumed from both continues its trails exactly.  Blocking. */
+int tcw_walk_read_states(tcw_walk* w, int64_t first, int64_t count, void* host_out);
+int tcw_walk_write_states(tcw_walk* w, int64_t first, int64_t count, const void* host_in);
+int tcw_walk_read_table(tcw_walk* w, void* host_out);
+int tcw_walk_write_table(tcw_walk* w, const void* host_in);
+int tcw_walk_end(tcw_walk* w);
+
+/* ---- search driver (depth loop, chunk loop, budgets; Sec. 3 and Appendix) ------------------ */
+#define TCW_ORDER_PLAIN 0
+#define TCW_ORDER_GIVEN 1
+
+typedef struct tcw_walk_params {
+    int32_t k_max;            /* deepest depth searched (plain order 0..k_max) */
+    int32_t delta;            /* theta = 2^-delta for walk spaces; < 0: 4, 8 or 12 by n = 2, 3, 4 */
+    int64_t walks;            /* concurrent walks */
+    int32_t log2_table;       /* table slots 2^log2_table */
+    uint64_t seed;            /* search seed */
+    uint32_t version;         /* first function version */
+    int32_t trail_cap_factor; /* cap = factor * 2^delta (default 20) */
+    int32_t budget_beta;      /* steps per (k, chunk) = beta * N * 2^delta, N = 2 xi^h (default 4) */
+    int32_t version_factor;   /* steps per function version = max(factor * N, 2 walks 2^delta) (default 2) */
+    int64_t enum_max;         /* enumerate spaces with N <= enum_max (default 65536) */
+    int32_t iters_per_launch; /* f evaluations per walk per launch (default by n) */
+    int32_t depth_order_kind; /* TCW_ORDER_PLAIN or TCW_ORDER_GIVEN */
+    int32_t depth_order_len;
+    int32_t depth_order[16];  /* depths to try in this order (GIVEN) */
+    int32_t chunk_first;      /* odd k: first chunk tried (default 1) */
+    int32_t chunk_last;       /* odd k: last chunk tried (default xi) */
+    double max_seconds;       /* wall-clock cap for the whole search (0: none) */
+} tcw_walk_params;
+
+typedef struct tcw_result {
+    int32_t status;                 /* 1: decomposition found and verified exactly; 0: not found */
+    int32_t t;                      /* its T-count (the depth k it was found at) */
+    int32_t n;
+    int32_t chunk;
+    uint16_t paulis[TCW_MAX_T];     /* P_t, ..., P_1 */
+    int32_t clifford_perm[TCW_MAX_R];
+    int8_t clifford_sign[TCW_MAX_R]; /* D P_q D^dag = sign[q] P_perm[q] */
+    tcw_walk_stats stats;           /* summed over every space searched */
+    int64_t spaces;                 /* (k, chunk) spaces searched */
+    int64_t versions;               /* function versions used */
+    int64_t launches;
+    int64_t false_claws;            /* candidates rejected by the exact check */
+    double seconds;
+} tcw_result;
+
+void tcw_default_params(tcw_walk_params* p, int n);
+/* Blocking.  Results written to *res (caller-allocated). */
+int tcw_search(tcw_ctx* ctx, const tcw_target* t, const tcw_walk_params* p, tcw_result* res);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TCW_H */

@@ -1,0 +1,886 @@
+// C ABI and host-side search driver.  Every arithmetic step of the method runs in the kernels of
+// exact.hip and walk.hip; this file validates arguments, owns device buffers, launches kernels on
+// the caller's stream and sequences the search (Sec. 3: depth loop, chunk loop, function
+// versions, budgets from the Appendix's runtime law).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tcw.h"
+#include "common.h"
+#include "internal.h"
+
+struct tcw_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int* flag = nullptr;          // device scratch flag
+    void* claw_scratch = nullptr;
+    size_t claw_scratch_bytes = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+struct tcw_target {
+    tcw_ctx* ctx = nullptr;
+    int n = 0;
+    tcw::ExactDev U;
+};
+
+namespace {
+
+using tcw::ExactDev;
+using tcw::SpaceDev;
+
+int fail(tcw_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(tcw_ctx* c, hipError_t e, const char* where) {
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    return fail(c, e == hipErrorOutOfMemory ? TCW_ENOMEM : TCW_EDEVICE, m);
+}
+
+#define HIP_TRY(ctx, expr)                                   \
+    do {                                                     \
+        hipError_t _e = (expr);                              \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, #expr); \
+    } while (0)
+
+uint32_t xi_of(int n) { return (1u << (2 * n)) - 1; }
+
+// xi^h, or 0 if it does not fit in 32 bits
+uint64_t n_half_of(int n, int h) {
+    uint64_t v = 1;
+    for (int i = 0; i < h; ++i) {
+        v *= xi_of(n);
+        if (v >= (1ull << 32)) return 0;
+    }
+    return v;
+}
+
+int clear_flag(tcw_ctx* c) {
+    HIP_TRY(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+    return TCW_OK;
+}
+
+int read_flag(tcw_ctx* c, int* out) {
+    HIP_TRY(c, hipMemcpyAsync(out, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TCW_OK;
+}
+
+// A prepared search space: S_c on the device (exact and int8-packed), keys, salts.
+struct Space {
+    tcw_ctx* ctx = nullptr;
+    int n = 0, k = 0, chunk = 0, delta = 0;
+    uint64_t seed = 0;
+    uint32_t version = 0;
+    ExactDev S;
+    int32_t e_s = 0;
+    uint32_t* phi = nullptr;
+    uint64_t* keys = nullptr;
+    SpaceDev dev{};
+
+    ~Space() {
+        tcw::exact_free(S);
+        if (phi) (void)hipFree(phi);
+        if (keys) (void)hipFree(keys);
+    }
+
+    void set_version(uint32_t v) {
+        version = v;
+        const uint64_t ctxi = ((uint64_t)v << 16) | ((uint64_t)k << 8) | (uint64_t)chunk;
+        dev.salt_h = tcw::sm64(tcw::sm64(seed, 2), ctxi);
+        dev.salt_d = tcw::sm64(tcw::sm64(seed, 3), ctxi);
+        dev.salt_s = tcw::sm64(tcw::sm64(seed, 4), ctxi);
+    }
+};
+
+int check_space(tcw_ctx* c, int n, const tcw_space* sp) {
+    if (!sp) return fail(c, TCW_EINVAL, "space is NULL");
+    if (sp->k < 1 || sp->k > TCW_MAX_T) return fail(c, TCW_EINVAL, "k must be in 1..64");
+    if (sp->k % 2 == 1) {
+        if (sp->chunk < 1 || (uint32_t)sp->chunk > xi_of(n)) return fail(c, TCW_EINVAL, "odd k needs chunk in 1..xi");
+    } else if (sp->chunk != 0) {
+        return fail(c, TCW_EINVAL, "even k needs chunk 0");
+    }
+    if (sp->delta < 0 || sp->delta > 32) return fail(c, TCW_EINVAL, "delta must be in 0..32");
+    if (n_half_of(n, sp->k / 2) == 0) return fail(c, TCW_EINVAL, "xi^h must be below 2^32");
+    if (sp->k > 255) return fail(c, TCW_EINVAL, "k too large");
+    return TCW_OK;
+}
+
+int prepare_space(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, Space& out) {
+    int rc = check_space(c, t->n, sp);
+    if (rc) return rc;
+    const int n = t->n;
+    const int R = 1 << (2 * n);
+    out.ctx = c;
+    out.n = n;
+    out.k = sp->k;
+    out.chunk = sp->chunk;
+    out.delta = sp->delta;
+    out.seed = sp->seed;
+    HIP_TRY(c, tcw::exact_alloc(out.S, n));
+    HIP_TRY(c, hipMalloc(&out.phi, (size_t)R * R / 2 * sizeof(uint32_t) + 16));
+    HIP_TRY(c, hipMalloc(&out.keys, 2 * (size_t)R * sizeof(uint64_t)));
+    if ((rc = clear_flag(c))) return rc;
+    // S_c = U R(c)^T for odd k, U for even k
+    uint16_t* seq = nullptr;
+    uint8_t* tr = nullptr;
+    int nseq = 0;
+    if (sp->k % 2 == 1) {
+        HIP_TRY(c, hipMalloc(&seq, sizeof(uint16_t)));
+        HIP_TRY(c, hipMalloc(&tr, 1));
+        const uint16_t cc = (uint16_t)sp->chunk;
+        const uint8_t one = 1;
+        HIP_TRY(c, hipMemcpyAsync(seq, &cc, sizeof(cc), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(tr, &one, 1, hipMemcpyHostToDevice, c->stream));
+        nseq = 1;
+    }
+    hipError_t e = tcw::exact_apply(out.S, t->U, seq, tr, nseq, c->flag, c->stream);
+    if (seq) (void)hipFree(seq);
+    if (tr) (void)hipFree(tr);
+    if (e != hipSuccess) return hip_fail(c, e, "chunk matrix");
+    HIP_TRY(c, tcw::exact_pack_phi(out.S, out.phi, c->flag, c->stream));
+    HIP_TRY(c, tcw::keys_fill(n, sp->seed, out.keys, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&out.e_s, out.S.e, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    int flag = 0;
+    if ((rc = read_flag(c, &flag))) return rc;
+    if (flag & 4) return fail(c, TCW_EOVERFLOW, "exact value out of range while forming S_c");
+    if (flag & 2) return fail(c, TCW_EOVERFLOW, "S_c entry outside int8 range (exponent too large)");
+    const int h = sp->k / 2;
+    out.dev.n_half = (uint32_t)n_half_of(n, h);
+    out.dev.h = h;
+    out.dev.delta = sp->delta;
+    out.dev.rot_e = (int32_t)((30ll * out.e_s) % 61);
+    out.dev.phi = out.phi;
+    out.dev.keys = out.keys;
+    out.set_version(sp->version);
+    return TCW_OK;
+}
+
+int default_delta(int n) { return n <= 2 ? 4 : (n == 3 ? 8 : 12); }
+int default_iters(int n) { return n <= 2 ? 64 : (n == 3 ? 32 : 8); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+struct tcw_walk {
+    tcw_ctx* ctx = nullptr;
+    Space space;
+    tcw::WalkDev wd{};
+    bool ended = false;
+
+    ~tcw_walk() {
+        if (wd.states) (void)hipFree(wd.states);
+        if (wd.table) (void)hipFree(wd.table);
+        if (wd.stats) (void)hipFree(wd.stats);
+        if (wd.claws) (void)hipFree(wd.claws);
+        if (wd.claw_count) (void)hipFree(wd.claw_count);
+    }
+};
+
+namespace {
+
+int walk_restart(tcw_walk* w) {
+    tcw_ctx* c = w->ctx;
+    HIP_TRY(c, tcw::launch_table_clear(w->wd.table, w->wd.log2_table, c->stream));
+    HIP_TRY(c, hipMemsetAsync(w->wd.stats, 0, tcw::ST_COUNT * sizeof(unsigned long long), c->stream));
+    HIP_TRY(c, hipMemsetAsync(w->wd.claw_count, 0, sizeof(unsigned long long), c->stream));
+    HIP_TRY(c, tcw::launch_walk_init(w->space.dev, w->wd, c->stream));
+    return TCW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tcw_create(tcw_ctx** out, int device, void* stream) {
+    if (!out) return TCW_EINVAL;
+    *out = nullptr;
+    tcw_ctx* c = new (std::nothrow) tcw_ctx();
+    if (!c) return TCW_ENOMEM;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        delete c;
+        return TCW_EDEVICE;
+    }
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    if (hipSetDevice(device) != hipSuccess || hipMalloc(&c->flag, sizeof(int)) != hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        delete c;
+        return TCW_EDEVICE;
+    }
+    *out = c;
+    return TCW_OK;
+}
+
+int tcw_destroy(tcw_ctx* c) {
+    if (!c) return TCW_EINVAL;
+    if (c->flag) (void)hipFree(c->flag);
+    if (c->claw_scratch) (void)hipFree(c->claw_scratch);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    delete c;
+    return TCW_OK;
+}
+
+const char* tcw_last_error(const tcw_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+int tcw_set_stream(tcw_ctx* c, void* stream) {
+    if (!c) return TCW_EINVAL;
+    c->stream = (hipStream_t)stream;
+    return TCW_OK;
+}
+
+int tcw_target_n(const tcw_target* t) { return t ? t->n : 0; }
+
+int tcw_target_from_words(tcw_ctx* c, int n, const uint16_t* paulis, int k, const uint16_t* clifford, int m,
+                          tcw_target** out) {
+    if (!c || !out) return TCW_EINVAL;
+    *out = nullptr;
+    if (n < 1 || n > 4) return fail(c, TCW_EINVAL, "n must be in 1..4");
+    if (k < 0 || m < 0 || (k > 0 && !paulis) || (m > 0 && !clifford)) return fail(c, TCW_EINVAL, "bad word arrays");
+    const uint32_t xi = xi_of(n);
+    // right-multiplication sequence: C_1 C_1 C_2 C_2 ... C_m C_m P_k ... P_1
+    std::vector<uint16_t> seq;
+    seq.reserve(2 * m + k);
+    for (int j = 0; j < m; ++j) {
+        if (clifford[j] < 1 || clifford[j] > xi) return fail(c, TCW_EINVAL, "Clifford Pauli out of range");
+        seq.push_back(clifford[j]);
+        seq.push_back(clifford[j]);
+    }
+    for (int j = k - 1; j >= 0; --j) {
+        if (paulis[j] < 1 || paulis[j] > xi) return fail(c, TCW_EINVAL, "Pauli out of range");
+        seq.push_back(paulis[j]);
+    }
+    tcw_target* t = new (std::nothrow) tcw_target();
+    if (!t) return TCW_ENOMEM;
+    t->ctx = c;
+    t->n = n;
+    hipError_t e = tcw::exact_alloc(t->U, n);
+    uint16_t* seq_dev = nullptr;
+    if (e == hipSuccess && !seq.empty()) e = hipMalloc(&seq_dev, seq.size() * sizeof(uint16_t));
+    if (e == hipSuccess && !seq.empty())
+        e = hipMemcpyAsync(seq_dev, seq.data(), seq.size() * sizeof(uint16_t), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->flag, 0, sizeof(int), c->stream);
+    if (e == hipSuccess) e = tcw::exact_build(t->U, seq_dev, nullptr, (int)seq.size(), c->flag, c->stream);
+    if (seq_dev) (void)hipFree(seq_dev);
+    if (e != hipSuccess) {
+        tcw::exact_free(t->U);
+        delete t;
+        return hip_fail(c, e, "target build");
+    }
+    int flag = 0;
+    int rc = read_flag(c, &flag);
+    if (rc == TCW_OK && flag) rc = fail(c, TCW_EOVERFLOW, "exact value out of range while building the target");
+    if (rc) {
+        tcw::exact_free(t->U);
+        delete t;
+        return rc;
+    }
+    *out = t;
+    return TCW_OK;
+}
+
+int tcw_target_from_channel(tcw_ctx* c, int n, const int32_t* a, const int32_t* b, int32_t e0, tcw_target** out) {
+    if (!c || !out || !a || !b) return TCW_EINVAL;
+    *out = nullptr;
+    if (n < 1 || n > 4) return fail(c, TCW_EINVAL, "n must be in 1..4");
+    if (e0 < 0 || e0 > 60) return fail(c, TCW_EINVAL, "exponent must be in 0..60");
+    const size_t rr = (size_t)1 << (4 * n);
+    tcw_target* t = new (std::nothrow) tcw_target();
+    if (!t) return TCW_ENOMEM;
+    t->ctx = c;
+    t->n = n;
+    int32_t *da = nullptr, *db = nullptr;
+    hipError_t e = tcw::exact_alloc(t->U, n);
+    if (e == hipSuccess) e = hipMalloc(&da, rr * 4);
+    if (e == hipSuccess) e = hipMalloc(&db, rr * 4);
+    if (e == hipSuccess) e = hipMemcpyAsync(da, a, rr * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(db, b, rr * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->flag, 0, sizeof(int), c->stream);
+    if (e == hipSuccess) e = tcw::exact_from_i32(t->U, da, db, e0, c->flag, c->stream);
+    if (e == hipSuccess) e = tcw::exact_check_orthogonal(t->U, c->flag, c->stream);
+    int flag = 0;
+    int rc = TCW_OK;
+    if (e == hipSuccess) {
+        rc = read_flag(c, &flag);
+    } else {
+        rc = hip_fail(c, e, "target upload");
+    }
+    if (da) (void)hipFree(da);
+    if (db) (void)hipFree(db);
+    if (rc == TCW_OK && (flag & 4)) rc = fail(c, TCW_EOVERFLOW, "entries too large");
+    if (rc == TCW_OK && (flag & 1)) rc = fail(c, TCW_EINVAL, "matrix is not orthogonal (X X^T != 2^e I)");
+    if (rc) {
+        tcw::exact_free(t->U);
+        delete t;
+        return rc;
+    }
+    *out = t;
+    return TCW_OK;
+}
+
+int tcw_target_free(tcw_target* t) {
+    if (!t) return TCW_EINVAL;
+    tcw::exact_free(t->U);
+    delete t;
+    return TCW_OK;
+}
+
+int tcw_target_channel(tcw_ctx* c, const tcw_target* t, int32_t* a, int32_t* b, int32_t* e) {
+    if (!c || !t || !a || !b || !e) return TCW_EINVAL;
+    const size_t rr = (size_t)1 << (4 * t->n);
+    int32_t *da = nullptr, *db = nullptr;
+    HIP_TRY(c, hipMalloc(&da, rr * 4));
+    HIP_TRY(c, hipMalloc(&db, rr * 4));
+    int rc = clear_flag(c);
+    if (!rc) {
+        hipError_t err = tcw::exact_to_i32(t->U, da, db, c->flag, c->stream);
+        if (err == hipSuccess) err = hipMemcpyAsync(a, da, rr * 4, hipMemcpyDeviceToHost, c->stream);
+        if (err == hipSuccess) err = hipMemcpyAsync(b, db, rr * 4, hipMemcpyDeviceToHost, c->stream);
+        if (err == hipSuccess) err = hipMemcpyAsync(e, t->U.e, 4, hipMemcpyDeviceToHost, c->stream);
+        if (err != hipSuccess) rc = hip_fail(c, err, "target copy");
+    }
+    int flag = 0;
+    if (!rc) rc = read_flag(c, &flag);
+    (void)hipFree(da);
+    (void)hipFree(db);
+    if (!rc && flag) rc = fail(c, TCW_EOVERFLOW, "entry does not fit int32");
+    return rc;
+}
+
+int tcw_step(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, const uint64_t* in, uint64_t* out, uint64_t* hash,
+             int64_t count) {
+    if (!c || !t || !in || !out || count < 0) return TCW_EINVAL;
+    Space s;
+    int rc = prepare_space(c, t, sp, s);
+    if (rc) return rc;
+    HIP_TRY(c, tcw::launch_step(t->n, s.dev, in, out, hash, count, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TCW_OK;
+}
+
+int tcw_trails(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, const uint64_t* starts, int64_t count,
+               uint32_t cap, uint64_t* dp, uint32_t* len) {
+    if (!c || !t || !starts || !dp || !len || count < 0 || cap == 0) return TCW_EINVAL;
+    Space s;
+    int rc = prepare_space(c, t, sp, s);
+    if (rc) return rc;
+    HIP_TRY(c, tcw::launch_trails(t->n, s.dev, starts, count, cap, dp, len, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TCW_OK;
+}
+
+int tcw_start_points(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, int64_t w0, uint32_t j, int64_t count,
+                     uint64_t* out) {
+    if (!c || !t || !out || count < 0 || w0 < 0 || w0 + count > (1ll << 32)) return TCW_EINVAL;
+    int rc = check_space(c, t->n, sp);
+    if (rc) return rc;
+    Space s;
+    s.k = sp->k;
+    s.chunk = sp->chunk;
+    s.seed = sp->seed;
+    s.dev.n_half = (uint32_t)n_half_of(t->n, sp->k / 2);
+    s.set_version(sp->version);
+    HIP_TRY(c, tcw::launch_starts(s.dev, w0, j, count, out, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TCW_OK;
+}
+
+int tcw_canon_hash(tcw_ctx* c, int n, const tcw_space* sp, const int32_t* a, const int32_t* b, const int32_t* e,
+                   int64_t count, uint64_t* h_out) {
+    if (!c || !sp || !a || !b || !e || !h_out || count < 0) return TCW_EINVAL;
+    if (n < 1 || n > 4) return fail(c, TCW_EINVAL, "n must be in 1..4");
+    if (count == 0) return TCW_OK;
+    const int R = 1 << (2 * n);
+    uint32_t* phi = nullptr;
+    uint64_t* keys = nullptr;
+    HIP_TRY(c, hipMalloc(&phi, (size_t)count * R * R / 2 * sizeof(uint32_t)));
+    HIP_TRY(c, hipMalloc(&keys, 2 * (size_t)R * sizeof(uint64_t)));
+    int rc = clear_flag(c);
+    Space s;
+    s.k = sp->k;
+    s.chunk = sp->chunk;
+    s.seed = sp->seed;
+    s.dev.keys = keys;
+    s.dev.delta = sp->delta;
+    s.set_version(sp->version);
+    hipError_t err = hipSuccess;
+    if (!rc) err = tcw::pack_phi_i32(n, a, b, count, phi, c->flag, c->stream);
+    if (!rc && err == hipSuccess) err = tcw::keys_fill(n, sp->seed, keys, c->stream);
+    int flag = 0;
+    if (!rc && err == hipSuccess) rc = read_flag(c, &flag);
+    if (!rc && err == hipSuccess && flag) rc = fail(c, TCW_EOVERFLOW, "matrix entry outside int8 range");
+    if (!rc && err == hipSuccess) err = tcw::launch_canon_hash(n, s.dev, phi, e, count, h_out, c->stream);
+    if (!rc && err == hipSuccess) err = hipStreamSynchronize(c->stream);
+    if (!rc && err != hipSuccess) rc = hip_fail(c, err, "canon hash");
+    (void)hipFree(phi);
+    (void)hipFree(keys);
+    return rc;
+}
+
+int tcw_claw_check(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, const uint64_t* u0, const uint64_t* u1,
+                   int64_t count, int32_t* ok, int32_t* perm, int8_t* sign) {
+    if (!c || !t || !u0 || !u1 || !ok || !perm || !sign || count < 0) return TCW_EINVAL;
+    Space s;
+    int rc = prepare_space(c, t, sp, s);
+    if (rc) return rc;
+    const size_t need = tcw::exact_claw_scratch_bytes(t->n);
+    if (c->claw_scratch_bytes < need) {
+        if (c->claw_scratch) (void)hipFree(c->claw_scratch);
+        c->claw_scratch = nullptr;
+        c->claw_scratch_bytes = 0;
+        HIP_TRY(c, hipMalloc(&c->claw_scratch, need));
+        c->claw_scratch_bytes = need;
+    }
+    HIP_TRY(c, tcw::exact_claw_check(s.S, sp->k, u0, u1, count, c->claw_scratch, c->claw_scratch_bytes, ok, perm,
+                                     sign, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TCW_OK;
+}
+
+// ---- walk sessions ----
+int tcw_walk_begin(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, int64_t walks, int log2_table, uint32_t cap,
+                   int enumerate, tcw_walk** out) {
+    if (!c || !t || !out) return TCW_EINVAL;
+    *out = nullptr;
+    if (walks < 1 || walks > (1ll << 31)) return fail(c, TCW_EINVAL, "walks must be in 1..2^31");
+    if (log2_table < 4 || log2_table > 32) return fail(c, TCW_EINVAL, "log2_table must be in 4..32");
+    if (cap == 0) return fail(c, TCW_EINVAL, "cap must be positive");
+    tcw_walk* w = new (std::nothrow) tcw_walk();
+    if (!w) return TCW_ENOMEM;
+    w->ctx = c;
+    int rc = prepare_space(c, t, sp, w->space);
+    if (rc) {
+        delete w;
+        return rc;
+    }
+    tcw::WalkDev& wd = w->wd;
+    wd.walks = walks;
+    wd.log2_table = log2_table;
+    wd.cap = cap;
+    wd.enumerate = enumerate ? 1 : 0;
+    wd.n_points = 2ull * w->space.dev.n_half;
+    wd.claw_cap = 4096;
+    hipError_t e = hipMalloc(&wd.states, (size_t)walks * sizeof(tcw::WalkState));
+    if (e == hipSuccess) e = hipMalloc(&wd.table, ((size_t)1 << log2_table) * 16);
+    if (e == hipSuccess) e = hipMalloc(&wd.stats, tcw::ST_COUNT * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc(&wd.claws, (size_t)wd.claw_cap * 16);
+    if (e == hipSuccess) e = hipMalloc(&wd.claw_count, sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        delete w;
+        return hip_fail(c, e, "walk session allocation");
+    }
+    rc = walk_restart(w);
+    if (rc) {
+        delete w;
+        return rc;
+    }
+    *out = w;
+    return TCW_OK;
+}
+
+int tcw_walk_run(tcw_walk* w, int iters) {
+    if (!w || iters < 1) return TCW_EINVAL;
+    tcw_ctx* c = w->ctx;
+    if (w->ended) return fail(c, TCW_ESTATE, "walk session ended");
+    HIP_TRY(c, hipMemsetAsync(&w->wd.stats[tcw::ST_ACTIVE], 0, sizeof(unsigned long long), c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+    HIP_TRY(c, tcw::launch_walk(w->space.n, w->space.dev, w->wd, iters, tcw::walk_grid_blocks(w->space.n, c->device),
+                                c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+    return TCW_OK;
+}
+
+int tcw_walk_stats_get(tcw_walk* w, tcw_walk_stats* out) {
+    if (!w || !out) return TCW_EINVAL;
+    tcw_ctx* c = w->ctx;
+    unsigned long long v[tcw::ST_COUNT];
+    HIP_TRY(c, hipMemcpyAsync(v, w->wd.stats, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    out->steps = (int64_t)v[tcw::ST_STEPS];
+    out->dps = (int64_t)v[tcw::ST_DPS];
+    out->inserts = (int64_t)v[tcw::ST_INSERTS];
+    out->abandoned = (int64_t)v[tcw::ST_ABANDONED];
+    out->robin_hood = (int64_t)v[tcw::ST_ROBIN];
+    out->same_side = (int64_t)v[tcw::ST_SAME];
+    out->reduction = (int64_t)v[tcw::ST_REDUCTION];
+    out->claws = (int64_t)v[tcw::ST_CLAWS];
+    out->table_full = (int64_t)v[tcw::ST_FULL];
+    out->spin_timeouts = (int64_t)v[tcw::ST_SPIN];
+    out->active_walks = (int64_t)v[tcw::ST_ACTIVE];
+    return TCW_OK;
+}
+
+int tcw_walk_claws(tcw_walk* w, uint64_t* u0, uint64_t* u1, int64_t max_pairs, int64_t* total) {
+    if (!w || !total || max_pairs < 0 || (max_pairs > 0 && (!u0 || !u1))) return TCW_EINVAL;
+    tcw_ctx* c = w->ctx;
+    unsigned long long cnt = 0;
+    HIP_TRY(c, hipMemcpyAsync(&cnt, w->wd.claw_count, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *total = (int64_t)cnt;
+    int64_t avail = (int64_t)(cnt < w->wd.claw_cap ? cnt : w->wd.claw_cap);
+    int64_t m = avail < max_pairs ? avail : max_pairs;
+    if (m > 0) {
+        std::vector<uint64_t> buf(2 * m);
+        HIP_TRY(c, hipMemcpyAsync(buf.data(), w->wd.claws, 16 * m, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (int64_t i = 0; i < m; ++i) {
+            u0[i] = buf[2 * i];
+            u1[i] = buf[2 * i + 1];
+        }
+    }
+    return TCW_OK;
+}
+
+int tcw_walk_reset(tcw_walk* w, uint32_t version) {
+    if (!w) return TCW_EINVAL;
+    w->space.set_version(version);
+    return walk_restart(w);
+}
+
+int tcw_walk_last_ms(tcw_walk* w, float* ms) {
+    if (!w || !ms) return TCW_EINVAL;
+    tcw_ctx* c = w->ctx;
+    HIP_TRY(c, hipEventSynchronize(c->ev1));
+    HIP_TRY(c, hipEventElapsedTime(ms, c->ev0, c->ev1));
+    return TCW_OK;
+}
+
+int tcw_walk_read_states(tcw_walk* w, int64_t first, int64_t count, void* host_out) {
+    if (!w || !host_out || first < 0 || count < 0 || first + count > w->wd.walks) return TCW_EINVAL;
+    tcw_ctx* c = w->ctx;
+    HIP_TRY(c, hipMemcpyAsync(host_out, w->wd.states + first, (size_t)count * sizeof(tcw::WalkState),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TCW_OK;
+}
+
+int tcw_walk_write_states(tcw_walk* w, int64_t first, int64_t count, const void* host_in) {
+    if (!w || !host_in || first < 0 || count < 0 || first + count > w->wd.walks) return TCW_EINVAL;
+    tcw_ctx* c = w->ctx;
+    HIP_TRY(c, hipMemcpyAsync(w->wd.states + first, host_in, (size_t)count * sizeof(tcw::WalkState),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TCW_OK;
+}
+
+int tcw_walk_read_table(tcw_walk* w, void* host_out) {
+    if (!w || !host_out) return TCW_EINVAL;
+    tcw_ctx* c = w->ctx;
+    HIP_TRY(c, hipMemcpyAsync(host_out, w->wd.table, ((size_t)1 << w->wd.log2_table) * 16, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TCW_OK;
+}
+
+int tcw_walk_write_table(tcw_walk* w, const void* host_in) {
+    if (!w || !host_in) return TCW_EINVAL;
+    tcw_ctx* c = w->ctx;
+    HIP_TRY(c, hipMemcpyAsync(w->wd.table, host_in, ((size_t)1 << w->wd.log2_table) * 16, hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TCW_OK;
+}
+
+int tcw_walk_end(tcw_walk* w) {
+    if (!w) return TCW_EINVAL;
+    (void)hipStreamSynchronize(w->ctx->stream);
+    delete w;
+    return TCW_OK;
+}
+
+// ---- search driver ----
+void tcw_default_params(tcw_walk_params* p, int n) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->k_max = 7;
+    p->delta = -1;
+    p->walks = n <= 2 ? 64 : (n == 3 ? (1 << 16) : (1 << 20));
+    p->log2_table = n <= 2 ? 12 : (n == 3 ? 20 : 26);
+    p->seed = 1;
+    p->version = 0;
+    p->trail_cap_factor = 20;
+    p->budget_beta = 4;
+    p->version_factor = 2;
+    p->enum_max = 1 << 16;
+    p->iters_per_launch = 0;
+    p->depth_order_kind = TCW_ORDER_PLAIN;
+    p->chunk_first = 0;
+    p->chunk_last = 0;
+    p->max_seconds = 0.0;
+}
+
+}  // extern "C"
+
+namespace {
+
+void decode_desc(uint64_t pt, int n, int h, std::vector<uint16_t>& out) {
+    uint32_t x = (uint32_t)pt;
+    const uint32_t xi = xi_of(n);
+    for (int t = 0; t < h; ++t) {
+        out.push_back((uint16_t)(x % xi + 1));
+        x /= xi;
+    }
+}
+
+void add_stats(tcw_walk_stats& a, const tcw_walk_stats& b) {
+    a.steps += b.steps;
+    a.dps += b.dps;
+    a.inserts += b.inserts;
+    a.abandoned += b.abandoned;
+    a.robin_hood += b.robin_hood;
+    a.same_side += b.same_side;
+    a.reduction += b.reduction;
+    a.claws += b.claws;
+    a.table_full += b.table_full;
+    a.spin_timeouts += b.spin_timeouts;
+}
+
+// Exact check of new claw candidates; fills res and returns 1 when one is a decomposition.
+int check_claws(tcw_ctx* c, tcw_walk* w, int64_t& seen, tcw_result* res, int* found) {
+    *found = 0;
+    int64_t total = 0;
+    std::vector<uint64_t> u0(4096), u1(4096);
+    int rc = tcw_walk_claws(w, u0.data(), u1.data(), 4096, &total);
+    if (rc) return rc;
+    const int64_t avail = total < 4096 ? total : 4096;
+    if (avail <= seen) return TCW_OK;
+    const int64_t m = avail - seen;
+    const int n = w->space.n;
+    const int R = 1 << (2 * n);
+    uint64_t *d0 = nullptr, *d1 = nullptr;
+    int32_t *dok = nullptr, *dperm = nullptr;
+    int8_t* dsign = nullptr;
+    HIP_TRY(c, hipMalloc(&d0, m * 8));
+    HIP_TRY(c, hipMalloc(&d1, m * 8));
+    HIP_TRY(c, hipMalloc(&dok, m * 4));
+    HIP_TRY(c, hipMalloc(&dperm, m * R * 4));
+    HIP_TRY(c, hipMalloc(&dsign, m * R));
+    HIP_TRY(c, hipMemcpyAsync(d0, u0.data() + seen, m * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d1, u1.data() + seen, m * 8, hipMemcpyHostToDevice, c->stream));
+    const size_t need = tcw::exact_claw_scratch_bytes(n);
+    if (c->claw_scratch_bytes < need) {
+        if (c->claw_scratch) (void)hipFree(c->claw_scratch);
+        c->claw_scratch = nullptr;
+        c->claw_scratch_bytes = 0;
+        HIP_TRY(c, hipMalloc(&c->claw_scratch, need));
+        c->claw_scratch_bytes = need;
+    }
+    HIP_TRY(c, tcw::exact_claw_check(w->space.S, w->space.k, d0, d1, m, c->claw_scratch, c->claw_scratch_bytes, dok,
+                                     dperm, dsign, c->stream));
+    std::vector<int32_t> ok(m), perm(m * R);
+    std::vector<int8_t> sign(m * R);
+    HIP_TRY(c, hipMemcpyAsync(ok.data(), dok, m * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(perm.data(), dperm, m * R * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(sign.data(), dsign, m * R, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(d0);
+    (void)hipFree(d1);
+    (void)hipFree(dok);
+    (void)hipFree(dperm);
+    (void)hipFree(dsign);
+    for (int64_t i = 0; i < m; ++i) {
+        if (!ok[i]) {
+            res->false_claws++;
+            continue;
+        }
+        uint64_t pv = u0[seen + i], pw = u1[seen + i];
+        if ((pv >> 32) & 1) std::swap(pv, pw);
+        const int h = w->space.k / 2;
+        std::vector<uint16_t> dv, dw, desc;
+        decode_desc(pv, n, h, dv);
+        decode_desc(pw, n, h, dw);
+        desc = dv;
+        for (int t = h - 1; t >= 0; --t) desc.push_back(dw[t]);
+        if (w->space.k % 2) desc.push_back((uint16_t)w->space.chunk);
+        res->status = 1;
+        res->t = w->space.k;
+        res->chunk = w->space.chunk;
+        for (size_t j = 0; j < desc.size() && j < TCW_MAX_T; ++j) res->paulis[j] = desc[j];
+        for (int q = 0; q < R; ++q) {
+            res->clifford_perm[q] = perm[i * R + q];
+            res->clifford_sign[q] = sign[i * R + q];
+        }
+        *found = 1;
+        break;
+    }
+    seen = avail;
+    return TCW_OK;
+}
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+extern "C" int tcw_search(tcw_ctx* c, const tcw_target* t, const tcw_walk_params* p, tcw_result* res) {
+    if (!c || !t || !p || !res) return TCW_EINVAL;
+    std::memset(res, 0, sizeof(*res));
+    const double t0 = now_s();
+    const int n = t->n;
+    const int R = 1 << (2 * n);
+    res->n = n;
+    if (p->k_max < 0 || p->k_max > TCW_MAX_T) return fail(c, TCW_EINVAL, "k_max out of range");
+    if (p->walks < 1) return fail(c, TCW_EINVAL, "walks must be positive");
+    std::vector<int> order;
+    if (p->depth_order_kind == TCW_ORDER_GIVEN) {
+        if (p->depth_order_len < 0 || p->depth_order_len > 16) return fail(c, TCW_EINVAL, "bad depth order");
+        for (int i = 0; i < p->depth_order_len; ++i) {
+            const int k = p->depth_order[i];
+            if (k < 0 || k > p->k_max) return fail(c, TCW_EINVAL, "depth order entry out of range");
+            bool dup = false;
+            for (int o : order) dup |= (o == k);
+            if (!dup) order.push_back(k);
+        }
+    }
+    // the plain increasing order is the fallback for depths the given order left out
+    for (int k = 0; k <= p->k_max; ++k) {
+        bool have = false;
+        for (int o : order) have |= (o == k);
+        if (!have) order.push_back(k);
+    }
+    const uint32_t xi = xi_of(n);
+    const int iters = p->iters_per_launch > 0 ? p->iters_per_launch : default_iters(n);
+    for (int k : order) {
+        if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) break;
+        if (k == 0) {
+            int32_t *dok = nullptr, *dperm = nullptr;
+            int8_t* dsign = nullptr;
+            HIP_TRY(c, hipMalloc(&dok, 4));
+            HIP_TRY(c, hipMalloc(&dperm, R * 4));
+            HIP_TRY(c, hipMalloc(&dsign, R));
+            HIP_TRY(c, tcw::exact_signed_perm(t->U, dok, dperm, dsign, c->stream));
+            int32_t ok = 0;
+            HIP_TRY(c, hipMemcpyAsync(&ok, dok, 4, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(res->clifford_perm, dperm, R * 4, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(res->clifford_sign, dsign, R, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            (void)hipFree(dok);
+            (void)hipFree(dperm);
+            (void)hipFree(dsign);
+            res->spaces++;
+            if (ok) {
+                res->status = 1;
+                res->t = 0;
+                res->seconds = now_s() - t0;
+                return TCW_OK;
+            }
+            continue;
+        }
+        const int h = k / 2;
+        const uint64_t nh = n_half_of(n, h);
+        if (nh == 0) continue;  // space beyond 32-bit points: not searchable here
+        const uint64_t npts = 2 * nh;
+        int cf = 0, cl = 0;
+        if (k % 2) {
+            cf = p->chunk_first > 0 ? p->chunk_first : 1;
+            cl = p->chunk_last > 0 ? p->chunk_last : (int)xi;
+            if (cl > (int)xi) cl = (int)xi;
+        }
+        const bool enumerate = (int64_t)npts <= p->enum_max;
+        const int delta = enumerate ? 0 : (p->delta >= 0 ? p->delta : default_delta(n));
+        for (int chunk = cf; chunk <= cl; ++chunk) {
+            if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) break;
+            tcw_space sp{k, chunk, p->seed, p->version, delta};
+            res->spaces++;
+            tcw_walk* w = nullptr;
+            int found = 0;
+            int64_t seen = 0;
+            if (enumerate) {
+                int64_t walks = (int64_t)npts < p->walks ? (int64_t)npts : p->walks;
+                if (walks < 64) walks = (int64_t)npts < 64 ? (int64_t)npts : 64;
+                int lg = 4;
+                while ((1ull << lg) < 4 * npts && lg < 30) ++lg;
+                int rc = tcw_walk_begin(c, t, &sp, walks, lg, 2, 1, &w);
+                if (rc) return rc;
+                res->versions++;
+                for (;;) {
+                    rc = tcw_walk_run(w, iters);
+                    res->launches++;
+                    tcw_walk_stats st{};
+                    if (!rc) rc = tcw_walk_stats_get(w, &st);
+                    if (!rc) rc = check_claws(c, w, seen, res, &found);
+                    if (rc) {
+                        tcw_walk_end(w);
+                        return rc;
+                    }
+                    if (found || st.active_walks == 0) {
+                        add_stats(res->stats, st);
+                        break;
+                    }
+                    // counters are cumulative within the session: add only at the end
+                    if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) {
+                        add_stats(res->stats, st);
+                        break;
+                    }
+                }
+                tcw_walk_end(w);
+            } else {
+                const uint64_t budget = (uint64_t)p->budget_beta * npts << delta;
+                uint64_t per_version = (uint64_t)p->version_factor * npts;
+                const uint64_t floor_v = 2ull * (uint64_t)p->walks << delta;
+                if (per_version < floor_v) per_version = floor_v;
+                const uint32_t cap = (uint32_t)p->trail_cap_factor << delta;
+                // a launch must not overrun a function version
+                int iters_v = iters;
+                const uint64_t fit = per_version / (uint64_t)p->walks;
+                if ((uint64_t)iters_v > fit) iters_v = fit > 0 ? (int)fit : 1;
+                int rc = tcw_walk_begin(c, t, &sp, p->walks, p->log2_table, cap, 0, &w);
+                if (rc) return rc;
+                uint64_t used = 0;
+                uint32_t version = p->version;
+                res->versions++;
+                uint64_t used_v = 0;
+                tcw_walk_stats st{};
+                while (used < budget) {
+                    rc = tcw_walk_run(w, iters_v);
+                    res->launches++;
+                    if (!rc) rc = tcw_walk_stats_get(w, &st);
+                    if (!rc) rc = check_claws(c, w, seen, res, &found);
+                    if (rc) {
+                        tcw_walk_end(w);
+                        return rc;
+                    }
+                    used = used - used_v + (uint64_t)st.steps;
+                    used_v = (uint64_t)st.steps;
+                    if (found) break;
+                    if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) break;
+                    if (used_v >= per_version && used < budget) {
+                        add_stats(res->stats, st);
+                        std::memset(&st, 0, sizeof(st));
+                        used_v = 0;
+                        seen = 0;
+                        ++version;
+                        res->versions++;
+                        rc = tcw_walk_reset(w, version);
+                        if (rc) {
+                            tcw_walk_end(w);
+                            return rc;
+                        }
+                    }
+                }
+                add_stats(res->stats, st);
+                tcw_walk_end(w);
+            }
+            if (found) {
+                res->seconds = now_s() - t0;
+                return TCW_OK;
+            }
+        }
+    }
+    res->status = 0;
+    res->seconds = now_s() - t0;
+    return TCW_OK;
+}

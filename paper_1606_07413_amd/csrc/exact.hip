@@ -1,0 +1,474 @@
+// Exact channel-representation arithmetic over Z[1/sqrt2] (Sec. 4.1) on the GPU.
+//
+// A matrix is M = (A + B sqrt2) / sqrt2^e with integer A, B (int64 for n <= 2, int32 for n >= 3)
+// and minimal e.  Right multiplication by the channel rep of R(P_p) follows its sparse column
+// rule: column q is e_q when <p, q> = 0, else (e_q + s(p, q) e_{p^q}) / sqrt2, so
+//   (M R)[:, q] = (M[:, q] + s M[:, p^q]) / sqrt2        (anticommuting q)
+//   (M R)[:, q] = (sqrt2 M[:, q]) / sqrt2, (a, b) -> (2b, a)   (commuting q)
+// and R^T flips s.  Every kernel here is single-block per matrix: these are set-up and
+// verification paths (target preparation, chunk matrices S_c, claw checks), not the walk loop.
+#include "common.h"
+#include "internal.h"
+
+namespace tcw {
+
+namespace {
+
+template <int NQ>
+struct EGeo {
+    static constexpr int R = 1 << (2 * NQ);
+};
+
+template <typename T>
+__device__ inline T lim_of();
+template <>
+__device__ inline int32_t lim_of<int32_t>() { return (int32_t)1 << 29; }
+template <>
+__device__ inline int64_t lim_of<int64_t>() { return (int64_t)1 << 60; }
+
+// (A, B, e) <- product with R(seq[0])^(T?) ... ; result left in (a, b).  Whole block cooperates.
+template <int NQ, typename T>
+__device__ void block_apply(T* a, T* b, T* ta, T* tb, int& e, const uint16_t* seq, const uint8_t* tr, int nseq,
+                            int* flag) {
+    constexpr int R = EGeo<NQ>::R;
+    const T lim = lim_of<T>();
+    T *ca = a, *cb = b, *na = ta, *nb = tb;
+    for (int s = 0; s < nseq; ++s) {
+        const uint32_t p = seq[s];
+        const bool t = tr != nullptr && tr[s] != 0;
+        for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) {
+            const uint32_t q = idx & (R - 1);
+            const int row = idx - (int)q;
+            T va, vb;
+            if (anticommutes<NQ>(p, q)) {
+                int sg = rotation_sign<NQ>(p, q);
+                if (t) sg = -sg;
+                const int j = row + (int)(q ^ p);
+                va = sg > 0 ? ca[idx] + ca[j] : ca[idx] - ca[j];
+                vb = sg > 0 ? cb[idx] + cb[j] : cb[idx] - cb[j];
+            } else {
+                va = cb[idx] * 2;
+                vb = ca[idx];
+            }
+            if (va > lim || va < -lim || vb > lim || vb < -lim) atomicOr(flag, 4);
+            na[idx] = va;
+            nb[idx] = vb;
+        }
+        __syncthreads();
+        T* x = ca; ca = na; na = x;
+        x = cb; cb = nb; nb = x;
+        e += 1;
+        // reduce: while every a is even, (a + b sqrt2)/sqrt2 = b + (a/2) sqrt2
+        while (e > 0) {
+            int odd = 0;
+            for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) odd |= (int)(ca[idx] & 1);
+            if (__syncthreads_or(odd)) break;
+            for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) {
+                const T va = ca[idx], vb = cb[idx];
+                ca[idx] = vb;
+                cb[idx] = va / 2;
+            }
+            e -= 1;
+            __syncthreads();
+        }
+    }
+    if (ca != a) {
+        for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) {
+            a[idx] = ca[idx];
+            b[idx] = cb[idx];
+        }
+        __syncthreads();
+    }
+}
+
+template <int NQ, typename T>
+__device__ void block_reduce(T* a, T* b, int& e) {
+    constexpr int R = EGeo<NQ>::R;
+    while (e > 0) {
+        int odd = 0;
+        for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) odd |= (int)(a[idx] & 1);
+        if (__syncthreads_or(odd)) break;
+        for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) {
+            const T va = a[idx], vb = b[idx];
+            a[idx] = vb;
+            b[idx] = va / 2;
+        }
+        e -= 1;
+        __syncthreads();
+    }
+}
+
+template <int NQ, typename T>
+__global__ __launch_bounds__(1024) void k_identity(T* a, T* b, int32_t* e) {
+    constexpr int R = EGeo<NQ>::R;
+    for (int idx = threadIdx.x + blockIdx.x * blockDim.x; idx < R * R; idx += blockDim.x * gridDim.x) {
+        const int r = idx / R, q = idx % R;
+        a[idx] = (r == q) ? 1 : 0;
+        b[idx] = 0;
+    }
+    if (threadIdx.x == 0 && blockIdx.x == 0) *e = 0;
+}
+
+template <int NQ, typename T>
+__global__ __launch_bounds__(1024) void k_apply(T* a, T* b, T* ta, T* tb, int32_t* e_io, const T* sa, const T* sb,
+                                                const int32_t* se, const uint16_t* seq, const uint8_t* tr, int nseq,
+                                                int* flag) {
+    constexpr int R = EGeo<NQ>::R;
+    if (sa != a) {
+        for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) {
+            a[idx] = sa[idx];
+            b[idx] = sb[idx];
+        }
+    }
+    __syncthreads();
+    int e = *se;
+    __syncthreads();
+    block_apply<NQ, T>(a, b, ta, tb, e, seq, tr, nseq, flag);
+    if (threadIdx.x == 0) *e_io = e;
+}
+
+template <int NQ, typename T>
+__global__ __launch_bounds__(1024) void k_from_i32(T* a, T* b, int32_t* e_io, const int32_t* ia, const int32_t* ib,
+                                                   int32_t e0) {
+    constexpr int R = EGeo<NQ>::R;
+    for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) {
+        a[idx] = (T)ia[idx];
+        b[idx] = (T)ib[idx];
+    }
+    __syncthreads();
+    int e = e0;
+    block_reduce<NQ, T>(a, b, e);
+    if (threadIdx.x == 0) *e_io = e;
+}
+
+template <int NQ, typename T>
+__global__ void k_to_i32(const T* a, const T* b, int32_t* oa, int32_t* ob, int* flag) {
+    constexpr int R = EGeo<NQ>::R;
+    for (int idx = threadIdx.x + blockIdx.x * blockDim.x; idx < R * R; idx += blockDim.x * gridDim.x) {
+        const T va = a[idx], vb = b[idx];
+        if (va > (T)INT32_MAX || va < (T)INT32_MIN || vb > (T)INT32_MAX || vb < (T)INT32_MIN) atomicOr(flag, 4);
+        oa[idx] = (int32_t)va;
+        ob[idx] = (int32_t)vb;
+    }
+}
+
+// X X^T = 2^e I with X = A + B sqrt2:  A A^T + 2 B B^T = 2^e I  and  A B^T + B A^T = 0.
+template <int NQ, typename T>
+__global__ void k_orthogonal(const T* a, const T* b, const int32_t* e_p, int* flag) {
+    constexpr int R = EGeo<NQ>::R;
+    const int idx = threadIdx.x + blockIdx.x * blockDim.x;
+    if (idx >= R * R) return;
+    const int i = idx / R, j = idx % R;
+    const int e = *e_p;
+    int64_t rat = 0, irr = 0;
+    for (int k = 0; k < R; ++k) {
+        const int64_t ai = a[i * R + k], bi = b[i * R + k], aj = a[j * R + k], bj = b[j * R + k];
+        if (ai > (1 << 24) || ai < -(1 << 24) || bi > (1 << 24) || bi < -(1 << 24)) {
+            atomicOr(flag, 4);
+            return;
+        }
+        rat += ai * aj + 2 * bi * bj;
+        irr += ai * bj + bi * aj;
+    }
+    const int64_t want = (i == j) ? ((e < 62) ? ((int64_t)1 << e) : -1) : 0;
+    if (rat != want || irr != 0) atomicOr(flag, 1);
+}
+
+// Signed permutation test on a reduced matrix: e = 0, B = 0, each column one +-1.
+template <int NQ, typename T>
+__global__ __launch_bounds__(256) void k_signed_perm(const T* a, const T* b, const int32_t* e_p, int32_t* ok,
+                                                     int32_t* perm, int8_t* sign) {
+    constexpr int R = EGeo<NQ>::R;
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = (*e_p != 0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < R; q += blockDim.x) {
+        int cnt = 0, row = -1, sg = 0;
+        for (int i = 0; i < R; ++i) {
+            const T va = a[i * R + q], vb = b[i * R + q];
+            if (vb != 0) cnt += 2;
+            if (va != 0) {
+                cnt += 1;
+                row = i;
+                sg = (va == 1) ? 1 : (va == -1 ? -1 : 0);
+            }
+        }
+        if (cnt != 1 || sg == 0) atomicOr(&bad, 1);
+        perm[q] = row;
+        sign[q] = (int8_t)sg;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *ok = bad ? 0 : 1;
+}
+
+// int8 packing of S for the walk kernels: phi[q4 * R + r] = bytes A[r][4 q4 .. 4 q4 + 3] (then B).
+template <int NQ, typename T>
+__global__ void k_pack_phi(const T* a, const T* b, uint32_t* phi, int* flag) {
+    constexpr int R = EGeo<NQ>::R;
+    constexpr int Q4 = R / 4;
+    const int idx = threadIdx.x + blockIdx.x * blockDim.x;
+    if (idx >= Q4 * R) return;
+    const int q4 = idx / R, r = idx % R;
+    uint32_t wa = 0, wb = 0;
+    for (int c = 0; c < 4; ++c) {
+        const T va = a[r * R + 4 * q4 + c], vb = b[r * R + 4 * q4 + c];
+        if (va > 127 || va < -127 || vb > 127 || vb < -127) atomicOr(flag, 2);
+        wa |= ((uint32_t)(uint8_t)(int8_t)va) << (8 * c);
+        wb |= ((uint32_t)(uint8_t)(int8_t)vb) << (8 * c);
+    }
+    phi[idx] = wa;
+    phi[Q4 * R + idx] = wb;
+}
+
+// Claw check of (u0, u1): V = R(p_0)...R(p_{h-1}) from the side-0 point, W = S R(q_0)^T ... from
+// the side-1 point, D = W V^T must be a signed permutation (Sec. 3, last merge case).
+template <int NQ, typename T>
+__global__ __launch_bounds__(1024) void k_claw(const T* sa, const T* sb, const int32_t* se, int k, const uint64_t* u0,
+                                               const uint64_t* u1, int64_t count, T* scratch, int32_t* ok,
+                                               int32_t* perm, int8_t* sign) {
+    constexpr int R = EGeo<NQ>::R;
+    constexpr uint32_t XI = R - 1;
+    __shared__ uint16_t seq[64];
+    __shared__ uint8_t trs[64];
+    __shared__ int cnt[R];
+    __shared__ int rowof[R];
+    __shared__ int sgn[R];
+    __shared__ int bad;
+    __shared__ int oflow;
+    T* va = scratch + (size_t)blockIdx.x * 6 * R * R;
+    T* vb = va + R * R;
+    T* wa = vb + R * R;
+    T* wb = wa + R * R;
+    T* ta = wb + R * R;
+    T* tb = ta + R * R;
+    const int h = k / 2;
+    for (int64_t pi = blockIdx.x; pi < count; pi += gridDim.x) {
+        uint64_t p0 = u0[pi], p1 = u1[pi];
+        if ((p0 >> 32) & 1) {
+            const uint64_t x = p0; p0 = p1; p1 = x;
+        }
+        const bool sides_ok = (((p0 >> 32) & 1) == 0) && (((p1 >> 32) & 1) == 1);
+        // V from the identity
+        for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) {
+            va[idx] = ((idx / R) == (idx % R)) ? 1 : 0;
+            vb[idx] = 0;
+            wa[idx] = sa[idx];
+            wb[idx] = sb[idx];
+        }
+        if (threadIdx.x == 0) {
+            uint32_t x = (uint32_t)p0;
+            for (int t = 0; t < h; ++t) {
+                seq[t] = (uint16_t)(x % XI + 1);
+                trs[t] = 0;
+                x /= XI;
+            }
+            bad = sides_ok ? 0 : 1;
+            oflow = 0;
+        }
+        __syncthreads();
+        int ev = 0;
+        block_apply<NQ, T>(va, vb, ta, tb, ev, seq, trs, h, &oflow);
+        if (threadIdx.x == 0) {
+            uint32_t x = (uint32_t)p1;
+            for (int t = 0; t < h; ++t) {
+                seq[t] = (uint16_t)(x % XI + 1);
+                trs[t] = 1;
+                x /= XI;
+            }
+        }
+        __syncthreads();
+        int ew = *se;
+        block_apply<NQ, T>(wa, wb, ta, tb, ew, seq, trs, h, &oflow);
+        for (int q = threadIdx.x; q < R; q += blockDim.x) {
+            cnt[q] = 0;
+            rowof[q] = -1;
+            sgn[q] = 0;
+        }
+        __syncthreads();
+        // D_iq = sum_k W_ik V_qk with exponent E = ew + ev; a unit entry is +-sqrt2^E
+        const int E = ew + ev;
+        const int64_t unit = (int64_t)1 << (E / 2);
+        for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) {
+            const int i = idx / R, q = idx % R;
+            int64_t da = 0, db = 0;
+            for (int kk = 0; kk < R; ++kk) {
+                const int64_t xa = wa[i * R + kk], xb = wb[i * R + kk];
+                const int64_t ya = va[q * R + kk], yb = vb[q * R + kk];
+                da += xa * ya + 2 * xb * yb;
+                db += xa * yb + xb * ya;
+            }
+            if (da != 0 || db != 0) {
+                atomicAdd(&cnt[q], 1);
+                int s = 0;
+                if (E % 2 == 0) {
+                    if (db == 0 && (da == unit || da == -unit)) s = da > 0 ? 1 : -1;
+                } else {
+                    if (da == 0 && (db == unit || db == -unit)) s = db > 0 ? 1 : -1;
+                }
+                if (s == 0) atomicOr(&bad, 1);
+                rowof[q] = i;
+                sgn[q] = s;
+            }
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < R; q += blockDim.x) {
+            if (cnt[q] != 1) atomicOr(&bad, 1);
+        }
+        __syncthreads();
+        const int good = (bad == 0 && oflow == 0) ? 1 : 0;
+        for (int q = threadIdx.x; q < R; q += blockDim.x) {
+            perm[pi * R + q] = good ? rowof[q] : -1;
+            sign[pi * R + q] = (int8_t)(good ? sgn[q] : 0);
+        }
+        if (threadIdx.x == 0) ok[pi] = good;
+        __syncthreads();
+    }
+}
+
+template <typename F>
+hipError_t dispatch_exact(int n, F&& f) {
+    switch (n) {
+        case 1: return f.template operator()<1, int64_t>();
+        case 2: return f.template operator()<2, int64_t>();
+        case 3: return f.template operator()<3, int32_t>();
+        case 4: return f.template operator()<4, int32_t>();
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t exact_alloc(ExactDev& m, int n) {
+    m.n = n;
+    m.r = 1 << (2 * n);
+    m.elem = n <= 2 ? 8 : 4;
+    const size_t bytes = (size_t)m.r * m.r * m.elem;
+    hipError_t err = hipMalloc(&m.a, bytes);
+    if (err == hipSuccess) err = hipMalloc(&m.b, bytes);
+    if (err == hipSuccess) err = hipMalloc(&m.e, sizeof(int32_t));
+    return err;
+}
+
+void exact_free(ExactDev& m) {
+    if (m.a) (void)hipFree(m.a);
+    if (m.b) (void)hipFree(m.b);
+    if (m.e) (void)hipFree(m.e);
+    m.a = m.b = nullptr;
+    m.e = nullptr;
+}
+
+namespace {
+struct ScratchPair {
+    void* ta = nullptr;
+    void* tb = nullptr;
+};
+hipError_t scratch_pair(const ExactDev& m, ScratchPair& sp) {
+    const size_t bytes = (size_t)m.r * m.r * m.elem;
+    hipError_t err = hipMalloc(&sp.ta, bytes);
+    if (err == hipSuccess) err = hipMalloc(&sp.tb, bytes);
+    return err;
+}
+void scratch_free(ScratchPair& sp) {
+    if (sp.ta) (void)hipFree(sp.ta);
+    if (sp.tb) (void)hipFree(sp.tb);
+}
+}  // namespace
+
+hipError_t exact_apply(ExactDev& dst, const ExactDev& src, const uint16_t* seq, const uint8_t* tr, int nseq,
+                       int* flag, hipStream_t s) {
+    ScratchPair sp;
+    hipError_t err = scratch_pair(dst, sp);
+    if (err != hipSuccess) {
+        scratch_free(sp);
+        return err;
+    }
+    auto f = [&]<int NQ, typename T>() -> hipError_t {
+        hipLaunchKernelGGL((k_apply<NQ, T>), dim3(1), dim3(1024), 0, s, (T*)dst.a, (T*)dst.b, (T*)sp.ta, (T*)sp.tb,
+                           dst.e, (const T*)src.a, (const T*)src.b, src.e, seq, tr, nseq, flag);
+        return hipGetLastError();
+    };
+    err = dispatch_exact(dst.n, f);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    scratch_free(sp);
+    return err;
+}
+
+hipError_t exact_build(ExactDev& m, const uint16_t* seq, const uint8_t* tr, int nseq, int* flag, hipStream_t s) {
+    auto f = [&]<int NQ, typename T>() -> hipError_t {
+        hipLaunchKernelGGL((k_identity<NQ, T>), dim3(64), dim3(1024), 0, s, (T*)m.a, (T*)m.b, m.e);
+        return hipGetLastError();
+    };
+    hipError_t err = dispatch_exact(m.n, f);
+    if (err != hipSuccess) return err;
+    return exact_apply(m, m, seq, tr, nseq, flag, s);
+}
+
+hipError_t exact_from_i32(ExactDev& m, const int32_t* a, const int32_t* b, int32_t e, int* flag, hipStream_t s) {
+    (void)flag;
+    auto f = [&]<int NQ, typename T>() -> hipError_t {
+        hipLaunchKernelGGL((k_from_i32<NQ, T>), dim3(1), dim3(1024), 0, s, (T*)m.a, (T*)m.b, m.e, a, b, e);
+        return hipGetLastError();
+    };
+    return dispatch_exact(m.n, f);
+}
+
+hipError_t exact_to_i32(const ExactDev& m, int32_t* a, int32_t* b, int* flag, hipStream_t s) {
+    auto f = [&]<int NQ, typename T>() -> hipError_t {
+        hipLaunchKernelGGL((k_to_i32<NQ, T>), dim3(64), dim3(1024), 0, s, (const T*)m.a, (const T*)m.b, a, b,
+                           flag);
+        return hipGetLastError();
+    };
+    return dispatch_exact(m.n, f);
+}
+
+hipError_t exact_check_orthogonal(const ExactDev& m, int* flag, hipStream_t s) {
+    auto f = [&]<int NQ, typename T>() -> hipError_t {
+        constexpr int R = 1 << (2 * NQ);
+        hipLaunchKernelGGL((k_orthogonal<NQ, T>), dim3((R * R + 255) / 256), dim3(256), 0, s, (const T*)m.a,
+                           (const T*)m.b, m.e, flag);
+        return hipGetLastError();
+    };
+    return dispatch_exact(m.n, f);
+}
+
+hipError_t exact_signed_perm(const ExactDev& m, int32_t* ok, int32_t* perm, int8_t* sign, hipStream_t s) {
+    auto f = [&]<int NQ, typename T>() -> hipError_t {
+        hipLaunchKernelGGL((k_signed_perm<NQ, T>), dim3(1), dim3(256), 0, s, (const T*)m.a, (const T*)m.b, m.e,
+                           ok, perm, sign);
+        return hipGetLastError();
+    };
+    return dispatch_exact(m.n, f);
+}
+
+hipError_t exact_pack_phi(const ExactDev& m, uint32_t* phi, int* flag, hipStream_t s) {
+    auto f = [&]<int NQ, typename T>() -> hipError_t {
+        constexpr int R = 1 << (2 * NQ);
+        const int nthr = R / 4 * R;
+        hipLaunchKernelGGL((k_pack_phi<NQ, T>), dim3((nthr + 255) / 256), dim3(256), 0, s, (const T*)m.a,
+                           (const T*)m.b, phi, flag);
+        return hipGetLastError();
+    };
+    return dispatch_exact(m.n, f);
+}
+
+size_t exact_claw_scratch_bytes(int n) {
+    const size_t r = (size_t)1 << (2 * n);
+    const size_t elem = n <= 2 ? 8 : 4;
+    return 16 * 6 * r * r * elem;  // 16 blocks, 6 matrices of R x R each
+}
+
+hipError_t exact_claw_check(const ExactDev& S, int k, const uint64_t* u0, const uint64_t* u1, int64_t count,
+                            void* scratch, size_t scratch_bytes, int32_t* ok, int32_t* perm, int8_t* sign,
+                            hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (scratch_bytes < exact_claw_scratch_bytes(S.n)) return hipErrorInvalidValue;
+    auto f = [&]<int NQ, typename T>() -> hipError_t {
+        const int blocks = (int)(count < 16 ? count : 16);
+        hipLaunchKernelGGL((k_claw<NQ, T>), dim3(blocks), dim3(1024), 0, s, (const T*)S.a, (const T*)S.b, S.e, k,
+                           u0, u1, count, (T*)scratch, ok, perm, sign);
+        return hipGetLastError();
+    };
+    return dispatch_exact(S.n, f);
+}
+
+}  // namespace tcw

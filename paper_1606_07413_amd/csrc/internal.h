@@ -1,0 +1,111 @@
+// Internal structures shared by the host driver (api.hip) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace tcw {
+
+// One search space (target x depth k x chunk x function version), as the walk kernels see it.
+struct SpaceDev {
+    uint32_t n_half;    // xi^h, points per side
+    int32_t h;          // rotations per half
+    int32_t delta;      // theta = 2^-delta
+    int32_t rot_e;      // (30 * e_S) mod 61: multiplication by phi(1/sqrt2)^e_S in Z/p
+    uint64_t salt_h;    // matrix-hash salt
+    uint64_t salt_d;    // distinguished-point salt
+    uint64_t salt_s;    // trail-start salt
+    const uint32_t* phi;   // S_c as int8: A packed [q4][r] dwords, then B packed the same way
+    const uint64_t* keys;  // K[R] (row-digest keys, < p) then K2[R] (odd position keys)
+};
+
+enum : uint32_t { MODE_WALK = 0, MODE_ALIGN = 1, MODE_LOCK = 2, MODE_DONE = 3 };
+
+// 64-byte walk state, kept in HBM between launches.
+struct WalkState {
+    uint64_t start;  // start point of the current trail
+    uint64_t cur;    // WALK: current point
+    uint64_t pa;     // backtracking: point on the own trail
+    uint64_t pb;     // backtracking: point on the stored trail
+    uint64_t na;     // LOCK phase 1: f(pa)
+    uint64_t ha;     // LOCK phase 1: matrix hash of pa
+    uint32_t len;    // WALK: steps in the trail; backtracking: common remaining length
+    uint32_t trail;  // trail index j
+    uint32_t mode;   // MODE_*; bit 8: which point ALIGN advances / LOCK phase
+    uint32_t rem;    // ALIGN / LOCK: steps left
+};
+static_assert(sizeof(WalkState) == 64, "walk state is 64 bytes");
+
+enum StatIdx {
+    ST_STEPS = 0, ST_DPS, ST_INSERTS, ST_ABANDONED, ST_ROBIN, ST_SAME, ST_REDUCTION, ST_CLAWS,
+    ST_FULL, ST_SPIN, ST_ACTIVE, ST_COUNT
+};
+
+struct WalkDev {
+    WalkState* states;
+    int64_t walks;
+    uint64_t* table;            // 2^log2_table slots of (key, value) u64 pairs
+    int32_t log2_table;
+    uint32_t cap;               // trail cap
+    int32_t enumerate;          // 1: trail j of walk w starts at point w + walks * j
+    uint64_t n_points;          // 2 * n_half
+    unsigned long long* stats;  // ST_COUNT counters
+    uint64_t* claws;            // claw candidate pairs (u0, u1)
+    unsigned long long* claw_count;
+    uint32_t claw_cap;
+};
+
+// ---- launchers (exact.hip) ----
+// Exact matrices live on the device as int32 pairs (int64 for n <= 2) with exponent e.
+struct ExactDev {
+    int n = 0;
+    int r = 0;
+    void* a = nullptr;   // R*R elements of int32 (n >= 3) or int64 (n <= 2)
+    void* b = nullptr;
+    int32_t* e = nullptr;  // device scalar exponent
+    size_t elem = 0;       // element size in bytes
+};
+
+hipError_t exact_alloc(ExactDev& m, int n);
+void exact_free(ExactDev& m);
+// m = prod_j R(C_j)^2 * R(P_k) ... R(P_1) (seq given as right-multiplications), reduced.
+hipError_t exact_build(ExactDev& m, const uint16_t* seq_dev, const uint8_t* transpose_dev, int nseq,
+                       int* flag_dev, hipStream_t s);
+// dst = src * R(seq[0])^(T?) * ... , reduced; dst and src may alias.
+hipError_t exact_apply(ExactDev& dst, const ExactDev& src, const uint16_t* seq_dev, const uint8_t* transpose_dev,
+                       int nseq, int* flag_dev, hipStream_t s);
+// load int32 host-provided values already on the device
+hipError_t exact_from_i32(ExactDev& m, const int32_t* a_dev, const int32_t* b_dev, int32_t e, int* flag_dev,
+                          hipStream_t s);
+hipError_t exact_to_i32(const ExactDev& m, int32_t* a_dev, int32_t* b_dev, int* flag_dev, hipStream_t s);
+// flag |= 1 if X X^T != 2^e I
+hipError_t exact_check_orthogonal(const ExactDev& m, int* flag_dev, hipStream_t s);
+// ok/perm/sign of a reduced matrix being a signed permutation
+hipError_t exact_signed_perm(const ExactDev& m, int32_t* ok_dev, int32_t* perm_dev, int8_t* sign_dev, hipStream_t s);
+// int8 packing of S for the walk kernels; flag |= 2 if a value is outside [-127, 127]
+hipError_t exact_pack_phi(const ExactDev& m, uint32_t* phi_dev, int* flag_dev, hipStream_t s);
+// claw checks: for each pair (u0, u1) compute V, W exactly and D = W V^T
+hipError_t exact_claw_check(const ExactDev& S, int k, const uint64_t* u0, const uint64_t* u1, int64_t count,
+                            void* scratch, size_t scratch_bytes, int32_t* ok, int32_t* perm, int8_t* sign,
+                            hipStream_t s);
+size_t exact_claw_scratch_bytes(int n);
+
+// ---- launchers (walk.hip) ----
+hipError_t keys_fill(int n, uint64_t seed, uint64_t* keys_dev, hipStream_t s);
+hipError_t launch_step(int n, const SpaceDev& sp, const uint64_t* in, uint64_t* out, uint64_t* hash, int64_t count,
+                       hipStream_t s);
+hipError_t launch_trails(int n, const SpaceDev& sp, const uint64_t* starts, int64_t count, uint32_t cap,
+                         uint64_t* dp, uint32_t* len, hipStream_t s);
+hipError_t launch_starts(const SpaceDev& sp, int64_t w0, uint32_t j, int64_t count, uint64_t* out, hipStream_t s);
+hipError_t launch_canon_hash(int n, const SpaceDev& sp, const uint32_t* phi_all, const int32_t* e, int64_t count,
+                             uint64_t* out, hipStream_t s);
+hipError_t launch_walk(int n, const SpaceDev& sp, const WalkDev& wd, int iters, int grid_blocks, hipStream_t s);
+hipError_t launch_walk_init(const SpaceDev& sp, const WalkDev& wd, hipStream_t s);
+hipError_t launch_table_clear(uint64_t* table, int log2_table, hipStream_t s);
+int walk_grid_blocks(int n, int device);
+hipError_t pack_phi_i32(int n, const int32_t* a, const int32_t* b, int64_t count, uint32_t* phi_out,
+                        int* flag_dev, hipStream_t s);
+
+}  // namespace tcw

@@ -1,0 +1,761 @@
+// The walk step of the deterministic-walk claw search (Sec. 2 and Sec. 3) on gfx950.
+//
+// One walk is owned by a group of G = min(4^n, 64) lanes of one wavefront; lane gl holds the
+// RPL = 4^n / G consecutive rows r = gl * RPL + j.  A step f(x, b) computes the matrix hash of
+//   side 0: M = R(p_0) ... R(p_{h-1}),   side 1: M = S_c R(p_0)^T ... R(p_{h-1})^T
+// (channel representations; p_j = base-xi digit j of x, plus one).  The hash needs only the row
+// digests S_r = sum_q K[q] phi(M_rq) in Z/p, p = 2^61 - 1, phi(sqrt2) = 2^31, i.e. the vector
+// phi(M) K.  By associativity that vector is computed without forming M:
+//   side 0: S = R(p_0) (R(p_1) ( ... (R(p_{h-1}) K)))
+//   side 1: S = phi(S_c) u,  u = R(p_0)^T ( ... (R(p_{h-1})^T K))
+// Each factor touches the vector by the channel rep's column rule (one butterfly per
+// anticommuting row; the 1/sqrt2 is a 61-bit rotation by 30), and the side-1 product with the
+// fixed chunk matrix S_c = (A + B sqrt2)/sqrt2^e runs as int8 dot products (v_dot4_i32_i8) of A
+// and B against 7-bit limbs of u, A and B resident in LDS.  Then (nu + h of Sec. 2):
+//   D_r = min(S_r, p - S_r)   (sign-normalised row: negating a row negates S_r)
+//   sort D ascending with a wavefront bitonic network            (left-Clifford canonical order)
+//   H = mix64(salt_h + sum_i K2[i] D_(i))                          (mod 2^64: order-independent)
+//   f(x, b) = (floor(H * xi^h / 2^64), H mod 2)                    (reduction back to a point)
+#include "common.h"
+#include "internal.h"
+
+namespace tcw {
+
+namespace {
+
+template <int NQ>
+struct Geo {
+    static constexpr int R = 1 << (2 * NQ);
+    static constexpr uint32_t XI = (uint32_t)R - 1;
+    static constexpr int G = R < 64 ? R : 64;       // lanes per walk
+    static constexpr int RPL = R / G;               // rows per lane (1 or 4)
+    static constexpr int LRPL = RPL == 4 ? 2 : 0;
+    static constexpr int WPW = 64 / G;              // walks per wavefront
+    static constexpr int Q4 = R / 4;                // 4-column groups
+    // most rotations per half with xi^h < 2^32
+    static constexpr int HMAX = NQ == 1 ? 20 : (NQ == 2 ? 8 : (NQ == 3 ? 5 : 4));
+};
+
+template <int NQ, int WAVES>
+struct Lds {
+    uint32_t phiA[Geo<NQ>::Q4 * Geo<NQ>::R];
+    uint32_t phiB[Geo<NQ>::Q4 * Geo<NQ>::R];
+    uint64_t K[Geo<NQ>::R];
+    uint64_t K2[Geo<NQ>::R];
+    uint32_t limbs[WAVES * Geo<NQ>::WPW][Geo<NQ>::Q4 * LIMB_STRIDE];
+};
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int NQ, int WAVES>
+__device__ void load_lds(Lds<NQ, WAVES>& L, const SpaceDev& sp) {
+    using Gm = Geo<NQ>;
+    constexpr int NPHI = Gm::Q4 * Gm::R;
+    for (int i = threadIdx.x; i < NPHI; i += blockDim.x) {
+        L.phiA[i] = sp.phi[i];
+        L.phiB[i] = sp.phi[NPHI + i];
+    }
+    for (int i = threadIdx.x; i < Gm::R; i += blockDim.x) {
+        L.K[i] = sp.keys[i];
+        L.K2[i] = sp.keys[Gm::R + i];
+    }
+}
+
+__device__ inline uint64_t pick4(const uint64_t* u, int i) {
+    const uint64_t lo = (i & 1) ? u[1] : u[0];
+    const uint64_t hi = (i & 1) ? u[3] : u[2];
+    return (i & 2) ? hi : lo;
+}
+
+// Sort RPL keys per lane across the G lanes of a group, ascending in index i = gl * RPL + j.
+template <int NQ>
+__device__ inline void bitonic_sort(uint64_t* d, int gl, int gbase) {
+    using Gm = Geo<NQ>;
+    constexpr int R = Gm::R, RPL = Gm::RPL;
+#pragma unroll
+    for (int k = 2; k <= R; k <<= 1) {
+#pragma unroll
+        for (int s = k >> 1; s > 0; s >>= 1) {
+            if (s >= RPL) {
+                const int src = gbase + (gl ^ (s / RPL));
+#pragma unroll
+                for (int j = 0; j < RPL; ++j) {
+                    const int i = gl * RPL + j;
+                    const uint64_t o = shfl64(d[j], src);
+                    const bool lower = (i & s) == 0;
+                    const bool asc = (i & k) == 0;
+                    const uint64_t mn = d[j] < o ? d[j] : o;
+                    const uint64_t mx = d[j] < o ? o : d[j];
+                    d[j] = (lower == asc) ? mn : mx;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < RPL; ++j) {
+                    if ((j & s) == 0) {
+                        const int i = gl * RPL + j;
+                        const bool asc = (i & k) == 0;
+                        const uint64_t a = d[j], b = d[j | s];
+                        const bool sw = asc ? (a > b) : (a < b);
+                        d[j] = sw ? b : a;
+                        d[j | s] = sw ? a : b;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// One evaluation of f on `pt` by the walk group; every lane of the group returns the same values.
+template <int NQ, int WAVES>
+__device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t* limbs, uint64_t pt, int gl,
+                          int gbase, uint64_t& out_pt, uint64_t& out_h) {
+    using Gm = Geo<NQ>;
+    constexpr int R = Gm::R, RPL = Gm::RPL, Q4 = Gm::Q4, HMAX = Gm::HMAX;
+    const uint32_t x = (uint32_t)pt;
+    const int side = (int)((pt >> 32) & 1);
+    const int h = sp.h;
+
+    // mu: base-xi digits, least significant first; Pauli p_t = d_t + 1
+    uint32_t dig[HMAX];
+    {
+        uint32_t xx = x;
+#pragma unroll
+        for (int t = 0; t < HMAX; ++t) {
+            dig[t] = xx % Gm::XI + 1;
+            xx /= Gm::XI;
+        }
+    }
+
+    // key vector through the rotations, p_{h-1} first
+    uint64_t u[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) u[j] = L.K[gl * RPL + j];
+#pragma unroll
+    for (int t = HMAX - 1; t >= 0; --t) {
+        if (t < h) {
+            const uint32_t p = dig[t];
+            uint64_t w[RPL];
+            if constexpr (RPL == 1) {
+                w[0] = u[0];
+            } else {
+                const int jx = (int)(p & (RPL - 1));
+#pragma unroll
+                for (int j = 0; j < RPL; ++j) w[j] = pick4(u, j ^ jx);
+            }
+            const int src = gbase + (gl ^ (int)(p >> Gm::LRPL));
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) {
+                const uint64_t part = shfl64(w[j], src);
+                const uint32_t r = (uint32_t)(gl * RPL + j);
+                if (anticommutes<NQ>(p, r)) {
+                    const int s = rotation_sign<NQ>(p, r);
+                    // side 0 (R u):   (u_r - s u_{r^p}) / sqrt2;  side 1 (R^T u): (u_r + s u_{r^p}) / sqrt2
+                    const bool plus = (side == 1) == (s > 0);
+                    const uint64_t v = plus ? m61_add(u[j], part) : m61_sub(u[j], part);
+                    u[j] = m61_rot(v, 30);
+                }
+            }
+        }
+    }
+
+    uint64_t S[RPL];
+    if (side) {
+        // 7-bit limbs of u, four columns per dword, into this group's LDS slot
+        if constexpr (RPL == 4) {
+#pragma unroll
+            for (int i = 0; i < NLIMB; ++i) {
+                uint32_t dw = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) dw |= (uint32_t)((u[j] >> (7 * i)) & 127) << (8 * j);
+                limbs[gl * LIMB_STRIDE + i] = dw;
+            }
+        } else {
+            uint8_t* lb = reinterpret_cast<uint8_t*>(limbs);
+#pragma unroll
+            for (int i = 0; i < NLIMB; ++i)
+                lb[((gl >> 2) * LIMB_STRIDE + i) * 4 + (gl & 3)] = (uint8_t)((u[0] >> (7 * i)) & 127);
+        }
+        wave_sync();
+        int32_t accA[RPL][NLIMB], accB[RPL][NLIMB];
+#pragma unroll
+        for (int j = 0; j < RPL; ++j)
+#pragma unroll
+            for (int i = 0; i < NLIMB; ++i) accA[j][i] = accB[j][i] = 0;
+#pragma unroll 2
+        for (int q4 = 0; q4 < Q4; ++q4) {
+            uint32_t U[NLIMB];
+#pragma unroll
+            for (int i = 0; i < NLIMB; ++i) U[i] = limbs[q4 * LIMB_STRIDE + i];
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) {
+                const int a = (int)L.phiA[q4 * R + gl * RPL + j];
+                const int b = (int)L.phiB[q4 * R + gl * RPL + j];
+#pragma unroll
+                for (int i = 0; i < NLIMB; ++i) {
+                    accA[j][i] = __builtin_amdgcn_sdot4(a, (int)U[i], accA[j][i], false);
+                    accB[j][i] = __builtin_amdgcn_sdot4(b, (int)U[i], accB[j][i], false);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+            uint64_t al = 0, be = 0;
+#pragma unroll
+            for (int i = 0; i < NLIMB; ++i) {
+                al = m61_add(al, m61_rot(m61_from_i32(accA[j][i]), 7 * i));
+                be = m61_add(be, m61_rot(m61_from_i32(accB[j][i]), 7 * i));
+            }
+            // phi(S_c) u = 2^(30 e) (A u + 2^31 B u)
+            S[j] = m61_rot(m61_add(al, m61_rot(be, 31)), sp.rot_e);
+        }
+        wave_sync();
+    } else {
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) S[j] = u[j];
+    }
+
+    // sign-normalised row digests, canonical order, matrix hash
+    uint64_t d[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+        const uint64_t c = m61_canon(S[j]);
+        const uint64_t c2 = P61 - c;
+        d[j] = c < c2 ? c : c2;
+    }
+    bitonic_sort<NQ>(d, gl, gbase);
+    uint64_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) acc += L.K2[gl * RPL + j] * d[j];
+#pragma unroll
+    for (int off = 1; off < Gm::G; off <<= 1) acc += shfl64(acc, gbase + (gl ^ off));
+    const uint64_t H = mix64(sp.salt_h + acc);
+    out_h = H;
+    out_pt = mulhi64(H, sp.n_half) | ((H & 1) << 32);
+}
+
+__device__ inline bool is_dist(const SpaceDev& sp, uint64_t pt) {
+    if (sp.delta == 0) return true;
+    const uint64_t x = pt & 0xffffffffull, b = (pt >> 32) & 1;
+    return (mix64(((x << 1) | b) ^ sp.salt_d) >> (64 - sp.delta)) == 0;
+}
+
+__device__ inline uint64_t start_point(const SpaceDev& sp, uint64_t w, uint32_t j) {
+    const uint64_t g = sm64(sp.salt_s, (w << 32) | j);
+    return mulhi64(g, sp.n_half) | ((g & 1) << 32);
+}
+
+constexpr int WAVES_SMALL = 4;
+template <int NQ>
+struct WalkWaves {
+    static constexpr int value = NQ == 4 ? 8 : WAVES_SMALL;
+};
+
+// ---- parity kernels ----
+template <int NQ, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_step(SpaceDev sp, const uint64_t* in, uint64_t* out,
+                                                     uint64_t* hash, int64_t count) {
+    using Gm = Geo<NQ>;
+    __shared__ Lds<NQ, WAVES> L;
+    load_lds(L, sp);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int gi = lane / Gm::G, gl = lane % Gm::G, gbase = gi * Gm::G;
+    uint32_t* limbs = L.limbs[wave * Gm::WPW + gi];
+    const int64_t stride = (int64_t)gridDim.x * WAVES * Gm::WPW;
+    for (int64_t base = ((int64_t)blockIdx.x * WAVES + wave) * Gm::WPW; base < count; base += stride) {
+        const int64_t i = base + gi;
+        if (i < count) {
+            uint64_t o, hh;
+            walk_step<NQ, WAVES>(sp, L, limbs, in[i], gl, gbase, o, hh);
+            if (gl == 0) {
+                out[i] = o;
+                if (hash) hash[i] = hh;
+            }
+        }
+    }
+}
+
+template <int NQ, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_trails(SpaceDev sp, const uint64_t* starts, int64_t count,
+                                                       uint32_t cap, uint64_t* dp, uint32_t* len) {
+    using Gm = Geo<NQ>;
+    __shared__ Lds<NQ, WAVES> L;
+    load_lds(L, sp);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int gi = lane / Gm::G, gl = lane % Gm::G, gbase = gi * Gm::G;
+    uint32_t* limbs = L.limbs[wave * Gm::WPW + gi];
+    const int64_t stride = (int64_t)gridDim.x * WAVES * Gm::WPW;
+    for (int64_t base = ((int64_t)blockIdx.x * WAVES + wave) * Gm::WPW; base < count; base += stride) {
+        const int64_t i = base + gi;
+        if (i < count) {
+            uint64_t pt = starts[i];
+            uint32_t d = 0, found = 0;
+            for (uint32_t t = 1; t <= cap; ++t) {
+                uint64_t nx, hh;
+                walk_step<NQ, WAVES>(sp, L, limbs, pt, gl, gbase, nx, hh);
+                pt = nx;
+                if (is_dist(sp, pt)) {
+                    d = t;
+                    found = 1;
+                    break;
+                }
+            }
+            if (gl == 0) {
+                dp[i] = found ? pt : 0;
+                len[i] = found ? d : 0;
+            }
+        }
+    }
+}
+
+// Canonical hash of explicit matrices: the side-1 product with u = K (no rotations).
+template <int NQ, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_canon(SpaceDev sp, const uint32_t* phi_all, const int32_t* e,
+                                                      int64_t count, uint64_t* out) {
+    using Gm = Geo<NQ>;
+    constexpr int NPHI = Gm::Q4 * Gm::R;
+    __shared__ Lds<NQ, WAVES> L;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int gi = lane / Gm::G, gl = lane % Gm::G, gbase = gi * Gm::G;
+    uint32_t* limbs = L.limbs[wave * Gm::WPW + gi];
+    for (int64_t m = blockIdx.x; m < count; m += gridDim.x) {
+        SpaceDev s2 = sp;
+        s2.phi = phi_all + (size_t)m * 2 * NPHI;
+        s2.h = 0;
+        s2.rot_e = (int32_t)((30ll * e[m]) % 61);
+        s2.n_half = 1;
+        __syncthreads();
+        load_lds(L, s2);
+        __syncthreads();
+        if (wave == 0 && gi == 0) {
+            uint64_t o, hh;
+            walk_step<NQ, WAVES>(s2, L, limbs, 1ull << 32, gl, gbase, o, hh);
+            if (gl == 0) out[m] = hh;
+        }
+    }
+}
+
+template <int NQ>
+__global__ void k_pack_i32(const int32_t* a, const int32_t* b, int64_t count, uint32_t* phi, int* flag) {
+    constexpr int R = Geo<NQ>::R, Q4 = Geo<NQ>::Q4;
+    const int64_t total = count * Q4 * R;
+    for (int64_t idx = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; idx < total;
+         idx += (int64_t)blockDim.x * gridDim.x) {
+        const int64_t m = idx / (Q4 * R);
+        const int rem = (int)(idx % (Q4 * R));
+        const int q4 = rem / R, r = rem % R;
+        const int32_t* am = a + m * R * R;
+        const int32_t* bm = b + m * R * R;
+        uint32_t wa = 0, wb = 0;
+        for (int c = 0; c < 4; ++c) {
+            const int32_t va = am[r * R + 4 * q4 + c], vb = bm[r * R + 4 * q4 + c];
+            if (va > 127 || va < -127 || vb > 127 || vb < -127) atomicOr(flag, 2);
+            wa |= ((uint32_t)(uint8_t)(int8_t)va) << (8 * c);
+            wb |= ((uint32_t)(uint8_t)(int8_t)vb) << (8 * c);
+        }
+        phi[m * 2 * Q4 * R + rem] = wa;
+        phi[m * 2 * Q4 * R + Q4 * R + rem] = wb;
+    }
+}
+
+__global__ void k_starts(SpaceDev sp, int64_t w0, uint32_t j, int64_t count, uint64_t* out) {
+    for (int64_t i = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; i < count; i += (int64_t)blockDim.x * gridDim.x)
+        out[i] = start_point(sp, (uint64_t)(w0 + i), j);
+}
+
+// K[q] = (sm64(s_0, q) >> 3) mod p, K2[i] = sm64(s_1, i) | 1, s_t = sm64(seed, t)
+__global__ void k_keys(int r, uint64_t seed, uint64_t* keys) {
+    const int i = threadIdx.x + blockIdx.x * blockDim.x;
+    if (i >= r) return;
+    const uint64_t s0 = sm64(seed, 0), s1 = sm64(seed, 1);
+    uint64_t k = sm64(s0, (uint64_t)i) >> 3;
+    if (k >= P61) k -= P61;
+    keys[i] = k;
+    keys[r + i] = sm64(s1, (uint64_t)i) | 1ull;
+}
+
+// ---- the walk kernel: trails, distinguished-point table, backtracking (Sec. 3) ----
+
+// Claim a slot for `dp` (linear probing).  Returns 1 = new (claimed), 2 = key present, 3 = full.
+__device__ inline int table_claim(const WalkDev& wd, uint64_t dp, uint64_t& slot) {
+    const uint64_t mask = (1ull << wd.log2_table) - 1;
+    uint64_t s = mix64(dp ^ 0x5bd1e9955bd1e995ull) & mask;
+    for (int probe = 0; probe < 64; ++probe) {
+        uint64_t expected = EMPTY_KEY;
+        const bool won = __hip_atomic_compare_exchange_strong(&wd.table[2 * s], &expected, dp, __ATOMIC_RELAXED,
+                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (won) {
+            slot = s;
+            return 1;
+        }
+        if (expected == dp) {
+            slot = s;
+            return 2;
+        }
+        s = (s + 1) & mask;
+    }
+    return 3;
+}
+
+__device__ inline uint64_t pack_value(uint64_t start, uint32_t len) {
+    return (start & 0x1ffffffffull) | ((uint64_t)(len & 0x3fffffffu) << 33) | (1ull << 63);
+}
+
+template <int NQ, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_walk(SpaceDev sp, WalkDev wd, int iters) {
+    using Gm = Geo<NQ>;
+    __shared__ Lds<NQ, WAVES> L;
+    load_lds(L, sp);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int gi = lane / Gm::G, gl = lane % Gm::G, gbase = gi * Gm::G;
+    const bool leader = gl == 0;
+    uint32_t* limbs = L.limbs[wave * Gm::WPW + gi];
+    uint64_t c_steps = 0, c_dps = 0, c_ins = 0, c_ab = 0, c_rh = 0, c_same = 0, c_red = 0, c_claw = 0, c_full = 0,
+             c_spin = 0, c_active = 0;
+    const int64_t stride = (int64_t)gridDim.x * WAVES * Gm::WPW;
+    for (int64_t base = ((int64_t)blockIdx.x * WAVES + wave) * Gm::WPW; base < wd.walks; base += stride) {
+        const int64_t w = base + gi;
+        if (w >= wd.walks) continue;
+        WalkState st = wd.states[w];
+        for (int it = 0; it < iters; ++it) {
+            const uint32_t mode = st.mode & 0xff;
+            if (mode == MODE_DONE) break;
+            const uint32_t which = (st.mode >> 8) & 1;
+            const uint64_t arg = mode == MODE_WALK ? st.cur : (which ? st.pb : st.pa);
+            uint64_t nxt, H;
+            walk_step<NQ, WAVES>(sp, L, limbs, arg, gl, gbase, nxt, H);
+            c_steps++;
+            bool restart = false;
+            if (mode == MODE_WALK && wd.enumerate) {
+                // exhaustive mode: every point once, the table keyed by its full matrix hash, so two
+                // points meet exactly when their cosets (or 64-bit hashes) coincide
+                c_dps++;
+                const uint64_t key = H == EMPTY_KEY ? (H ^ 1) : H;
+                int kind = 0;
+                uint64_t slot = 0, other = 0;
+                if (leader) kind = table_claim(wd, key, slot);
+                if (leader && kind == 1)
+                    __hip_atomic_store(&wd.table[2 * slot + 1], pack_value(st.start, 1), __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                if (leader && kind == 2) {
+                    int spin = 0;
+                    do {
+                        other = __hip_atomic_load(&wd.table[2 * slot + 1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    } while (other == 0 && ++spin < (1 << 20));
+                    if (other == 0) kind = 4;
+                }
+                if (leader) {
+                    if (kind == 1) {
+                        c_ins++;
+                    } else if (kind == 3) {
+                        c_full++;
+                    } else if (kind == 4) {
+                        c_spin++;
+                    } else {
+                        const uint64_t ostart = other & 0x1ffffffffull;
+                        if (((ostart >> 32) & 1) == ((st.start >> 32) & 1)) {
+                            c_same++;
+                        } else {
+                            c_claw++;
+                            const unsigned long long idx = atomicAdd(wd.claw_count, 1ull);
+                            if (idx < wd.claw_cap) {
+                                wd.claws[2 * idx] = ostart;
+                                wd.claws[2 * idx + 1] = st.start;
+                            }
+                        }
+                    }
+                }
+                restart = true;
+            } else if (mode == MODE_WALK) {
+                st.len++;
+                if (is_dist(sp, nxt)) {
+                    c_dps++;
+                    int kind = 0;
+                    uint64_t slot = 0, other = 0;
+                    if (leader) kind = table_claim(wd, nxt, slot);
+                    if (leader && kind == 1)
+                        __hip_atomic_store(&wd.table[2 * slot + 1], pack_value(st.start, st.len), __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    if (leader && kind == 2) {
+                        // the slot's writer publishes its value right after its claim
+                        int spin = 0;
+                        do {
+                            other = __hip_atomic_load(&wd.table[2 * slot + 1], __ATOMIC_ACQUIRE,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                        } while (other == 0 && ++spin < (1 << 20));
+                        if (other == 0) kind = 4;
+                    }
+                    kind = (int)shfl32((uint32_t)kind, gbase);
+                    other = shfl64(other, gbase);
+                    restart = true;
+                    if (kind == 1) {
+                        c_ins++;
+                    } else if (kind == 3) {
+                        c_full++;
+                    } else if (kind == 4) {
+                        c_spin++;
+                    } else if (kind == 2) {
+                        const uint64_t ostart = other & 0x1ffffffffull;
+                        const uint32_t olen = (uint32_t)((other >> 33) & 0x3fffffffu);
+                        if (ostart != st.start) {
+                            // backtrack the two trails (Sec. 3, Fig. 2)
+                            restart = false;
+                            st.pa = st.start;
+                            st.pb = ostart;
+                            const uint32_t la = st.len, lb = olen;
+                            if (la > lb) {
+                                st.mode = MODE_ALIGN;
+                                st.rem = la - lb;
+                                st.len = lb;
+                            } else if (lb > la) {
+                                st.mode = MODE_ALIGN | (1u << 8);
+                                st.rem = lb - la;
+                                st.len = la;
+                            } else {
+                                st.mode = MODE_LOCK;
+                                st.rem = la;
+                            }
+                        }
+                    }
+                } else if (st.len >= wd.cap) {
+                    c_ab++;
+                    restart = true;
+                } else {
+                    st.cur = nxt;
+                }
+            } else if (mode == MODE_ALIGN) {
+                if (which) st.pb = nxt; else st.pa = nxt;
+                if (--st.rem == 0) {
+                    if (st.pa == st.pb) {
+                        c_rh++;  // one trail started on the other
+                        restart = true;
+                    } else {
+                        st.mode = MODE_LOCK;
+                        st.rem = st.len;
+                    }
+                }
+            } else {  // MODE_LOCK
+                if (!which) {
+                    st.na = nxt;
+                    st.ha = H;
+                    st.mode = MODE_LOCK | (1u << 8);
+                } else {
+                    if (st.na == nxt) {
+                        // f(pa) = f(pb) with pa != pb: the merge
+                        const uint64_t sa = (st.pa >> 32) & 1, sb = (st.pb >> 32) & 1;
+                        if (sa == sb) {
+                            c_same++;
+                        } else if (st.ha != H) {
+                            c_red++;
+                        } else {
+                            c_claw++;
+                            if (leader) {
+                                const unsigned long long idx = atomicAdd(wd.claw_count, 1ull);
+                                if (idx < wd.claw_cap) {
+                                    wd.claws[2 * idx] = st.pa;
+                                    wd.claws[2 * idx + 1] = st.pb;
+                                }
+                            }
+                        }
+                        restart = true;
+                    } else {
+                        st.pa = st.na;
+                        st.pb = nxt;
+                        st.mode = MODE_LOCK;
+                        if (--st.rem == 0) restart = true;  // cannot happen for two trails with one end
+                    }
+                }
+            }
+            if (restart) {
+                st.trail++;
+                st.len = 0;
+                st.mode = MODE_WALK;
+                if (wd.enumerate) {
+                    const uint64_t idx = (uint64_t)w + (uint64_t)wd.walks * st.trail;
+                    if (idx >= wd.n_points) {
+                        st.mode = MODE_DONE;
+                    } else {
+                        st.start = (idx % sp.n_half) | ((idx / sp.n_half) << 32);
+                    }
+                } else {
+                    st.start = start_point(sp, (uint64_t)w, st.trail);
+                }
+                st.cur = st.start;
+            }
+        }
+        if ((st.mode & 0xff) != MODE_DONE) c_active++;
+        if (leader) wd.states[w] = st;
+    }
+    if (leader) {
+        atomicAdd(&wd.stats[ST_STEPS], (unsigned long long)c_steps);
+        atomicAdd(&wd.stats[ST_DPS], (unsigned long long)c_dps);
+        atomicAdd(&wd.stats[ST_INSERTS], (unsigned long long)c_ins);
+        atomicAdd(&wd.stats[ST_ABANDONED], (unsigned long long)c_ab);
+        atomicAdd(&wd.stats[ST_ROBIN], (unsigned long long)c_rh);
+        atomicAdd(&wd.stats[ST_SAME], (unsigned long long)c_same);
+        atomicAdd(&wd.stats[ST_REDUCTION], (unsigned long long)c_red);
+        atomicAdd(&wd.stats[ST_CLAWS], (unsigned long long)c_claw);
+        atomicAdd(&wd.stats[ST_FULL], (unsigned long long)c_full);
+        atomicAdd(&wd.stats[ST_SPIN], (unsigned long long)c_spin);
+        atomicAdd(&wd.stats[ST_ACTIVE], (unsigned long long)c_active);
+    }
+}
+
+__global__ void k_walk_init(SpaceDev sp, WalkDev wd) {
+    for (int64_t w = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; w < wd.walks;
+         w += (int64_t)blockDim.x * gridDim.x) {
+        WalkState st;
+        st.trail = 0;
+        st.len = 0;
+        st.mode = MODE_WALK;
+        st.rem = 0;
+        st.pa = st.pb = st.na = st.ha = 0;
+        if (wd.enumerate) {
+            const uint64_t idx = (uint64_t)w;
+            if (idx >= wd.n_points) {
+                st.mode = MODE_DONE;
+                st.start = 0;
+            } else {
+                st.start = (idx % sp.n_half) | ((idx / sp.n_half) << 32);
+            }
+        } else {
+            st.start = start_point(sp, (uint64_t)w, 0);
+        }
+        st.cur = st.start;
+        wd.states[w] = st;
+    }
+}
+
+__global__ void k_table_clear(uint64_t* table, uint64_t slots) {
+    for (uint64_t i = threadIdx.x + (uint64_t)blockIdx.x * blockDim.x; i < slots;
+         i += (uint64_t)blockDim.x * gridDim.x) {
+        table[2 * i] = EMPTY_KEY;
+        table[2 * i + 1] = 0;
+    }
+}
+
+template <typename F>
+hipError_t dispatch_n(int n, F&& f) {
+    switch (n) {
+        case 1: return f.template operator()<1>();
+        case 2: return f.template operator()<2>();
+        case 3: return f.template operator()<3>();
+        case 4: return f.template operator()<4>();
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int cu_count(int device) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+        cus = 256;
+    return cus;
+}
+
+}  // namespace
+
+int walk_grid_blocks(int n, int device) {
+    // one persistent block per CU for n = 4 (the int8 S_c fills most of the 160 KiB LDS), more for small n
+    const int cus = cu_count(device);
+    return n == 4 ? cus : cus * 4;
+}
+
+hipError_t keys_fill(int n, uint64_t seed, uint64_t* keys, hipStream_t s) {
+    const int r = 1 << (2 * n);
+    hipLaunchKernelGGL(k_keys, dim3((r + 255) / 256), dim3(256), 0, s, r, seed, keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(int n, const SpaceDev& sp, const uint64_t* in, uint64_t* out, uint64_t* hash, int64_t count,
+                       hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    auto f = [&]<int NQ>() -> hipError_t {
+        constexpr int W = WalkWaves<NQ>::value;
+        const int64_t per_block = (int64_t)W * Geo<NQ>::WPW;
+        int64_t blocks = (count + per_block - 1) / per_block;
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL((k_step<NQ, W>), dim3((unsigned)blocks), dim3(W * 64), 0, s, sp, in, out, hash, count);
+        return hipGetLastError();
+    };
+    return dispatch_n(n, f);
+}
+
+hipError_t launch_trails(int n, const SpaceDev& sp, const uint64_t* starts, int64_t count, uint32_t cap, uint64_t* dp,
+                         uint32_t* len, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    auto f = [&]<int NQ>() -> hipError_t {
+        constexpr int W = WalkWaves<NQ>::value;
+        const int64_t per_block = (int64_t)W * Geo<NQ>::WPW;
+        int64_t blocks = (count + per_block - 1) / per_block;
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL((k_trails<NQ, W>), dim3((unsigned)blocks), dim3(W * 64), 0, s, sp, starts, count, cap,
+                           dp, len);
+        return hipGetLastError();
+    };
+    return dispatch_n(n, f);
+}
+
+hipError_t launch_starts(const SpaceDev& sp, int64_t w0, uint32_t j, int64_t count, uint64_t* out, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65535) blocks = 65535;
+    hipLaunchKernelGGL(k_starts, dim3((unsigned)blocks), dim3(256), 0, s, sp, w0, j, count, out);
+    return hipGetLastError();
+}
+
+hipError_t pack_phi_i32(int n, const int32_t* a, const int32_t* b, int64_t count, uint32_t* phi, int* flag,
+                        hipStream_t s) {
+    auto f = [&]<int NQ>() -> hipError_t {
+        hipLaunchKernelGGL((k_pack_i32<NQ>), dim3(1024), dim3(256), 0, s, a, b, count, phi, flag);
+        return hipGetLastError();
+    };
+    return dispatch_n(n, f);
+}
+
+hipError_t launch_canon_hash(int n, const SpaceDev& sp, const uint32_t* phi_all, const int32_t* e, int64_t count,
+                             uint64_t* out, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    auto f = [&]<int NQ>() -> hipError_t {
+        constexpr int W = WalkWaves<NQ>::value;
+        const int64_t blocks = count < 1024 ? count : 1024;
+        hipLaunchKernelGGL((k_canon<NQ, W>), dim3((unsigned)blocks), dim3(W * 64), 0, s, sp, phi_all, e, count,
+                           out);
+        return hipGetLastError();
+    };
+    return dispatch_n(n, f);
+}
+
+hipError_t launch_walk(int n, const SpaceDev& sp, const WalkDev& wd, int iters, int grid_blocks, hipStream_t s) {
+    auto f = [&]<int NQ>() -> hipError_t {
+        constexpr int W = WalkWaves<NQ>::value;
+        const int64_t per_block = (int64_t)W * Geo<NQ>::WPW;
+        int64_t blocks = (wd.walks + per_block - 1) / per_block;
+        if (blocks > grid_blocks) blocks = grid_blocks;
+        hipLaunchKernelGGL((k_walk<NQ, W>), dim3((unsigned)blocks), dim3(W * 64), 0, s, sp, wd, iters);
+        return hipGetLastError();
+    };
+    return dispatch_n(n, f);
+}
+
+hipError_t launch_walk_init(const SpaceDev& sp, const WalkDev& wd, hipStream_t s) {
+    int64_t blocks = (wd.walks + 255) / 256;
+    if (blocks > 65535) blocks = 65535;
+    hipLaunchKernelGGL(k_walk_init, dim3((unsigned)blocks), dim3(256), 0, s, sp, wd);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_clear(uint64_t* table, int log2_table, hipStream_t s) {
+    const uint64_t slots = 1ull << log2_table;
+    uint64_t blocks = (slots + 255) / 256;
+    if (blocks > 65535) blocks = 65535;
+    hipLaunchKernelGGL(k_table_clear, dim3((unsigned)blocks), dim3(256), 0, s, table, slots);
+    return hipGetLastError();
+}
+
+}  // namespace tcw

@@ -1,0 +1,330 @@
+"""ctypes binding of libtcw.so (include/tcw.h): argument marshalling only.
+
+Device arrays are torch CUDA tensors (their data_ptr is passed through); streams are
+torch streams.  Every computation runs in the HIP library; when the library is not
+built this module raises instead of computing anything itself.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtcw.so")
+
+TCW_OK = 0
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW", -5: "ESTATE"}
+MAX_T = 64
+MAX_R = 256
+ORDER_PLAIN = 0
+ORDER_GIVEN = 1
+
+
+class TcwError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tcw {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Space(C.Structure):
+    _fields_ = [("k", C.c_int32), ("chunk", C.c_int32), ("seed", C.c_uint64), ("version", C.c_uint32),
+                ("delta", C.c_int32)]
+
+
+class WalkStats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("steps", "dps", "inserts", "abandoned", "robin_hood", "same_side",
+                                          "reduction", "claws", "table_full", "spin_timeouts", "active_walks")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class WalkParams(C.Structure):
+    _fields_ = [
+        ("k_max", C.c_int32), ("delta", C.c_int32), ("walks", C.c_int64), ("log2_table", C.c_int32),
+        ("seed", C.c_uint64), ("version", C.c_uint32), ("trail_cap_factor", C.c_int32),
+        ("budget_beta", C.c_int32), ("version_factor", C.c_int32), ("enum_max", C.c_int64),
+        ("iters_per_launch", C.c_int32), ("depth_order_kind", C.c_int32), ("depth_order_len", C.c_int32),
+        ("depth_order", C.c_int32 * 16), ("chunk_first", C.c_int32), ("chunk_last", C.c_int32),
+        ("max_seconds", C.c_double),
+    ]
+
+
+class Result(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("t", C.c_int32), ("n", C.c_int32), ("chunk", C.c_int32),
+        ("paulis", C.c_uint16 * MAX_T), ("clifford_perm", C.c_int32 * MAX_R), ("clifford_sign", C.c_int8 * MAX_R),
+        ("stats", WalkStats), ("spaces", C.c_int64), ("versions", C.c_int64), ("launches", C.c_int64),
+        ("false_claws", C.c_int64), ("seconds", C.c_double),
+    ]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "tcw_create": (C.c_int, [C.POINTER(_P), C.c_int, _P]),
+    "tcw_destroy": (C.c_int, [_P]),
+    "tcw_last_error": (C.c_char_p, [_P]),
+    "tcw_set_stream": (C.c_int, [_P, _P]),
+    "tcw_target_from_words": (C.c_int, [_P, C.c_int, C.POINTER(C.c_uint16), C.c_int, C.POINTER(C.c_uint16),
+                                        C.c_int, C.POINTER(_P)]),
+    "tcw_target_from_channel": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
+                                          C.POINTER(_P)]),
+    "tcw_target_free": (C.c_int, [_P]),
+    "tcw_target_channel": (C.c_int, [_P, _P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "tcw_target_n": (C.c_int, [_P]),
+    "tcw_step": (C.c_int, [_P, _P, C.POINTER(Space), _P, _P, _P, C.c_int64]),
+    "tcw_trails": (C.c_int, [_P, _P, C.POINTER(Space), _P, C.c_int64, C.c_uint32, _P, _P]),
+    "tcw_start_points": (C.c_int, [_P, _P, C.POINTER(Space), C.c_int64, C.c_uint32, C.c_int64, _P]),
+    "tcw_canon_hash": (C.c_int, [_P, C.c_int, C.POINTER(Space), _P, _P, _P, C.c_int64, _P]),
+    "tcw_claw_check": (C.c_int, [_P, _P, C.POINTER(Space), _P, _P, C.c_int64, _P, _P, _P]),
+    "tcw_walk_begin": (C.c_int, [_P, _P, C.POINTER(Space), C.c_int64, C.c_int, C.c_uint32, C.c_int,
+                                 C.POINTER(_P)]),
+    "tcw_walk_run": (C.c_int, [_P, C.c_int]),
+    "tcw_walk_stats_get": (C.c_int, [_P, C.POINTER(WalkStats)]),
+    "tcw_walk_claws": (C.c_int, [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.c_int64,
+                                 C.POINTER(C.c_int64)]),
+    "tcw_walk_reset": (C.c_int, [_P, C.c_uint32]),
+    "tcw_walk_last_ms": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "tcw_walk_read_states": (C.c_int, [_P, C.c_int64, C.c_int64, _P]),
+    "tcw_walk_write_states": (C.c_int, [_P, C.c_int64, C.c_int64, _P]),
+    "tcw_walk_read_table": (C.c_int, [_P, _P]),
+    "tcw_walk_write_table": (C.c_int, [_P, _P]),
+    "tcw_walk_end": (C.c_int, [_P]),
+    "tcw_default_params": (None, [C.POINTER(WalkParams), C.c_int]),
+    "tcw_search": (C.c_int, [_P, _P, C.POINTER(WalkParams), C.POINTER(Result)]),
+}
+
+EXPORTED = sorted(_SIGS)
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libtcw.so with typed entry points; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = C.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("device arrays must be contiguous CUDA tensors")
+    return t.data_ptr()
+
+
+def _u16_array(vals: Sequence[int]):
+    arr = (C.c_uint16 * max(1, len(vals)))(*vals)
+    return arr
+
+
+@dataclass
+class Decomposition:
+    t: int
+    paulis_desc: List[int]   # P_t .. P_1
+    perm: List[int]
+    sign: List[int]
+    chunk: int
+
+
+class Context:
+    """One library context bound to a device and a torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load()
+        self.device = device
+        torch.cuda.set_device(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = _P()
+        self._check(self.lib.tcw_create(C.byref(h), device, _P(stream.cuda_stream)), None)
+        self.h = h
+
+    def _check(self, rc: int, h=None):
+        if rc != TCW_OK:
+            msg = self.lib.tcw_last_error(h if h is not None else getattr(self, "h", None))
+            raise TcwError(rc, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tcw_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- targets ----
+    def target_from_words(self, n: int, paulis: Sequence[int], clifford: Sequence[int]) -> "Target":
+        out = _P()
+        self._check(self.lib.tcw_target_from_words(self.h, n, _u16_array(paulis), len(paulis), _u16_array(clifford),
+                                                   len(clifford), C.byref(out)))
+        return Target(self, out, n)
+
+    def target_from_channel(self, n: int, a, b, e: int) -> "Target":
+        import numpy as np
+        a = np.ascontiguousarray(a, dtype=np.int32)
+        b = np.ascontiguousarray(b, dtype=np.int32)
+        out = _P()
+        self._check(self.lib.tcw_target_from_channel(self.h, n, a.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                     b.ctypes.data_as(C.POINTER(C.c_int32)), int(e), C.byref(out)))
+        return Target(self, out, n)
+
+    # ---- parity entry points ----
+    def step(self, target, k, chunk, seed, delta, pts_in, pts_out, hash_out=None, version=0):
+        sp = Space(k, chunk, seed, version, delta)
+        self._check(self.lib.tcw_step(self.h, target.h, C.byref(sp), _ptr(pts_in), _ptr(pts_out), _ptr(hash_out),
+                                      pts_in.numel()))
+
+    def trails(self, target, k, chunk, seed, delta, starts, cap, dp_out, len_out, version=0):
+        sp = Space(k, chunk, seed, version, delta)
+        self._check(self.lib.tcw_trails(self.h, target.h, C.byref(sp), _ptr(starts), starts.numel(), cap,
+                                        _ptr(dp_out), _ptr(len_out)))
+
+    def start_points(self, target, k, chunk, seed, w0, j, count, out, version=0):
+        sp = Space(k, chunk, seed, version, 0)
+        self._check(self.lib.tcw_start_points(self.h, target.h, C.byref(sp), w0, j, count, _ptr(out)))
+
+    def canon_hash(self, n, k, chunk, seed, a, b, e, out, version=0):
+        sp = Space(k, chunk, seed, version, 0)
+        self._check(self.lib.tcw_canon_hash(self.h, n, C.byref(sp), _ptr(a), _ptr(b), _ptr(e), e.numel(),
+                                            _ptr(out)))
+
+    def claw_check(self, target, k, chunk, seed, u0, u1, ok, perm, sign, version=0):
+        sp = Space(k, chunk, seed, version, 0)
+        self._check(self.lib.tcw_claw_check(self.h, target.h, C.byref(sp), _ptr(u0), _ptr(u1), u0.numel(),
+                                            _ptr(ok), _ptr(perm), _ptr(sign)))
+
+    # ---- walks and search ----
+    def walk(self, target, k, chunk, seed, delta, walks, log2_table, cap, enumerate=False, version=0) -> "Walk":
+        sp = Space(k, chunk, seed, version, delta)
+        out = _P()
+        self._check(self.lib.tcw_walk_begin(self.h, target.h, C.byref(sp), walks, log2_table, cap,
+                                            1 if enumerate else 0, C.byref(out)))
+        return Walk(self, out)
+
+    def default_params(self, n: int) -> WalkParams:
+        p = WalkParams()
+        self.lib.tcw_default_params(C.byref(p), n)
+        return p
+
+    def search(self, target, params: WalkParams) -> Result:
+        res = Result()
+        self._check(self.lib.tcw_search(self.h, target.h, C.byref(params), C.byref(res)))
+        return res
+
+
+def decomposition_of(res: Result) -> Optional[Decomposition]:
+    if res.status != 1:
+        return None
+    r = 4 ** res.n
+    return Decomposition(t=res.t, paulis_desc=list(res.paulis[:res.t]), perm=list(res.clifford_perm[:r]),
+                         sign=list(res.clifford_sign[:r]), chunk=res.chunk)
+
+
+class Target:
+    def __init__(self, ctx: Context, h, n: int):
+        self.ctx, self.h, self.n = ctx, h, n
+
+    def channel(self):
+        import numpy as np
+        r = 4 ** self.n
+        a = np.zeros((r, r), dtype=np.int32)
+        b = np.zeros((r, r), dtype=np.int32)
+        e = C.c_int32(0)
+        self.ctx._check(self.ctx.lib.tcw_target_channel(self.ctx.h, self.h, a.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                        b.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(e)))
+        return a, b, e.value
+
+    def free(self):
+        if self.h:
+            self.ctx.lib.tcw_target_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Walk:
+    def __init__(self, ctx: Context, h):
+        self.ctx, self.h = ctx, h
+
+    def run(self, iters: int):
+        self.ctx._check(self.ctx.lib.tcw_walk_run(self.h, iters))
+
+    def stats(self) -> WalkStats:
+        st = WalkStats()
+        self.ctx._check(self.ctx.lib.tcw_walk_stats_get(self.h, C.byref(st)))
+        return st
+
+    def claws(self, max_pairs: int = 4096):
+        u0 = (C.c_uint64 * max(1, max_pairs))()
+        u1 = (C.c_uint64 * max(1, max_pairs))()
+        total = C.c_int64(0)
+        self.ctx._check(self.ctx.lib.tcw_walk_claws(self.h, u0, u1, max_pairs, C.byref(total)))
+        m = min(total.value, max_pairs, 4096)
+        return [(u0[i], u1[i]) for i in range(m)], total.value
+
+    STATE_DTYPE = [("start", "<u8"), ("cur", "<u8"), ("pa", "<u8"), ("pb", "<u8"), ("na", "<u8"), ("ha", "<u8"),
+                   ("len", "<u4"), ("trail", "<u4"), ("mode", "<u4"), ("rem", "<u4")]
+
+    def read_states(self, first: int, count: int):
+        import numpy as np
+        out = np.zeros(count, dtype=self.STATE_DTYPE)
+        self.ctx._check(self.ctx.lib.tcw_walk_read_states(self.h, first, count, out.ctypes.data))
+        return out
+
+    def write_states(self, first: int, states):
+        import numpy as np
+        states = np.ascontiguousarray(states, dtype=self.STATE_DTYPE)
+        self.ctx._check(self.ctx.lib.tcw_walk_write_states(self.h, first, len(states), states.ctypes.data))
+
+    def read_table(self, log2_table: int):
+        import numpy as np
+        out = np.zeros((1 << log2_table, 2), dtype=np.uint64)
+        self.ctx._check(self.ctx.lib.tcw_walk_read_table(self.h, out.ctypes.data))
+        return out
+
+    def write_table(self, table):
+        import numpy as np
+        table = np.ascontiguousarray(table, dtype=np.uint64)
+        self.ctx._check(self.ctx.lib.tcw_walk_write_table(self.h, table.ctypes.data))
+
+    def reset(self, version: int):
+        self.ctx._check(self.ctx.lib.tcw_walk_reset(self.h, version))
+
+    def last_ms(self) -> float:
+        ms = C.c_float(0)
+        self.ctx._check(self.ctx.lib.tcw_walk_last_ms(self.h, C.byref(ms)))
+        return ms.value
+
+    def end(self):
+        if self.h:
+            self.ctx.lib.tcw_walk_end(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.end()
+        except Exception:
+            pass
