@@ -24,20 +24,29 @@ sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 32-bit VALU lane-operations per second.
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# dense int8 MFMA peak (MI355X): 5.0e15 ops/s
+MFMA_I8_PEAK_OPS = 5.0e15
 
 
-def algorithmic_ops_per_step(n: int, h: int) -> float:
-    """32-bit VALU lane-operations the walk step needs per evaluation of f (mean over the two sides).
+def valu_ops_per_step(n: int, h: int) -> float:
+    """32-bit VALU lane-operations the n = 4 walk step needs per evaluation of f (mean over sides).
 
-    side 1 only: the S_c product as int8 dot products: R^2 entries x 2 (A, B) x 9 limbs / 4 per dot4
-    both sides:  h R/2 butterflies x 12 ops, R folds x 6, bitonic sort log2R(log2R+1)/2 stages x R x 4,
-                 position-keyed sum R x 6
+    both sides: h R/2 butterflies x 12 (64-bit modular add + 61-bit rotation + sign), R x 6 (fold),
+                bitonic sort log2R(log2R+1)/2 stages x R keys x 5 (exchange, compare, select),
+                R x 6 (position-keyed sum) + log2(64) x 4 (wave reduction, per lane)
+    side 1:     limb packing 2 sets x 9 limbs x R x 3, limb recombination R x 9 x 4 plus the
+                reduce-scatter (12 values x 64 lanes x 8) -- the S_c product itself runs on MFMA
     """
     r = 4 ** n
     lg = 2 * n
-    common = h * (r // 2) * 12 + r * 6 + (lg * (lg + 1) // 2) * r * 4 + r * 6
-    side1 = r * r * 2 * 9 / 4
+    common = h * (r // 2) * 12 + r * 6 + (lg * (lg + 1) // 2) * r * 5 + r * 6 + 6 * 4 * 64
+    side1 = 2 * 9 * r * 3 + r * 9 * 4 + 12 * 64 * 8
     return common + 0.5 * side1
+
+
+def mfma_ops_per_step(n: int) -> float:
+    """int8 MFMA operations per step (mean over sides): 16 x 16 x 64 tiles x 16 x 8 on side 1."""
+    return 0.5 * (16 * 16 * 64 * 2) * 16 * 8
 
 
 def _oracle_worker(args):
@@ -119,9 +128,10 @@ def main():
     value = steps / elapsed
     avg_ms = sum(kernel_ms) / len(kernel_ms)
     per_launch_steps = args.walks * args.iters
-    ops = algorithmic_ops_per_step(n, k // 2) * per_launch_steps
+    ops = valu_ops_per_step(n, k // 2) * per_launch_steps
     achieved = ops / (avg_ms * 1e-3) / 1e12
     peak = VALU_PEAK_OPS / 1e12
+    mfma_achieved = mfma_ops_per_step(n) * per_launch_steps / (avg_ms * 1e-3)
     w.end()
 
     extra = {}
@@ -160,7 +170,9 @@ def main():
         "config": {"workload": "n4k7", "n": n, "k": k, "chunk": chunk, "walks": args.walks, "delta": delta,
                    "log2_table": log2_table, "iters_per_launch": args.iters, "parallelism": "1 GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s", "frac": achieved / peak,
-                     "traffic": None, "kernel": "k_walk<4,8>", "kernel_ms": avg_ms},
+                     "traffic": None, "kernel": "k_walk<4,8>", "kernel_ms": avg_ms,
+                     "mfma_i8": {"achieved": mfma_achieved / 1e12, "peak": MFMA_I8_PEAK_OPS / 1e12, "unit": "Tops/s",
+                                 "frac": mfma_achieved / MFMA_I8_PEAK_OPS}},
         "walk_stats": st.as_dict(),
     }
     out.update(extra)

@@ -36,6 +36,9 @@ struct Geo {
     static constexpr int HMAX = NQ == 1 ? 20 : (NQ == 2 ? 8 : (NQ == 3 ? 5 : 4));
 };
 
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// n <= 3: S_c as int8 dwords [q/4][r] for v_dot4; per-walk limb buffer [q/4][limb].
 template <int NQ, int WAVES>
 struct Lds {
     uint32_t phiA[Geo<NQ>::Q4 * Geo<NQ>::R];
@@ -43,6 +46,20 @@ struct Lds {
     uint64_t K[Geo<NQ>::R];
     uint64_t K2[Geo<NQ>::R];
     uint32_t limbs[WAVES * Geo<NQ>::WPW][Geo<NQ>::Q4 * LIMB_STRIDE];
+};
+
+// n = 4: S_c as MFMA B-operand fragments.  With K stacked as [A | B] (512 columns), fragment
+// (nt, kk) holds, for lane l, the 16 bytes S''[nt*16 + l%16][kk*64 + (l/16)*16 + 0..15] where
+// S''[r][q] = A[r][q] for q < 256 and B[r][q - 256] otherwise; one ds_read_b128 per lane per MFMA.
+// Per walk: limb rows [9][68] (7-bit limbs of the rotated key vector, 4 columns per dword; the row
+// stride of 68 dwords keeps the MFMA A-operand reads free of bank conflicts).
+constexpr int N4_NT = 16, N4_KK = 8, N4_ROW = 68;
+template <int WAVES>
+struct Lds<4, WAVES> {
+    v4i frag[N4_NT * N4_KK * 64];
+    uint64_t K[256];
+    uint64_t K2[256];
+    uint32_t limbs[WAVES][NLIMB * N4_ROW];
 };
 
 __device__ inline void wave_sync() {
@@ -55,9 +72,14 @@ template <int NQ, int WAVES>
 __device__ void load_lds(Lds<NQ, WAVES>& L, const SpaceDev& sp) {
     using Gm = Geo<NQ>;
     constexpr int NPHI = Gm::Q4 * Gm::R;
-    for (int i = threadIdx.x; i < NPHI; i += blockDim.x) {
-        L.phiA[i] = sp.phi[i];
-        L.phiB[i] = sp.phi[NPHI + i];
+    if constexpr (NQ == 4) {
+        const v4i* src = reinterpret_cast<const v4i*>(sp.phi);
+        for (int i = threadIdx.x; i < N4_NT * N4_KK * 64; i += blockDim.x) L.frag[i] = src[i];
+    } else {
+        for (int i = threadIdx.x; i < NPHI; i += blockDim.x) {
+            L.phiA[i] = sp.phi[i];
+            L.phiB[i] = sp.phi[NPHI + i];
+        }
     }
     for (int i = threadIdx.x; i < Gm::R; i += blockDim.x) {
         L.K[i] = sp.keys[i];
@@ -71,9 +93,41 @@ __device__ inline uint64_t pick4(const uint64_t* u, int i) {
     return (i & 2) ? hi : lo;
 }
 
-// Sort RPL keys per lane across the G lanes of a group, ascending in index i = gl * RPL + j.
+// Lane exchange with the partner lane ^ X (X a compile-time power of two below 64): DPP quad
+// permutes for 1 and 2, ds_swizzle's xor mode for 4..16 (within 32 lanes), ds_bpermute for 32.
+template <int X>
+__device__ inline uint32_t xchg32(uint32_t v, int lane) {
+    if constexpr (X == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
+    } else if constexpr (X == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+    } else if constexpr (X == 4 || X == 8 || X == 16) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (X << 10));   // and 0x1f, xor X
+    } else {
+        return shfl32(v, lane ^ X);
+    }
+}
+template <int X>
+__device__ inline uint64_t xchg64(uint64_t v, int lane) {
+    const uint32_t lo = xchg32<X>((uint32_t)v, lane);
+    const uint32_t hi = xchg32<X>((uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline uint64_t xchg64_dyn(uint64_t v, int x, int lane) {
+    switch (x) {
+        case 1: return xchg64<1>(v, lane);
+        case 2: return xchg64<2>(v, lane);
+        case 4: return xchg64<4>(v, lane);
+        case 8: return xchg64<8>(v, lane);
+        case 16: return xchg64<16>(v, lane);
+        default: return xchg64<32>(v, lane);
+    }
+}
+
+// Sort RPL keys per lane across the G lanes of a group, ascending in index i = gl * RPL + j
+// (bitonic network; the group is aligned in the wave, so lane ^ x stays inside it for x < G).
 template <int NQ>
-__device__ inline void bitonic_sort(uint64_t* d, int gl, int gbase) {
+__device__ inline void bitonic_sort(uint64_t* d, int gl, int lane) {
     using Gm = Geo<NQ>;
     constexpr int R = Gm::R, RPL = Gm::RPL;
 #pragma unroll
@@ -81,16 +135,14 @@ __device__ inline void bitonic_sort(uint64_t* d, int gl, int gbase) {
 #pragma unroll
         for (int s = k >> 1; s > 0; s >>= 1) {
             if (s >= RPL) {
-                const int src = gbase + (gl ^ (s / RPL));
+                // s, k >= RPL: the direction depends on the lane only
+                const int i0 = gl * RPL;
+                const bool keep_min = ((i0 & s) == 0) == ((i0 & k) == 0);
 #pragma unroll
                 for (int j = 0; j < RPL; ++j) {
-                    const int i = gl * RPL + j;
-                    const uint64_t o = shfl64(d[j], src);
-                    const bool lower = (i & s) == 0;
-                    const bool asc = (i & k) == 0;
-                    const uint64_t mn = d[j] < o ? d[j] : o;
-                    const uint64_t mx = d[j] < o ? o : d[j];
-                    d[j] = (lower == asc) ? mn : mx;
+                    const uint64_t o = xchg64_dyn(d[j], s / RPL, lane);
+                    const bool take_own = (d[j] < o) == keep_min;
+                    d[j] = take_own ? d[j] : o;
                 }
             } else {
 #pragma unroll
@@ -99,13 +151,151 @@ __device__ inline void bitonic_sort(uint64_t* d, int gl, int gbase) {
                         const int i = gl * RPL + j;
                         const bool asc = (i & k) == 0;
                         const uint64_t a = d[j], b = d[j | s];
-                        const bool sw = asc ? (a > b) : (a < b);
+                        const bool sw = (a > b) == asc;
                         d[j] = sw ? b : a;
                         d[j | s] = sw ? a : b;
                     }
                 }
             }
         }
+    }
+}
+
+// x * 2^s mod p for a lane-dependent 0 <= s < 61 (x in [0, p])
+__device__ inline uint64_t m61_rotv(uint64_t x, uint32_t s) {
+    return ((x << s) | (x >> (61 - s))) & P61;
+}
+
+// sum_i acc_i 2^(7 i) mod p for nine signed limb sums |acc_i| < 2^24, exactly: the low five and
+// the high four limbs are combined in 64-bit integers, then reduced.
+__device__ inline uint64_t limbs_to_m61(const int32_t* acc) {
+    uint64_t lo = 0, hi = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) lo += (uint64_t)(int64_t)acc[i] << (7 * i);
+#pragma unroll
+    for (int i = 5; i < NLIMB; ++i) hi += (uint64_t)(int64_t)acc[i] << (7 * (i - 5));
+    // |lo| < 2^53, |hi| < 2^46: adding 4p keeps the exact value positive and below 2^64
+    const uint64_t l = m61_fold(lo + 4 * P61), hh = m61_fold(hi + 4 * P61);
+    return m61_add(l, m61_rot(hh, 35));
+}
+
+// n <= 3: phi(S_c) u with v_dot4_i32_i8 on A, B (int8, LDS) and 7-bit limbs of u.
+template <int NQ, int WAVES>
+__device__ inline void side1_dot4(const Lds<NQ, WAVES>& L, uint32_t* limbs, const uint64_t* u, int gl, int rot_e,
+                                  uint64_t* S) {
+    using Gm = Geo<NQ>;
+    constexpr int R = Gm::R, RPL = Gm::RPL, Q4 = Gm::Q4;
+    // 7-bit limbs of u, four columns per dword, into this group's LDS slot
+    if constexpr (RPL == 4) {
+#pragma unroll
+        for (int i = 0; i < NLIMB; ++i) {
+            uint32_t dw = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dw |= (uint32_t)((u[j] >> (7 * i)) & 127) << (8 * j);
+            limbs[gl * LIMB_STRIDE + i] = dw;
+        }
+    } else {
+        uint8_t* lb = reinterpret_cast<uint8_t*>(limbs);
+#pragma unroll
+        for (int i = 0; i < NLIMB; ++i)
+            lb[((gl >> 2) * LIMB_STRIDE + i) * 4 + (gl & 3)] = (uint8_t)((u[0] >> (7 * i)) & 127);
+    }
+    wave_sync();
+    int32_t accA[RPL][NLIMB], accB[RPL][NLIMB];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j)
+#pragma unroll
+        for (int i = 0; i < NLIMB; ++i) accA[j][i] = accB[j][i] = 0;
+#pragma unroll 2
+    for (int q4 = 0; q4 < Q4; ++q4) {
+        uint32_t U[NLIMB];
+#pragma unroll
+        for (int i = 0; i < NLIMB; ++i) U[i] = limbs[q4 * LIMB_STRIDE + i];
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+            const int a = (int)L.phiA[q4 * R + gl * RPL + j];
+            const int b = (int)L.phiB[q4 * R + gl * RPL + j];
+#pragma unroll
+            for (int i = 0; i < NLIMB; ++i) {
+                accA[j][i] = __builtin_amdgcn_sdot4(a, (int)U[i], accA[j][i], false);
+                accB[j][i] = __builtin_amdgcn_sdot4(b, (int)U[i], accB[j][i], false);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+        // phi(S_c) u = 2^(30 e) (A u + 2^31 B u)
+        const uint64_t al = limbs_to_m61(accA[j]), be = limbs_to_m61(accB[j]);
+        S[j] = m61_rot(m61_add(al, m61_rot(be, 31)), rot_e);
+    }
+    wave_sync();
+}
+
+// n = 4: phi(S_c) u on MFMA.  D[m][r] = sum_q A_rq limb_m(u_q) + sum_q B_rq limb_m(2^31 u_q) over the
+// stacked K = 512 columns (v_mfma_i32_16x16x64_i8: M = 16 limb rows, 9 used; N = 16 matrix rows per
+// tile, 16 tiles; 8 K steps), so sum_m 2^(7m) D[m][r] = A u + 2^31 B u = 2^(-30 e) S_r (mod p).  Lane l
+// holds limbs 4g..4g+3 (g = l/16) of row l%16 of every tile; the limb groups are combined by a
+// reduce-scatter over lanes l^32, l^16, leaving each lane the rows (4g + j)*16 + l%16, j = 0..3.
+template <int WAVES>
+__device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const uint64_t* u, int lane, int rot_e,
+                                  uint64_t* S) {
+    const int g = lane >> 4, n16 = lane & 15;
+    const int mr = n16 < NLIMB ? n16 : NLIMB - 1;  // limb rows 9..15 of the A operand are unused
+    v4i afr[N4_KK];
+#pragma unroll
+    for (int set = 0; set < 2; ++set) {
+        uint64_t w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) w[j] = set ? m61_rot(u[j], 31) : u[j];
+#pragma unroll
+        for (int m = 0; m < NLIMB; ++m) {
+            uint32_t dw = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dw |= (uint32_t)((w[j] >> (7 * m)) & 127) << (8 * j);
+            limbs[m * N4_ROW + lane] = dw;  // columns q = 4 lane .. 4 lane + 3
+        }
+        wave_sync();
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq)
+            afr[set * 4 + kq] = *reinterpret_cast<const v4i*>(&limbs[mr * N4_ROW + kq * 16 + g * 4]);
+        wave_sync();
+    }
+    v4i acc[N4_NT];
+#pragma unroll
+    for (int nt = 0; nt < N4_NT; ++nt) acc[nt] = v4i{0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < N4_KK; ++kk) {
+#pragma unroll
+        for (int nt = 0; nt < N4_NT; ++nt)
+            acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(afr[kk], L.frag[(nt * N4_KK + kk) * 64 + lane], acc[nt],
+                                                            0, 0, 0);
+    }
+    // this lane's partial sums: limbs m = 4g + j <= 8, weight 2^(7m) = 2^(28g) 2^(7j)
+    const bool v0 = 4 * g <= 8, v1 = 4 * g + 1 <= 8, v2 = 4 * g + 2 <= 8, v3 = 4 * g + 3 <= 8;
+    const uint32_t sh = (uint32_t)((28 * g) % 61);
+    uint64_t P[N4_NT];
+#pragma unroll
+    for (int nt = 0; nt < N4_NT; ++nt) {
+        uint64_t x = v0 ? (uint64_t)(int64_t)acc[nt][0] : 0;
+        x += v1 ? ((uint64_t)(int64_t)acc[nt][1] << 7) : 0;
+        x += v2 ? ((uint64_t)(int64_t)acc[nt][2] << 14) : 0;
+        x += v3 ? ((uint64_t)(int64_t)acc[nt][3] << 21) : 0;
+        P[nt] = m61_rotv(m61_fold(x + 4 * P61), sh);
+    }
+    // reduce-scatter over the four limb groups: lanes l^32, then l^16
+    const bool lowpair = g < 2, even = (g & 1) == 0;
+    uint64_t Q[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const uint64_t send = lowpair ? P[8 + i] : P[i];
+        const uint64_t mine = lowpair ? P[i] : P[8 + i];
+        Q[i] = m61_add(mine, xchg64<32>(send, lane));
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint64_t send = even ? Q[4 + i] : Q[i];
+        const uint64_t mine = even ? Q[i] : Q[4 + i];
+        S[i] = m61_rot(m61_add(mine, xchg64<16>(send, lane)), rot_e);
     }
 }
 
@@ -164,55 +354,11 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
 
     uint64_t S[RPL];
     if (side) {
-        // 7-bit limbs of u, four columns per dword, into this group's LDS slot
-        if constexpr (RPL == 4) {
-#pragma unroll
-            for (int i = 0; i < NLIMB; ++i) {
-                uint32_t dw = 0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) dw |= (uint32_t)((u[j] >> (7 * i)) & 127) << (8 * j);
-                limbs[gl * LIMB_STRIDE + i] = dw;
-            }
+        if constexpr (NQ == 4) {
+            side1_mfma<WAVES>(L, limbs, u, gl, sp.rot_e, S);
         } else {
-            uint8_t* lb = reinterpret_cast<uint8_t*>(limbs);
-#pragma unroll
-            for (int i = 0; i < NLIMB; ++i)
-                lb[((gl >> 2) * LIMB_STRIDE + i) * 4 + (gl & 3)] = (uint8_t)((u[0] >> (7 * i)) & 127);
+            side1_dot4<NQ, WAVES>(L, limbs, u, gl, sp.rot_e, S);
         }
-        wave_sync();
-        int32_t accA[RPL][NLIMB], accB[RPL][NLIMB];
-#pragma unroll
-        for (int j = 0; j < RPL; ++j)
-#pragma unroll
-            for (int i = 0; i < NLIMB; ++i) accA[j][i] = accB[j][i] = 0;
-#pragma unroll 2
-        for (int q4 = 0; q4 < Q4; ++q4) {
-            uint32_t U[NLIMB];
-#pragma unroll
-            for (int i = 0; i < NLIMB; ++i) U[i] = limbs[q4 * LIMB_STRIDE + i];
-#pragma unroll
-            for (int j = 0; j < RPL; ++j) {
-                const int a = (int)L.phiA[q4 * R + gl * RPL + j];
-                const int b = (int)L.phiB[q4 * R + gl * RPL + j];
-#pragma unroll
-                for (int i = 0; i < NLIMB; ++i) {
-                    accA[j][i] = __builtin_amdgcn_sdot4(a, (int)U[i], accA[j][i], false);
-                    accB[j][i] = __builtin_amdgcn_sdot4(b, (int)U[i], accB[j][i], false);
-                }
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < RPL; ++j) {
-            uint64_t al = 0, be = 0;
-#pragma unroll
-            for (int i = 0; i < NLIMB; ++i) {
-                al = m61_add(al, m61_rot(m61_from_i32(accA[j][i]), 7 * i));
-                be = m61_add(be, m61_rot(m61_from_i32(accB[j][i]), 7 * i));
-            }
-            // phi(S_c) u = 2^(30 e) (A u + 2^31 B u)
-            S[j] = m61_rot(m61_add(al, m61_rot(be, 31)), sp.rot_e);
-        }
-        wave_sync();
     } else {
 #pragma unroll
         for (int j = 0; j < RPL; ++j) S[j] = u[j];
@@ -226,12 +372,12 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
         const uint64_t c2 = P61 - c;
         d[j] = c < c2 ? c : c2;
     }
-    bitonic_sort<NQ>(d, gl, gbase);
+    bitonic_sort<NQ>(d, gl, gbase + gl);
     uint64_t acc = 0;
 #pragma unroll
     for (int j = 0; j < RPL; ++j) acc += L.K2[gl * RPL + j] * d[j];
 #pragma unroll
-    for (int off = 1; off < Gm::G; off <<= 1) acc += shfl64(acc, gbase + (gl ^ off));
+    for (int off = 1; off < Gm::G; off <<= 1) acc += xchg64_dyn(acc, off, gbase + gl);
     const uint64_t H = mix64(sp.salt_h + acc);
     out_h = H;
     out_pt = mulhi64(H, sp.n_half) | ((H & 1) << 32);
@@ -343,6 +489,30 @@ __global__ __launch_bounds__(WAVES * 64) void k_canon(SpaceDev sp, const uint32_
 template <int NQ>
 __global__ void k_pack_i32(const int32_t* a, const int32_t* b, int64_t count, uint32_t* phi, int* flag) {
     constexpr int R = Geo<NQ>::R, Q4 = Geo<NQ>::Q4;
+    if constexpr (NQ == 4) {
+        // MFMA fragment layout (see Lds<4>): 2 * Q4 * R dwords per matrix
+        const int64_t total4 = count * 2 * Q4 * R;
+        for (int64_t idx = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; idx < total4;
+             idx += (int64_t)blockDim.x * gridDim.x) {
+            const int64_t m = idx / (2 * Q4 * R);
+            const int rem = (int)(idx % (2 * Q4 * R));
+            const int fi = rem >> 2, w = rem & 3;
+            const int l = fi & 63, fk = fi >> 6;
+            const int nt = fk >> 3, kk = fk & 7;
+            const int r = nt * 16 + (l & 15);
+            const int32_t* am = a + m * R * R;
+            const int32_t* bm = b + m * R * R;
+            uint32_t word = 0;
+            for (int c = 0; c < 4; ++c) {
+                const int qq = kk * 64 + (l >> 4) * 16 + 4 * w + c;
+                const int32_t v = qq < R ? am[r * R + qq] : bm[r * R + qq - R];
+                if (v > 127 || v < -127) atomicOr(flag, 2);
+                word |= ((uint32_t)(uint8_t)(int8_t)v) << (8 * c);
+            }
+            phi[m * 2 * Q4 * R + rem] = word;
+        }
+        return;
+    }
     const int64_t total = count * Q4 * R;
     for (int64_t idx = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; idx < total;
          idx += (int64_t)blockDim.x * gridDim.x) {
