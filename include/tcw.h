@@ -172,7 +172,7 @@ typedef struct tcw_walk_params {
     uint64_t seed;            /* search seed */
     uint32_t version;         /* first function version */
     int32_t trail_cap_factor; /* cap = factor * 2^delta (default 20) */
-    int32_t budget_beta;      /* steps per (k, chunk) = beta * N * 2^delta, N = 2 xi^h (default 4) */
+    int32_t budget_beta;      /* steps per (k, chunk) = beta * N * 2^delta, N = 2 xi^h (default 16) */
     int32_t version_factor;   /* steps per function version = max(factor * N, 2 walks 2^delta) (default 2) */
     int64_t enum_max;         /* enumerate spaces with N <= enum_max (default 65536) */
     int32_t iters_per_launch; /* f evaluations per walk per launch (default by n) */
@@ -203,6 +203,25 @@ typedef struct tcw_result {
 void tcw_default_params(tcw_walk_params* p, int n);
 /* Blocking.  Results written to *res (caller-allocated). */
 int tcw_search(tcw_ctx* ctx, const tcw_target* t, const tcw_walk_params* p, tcw_result* res);
+
+/* ---- batching: many targets of mixed n and k in one graph-captured launch per round ----------
+ * tcw_search_batch: targets[i] is searched with params[i] (its own k_max, seed, budgets, wall-clock
+ * cap max_seconds); walks <= 0, log2_table <= 0 or iters_per_launch <= 0 take the autotuner's
+ * choice for that (n, k).  Depth 0 and small spaces are searched on the spot; every target that is
+ * in a walk space advances together: each round replays one hipGraph whose parallel branches run one
+ * persistent batch kernel per qubit count, each block serving one target (its own S_c, keys, walk
+ * states and table).  Between rounds the host checks claw candidates exactly, switches function
+ * versions, chunks and depths per target.  results[i] as for tcw_search (status 0: not found within
+ * budget or cap).  *aggregate_steps_per_s (may be NULL): walk steps of all targets per second of
+ * graph execution.  Blocking.
+ * tcw_autotune: times short walk launches of (n, k) over walk counts 64, 256, ... up to min(N/4, 2^20)
+ * and returns the smallest count within 85% of the best rate, launch iterations for ~4 ms launches
+ * and a table size holding a version's distinguished points with 4x headroom.  Results are cached
+ * in the context per (n, k, delta).  Blocking. */
+int tcw_search_batch(tcw_ctx* ctx, const tcw_target* const* targets, int count, const tcw_walk_params* params,
+                     tcw_result* results, double* aggregate_steps_per_s);
+int tcw_autotune(tcw_ctx* ctx, const tcw_target* t, int k, int chunk, int delta, uint64_t seed, int64_t* walks,
+                 int* iters, int* log2_table, double* steps_per_s);
 
 #ifdef __cplusplus
 }

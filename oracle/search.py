@@ -12,8 +12,8 @@ Plain, sequential restatement:
   claw candidate, accepted only when D = W V^T is exactly a signed permutation.
 * Driver: depths in the given order; odd depths loop over the xi chunks in
   ascending order; a space with N = 2 xi^h <= enum_max points is enumerated;
-  otherwise walks run with a budget of beta N / theta steps (Appendix: about
-  N/theta steps per golden collision when memory exceeds the space), split
+  otherwise walks run with a budget of beta N / theta steps, beta = 16 (Appendix:
+  order N/theta steps per golden collision when memory exceeds the space), split
   into function versions of max(version_factor * N, 2 m / theta) steps each.  A version changes
   every salt, hence f, and starts from an empty table (re-salting, as in van
   Oorschot-Wiener's golden-collision search; the paper cites it for the method).
@@ -199,7 +199,7 @@ class SearchResult:
 
 
 def search(u: zmat.ZMat, n: int, k_max: int, seed: int, delta_of_k, walks: int = 64,
-           cap_factor: int = 20, beta: int = 4, enum_max: int = 1 << 16,
+           cap_factor: int = 20, beta: int = 16, enum_max: int = 1 << 16,
            depth_order: Optional[List[int]] = None, version: int = 0,
            version_factor: int = 2) -> SearchResult:
     """Find e^{i phi} U = D R(P_t) ... R(P_1) at the first depth in `depth_order` that succeeds."""

@@ -7,6 +7,8 @@
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -15,7 +17,15 @@
 #include "common.h"
 #include "internal.h"
 
+struct TunedCfg {
+    int64_t walks = 0;
+    int iters = 0;
+    int log2_table = 0;
+    double rate = 0;
+};
+
 struct tcw_ctx {
+    std::map<uint64_t, TunedCfg> tuned;  // autotuner results by (n, k, delta)
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
@@ -611,7 +621,7 @@ void tcw_default_params(tcw_walk_params* p, int n) {
     p->seed = 1;
     p->version = 0;
     p->trail_cap_factor = 20;
-    p->budget_beta = 4;
+    p->budget_beta = 16;
     p->version_factor = 2;
     p->enum_max = 1 << 16;
     p->iters_per_launch = 0;
@@ -647,17 +657,12 @@ void add_stats(tcw_walk_stats& a, const tcw_walk_stats& b) {
     a.spin_timeouts += b.spin_timeouts;
 }
 
-// Exact check of new claw candidates; fills res and returns 1 when one is a decomposition.
-int check_claws(tcw_ctx* c, tcw_walk* w, int64_t& seen, tcw_result* res, int* found) {
+// Exact check of claw candidate pairs (host arrays) of a space: the first that passes fills res.
+int check_pairs(tcw_ctx* c, const Space& sp, const uint64_t* u0, const uint64_t* u1, int64_t m, tcw_result* res,
+                int* found) {
     *found = 0;
-    int64_t total = 0;
-    std::vector<uint64_t> u0(4096), u1(4096);
-    int rc = tcw_walk_claws(w, u0.data(), u1.data(), 4096, &total);
-    if (rc) return rc;
-    const int64_t avail = total < 4096 ? total : 4096;
-    if (avail <= seen) return TCW_OK;
-    const int64_t m = avail - seen;
-    const int n = w->space.n;
+    if (m <= 0) return TCW_OK;
+    const int n = sp.n;
     const int R = 1 << (2 * n);
     uint64_t *d0 = nullptr, *d1 = nullptr;
     int32_t *dok = nullptr, *dperm = nullptr;
@@ -667,8 +672,8 @@ int check_claws(tcw_ctx* c, tcw_walk* w, int64_t& seen, tcw_result* res, int* fo
     HIP_TRY(c, hipMalloc(&dok, m * 4));
     HIP_TRY(c, hipMalloc(&dperm, m * R * 4));
     HIP_TRY(c, hipMalloc(&dsign, m * R));
-    HIP_TRY(c, hipMemcpyAsync(d0, u0.data() + seen, m * 8, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(d1, u1.data() + seen, m * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d0, u0, m * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d1, u1, m * 8, hipMemcpyHostToDevice, c->stream));
     const size_t need = tcw::exact_claw_scratch_bytes(n);
     if (c->claw_scratch_bytes < need) {
         if (c->claw_scratch) (void)hipFree(c->claw_scratch);
@@ -677,8 +682,8 @@ int check_claws(tcw_ctx* c, tcw_walk* w, int64_t& seen, tcw_result* res, int* fo
         HIP_TRY(c, hipMalloc(&c->claw_scratch, need));
         c->claw_scratch_bytes = need;
     }
-    HIP_TRY(c, tcw::exact_claw_check(w->space.S, w->space.k, d0, d1, m, c->claw_scratch, c->claw_scratch_bytes, dok,
-                                     dperm, dsign, c->stream));
+    HIP_TRY(c, tcw::exact_claw_check(sp.S, sp.k, d0, d1, m, c->claw_scratch, c->claw_scratch_bytes, dok, dperm, dsign,
+                                     c->stream));
     std::vector<int32_t> ok(m), perm(m * R);
     std::vector<int8_t> sign(m * R);
     HIP_TRY(c, hipMemcpyAsync(ok.data(), dok, m * 4, hipMemcpyDeviceToHost, c->stream));
@@ -695,18 +700,18 @@ int check_claws(tcw_ctx* c, tcw_walk* w, int64_t& seen, tcw_result* res, int* fo
             res->false_claws++;
             continue;
         }
-        uint64_t pv = u0[seen + i], pw = u1[seen + i];
+        uint64_t pv = u0[i], pw = u1[i];
         if ((pv >> 32) & 1) std::swap(pv, pw);
-        const int h = w->space.k / 2;
+        const int h = sp.k / 2;
         std::vector<uint16_t> dv, dw, desc;
         decode_desc(pv, n, h, dv);
         decode_desc(pw, n, h, dw);
         desc = dv;
         for (int t = h - 1; t >= 0; --t) desc.push_back(dw[t]);
-        if (w->space.k % 2) desc.push_back((uint16_t)w->space.chunk);
+        if (sp.k % 2) desc.push_back((uint16_t)sp.chunk);
         res->status = 1;
-        res->t = w->space.k;
-        res->chunk = w->space.chunk;
+        res->t = sp.k;
+        res->chunk = sp.chunk;
         for (size_t j = 0; j < desc.size() && j < TCW_MAX_T; ++j) res->paulis[j] = desc[j];
         for (int q = 0; q < R; ++q) {
             res->clifford_perm[q] = perm[i * R + q];
@@ -715,26 +720,30 @@ int check_claws(tcw_ctx* c, tcw_walk* w, int64_t& seen, tcw_result* res, int* fo
         *found = 1;
         break;
     }
-    seen = avail;
     return TCW_OK;
+}
+
+// New claw candidates of a walk session; `seen` counts those already checked.
+int check_claws(tcw_ctx* c, tcw_walk* w, int64_t& seen, tcw_result* res, int* found) {
+    *found = 0;
+    int64_t total = 0;
+    std::vector<uint64_t> u0(4096), u1(4096);
+    int rc = tcw_walk_claws(w, u0.data(), u1.data(), 4096, &total);
+    if (rc) return rc;
+    const int64_t avail = total < 4096 ? total : 4096;
+    if (avail <= seen) return TCW_OK;
+    rc = check_pairs(c, w->space, u0.data() + seen, u1.data() + seen, avail - seen, res, found);
+    seen = avail;
+    return rc;
 }
 
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-}  // namespace
-
-extern "C" int tcw_search(tcw_ctx* c, const tcw_target* t, const tcw_walk_params* p, tcw_result* res) {
-    if (!c || !t || !p || !res) return TCW_EINVAL;
-    std::memset(res, 0, sizeof(*res));
-    const double t0 = now_s();
-    const int n = t->n;
-    const int R = 1 << (2 * n);
-    res->n = n;
+int depth_order_of(tcw_ctx* c, const tcw_walk_params* p, std::vector<int>& order) {
+    order.clear();
     if (p->k_max < 0 || p->k_max > TCW_MAX_T) return fail(c, TCW_EINVAL, "k_max out of range");
-    if (p->walks < 1) return fail(c, TCW_EINVAL, "walks must be positive");
-    std::vector<int> order;
     if (p->depth_order_kind == TCW_ORDER_GIVEN) {
         if (p->depth_order_len < 0 || p->depth_order_len > 16) return fail(c, TCW_EINVAL, "bad depth order");
         for (int i = 0; i < p->depth_order_len; ++i) {
@@ -751,29 +760,106 @@ extern "C" int tcw_search(tcw_ctx* c, const tcw_target* t, const tcw_walk_params
         for (int o : order) have |= (o == k);
         if (!have) order.push_back(k);
     }
+    return TCW_OK;
+}
+
+// Depth 0: is U_hat itself a signed permutation (a Clifford)?
+int search_k0(tcw_ctx* c, const tcw_target* t, tcw_result* res, int* found) {
+    const int R = 1 << (2 * t->n);
+    *found = 0;
+    int32_t *dok = nullptr, *dperm = nullptr;
+    int8_t* dsign = nullptr;
+    HIP_TRY(c, hipMalloc(&dok, 4));
+    HIP_TRY(c, hipMalloc(&dperm, R * 4));
+    HIP_TRY(c, hipMalloc(&dsign, R));
+    HIP_TRY(c, tcw::exact_signed_perm(t->U, dok, dperm, dsign, c->stream));
+    int32_t ok = 0;
+    std::vector<int32_t> perm(R);
+    std::vector<int8_t> sign(R);
+    HIP_TRY(c, hipMemcpyAsync(&ok, dok, 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(perm.data(), dperm, R * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(sign.data(), dsign, R, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(dok);
+    (void)hipFree(dperm);
+    (void)hipFree(dsign);
+    res->spaces++;
+    if (ok) {
+        res->status = 1;
+        res->t = 0;
+        for (int q = 0; q < R; ++q) {
+            res->clifford_perm[q] = perm[q];
+            res->clifford_sign[q] = sign[q];
+        }
+        *found = 1;
+    }
+    return TCW_OK;
+}
+
+// A small space: every point once, keyed by the full matrix hash.
+int search_enum(tcw_ctx* c, const tcw_target* t, const tcw_walk_params* p, int k, int chunk, int iters,
+                tcw_result* res, int* found, double t0) {
+    *found = 0;
+    const uint64_t npts = 2 * n_half_of(t->n, k / 2);
+    tcw_space sp{k, chunk, p->seed, p->version, 0};
+    res->spaces++;
+    res->versions++;
+    int64_t walks = (int64_t)npts < p->walks ? (int64_t)npts : p->walks;
+    if (walks < 64) walks = (int64_t)npts < 64 ? (int64_t)npts : 64;
+    int lg = 4;
+    while ((1ull << lg) < 4 * npts && lg < 30) ++lg;
+    tcw_walk* w = nullptr;
+    int rc = tcw_walk_begin(c, t, &sp, walks, lg, 2, 1, &w);
+    if (rc) return rc;
+    int64_t seen = 0;
+    // each point costs one evaluation; a bounded number of launches covers them all
+    const int64_t max_launches = (int64_t)(npts / (uint64_t)walks + 2) / iters + 4;
+    for (int64_t launch = 0;; ++launch) {
+        rc = tcw_walk_run(w, iters);
+        res->launches++;
+        tcw_walk_stats st{};
+        if (!rc) rc = tcw_walk_stats_get(w, &st);
+        if (!rc) rc = check_claws(c, w, seen, res, found);
+        if (rc) {
+            tcw_walk_end(w);
+            return rc;
+        }
+        if (*found || st.active_walks == 0 || launch >= max_launches ||
+            (p->max_seconds > 0 && now_s() - t0 > p->max_seconds)) {
+            add_stats(res->stats, st);
+            break;
+        }
+    }
+    tcw_walk_end(w);
+    return TCW_OK;
+}
+
+uint64_t version_steps(const tcw_walk_params* p, uint64_t npts, int delta, int64_t walks) {
+    uint64_t per_version = (uint64_t)p->version_factor * npts;
+    const uint64_t floor_v = 2ull * (uint64_t)walks << delta;
+    return per_version < floor_v ? floor_v : per_version;
+}
+
+}  // namespace
+
+extern "C" int tcw_search(tcw_ctx* c, const tcw_target* t, const tcw_walk_params* p, tcw_result* res) {
+    if (!c || !t || !p || !res) return TCW_EINVAL;
+    std::memset(res, 0, sizeof(*res));
+    const double t0 = now_s();
+    const int n = t->n;
+    res->n = n;
+    if (p->walks < 1) return fail(c, TCW_EINVAL, "walks must be positive");
+    std::vector<int> order;
+    int rc = depth_order_of(c, p, order);
+    if (rc) return rc;
     const uint32_t xi = xi_of(n);
     const int iters = p->iters_per_launch > 0 ? p->iters_per_launch : default_iters(n);
     for (int k : order) {
         if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) break;
+        int found = 0;
         if (k == 0) {
-            int32_t *dok = nullptr, *dperm = nullptr;
-            int8_t* dsign = nullptr;
-            HIP_TRY(c, hipMalloc(&dok, 4));
-            HIP_TRY(c, hipMalloc(&dperm, R * 4));
-            HIP_TRY(c, hipMalloc(&dsign, R));
-            HIP_TRY(c, tcw::exact_signed_perm(t->U, dok, dperm, dsign, c->stream));
-            int32_t ok = 0;
-            HIP_TRY(c, hipMemcpyAsync(&ok, dok, 4, hipMemcpyDeviceToHost, c->stream));
-            HIP_TRY(c, hipMemcpyAsync(res->clifford_perm, dperm, R * 4, hipMemcpyDeviceToHost, c->stream));
-            HIP_TRY(c, hipMemcpyAsync(res->clifford_sign, dsign, R, hipMemcpyDeviceToHost, c->stream));
-            HIP_TRY(c, hipStreamSynchronize(c->stream));
-            (void)hipFree(dok);
-            (void)hipFree(dperm);
-            (void)hipFree(dsign);
-            res->spaces++;
-            if (ok) {
-                res->status = 1;
-                res->t = 0;
+            if ((rc = search_k0(c, t, res, &found))) return rc;
+            if (found) {
                 res->seconds = now_s() - t0;
                 return TCW_OK;
             }
@@ -790,97 +876,522 @@ extern "C" int tcw_search(tcw_ctx* c, const tcw_target* t, const tcw_walk_params
             if (cl > (int)xi) cl = (int)xi;
         }
         const bool enumerate = (int64_t)npts <= p->enum_max;
-        const int delta = enumerate ? 0 : (p->delta >= 0 ? p->delta : default_delta(n));
-        for (int chunk = cf; chunk <= cl; ++chunk) {
+        const int delta = p->delta >= 0 ? p->delta : default_delta(n);
+        for (int chunk = cf; chunk <= cl && !found; ++chunk) {
             if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) break;
+            if (enumerate) {
+                if ((rc = search_enum(c, t, p, k, chunk, iters, res, &found, t0))) return rc;
+                continue;
+            }
             tcw_space sp{k, chunk, p->seed, p->version, delta};
             res->spaces++;
+            const uint64_t budget = (uint64_t)p->budget_beta * npts << delta;
+            const uint64_t per_version = version_steps(p, npts, delta, p->walks);
+            const uint32_t cap = (uint32_t)p->trail_cap_factor << delta;
+            // a launch must not overrun a function version
+            int iters_v = iters;
+            const uint64_t fit = per_version / (uint64_t)p->walks;
+            if ((uint64_t)iters_v > fit) iters_v = fit > 0 ? (int)fit : 1;
             tcw_walk* w = nullptr;
-            int found = 0;
+            rc = tcw_walk_begin(c, t, &sp, p->walks, p->log2_table, cap, 0, &w);
+            if (rc) return rc;
+            uint64_t used = 0, used_v = 0;
+            uint32_t version = p->version;
             int64_t seen = 0;
-            if (enumerate) {
-                int64_t walks = (int64_t)npts < p->walks ? (int64_t)npts : p->walks;
-                if (walks < 64) walks = (int64_t)npts < 64 ? (int64_t)npts : 64;
-                int lg = 4;
-                while ((1ull << lg) < 4 * npts && lg < 30) ++lg;
-                int rc = tcw_walk_begin(c, t, &sp, walks, lg, 2, 1, &w);
-                if (rc) return rc;
-                res->versions++;
-                for (;;) {
-                    rc = tcw_walk_run(w, iters);
-                    res->launches++;
-                    tcw_walk_stats st{};
-                    if (!rc) rc = tcw_walk_stats_get(w, &st);
-                    if (!rc) rc = check_claws(c, w, seen, res, &found);
+            res->versions++;
+            tcw_walk_stats st{};
+            while (used < budget) {
+                rc = tcw_walk_run(w, iters_v);
+                res->launches++;
+                if (!rc) rc = tcw_walk_stats_get(w, &st);
+                if (!rc) rc = check_claws(c, w, seen, res, &found);
+                if (rc) {
+                    tcw_walk_end(w);
+                    return rc;
+                }
+                used = used - used_v + (uint64_t)st.steps;
+                used_v = (uint64_t)st.steps;
+                if (found) break;
+                if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) break;
+                if (used_v >= per_version && used < budget) {
+                    add_stats(res->stats, st);
+                    std::memset(&st, 0, sizeof(st));
+                    used_v = 0;
+                    seen = 0;
+                    ++version;
+                    res->versions++;
+                    rc = tcw_walk_reset(w, version);
                     if (rc) {
                         tcw_walk_end(w);
                         return rc;
                     }
-                    if (found || st.active_walks == 0) {
-                        add_stats(res->stats, st);
-                        break;
-                    }
-                    // counters are cumulative within the session: add only at the end
-                    if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) {
-                        add_stats(res->stats, st);
-                        break;
-                    }
                 }
-                tcw_walk_end(w);
-            } else {
-                const uint64_t budget = (uint64_t)p->budget_beta * npts << delta;
-                uint64_t per_version = (uint64_t)p->version_factor * npts;
-                const uint64_t floor_v = 2ull * (uint64_t)p->walks << delta;
-                if (per_version < floor_v) per_version = floor_v;
-                const uint32_t cap = (uint32_t)p->trail_cap_factor << delta;
-                // a launch must not overrun a function version
-                int iters_v = iters;
-                const uint64_t fit = per_version / (uint64_t)p->walks;
-                if ((uint64_t)iters_v > fit) iters_v = fit > 0 ? (int)fit : 1;
-                int rc = tcw_walk_begin(c, t, &sp, p->walks, p->log2_table, cap, 0, &w);
-                if (rc) return rc;
-                uint64_t used = 0;
-                uint32_t version = p->version;
-                res->versions++;
-                uint64_t used_v = 0;
-                tcw_walk_stats st{};
-                while (used < budget) {
-                    rc = tcw_walk_run(w, iters_v);
-                    res->launches++;
-                    if (!rc) rc = tcw_walk_stats_get(w, &st);
-                    if (!rc) rc = check_claws(c, w, seen, res, &found);
-                    if (rc) {
-                        tcw_walk_end(w);
-                        return rc;
-                    }
-                    used = used - used_v + (uint64_t)st.steps;
-                    used_v = (uint64_t)st.steps;
-                    if (found) break;
-                    if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) break;
-                    if (used_v >= per_version && used < budget) {
-                        add_stats(res->stats, st);
-                        std::memset(&st, 0, sizeof(st));
-                        used_v = 0;
-                        seen = 0;
-                        ++version;
-                        res->versions++;
-                        rc = tcw_walk_reset(w, version);
-                        if (rc) {
-                            tcw_walk_end(w);
-                            return rc;
-                        }
-                    }
-                }
-                add_stats(res->stats, st);
-                tcw_walk_end(w);
             }
-            if (found) {
-                res->seconds = now_s() - t0;
-                return TCW_OK;
-            }
+            add_stats(res->stats, st);
+            tcw_walk_end(w);
+        }
+        if (found) {
+            res->seconds = now_s() - t0;
+            return TCW_OK;
         }
     }
     res->status = 0;
     res->seconds = now_s() - t0;
+    return TCW_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Autotuner and batched search (many targets of mixed n and k)
+namespace {
+
+int64_t floor_pow2(uint64_t v) {
+    int64_t p = 1;
+    while ((uint64_t)(p * 2) <= v) p *= 2;
+    return p;
+}
+
+int autotune(tcw_ctx* c, const tcw_target* t, int k, int chunk, int delta, uint64_t seed, TunedCfg* out) {
+    const int n = t->n;
+    const uint64_t key = ((uint64_t)n << 40) | ((uint64_t)k << 20) | (uint64_t)delta;
+    auto it = c->tuned.find(key);
+    if (it != c->tuned.end()) {
+        *out = it->second;
+        return TCW_OK;
+    }
+    const uint64_t npts = 2 * n_half_of(n, k / 2);
+    if (npts == 0) return fail(c, TCW_EINVAL, "space too large");
+    // walks beyond N/4 only add warm-up (m / theta steps before the first distinguished points)
+    const int64_t wmax = std::min<int64_t>(1 << 20, std::max<int64_t>(64, floor_pow2(npts / 4)));
+    std::vector<int64_t> cands;
+    for (int64_t w = 64; w < wmax; w *= 4) cands.push_back(w);
+    cands.push_back(wmax);
+    tcw_space sp{k, chunk, seed, 0xFFFFu, delta};
+    std::vector<double> rates;
+    for (int64_t w : cands) {
+        tcw_walk* ws = nullptr;
+        int rc = tcw_walk_begin(c, t, &sp, w, 16, (uint32_t)20 << delta, 0, &ws);
+        if (rc) return rc;
+        const int iters = (int)std::max<int64_t>(1, std::min<int64_t>(64, (1 << 21) / w));
+        float ms = 0, tot = 0;
+        rc = tcw_walk_run(ws, iters);
+        if (!rc) rc = tcw_walk_last_ms(ws, &ms);
+        for (int r = 0; r < 2 && !rc; ++r) {
+            rc = tcw_walk_run(ws, iters);
+            if (!rc) rc = tcw_walk_last_ms(ws, &ms);
+            tot += ms;
+        }
+        tcw_walk_end(ws);
+        if (rc) return rc;
+        rates.push_back((double)w * iters * 2 / (tot * 1e-3));
+    }
+    double best = 0;
+    for (double r : rates) best = std::max(best, r);
+    size_t pick = cands.size() - 1;
+    for (size_t i = 0; i < cands.size(); ++i)
+        if (rates[i] >= 0.85 * best) {
+            pick = i;
+            break;
+        }
+    TunedCfg cfg;
+    cfg.walks = cands[pick];
+    cfg.rate = rates[pick];
+    // launches of about 4 ms between host checks
+    cfg.iters = (int)std::max(1.0, std::min(64.0, cfg.rate * 4e-3 / (double)cfg.walks));
+    // the table holds every distinguished point of a version: max(2 N theta, 2 m) of them, 4x headroom
+    const double dps = std::max(2.0 * (double)npts / (double)(1ull << delta), 2.0 * (double)cfg.walks);
+    int lg = 10;
+    while ((double)(1ull << lg) < 4 * dps && lg < 26) ++lg;
+    cfg.log2_table = lg;
+    c->tuned[key] = cfg;
+    *out = cfg;
+    return TCW_OK;
+}
+
+constexpr uint32_t BATCH_CLAW_CAP = 1024;
+
+struct BatchTarget {
+    const tcw_target* t = nullptr;
+    tcw_walk_params p{};
+    tcw_result* res = nullptr;
+    std::vector<int> order;
+    size_t oi = 0;
+    int k = -1, chunk = 0, cl = 0;
+    bool walking = false, done = false;
+    std::unique_ptr<Space> space;
+    tcw::WalkDev wd{};
+    int64_t walks = 0;
+    int iters = 0, log2 = 0, blocks = 0;
+    uint64_t budget = 0, per_version = 0, used = 0, used_v = 0;
+    uint32_t version = 0;
+    int64_t seen = 0;
+    size_t states_cap = 0;
+    int table_cap = 0;
+};
+
+struct BatchBuffers {
+    unsigned long long* stats = nullptr;   // count x ST_COUNT
+    unsigned long long* claw_count = nullptr;
+    uint64_t* claws = nullptr;             // count x BATCH_CLAW_CAP x 2
+    tcw::SpaceDev* sps = nullptr;          // count
+    tcw::WalkDev* wds = nullptr;           // count
+    int32_t* blk_target[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int32_t* tgt_first = nullptr;          // count
+    int32_t* tgt_blocks = nullptr;         // count
+    ~BatchBuffers() {
+        for (void* q : {(void*)stats, (void*)claw_count, (void*)claws, (void*)sps, (void*)wds, (void*)tgt_first,
+                        (void*)tgt_blocks})
+            if (q) (void)hipFree(q);
+        for (auto* q : blk_target)
+            if (q) (void)hipFree(q);
+    }
+};
+
+void free_walk_buffers(BatchTarget& b) {
+    if (b.wd.states) (void)hipFree(b.wd.states);
+    if (b.wd.table) (void)hipFree(b.wd.table);
+    b.wd.states = nullptr;
+    b.wd.table = nullptr;
+    b.states_cap = 0;
+    b.table_cap = 0;
+}
+
+// (Re)start the walks of a target's current space on stream s: table cleared, counters zeroed.
+int batch_restart(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStream_t s) {
+    HIP_TRY(c, tcw::launch_table_clear(b.wd.table, b.wd.log2_table, s));
+    HIP_TRY(c, hipMemsetAsync(bb.stats + (size_t)slot * tcw::ST_COUNT, 0, tcw::ST_COUNT * 8, s));
+    HIP_TRY(c, hipMemsetAsync(bb.claw_count + slot, 0, 8, s));
+    HIP_TRY(c, tcw::launch_walk_init(b.space->dev, b.wd, s));
+    return TCW_OK;
+}
+
+// Move a target to its next space: depth 0 and small spaces are searched on the spot, the first
+// walk space leaves the target `walking`.
+int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStream_t s, double t0) {
+    const int n = b.t->n;
+    const uint32_t xi = xi_of(n);
+    while (!b.done) {
+        if (b.p.max_seconds > 0 && now_s() - t0 > b.p.max_seconds) {
+            b.done = true;
+            break;
+        }
+        // next (k, chunk)
+        if (b.k >= 0 && b.k % 2 == 1 && b.chunk < b.cl) {
+            b.chunk++;
+        } else {
+            if (b.oi >= b.order.size()) {
+                b.done = true;
+                break;
+            }
+            b.k = b.order[b.oi++];
+            b.chunk = 0;
+            b.cl = 0;
+            if (b.k % 2) {
+                b.chunk = b.p.chunk_first > 0 ? b.p.chunk_first : 1;
+                b.cl = b.p.chunk_last > 0 ? std::min<int>(b.p.chunk_last, (int)xi) : (int)xi;
+            }
+        }
+        int found = 0, rc = 0;
+        if (b.k == 0) {
+            if ((rc = search_k0(c, b.t, b.res, &found))) return rc;
+            if (found) b.done = true;
+            continue;
+        }
+        const uint64_t nh = n_half_of(n, b.k / 2);
+        if (nh == 0) {
+            b.chunk = b.cl;
+            continue;
+        }
+        const uint64_t npts = 2 * nh;
+        if ((int64_t)npts <= b.p.enum_max) {
+            const int iters = default_iters(n);
+            if ((rc = search_enum(c, b.t, &b.p, b.k, b.chunk, iters, b.res, &found, t0))) return rc;
+            if (found) b.done = true;
+            continue;
+        }
+        // a walk space
+        const int delta = b.p.delta >= 0 ? b.p.delta : default_delta(n);
+        TunedCfg cfg;
+        if (b.p.walks <= 0 || b.p.log2_table <= 0 || b.p.iters_per_launch <= 0) {
+            if ((rc = autotune(c, b.t, b.k, b.chunk, delta, b.p.seed, &cfg))) return rc;
+        }
+        b.walks = b.p.walks > 0 ? b.p.walks : cfg.walks;
+        b.log2 = b.p.log2_table > 0 ? b.p.log2_table : cfg.log2_table;
+        b.iters = b.p.iters_per_launch > 0 ? b.p.iters_per_launch : cfg.iters;
+        b.space.reset(new Space());
+        tcw_space sp{b.k, b.chunk, b.p.seed, b.p.version, delta};
+        if ((rc = prepare_space(c, b.t, &sp, *b.space))) return rc;
+        b.res->spaces++;
+        b.res->versions++;
+        b.version = b.p.version;
+        b.budget = (uint64_t)b.p.budget_beta * npts << delta;
+        b.per_version = version_steps(&b.p, npts, delta, b.walks);
+        const uint64_t fit = b.per_version / (uint64_t)b.walks;
+        if ((uint64_t)b.iters > fit) b.iters = fit > 0 ? (int)fit : 1;
+        b.used = b.used_v = 0;
+        b.seen = 0;
+        // walk buffers (kept across spaces when large enough)
+        const size_t sbytes = (size_t)b.walks * sizeof(tcw::WalkState);
+        if (b.states_cap < sbytes) {
+            if (b.wd.states) (void)hipFree(b.wd.states);
+            HIP_TRY(c, hipMalloc(&b.wd.states, sbytes));
+            b.states_cap = sbytes;
+        }
+        if (b.table_cap < b.log2) {
+            if (b.wd.table) (void)hipFree(b.wd.table);
+            HIP_TRY(c, hipMalloc(&b.wd.table, ((size_t)1 << b.log2) * 16));
+            b.table_cap = b.log2;
+        }
+        b.wd.walks = b.walks;
+        b.wd.log2_table = b.log2;
+        b.wd.cap = (uint32_t)b.p.trail_cap_factor << delta;
+        b.wd.enumerate = 0;
+        b.wd.n_points = npts;
+        b.wd.stats = bb.stats + (size_t)slot * tcw::ST_COUNT;
+        b.wd.claws = bb.claws + (size_t)slot * BATCH_CLAW_CAP * 2;
+        b.wd.claw_count = bb.claw_count + slot;
+        b.wd.claw_cap = BATCH_CLAW_CAP;
+        if ((rc = batch_restart(c, b, slot, bb, s))) return rc;
+        b.walking = true;
+        return TCW_OK;
+    }
+    b.walking = false;
+    free_walk_buffers(b);
+    return TCW_OK;
+}
+
+}  // namespace
+
+extern "C" int tcw_autotune(tcw_ctx* c, const tcw_target* t, int k, int chunk, int delta, uint64_t seed,
+                            int64_t* walks, int* iters, int* log2_table, double* steps_per_s) {
+    if (!c || !t || !walks || !iters || !log2_table || !steps_per_s) return TCW_EINVAL;
+    tcw_space sp{k, chunk, seed, 0, delta};
+    int rc = check_space(c, t->n, &sp);
+    if (rc) return rc;
+    TunedCfg cfg;
+    rc = autotune(c, t, k, chunk, delta, seed, &cfg);
+    if (rc) return rc;
+    *walks = cfg.walks;
+    *iters = cfg.iters;
+    *log2_table = cfg.log2_table;
+    *steps_per_s = cfg.rate;
+    return TCW_OK;
+}
+
+extern "C" int tcw_search_batch(tcw_ctx* c, const tcw_target* const* targets, int count, const tcw_walk_params* params,
+                                tcw_result* results, double* aggregate_steps_per_s) {
+    if (!c || !targets || !params || !results || count < 1) return TCW_EINVAL;
+    for (int i = 0; i < count; ++i)
+        if (!targets[i]) return fail(c, TCW_EINVAL, "NULL target in batch");
+    const double t0 = now_s();
+    BatchBuffers bb;
+    HIP_TRY(c, hipMalloc(&bb.stats, (size_t)count * tcw::ST_COUNT * 8));
+    HIP_TRY(c, hipMalloc(&bb.claw_count, (size_t)count * 8));
+    HIP_TRY(c, hipMalloc(&bb.claws, (size_t)count * BATCH_CLAW_CAP * 16));
+    HIP_TRY(c, hipMalloc(&bb.sps, (size_t)count * sizeof(tcw::SpaceDev)));
+    HIP_TRY(c, hipMalloc(&bb.wds, (size_t)count * sizeof(tcw::WalkDev)));
+    HIP_TRY(c, hipMalloc(&bb.tgt_first, (size_t)count * 4));
+    HIP_TRY(c, hipMalloc(&bb.tgt_blocks, (size_t)count * 4));
+    HIP_TRY(c, hipMemsetAsync(bb.stats, 0, (size_t)count * tcw::ST_COUNT * 8, c->stream));
+    HIP_TRY(c, hipMemsetAsync(bb.claw_count, 0, (size_t)count * 8, c->stream));
+    std::vector<BatchTarget> bt(count);
+    int rc = TCW_OK;
+    for (int i = 0; i < count && !rc; ++i) {
+        BatchTarget& b = bt[i];
+        b.t = targets[i];
+        b.p = params[i];
+        b.res = &results[i];
+        std::memset(b.res, 0, sizeof(tcw_result));
+        b.res->n = b.t->n;
+        rc = depth_order_of(c, &b.p, b.order);
+    }
+    if (rc) return rc;
+    for (int i = 0; i < count && !rc; ++i) {
+        rc = batch_advance(c, bt[i], i, bb, c->stream, t0);
+        if (bt[i].done) bt[i].res->seconds = now_s() - t0;
+    }
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+
+    // streams for the graph: one branch per qubit count (default priority)
+    hipStream_t gs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    HIP_TRY(c, hipStreamCreateWithFlags(&gs[0], hipStreamNonBlocking));
+    for (int n = 1; n <= 4; ++n) {
+        HIP_TRY(c, hipStreamCreateWithFlags(&gs[n], hipStreamNonBlocking));
+        HIP_TRY(c, hipEventCreateWithFlags(&join[n], hipEventDisableTiming));
+    }
+    HIP_TRY(c, hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    bool dirty = true;
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    int64_t total_steps = 0;
+    double walk_seconds = 0;
+    std::vector<unsigned long long> stats((size_t)count * tcw::ST_COUNT), ccount(count);
+    std::vector<tcw::SpaceDev> h_sps(count);
+    std::vector<tcw::WalkDev> h_wds(count);
+    std::vector<int32_t> h_first(count, 0), h_blocks(count, 0);
+    int iters_n[5] = {0, 0, 0, 0, 0}, blocks_n[5] = {0, 0, 0, 0, 0};
+    auto cleanup = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (int n = 0; n <= 4; ++n) {
+            if (gs[n]) (void)hipStreamDestroy(gs[n]);
+            if (join[n]) (void)hipEventDestroy(join[n]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
+        for (auto& b : bt) free_walk_buffers(b);
+    };
+#define BATCH_TRY(expr)                      \
+    do {                                     \
+        hipError_t _e = (expr);              \
+        if (_e != hipSuccess) {              \
+            cleanup();                       \
+            return hip_fail(c, _e, #expr);   \
+        }                                    \
+    } while (0)
+    for (;;) {
+        bool any = false;
+        for (auto& b : bt) any |= b.walking;
+        if (!any) break;
+        if (dirty) {
+            // block ranges per target, per qubit count
+            std::vector<int32_t> blk[5];
+            for (int n = 1; n <= 4; ++n) {
+                int active = 0;
+                for (auto& b : bt) active += (b.walking && b.t->n == n);
+                if (!active) {
+                    blocks_n[n] = 0;
+                    continue;
+                }
+                const int cap_blocks = std::max(1, (n == 4 ? cus : 4 * cus) / active);
+                iters_n[n] = 1 << 30;
+                for (int i = 0; i < count; ++i) {
+                    BatchTarget& b = bt[i];
+                    if (!b.walking || b.t->n != n) continue;
+                    const int wpb = tcw::walks_per_block(n);
+                    b.blocks = (int)std::min<int64_t>((b.walks + wpb - 1) / wpb, cap_blocks);
+                    h_first[i] = (int32_t)blk[n].size();
+                    h_blocks[i] = b.blocks;
+                    for (int j = 0; j < b.blocks; ++j) blk[n].push_back(i);
+                    iters_n[n] = std::min(iters_n[n], b.iters);
+                }
+                blocks_n[n] = (int)blk[n].size();
+                if (bb.blk_target[n]) (void)hipFree(bb.blk_target[n]);
+                BATCH_TRY(hipMalloc(&bb.blk_target[n], blk[n].size() * 4));
+                BATCH_TRY(hipMemcpy(bb.blk_target[n], blk[n].data(), blk[n].size() * 4, hipMemcpyHostToDevice));
+            }
+            BATCH_TRY(hipMemcpy(bb.tgt_first, h_first.data(), count * 4, hipMemcpyHostToDevice));
+            BATCH_TRY(hipMemcpy(bb.tgt_blocks, h_blocks.data(), count * 4, hipMemcpyHostToDevice));
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            exec = nullptr;
+            graph = nullptr;
+            // capture: fork one branch per qubit count, join
+            BATCH_TRY(hipStreamBeginCapture(gs[0], hipStreamCaptureModeThreadLocal));
+            BATCH_TRY(hipEventRecord(fork, gs[0]));
+            for (int n = 1; n <= 4; ++n) {
+                if (!blocks_n[n]) continue;
+                BATCH_TRY(hipStreamWaitEvent(gs[n], fork, 0));
+                BATCH_TRY(tcw::launch_walk_batch(n, bb.sps, bb.wds, bb.blk_target[n], bb.tgt_first, bb.tgt_blocks,
+                                                 blocks_n[n], iters_n[n], gs[n]));
+                BATCH_TRY(hipEventRecord(join[n], gs[n]));
+                BATCH_TRY(hipStreamWaitEvent(gs[0], join[n], 0));
+            }
+            BATCH_TRY(hipStreamEndCapture(gs[0], &graph));
+            BATCH_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            dirty = false;
+        }
+        // descriptors of this round (salts change with versions)
+        for (int i = 0; i < count; ++i) {
+            if (!bt[i].walking) continue;
+            h_sps[i] = bt[i].space->dev;
+            h_wds[i] = bt[i].wd;
+        }
+        BATCH_TRY(hipMemcpyAsync(bb.sps, h_sps.data(), count * sizeof(tcw::SpaceDev), hipMemcpyHostToDevice, gs[0]));
+        BATCH_TRY(hipMemcpyAsync(bb.wds, h_wds.data(), count * sizeof(tcw::WalkDev), hipMemcpyHostToDevice, gs[0]));
+        const double tl = now_s();
+        BATCH_TRY(hipGraphLaunch(exec, gs[0]));
+        BATCH_TRY(hipMemcpyAsync(stats.data(), bb.stats, stats.size() * 8, hipMemcpyDeviceToHost, gs[0]));
+        BATCH_TRY(hipMemcpyAsync(ccount.data(), bb.claw_count, count * 8, hipMemcpyDeviceToHost, gs[0]));
+        BATCH_TRY(hipStreamSynchronize(gs[0]));
+        walk_seconds += now_s() - tl;
+        for (int i = 0; i < count; ++i) {
+            BatchTarget& b = bt[i];
+            if (!b.walking) continue;
+            b.res->launches++;
+            const unsigned long long* st = &stats[(size_t)i * tcw::ST_COUNT];
+            const uint64_t steps_now = st[tcw::ST_STEPS];
+            total_steps += (int64_t)(steps_now - b.used_v);
+            b.used += steps_now - b.used_v;
+            b.used_v = steps_now;
+            int found = 0;
+            const int64_t avail = (int64_t)std::min<unsigned long long>(ccount[i], BATCH_CLAW_CAP);
+            if (avail > b.seen) {
+                const int64_t m = avail - b.seen;
+                std::vector<uint64_t> pairs(2 * m);
+                BATCH_TRY(hipMemcpy(pairs.data(), b.wd.claws + 2 * b.seen, 16 * m, hipMemcpyDeviceToHost));
+                std::vector<uint64_t> u0(m), u1(m);
+                for (int64_t j = 0; j < m; ++j) {
+                    u0[j] = pairs[2 * j];
+                    u1[j] = pairs[2 * j + 1];
+                }
+                rc = check_pairs(c, *b.space, u0.data(), u1.data(), m, b.res, &found);
+                if (rc) {
+                    cleanup();
+                    return rc;
+                }
+                b.seen = avail;
+            }
+            tcw_walk_stats ws{};
+            ws.steps = (int64_t)st[tcw::ST_STEPS];
+            ws.dps = (int64_t)st[tcw::ST_DPS];
+            ws.inserts = (int64_t)st[tcw::ST_INSERTS];
+            ws.abandoned = (int64_t)st[tcw::ST_ABANDONED];
+            ws.robin_hood = (int64_t)st[tcw::ST_ROBIN];
+            ws.same_side = (int64_t)st[tcw::ST_SAME];
+            ws.reduction = (int64_t)st[tcw::ST_REDUCTION];
+            ws.claws = (int64_t)st[tcw::ST_CLAWS];
+            ws.table_full = (int64_t)st[tcw::ST_FULL];
+            ws.spin_timeouts = (int64_t)st[tcw::ST_SPIN];
+            const bool over_time = b.p.max_seconds > 0 && now_s() - t0 > b.p.max_seconds;
+            if (found || over_time || b.used >= b.budget) {
+                add_stats(b.res->stats, ws);
+                b.walking = false;
+                dirty = true;
+                if (found || over_time) {
+                    b.done = true;
+                    b.res->seconds = now_s() - t0;
+                    free_walk_buffers(b);
+                } else {
+                    rc = batch_advance(c, b, i, bb, gs[0], t0);
+                    if (rc) {
+                        cleanup();
+                        return rc;
+                    }
+                    if (b.done) b.res->seconds = now_s() - t0;
+                }
+            } else if (b.used_v >= b.per_version) {
+                add_stats(b.res->stats, ws);
+                b.version++;
+                b.res->versions++;
+                b.space->set_version(b.version);
+                b.used_v = 0;
+                b.seen = 0;
+                rc = batch_restart(c, b, i, bb, gs[0]);
+                if (rc) {
+                    cleanup();
+                    return rc;
+                }
+            }
+        }
+        BATCH_TRY(hipStreamSynchronize(gs[0]));
+    }
+#undef BATCH_TRY
+    cleanup();
+    for (auto& b : bt)
+        if (b.res->seconds == 0) b.res->seconds = now_s() - t0;
+    if (aggregate_steps_per_s) *aggregate_steps_per_s = walk_seconds > 0 ? (double)total_steps / walk_seconds : 0.0;
     return TCW_OK;
 }

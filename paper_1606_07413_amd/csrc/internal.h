@@ -103,6 +103,9 @@ hipError_t launch_canon_hash(int n, const SpaceDev& sp, const uint32_t* phi_all,
                              uint64_t* out, hipStream_t s);
 hipError_t launch_walk(int n, const SpaceDev& sp, const WalkDev& wd, int iters, int grid_blocks, hipStream_t s);
 hipError_t launch_walk_init(const SpaceDev& sp, const WalkDev& wd, hipStream_t s);
+hipError_t launch_walk_batch(int n, const SpaceDev* sps, const WalkDev* wds, const int32_t* blk_target,
+                             const int32_t* tgt_first, const int32_t* tgt_blocks, int blocks, int iters, hipStream_t s);
+int walks_per_block(int n);
 hipError_t launch_table_clear(uint64_t* table, int log2_table, hipStream_t s);
 int walk_grid_blocks(int n, int device);
 hipError_t pack_phi_i32(int n, const int32_t* a, const int32_t* b, int64_t count, uint32_t* phi_out,

@@ -576,20 +576,19 @@ __device__ inline uint64_t pack_value(uint64_t start, uint32_t len) {
     return (start & 0x1ffffffffull) | ((uint64_t)(len & 0x3fffffffu) << 33) | (1ull << 63);
 }
 
+// The walks of one block: walk slots first_block * WAVES * WPW + ... strided by nblocks blocks.
 template <int NQ, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void k_walk(SpaceDev sp, WalkDev wd, int iters) {
+__device__ void walk_block(const SpaceDev& sp, const WalkDev& wd, int iters, Lds<NQ, WAVES>& L, int64_t block,
+                           int64_t nblocks) {
     using Gm = Geo<NQ>;
-    __shared__ Lds<NQ, WAVES> L;
-    load_lds(L, sp);
-    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int gi = lane / Gm::G, gl = lane % Gm::G, gbase = gi * Gm::G;
     const bool leader = gl == 0;
     uint32_t* limbs = L.limbs[wave * Gm::WPW + gi];
     uint64_t c_steps = 0, c_dps = 0, c_ins = 0, c_ab = 0, c_rh = 0, c_same = 0, c_red = 0, c_claw = 0, c_full = 0,
              c_spin = 0, c_active = 0;
-    const int64_t stride = (int64_t)gridDim.x * WAVES * Gm::WPW;
-    for (int64_t base = ((int64_t)blockIdx.x * WAVES + wave) * Gm::WPW; base < wd.walks; base += stride) {
+    const int64_t stride = nblocks * WAVES * Gm::WPW;
+    for (int64_t base = (block * WAVES + wave) * Gm::WPW; base < wd.walks; base += stride) {
         const int64_t w = base + gi;
         if (w >= wd.walks) continue;
         WalkState st = wd.states[w];
@@ -777,6 +776,31 @@ __global__ __launch_bounds__(WAVES * 64) void k_walk(SpaceDev sp, WalkDev wd, in
     }
 }
 
+template <int NQ, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_walk(SpaceDev sp, WalkDev wd, int iters) {
+    __shared__ Lds<NQ, WAVES> L;
+    load_lds(L, sp);
+    __syncthreads();
+    walk_block<NQ, WAVES>(sp, wd, iters, L, blockIdx.x, gridDim.x);
+}
+
+// Many targets in one launch: block b serves target blk_target[b] (< 0: idle) as its
+// (b - tgt_first[t])-th of tgt_blocks[t] blocks; every target brings its own S_c, keys, salts,
+// walk states, table and counters.
+template <int NQ, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_walk_batch(const SpaceDev* sps, const WalkDev* wds,
+                                                            const int32_t* blk_target, const int32_t* tgt_first,
+                                                            const int32_t* tgt_blocks, int iters) {
+    __shared__ Lds<NQ, WAVES> L;
+    const int t = blk_target[blockIdx.x];
+    if (t < 0) return;
+    const SpaceDev sp = sps[t];
+    const WalkDev wd = wds[t];
+    load_lds(L, sp);
+    __syncthreads();
+    walk_block<NQ, WAVES>(sp, wd, iters, L, (int64_t)blockIdx.x - tgt_first[t], tgt_blocks[t]);
+}
+
 __global__ void k_walk_init(SpaceDev sp, WalkDev wd) {
     for (int64_t w = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; w < wd.walks;
          w += (int64_t)blockDim.x * gridDim.x) {
@@ -911,6 +935,27 @@ hipError_t launch_walk(int n, const SpaceDev& sp, const WalkDev& wd, int iters, 
         return hipGetLastError();
     };
     return dispatch_n(n, f);
+}
+
+hipError_t launch_walk_batch(int n, const SpaceDev* sps, const WalkDev* wds, const int32_t* blk_target,
+                             const int32_t* tgt_first, const int32_t* tgt_blocks, int blocks, int iters, hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    auto f = [&]<int NQ>() -> hipError_t {
+        constexpr int W = WalkWaves<NQ>::value;
+        hipLaunchKernelGGL((k_walk_batch<NQ, W>), dim3((unsigned)blocks), dim3(W * 64), 0, s, sps, wds, blk_target,
+                           tgt_first, tgt_blocks, iters);
+        return hipGetLastError();
+    };
+    return dispatch_n(n, f);
+}
+
+int walks_per_block(int n) {
+    switch (n) {
+        case 1: return WalkWaves<1>::value * Geo<1>::WPW;
+        case 2: return WalkWaves<2>::value * Geo<2>::WPW;
+        case 3: return WalkWaves<3>::value * Geo<3>::WPW;
+        default: return WalkWaves<4>::value * Geo<4>::WPW;
+    }
 }
 
 hipError_t launch_walk_init(const SpaceDev& sp, const WalkDev& wd, hipStream_t s) {

@@ -95,6 +95,10 @@ _SIGS = {
     "tcw_walk_end": (C.c_int, [_P]),
     "tcw_default_params": (None, [C.POINTER(WalkParams), C.c_int]),
     "tcw_search": (C.c_int, [_P, _P, C.POINTER(WalkParams), C.POINTER(Result)]),
+    "tcw_search_batch": (C.c_int, [_P, C.POINTER(_P), C.c_int, C.POINTER(WalkParams), C.POINTER(Result),
+                                   C.POINTER(C.c_double)]),
+    "tcw_autotune": (C.c_int, [_P, _P, C.c_int, C.c_int, C.c_int, C.c_uint64, C.POINTER(C.c_int64),
+                               C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
 }
 
 EXPORTED = sorted(_SIGS)
@@ -229,6 +233,28 @@ class Context:
         res = Result()
         self._check(self.lib.tcw_search(self.h, target.h, C.byref(params), C.byref(res)))
         return res
+
+
+def _search_batch(self, targets, params):
+    """Search many targets together; returns (results, aggregate walk steps/s)."""
+    n = len(targets)
+    th = (_P * n)(*[t.h for t in targets])
+    ps = (WalkParams * n)(*params)
+    rs = (Result * n)()
+    agg = C.c_double(0)
+    self._check(self.lib.tcw_search_batch(self.h, th, n, ps, rs, C.byref(agg)))
+    return list(rs), agg.value
+
+
+def _autotune(self, target, k, chunk, delta, seed):
+    w, it, lg, rate = C.c_int64(0), C.c_int(0), C.c_int(0), C.c_double(0)
+    self._check(self.lib.tcw_autotune(self.h, target.h, k, chunk, delta, seed, C.byref(w), C.byref(it),
+                                      C.byref(lg), C.byref(rate)))
+    return {"walks": w.value, "iters": it.value, "log2_table": lg.value, "steps_per_s": rate.value}
+
+
+Context.search_batch = _search_batch
+Context.autotune = _autotune
 
 
 def decomposition_of(res: Result) -> Optional[Decomposition]:

@@ -319,3 +319,52 @@ def test_search_n3_cfg2(ctx):
     d = osearch.Decomposition(t=dec.t, paulis_desc=dec.paulis_desc, perm=dec.perm, sign=dec.sign)
     assert osearch.reconstruct(3, d).equals(u)
     say("n3 k6 search", res.seconds, "s", res.stats.steps, "steps", res.versions, "versions")
+
+
+def test_autotune_choices(ctx):
+    say("autotune")
+    for n, k, delta in [(2, 4, 4), (3, 6, 8)]:
+        tw, u = oracle_target(n, k, 5)
+        tgt = ctx.target_from_words(n, tw.paulis, tw.clifford)
+        cfg = ctx.autotune(tgt, k, 0, delta, 7)
+        npts = 2 * (4 ** n - 1) ** (k // 2)
+        assert 64 <= cfg["walks"] <= max(64, npts // 4)
+        assert 1 <= cfg["iters"] <= 64 and 10 <= cfg["log2_table"] <= 26 and cfg["steps_per_s"] > 0
+
+
+def test_search_batch_mixed(ctx):
+    """Mixed n and k in one batched search: every decomposition found reconstructs its target
+    exactly, with T-count at most the generating k; n <= 2 minima match brute force."""
+    from paper_1606_07413_amd import tcw
+    say("batch")
+    _, seen1, _ = bfs.cosets_by_tcount(1, 7)
+    _, seen2, _ = bfs.cosets_by_tcount(2, 3)
+    specs = [(1, 5, 1), (1, 7, 2), (2, 3, 3), (2, 4, 4), (2, 5, 5), (3, 3, 6), (3, 4, 7), (3, 6, 8), (2, 4, 9),
+             (1, 6, 10)]
+    targets, params, oracle_u = [], [], []
+    for n, k, seed in specs:
+        tw, u = oracle_target(n, k, 200 + seed)
+        targets.append(ctx.target_from_words(n, tw.paulis, tw.clifford))
+        oracle_u.append(u)
+        p = ctx.default_params(n)
+        p.k_max = k
+        p.seed = 300 + seed
+        p.walks = 0          # autotuner
+        p.log2_table = 0
+        p.iters_per_launch = 0
+        p.budget_beta = 16
+        p.max_seconds = 60
+        params.append(p)
+    results, agg = ctx.search_batch(targets, params)
+    assert agg > 0
+    for (n, k, seed), u, r in zip(specs, oracle_u, results):
+        dec = tcw.decomposition_of(r)
+        assert dec is not None, (n, k, seed)
+        assert dec.t <= k
+        d = osearch.Decomposition(t=dec.t, paulis_desc=dec.paulis_desc, perm=dec.perm, sign=dec.sign)
+        assert osearch.reconstruct(n, d).equals(u)
+        if n == 1:
+            assert dec.t == bfs.min_tcount(u, seen1)
+        if n == 2:
+            tmin = bfs.min_tcount(u, seen2)
+            assert dec.t == (tmin if tmin is not None else dec.t)

@@ -69,4 +69,4 @@ def test_default_params_per_n():
     for n, walks, lg in [(2, 64, 12), (3, 1 << 16, 20), (4, 1 << 20, 26)]:
         p = tcw.WalkParams()
         lib.tcw_default_params(ctypes.byref(p), n)
-        assert p.walks == walks and p.log2_table == lg and p.trail_cap_factor == 20 and p.budget_beta == 4
+        assert p.walks == walks and p.log2_table == lg and p.trail_cap_factor == 20 and p.budget_beta == 16
