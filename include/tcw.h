@@ -223,6 +223,43 @@ int tcw_search_batch(tcw_ctx* ctx, const tcw_target* const* targets, int count, 
 int tcw_autotune(tcw_ctx* ctx, const tcw_target* t, int k, int chunk, int delta, uint64_t seed, int64_t* walks,
                  int* iters, int* log2_table, double* steps_per_s);
 
+/* ---- learned depth order (the network that orders which depths k are searched first) ---------
+ * Input: the target's canonical channel rep (rows sign-normalised by their first nonzero entry,
+ * sorted lexicographically as integer sequences, minimal exponent e), entries
+ * (a + b sqrt2) 2^(-e/2) as FP32 (n <= 3, so 4^n x 4^n features).  Network: depth hidden layers of
+ * width `hidden` with GELU (erf form), a linear layer to `classes` T-counts 0..classes-1, softmax,
+ * cross-entropy; BF16 weights and activations on MFMA with FP32 accumulation, FP32 master weights,
+ * Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * tcw_features: features of one target into out_dev (4^n * 4^n floats, device).
+ * tcw_label_batch: `count` targets given as words (words[offsets[i] .. offsets[i+1]) = P_1..P_k then
+ * C_1..C_m, k = kof[i]) are built exactly on the GPU; features_dev[i] gets their features and
+ * labels_dev[i] their minimal T-count when it is at most 2 h_max (meet in the middle: every coset
+ * of T-count <= h_max from the identity side against every product of <= h_max rotations on the
+ * target side, by matrix hash), else -1.
+ * tcw_mlp_create: parameters are W_0, b_0, W_1, b_1, ... (W_l row-major in x out); init (host,
+ * optional) gives them, else W_l uniform in [-1/sqrt(in), 1/sqrt(in)] from SplitMix64(seed) of the
+ * running weight index (u = (r >> 40) / 2^24) and b_l = 0.
+ * tcw_mlp_forward: probs_dev[batch x classes] from x_dev[batch x in].  tcw_mlp_gradients: gradients
+ * of the mean cross-entropy (host array of param_count floats) and the loss, no update.
+ * tcw_mlp_train_step: one Adam step on a batch.  tcw_mlp_depth_order: order_out[0..k_max] = depths
+ * 0..k_max by descending predicted probability (ties: smaller first); probs_out (host, may be NULL).
+ * All blocking except where noted; device pointers as elsewhere. */
+typedef struct tcw_mlp tcw_mlp;
+int tcw_features(tcw_ctx* ctx, const tcw_target* t, float* out_dev);
+int tcw_label_batch(tcw_ctx* ctx, int n, int count, const uint16_t* words, const int32_t* offsets, const int32_t* kof,
+                    int h_max, uint64_t seed, float* features_dev, int32_t* labels_dev);
+int tcw_mlp_create(tcw_ctx* ctx, int inp, int hidden, int depth, int classes, const float* init, uint64_t seed,
+                   tcw_mlp** out);
+int tcw_mlp_free(tcw_mlp* m);
+int tcw_mlp_param_count(const tcw_mlp* m, int64_t* count);
+int tcw_mlp_get_params(tcw_mlp* m, float* host_out);
+int tcw_mlp_set_params(tcw_mlp* m, const float* host_in);
+int tcw_mlp_forward(tcw_mlp* m, const float* x_dev, int batch, float* probs_dev);
+int tcw_mlp_gradients(tcw_mlp* m, const float* x_dev, const int32_t* labels_dev, int batch, float* grads_host,
+                      float* loss);
+int tcw_mlp_train_step(tcw_mlp* m, const float* x_dev, const int32_t* labels_dev, int batch, float lr, float* loss);
+int tcw_mlp_depth_order(tcw_mlp* m, const tcw_target* t, int k_max, int32_t* order_out, float* probs_out);
+
 #ifdef __cplusplus
 }
 #endif

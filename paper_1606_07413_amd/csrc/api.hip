@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <memory>
 #include <new>
@@ -1393,5 +1394,365 @@ extern "C" int tcw_search_batch(tcw_ctx* c, const tcw_target* const* targets, in
     for (auto& b : bt)
         if (b.res->seconds == 0) b.res->seconds = now_s() - t0;
     if (aggregate_steps_per_s) *aggregate_steps_per_s = walk_seconds > 0 ? (double)total_steps / walk_seconds : 0.0;
+    return TCW_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Depth-order network: canonical features, exact labels by meet in the middle, BF16 MFMA training.
+struct tcw_mlp {
+    tcw_ctx* ctx = nullptr;
+    int inp = 0, hidden = 0, depth = 0, classes = 0, L = 0;
+    std::vector<int> sz;
+    std::vector<int64_t> w_off, b_off;
+    int64_t count = 0;
+    float *P = nullptr, *G = nullptr, *M = nullptr, *V = nullptr;
+    std::vector<void*> Wb;
+    int step = 0;
+    int cap_b = 0;
+    void* Xb = nullptr;
+    std::vector<float*> Z, Gf;
+    std::vector<void*> Hb, Gb;
+    float *logits = nullptr, *probs = nullptr, *loss = nullptr, *xdev = nullptr;
+
+    void free_batch() {
+        for (void* q : {Xb, (void*)logits, (void*)probs})
+            if (q) (void)hipFree(q);
+        for (auto* q : Z)
+            if (q) (void)hipFree(q);
+        for (auto* q : Gf)
+            if (q) (void)hipFree(q);
+        for (auto* q : Hb)
+            if (q) (void)hipFree(q);
+        for (auto* q : Gb)
+            if (q) (void)hipFree(q);
+        Xb = nullptr;
+        logits = probs = nullptr;
+        Z.clear();
+        Gf.clear();
+        Hb.clear();
+        Gb.clear();
+        cap_b = 0;
+    }
+    ~tcw_mlp() {
+        free_batch();
+        for (void* q : {(void*)P, (void*)G, (void*)M, (void*)V, (void*)loss, (void*)xdev})
+            if (q) (void)hipFree(q);
+        for (auto* q : Wb)
+            if (q) (void)hipFree(q);
+    }
+};
+
+namespace {
+
+int mlp_ensure_batch(tcw_mlp* m, int b) {
+    tcw_ctx* c = m->ctx;
+    if (b <= m->cap_b) return TCW_OK;
+    m->free_batch();
+    HIP_TRY(c, hipMalloc(&m->Xb, (size_t)b * m->inp * 2));
+    m->Z.assign(m->depth, nullptr);
+    m->Hb.assign(m->depth, nullptr);
+    m->Gf.assign(m->L, nullptr);
+    m->Gb.assign(m->L, nullptr);
+    for (int l = 0; l < m->depth; ++l) {
+        HIP_TRY(c, hipMalloc(&m->Z[l], (size_t)b * m->hidden * 4));
+        HIP_TRY(c, hipMalloc(&m->Hb[l], (size_t)b * m->hidden * 2));
+    }
+    for (int l = 0; l < m->L; ++l) {
+        HIP_TRY(c, hipMalloc(&m->Gf[l], (size_t)b * m->sz[l + 1] * 4));
+        HIP_TRY(c, hipMalloc(&m->Gb[l], (size_t)b * m->sz[l + 1] * 2));
+    }
+    HIP_TRY(c, hipMalloc(&m->logits, (size_t)b * m->classes * 4));
+    HIP_TRY(c, hipMalloc(&m->probs, (size_t)b * m->classes * 4));
+    m->cap_b = b;
+    return TCW_OK;
+}
+
+int mlp_sync_bf16(tcw_mlp* m) {
+    for (int l = 0; l < m->L; ++l)
+        HIP_TRY(m->ctx, tcw::mlp_to_bf16(m->P + m->w_off[l], m->Wb[l], (int64_t)m->sz[l] * m->sz[l + 1], m->ctx->stream));
+    return TCW_OK;
+}
+
+// forward over a batch; with labels also the loss sum and the output-layer gradient
+int mlp_forward(tcw_mlp* m, const float* x, int b, const int32_t* labels) {
+    tcw_ctx* c = m->ctx;
+    int rc = mlp_ensure_batch(m, b);
+    if (rc) return rc;
+    HIP_TRY(c, tcw::mlp_to_bf16(x, m->Xb, (int64_t)b * m->inp, c->stream));
+    for (int l = 0; l < m->L; ++l) {
+        const void* A = l == 0 ? m->Xb : m->Hb[l - 1];
+        const int K = m->sz[l], N = m->sz[l + 1];
+        if (l < m->L - 1) {
+            HIP_TRY(c, tcw::mlp_gemm(1, A, m->Wb[l], b, N, K, K, N, m->Z[l], N, m->P + m->b_off[l], nullptr, m->Hb[l],
+                                     c->stream));
+        } else {
+            HIP_TRY(c, tcw::mlp_gemm(2, A, m->Wb[l], b, N, K, K, N, m->logits, N, m->P + m->b_off[l], nullptr, nullptr,
+                                     c->stream));
+        }
+    }
+    if (labels) HIP_TRY(c, hipMemsetAsync(m->loss, 0, 4, c->stream));
+    HIP_TRY(c, tcw::mlp_softmax_ce(m->logits, labels, b, m->classes, m->probs, labels ? m->Gf[m->L - 1] : nullptr,
+                                   labels ? m->Gb[m->L - 1] : nullptr, labels ? m->loss : nullptr, c->stream));
+    return TCW_OK;
+}
+
+int mlp_backward(tcw_mlp* m, int b) {
+    tcw_ctx* c = m->ctx;
+    for (int l = m->L - 1; l >= 0; --l) {
+        const void* Hin = l == 0 ? m->Xb : m->Hb[l - 1];
+        const int in = m->sz[l], out = m->sz[l + 1];
+        // dW_l = H_in^T G_l
+        HIP_TRY(c, tcw::mlp_gemm(3, Hin, m->Gb[l], in, out, b, in, out, m->G + m->w_off[l], out, nullptr, nullptr,
+                                 nullptr, c->stream));
+        HIP_TRY(c, tcw::mlp_colsum(m->Gf[l], b, out, m->G + m->b_off[l], c->stream));
+        if (l > 0) {
+            // G_{l-1} = (G_l W_l^T) * gelu'(Z_{l-1})
+            HIP_TRY(c, tcw::mlp_gemm(4, m->Gb[l], m->Wb[l], b, in, out, out, out, m->Gf[l - 1], in, nullptr, m->Z[l - 1],
+                                     m->Gb[l - 1], c->stream));
+        }
+    }
+    return TCW_OK;
+}
+
+}  // namespace
+
+extern "C" int tcw_mlp_create(tcw_ctx* c, int inp, int hidden, int depth, int classes, const float* init, uint64_t seed,
+                              tcw_mlp** out) {
+    if (!c || !out || inp < 1 || hidden < 1 || depth < 0 || depth > 16 || classes < 2) return TCW_EINVAL;
+    *out = nullptr;
+    tcw_mlp* m = new (std::nothrow) tcw_mlp();
+    if (!m) return TCW_ENOMEM;
+    m->ctx = c;
+    m->inp = inp;
+    m->hidden = hidden;
+    m->depth = depth;
+    m->classes = classes;
+    m->L = depth + 1;
+    m->sz.push_back(inp);
+    for (int l = 0; l < depth; ++l) m->sz.push_back(hidden);
+    m->sz.push_back(classes);
+    int64_t off = 0;
+    for (int l = 0; l < m->L; ++l) {
+        m->w_off.push_back(off);
+        off += (int64_t)m->sz[l] * m->sz[l + 1];
+        m->b_off.push_back(off);
+        off += m->sz[l + 1];
+    }
+    m->count = off;
+    auto bail = [&](hipError_t e) {
+        delete m;
+        return hip_fail(c, e, "network allocation");
+    };
+    hipError_t e = hipMalloc(&m->P, off * 4);
+    if (e == hipSuccess) e = hipMalloc(&m->G, off * 4);
+    if (e == hipSuccess) e = hipMalloc(&m->M, off * 4);
+    if (e == hipSuccess) e = hipMalloc(&m->V, off * 4);
+    if (e == hipSuccess) e = hipMalloc(&m->loss, 4);
+    if (e != hipSuccess) return bail(e);
+    m->Wb.assign(m->L, nullptr);
+    for (int l = 0; l < m->L && e == hipSuccess; ++l) e = hipMalloc(&m->Wb[l], (size_t)m->sz[l] * m->sz[l + 1] * 2);
+    if (e == hipSuccess) e = hipMemsetAsync(m->M, 0, off * 4, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(m->V, 0, off * 4, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(m->P, 0, off * 4, c->stream);
+    if (e != hipSuccess) return bail(e);
+    if (init) {
+        e = hipMemcpyAsync(m->P, init, off * 4, hipMemcpyHostToDevice, c->stream);
+    } else {
+        int64_t idx = 0;
+        for (int l = 0; l < m->L && e == hipSuccess; ++l) {
+            const int64_t cnt = (int64_t)m->sz[l] * m->sz[l + 1];
+            e = tcw::mlp_init(m->P + m->w_off[l], cnt, idx, m->sz[l], seed, c->stream);
+            idx += cnt;
+        }
+    }
+    if (e != hipSuccess) return bail(e);
+    int rc = mlp_sync_bf16(m);
+    if (!rc) {
+        hipError_t se = hipStreamSynchronize(c->stream);
+        if (se != hipSuccess) rc = hip_fail(c, se, "network init");
+    }
+    if (rc) {
+        delete m;
+        return rc;
+    }
+    *out = m;
+    return TCW_OK;
+}
+
+extern "C" int tcw_mlp_free(tcw_mlp* m) {
+    if (!m) return TCW_EINVAL;
+    (void)hipStreamSynchronize(m->ctx->stream);
+    delete m;
+    return TCW_OK;
+}
+
+extern "C" int tcw_mlp_param_count(const tcw_mlp* m, int64_t* count) {
+    if (!m || !count) return TCW_EINVAL;
+    *count = m->count;
+    return TCW_OK;
+}
+
+extern "C" int tcw_mlp_get_params(tcw_mlp* m, float* host) {
+    if (!m || !host) return TCW_EINVAL;
+    HIP_TRY(m->ctx, hipMemcpyAsync(host, m->P, m->count * 4, hipMemcpyDeviceToHost, m->ctx->stream));
+    HIP_TRY(m->ctx, hipStreamSynchronize(m->ctx->stream));
+    return TCW_OK;
+}
+
+extern "C" int tcw_mlp_set_params(tcw_mlp* m, const float* host) {
+    if (!m || !host) return TCW_EINVAL;
+    HIP_TRY(m->ctx, hipMemcpyAsync(m->P, host, m->count * 4, hipMemcpyHostToDevice, m->ctx->stream));
+    int rc = mlp_sync_bf16(m);
+    if (rc) return rc;
+    HIP_TRY(m->ctx, hipStreamSynchronize(m->ctx->stream));
+    return TCW_OK;
+}
+
+extern "C" int tcw_mlp_forward(tcw_mlp* m, const float* x, int batch, float* probs) {
+    if (!m || !x || !probs || batch < 1) return TCW_EINVAL;
+    int rc = mlp_forward(m, x, batch, nullptr);
+    if (rc) return rc;
+    HIP_TRY(m->ctx, hipMemcpyAsync(probs, m->probs, (size_t)batch * m->classes * 4, hipMemcpyDeviceToDevice,
+                                   m->ctx->stream));
+    HIP_TRY(m->ctx, hipStreamSynchronize(m->ctx->stream));
+    return TCW_OK;
+}
+
+extern "C" int tcw_mlp_gradients(tcw_mlp* m, const float* x, const int32_t* labels, int batch, float* grads_host,
+                                 float* loss) {
+    if (!m || !x || !labels || batch < 1) return TCW_EINVAL;
+    int rc = mlp_forward(m, x, batch, labels);
+    if (!rc) rc = mlp_backward(m, batch);
+    if (rc) return rc;
+    float ls = 0;
+    HIP_TRY(m->ctx, hipMemcpyAsync(&ls, m->loss, 4, hipMemcpyDeviceToHost, m->ctx->stream));
+    if (grads_host) HIP_TRY(m->ctx, hipMemcpyAsync(grads_host, m->G, m->count * 4, hipMemcpyDeviceToHost, m->ctx->stream));
+    HIP_TRY(m->ctx, hipStreamSynchronize(m->ctx->stream));
+    if (loss) *loss = ls / (float)batch;
+    return TCW_OK;
+}
+
+extern "C" int tcw_mlp_train_step(tcw_mlp* m, const float* x, const int32_t* labels, int batch, float lr, float* loss) {
+    if (!m || !x || !labels || batch < 1 || !(lr > 0)) return TCW_EINVAL;
+    int rc = mlp_forward(m, x, batch, labels);
+    if (!rc) rc = mlp_backward(m, batch);
+    if (rc) return rc;
+    m->step++;
+    HIP_TRY(m->ctx, tcw::mlp_adam(m->P, m->G, m->M, m->V, m->count, lr, 0.9f, 0.999f, 1e-8f, m->step, m->ctx->stream));
+    rc = mlp_sync_bf16(m);
+    if (rc) return rc;
+    if (loss) {
+        float ls = 0;
+        HIP_TRY(m->ctx, hipMemcpyAsync(&ls, m->loss, 4, hipMemcpyDeviceToHost, m->ctx->stream));
+        HIP_TRY(m->ctx, hipStreamSynchronize(m->ctx->stream));
+        *loss = ls / (float)batch;
+    }
+    return TCW_OK;
+}
+
+extern "C" int tcw_features(tcw_ctx* c, const tcw_target* t, float* out_dev) {
+    if (!c || !t || !out_dev) return TCW_EINVAL;
+    if (t->n > 3) return fail(c, TCW_EINVAL, "features are defined for n <= 3");
+    HIP_TRY(c, tcw::exact_features(t->U, out_dev, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TCW_OK;
+}
+
+extern "C" int tcw_mlp_depth_order(tcw_mlp* m, const tcw_target* t, int k_max, int32_t* order_out, float* probs_out) {
+    if (!m || !t || !order_out || k_max < 0) return TCW_EINVAL;
+    tcw_ctx* c = m->ctx;
+    const int R = 1 << (2 * t->n);
+    if (R * R != m->inp) return fail(c, TCW_EINVAL, "network input size does not match the target");
+    if (!m->xdev) HIP_TRY(c, hipMalloc(&m->xdev, (size_t)m->inp * 4));
+    int rc = tcw_features(c, t, m->xdev);
+    if (!rc) rc = mlp_forward(m, m->xdev, 1, nullptr);
+    if (rc) return rc;
+    std::vector<float> p(m->classes);
+    HIP_TRY(c, hipMemcpyAsync(p.data(), m->probs, m->classes * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (probs_out)
+        for (int i = 0; i < m->classes; ++i) probs_out[i] = p[i];
+    // depths 0..k_max by descending probability (ties: smaller depth first)
+    std::vector<int> ks;
+    for (int k = 0; k <= k_max; ++k) ks.push_back(k);
+    auto prob = [&](int k) { return k < m->classes ? p[k] : -1.0f; };
+    std::stable_sort(ks.begin(), ks.end(), [&](int a, int b) { return prob(a) > prob(b); });
+    for (int i = 0; i <= k_max; ++i) order_out[i] = ks[i];
+    return TCW_OK;
+}
+
+extern "C" int tcw_label_batch(tcw_ctx* c, int n, int count, const uint16_t* words, const int32_t* offsets,
+                               const int32_t* kof, int h_max, uint64_t seed, float* features_dev, int32_t* labels_dev) {
+    if (!c || !words || !offsets || !kof || !features_dev || !labels_dev || count < 1) return TCW_EINVAL;
+    if (n < 1 || n > 3) return fail(c, TCW_EINVAL, "labels are built for n <= 3");
+    if (h_max < 0 || n_half_of(n, h_max) == 0) return fail(c, TCW_EINVAL, "h_max too large");
+    const int R = 1 << (2 * n);
+    const int64_t nw = offsets[count];
+    uint16_t* dwords = nullptr;
+    int32_t *doff = nullptr, *dk = nullptr, *rot = nullptr;
+    uint32_t *phi = nullptr, *zero_phi = nullptr;
+    uint64_t *keys = nullptr, *table = nullptr;
+    void* scratch = nullptr;
+    const int chunk = 1024, blocks = 256;
+    int rc = TCW_OK;
+    auto cleanup = [&]() {
+        for (void* q : {(void*)dwords, (void*)doff, (void*)dk, (void*)rot, (void*)phi, (void*)zero_phi, (void*)keys,
+                        (void*)table, scratch})
+            if (q) (void)hipFree(q);
+    };
+#define LB_TRY(expr)                         \
+    do {                                     \
+        hipError_t _e = (expr);              \
+        if (_e != hipSuccess) {              \
+            cleanup();                       \
+            return hip_fail(c, _e, #expr);   \
+        }                                    \
+    } while (0)
+    LB_TRY(hipMalloc(&dwords, nw * 2 + 2));
+    LB_TRY(hipMalloc(&doff, (count + 1) * 4));
+    LB_TRY(hipMalloc(&dk, count * 4));
+    LB_TRY(hipMemcpyAsync(dwords, words, nw * 2, hipMemcpyHostToDevice, c->stream));
+    LB_TRY(hipMemcpyAsync(doff, offsets, (count + 1) * 4, hipMemcpyHostToDevice, c->stream));
+    LB_TRY(hipMemcpyAsync(dk, kof, count * 4, hipMemcpyHostToDevice, c->stream));
+    LB_TRY(hipMalloc(&rot, chunk * 4));
+    LB_TRY(hipMalloc(&phi, (size_t)chunk * R * R / 2 * 4));
+    LB_TRY(hipMalloc(&zero_phi, (size_t)R * R / 2 * 4));
+    LB_TRY(hipMemsetAsync(zero_phi, 0, (size_t)R * R / 2 * 4, c->stream));
+    LB_TRY(hipMalloc(&keys, 2 * (size_t)R * 8));
+    LB_TRY(tcw::keys_fill(n, seed, keys, c->stream));
+    LB_TRY(hipMalloc(&scratch, tcw::build_batch_scratch_bytes(n, blocks)));
+    // level table of every coset reached by <= h_max rotations from the identity
+    uint64_t entries = 0;
+    for (int h = 0; h <= h_max; ++h) entries += n_half_of(n, h);
+    int lg = 10;
+    while ((1ull << lg) < 4 * entries && lg < 30) ++lg;
+    LB_TRY(hipMalloc(&table, ((size_t)1 << lg) * 16));
+    LB_TRY(tcw::launch_table_clear(table, lg, c->stream));
+    tcw::SpaceDev sp{};
+    sp.delta = 0;
+    sp.salt_h = tcw::sm64(tcw::sm64(seed, 2), 0x4C4142454Cull);
+    sp.keys = keys;
+    sp.phi = zero_phi;
+    for (int h = 0; h <= h_max; ++h) {
+        sp.h = h;
+        sp.n_half = (uint32_t)n_half_of(n, h);
+        LB_TRY(tcw::mitm_levels(n, sp, h, table, lg, c->stream));
+    }
+    if ((rc = clear_flag(c))) {
+        cleanup();
+        return rc;
+    }
+    for (int first = 0; first < count; first += chunk) {
+        const int cnt = std::min(chunk, count - first);
+        LB_TRY(tcw::build_batch(n, dwords, doff + first, dk + first, cnt, scratch, blocks, phi, rot,
+                                features_dev + (size_t)first * R * R, c->flag, c->stream));
+        LB_TRY(tcw::mitm_probe(n, sp, phi, rot, cnt, h_max, table, lg, labels_dev + first, c->stream));
+    }
+    int flag = 0;
+    rc = read_flag(c, &flag);
+    cleanup();
+#undef LB_TRY
+    if (rc) return rc;
+    if (flag) return fail(c, TCW_EOVERFLOW, "target outside the int8 / int32 range or word too long");
     return TCW_OK;
 }

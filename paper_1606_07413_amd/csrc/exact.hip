@@ -343,6 +343,129 @@ __global__ __launch_bounds__(1024) void k_claw(const T* sa, const T* sb, const i
     }
 }
 
+// Canonical FP32 features of the exact matrix (a, b, e) held by the block (n <= 3): rows
+// sign-normalised (first nonzero entry positive, decided exactly), sorted lexicographically as the
+// integer sequences (a_0, b_0, a_1, b_1, ...), each entry (a + b sqrt2) 2^(-e/2) formed in double as
+// t = a + b * SQRT2, t *= SQRT1_2 for odd e, t *= 2^(-floor(e/2)), rounded to float.
+template <int NQ, typename T>
+__device__ void block_features(const T* a, const T* b, int e, int32_t* rows /* R x 2R shared */,
+                               int32_t* idx /* R shared */, float* out) {
+    constexpr int R = EGeo<NQ>::R;
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        int sg = 0;
+        for (int q = 0; q < R && sg == 0; ++q) {
+            const int64_t va = a[r * R + q], vb = b[r * R + q];
+            if (va == 0 && vb == 0) continue;
+            if (va >= 0 && vb >= 0) sg = 1;
+            else if (va <= 0 && vb <= 0) sg = -1;
+            else if (va > 0) sg = (va * va > 2 * vb * vb) ? 1 : -1;
+            else sg = (2 * vb * vb > va * va) ? 1 : -1;
+        }
+        if (sg == 0) sg = 1;
+        for (int q = 0; q < R; ++q) {
+            rows[r * 2 * R + 2 * q] = (int32_t)(sg * a[r * R + q]);
+            rows[r * 2 * R + 2 * q + 1] = (int32_t)(sg * b[r * R + q]);
+        }
+        idx[r] = r;
+    }
+    __syncthreads();
+    // bitonic sort of the row indices by lexicographic row order
+    for (int k = 2; k <= R; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < R; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int ri = idx[i], rl = idx[l];
+                    int cmp = 0;
+                    for (int c = 0; c < 2 * R && cmp == 0; ++c) {
+                        const int32_t x = rows[ri * 2 * R + c], y = rows[rl * 2 * R + c];
+                        cmp = (x < y) ? -1 : (x > y ? 1 : 0);
+                    }
+                    const bool asc = (i & k) == 0;
+                    if ((asc && cmp > 0) || (!asc && cmp < 0)) {
+                        idx[i] = rl;
+                        idx[l] = ri;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const double sqrt2 = 1.4142135623730951, sqrt1_2 = 0.7071067811865476;
+    const double scale = ldexp(1.0, -(e / 2));
+    for (int t = threadIdx.x; t < R * R; t += blockDim.x) {
+        const int i = t / R, q = t % R;
+        const int r = idx[i];
+        double v = __dadd_rn((double)rows[r * 2 * R + 2 * q], __dmul_rn((double)rows[r * 2 * R + 2 * q + 1], sqrt2));
+        if (e & 1) v = __dmul_rn(v, sqrt1_2);
+        out[t] = (float)__dmul_rn(v, scale);
+    }
+    __syncthreads();
+}
+
+template <int NQ, typename T>
+__global__ __launch_bounds__(256) void k_features(const T* a, const T* b, const int32_t* e, float* out) {
+    constexpr int R = EGeo<NQ>::R;
+    __shared__ int32_t rows[R * 2 * R];
+    __shared__ int32_t idx[R];
+    block_features<NQ, T>(a, b, *e, rows, idx, out);
+}
+
+// Network data: targets built exactly from their words (Clifford word then rotations), packed as
+// int8 for the walk step (n <= 3 layout) and turned into canonical features.  One block per target.
+template <int NQ, typename T>
+__global__ __launch_bounds__(1024) void k_build_batch(const uint16_t* words, const int32_t* offsets,
+                                                      const int32_t* kof, int count, T* scratch, uint32_t* phi_out,
+                                                      int32_t* rot_e_out, float* feat_out, int* flag) {
+    constexpr int R = EGeo<NQ>::R;
+    constexpr int Q4 = R / 4;
+    __shared__ uint16_t seq[256];
+    __shared__ int32_t rows[R * 2 * R];
+    __shared__ int32_t idx[R];
+    T* a = scratch + (size_t)blockIdx.x * 4 * R * R;
+    T* b = a + R * R;
+    T* ta = b + R * R;
+    T* tb = ta + R * R;
+    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+        const int w0 = offsets[t], w1 = offsets[t + 1], k = kof[t];
+        const int m = w1 - w0 - k;
+        int nseq = 2 * m + k;
+        if (nseq > 256) {
+            if (threadIdx.x == 0) atomicOr(flag, 8);
+            nseq = 0;
+        }
+        if (threadIdx.x == 0 && nseq > 0) {
+            int s = 0;
+            for (int j = 0; j < m; ++j) {
+                seq[s++] = words[w0 + k + j];
+                seq[s++] = words[w0 + k + j];
+            }
+            for (int j = k - 1; j >= 0; --j) seq[s++] = words[w0 + j];
+        }
+        for (int i = threadIdx.x; i < R * R; i += blockDim.x) {
+            a[i] = (i / R == i % R) ? 1 : 0;
+            b[i] = 0;
+        }
+        __syncthreads();
+        int e = 0;
+        block_apply<NQ, T>(a, b, ta, tb, e, seq, nullptr, nseq, flag);
+        for (int i = threadIdx.x; i < Q4 * R; i += blockDim.x) {
+            const int q4 = i / R, r = i % R;
+            uint32_t wa = 0, wb = 0;
+            for (int c = 0; c < 4; ++c) {
+                const T va = a[r * R + 4 * q4 + c], vb = b[r * R + 4 * q4 + c];
+                if (va > 127 || va < -127 || vb > 127 || vb < -127) atomicOr(flag, 2);
+                wa |= ((uint32_t)(uint8_t)(int8_t)va) << (8 * c);
+                wb |= ((uint32_t)(uint8_t)(int8_t)vb) << (8 * c);
+            }
+            phi_out[(size_t)t * 2 * Q4 * R + i] = wa;
+            phi_out[(size_t)t * 2 * Q4 * R + Q4 * R + i] = wb;
+        }
+        if (threadIdx.x == 0) rot_e_out[t] = (int32_t)((30ll * e) % 61);
+        block_features<NQ, T>(a, b, e, rows, idx, feat_out + (size_t)t * R * R);
+    }
+}
+
 template <typename F>
 hipError_t dispatch_exact(int n, F&& f) {
     switch (n) {
@@ -487,6 +610,42 @@ hipError_t exact_claw_check(const ExactDev& S, int k, const uint64_t* u0, const 
         return hipGetLastError();
     };
     return dispatch_exact(S.n, f);
+}
+
+}  // namespace tcw
+
+namespace tcw {
+
+hipError_t exact_features(const ExactDev& m, float* out, hipStream_t s) {
+    auto f = [&]<int NQ, typename T>() -> hipError_t {
+        if constexpr (NQ <= 3) {
+            hipLaunchKernelGGL((k_features<NQ, T>), dim3(1), dim3(256), 0, s, (const T*)m.a, (const T*)m.b, m.e, out);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    };
+    return dispatch_exact(m.n, f);
+}
+
+size_t build_batch_scratch_bytes(int n, int blocks) {
+    const size_t r = (size_t)1 << (2 * n);
+    return (size_t)blocks * 4 * r * r * (n <= 2 ? 8 : 4);
+}
+
+hipError_t build_batch(int n, const uint16_t* words, const int32_t* offsets, const int32_t* kof, int count,
+                       void* scratch, int blocks, uint32_t* phi_out, int32_t* rot_e_out, float* feat_out, int* flag,
+                       hipStream_t s) {
+    auto f = [&]<int NQ, typename T>() -> hipError_t {
+        if constexpr (NQ <= 3) {
+            hipLaunchKernelGGL((k_build_batch<NQ, T>), dim3(blocks), dim3(1024), 0, s, words, offsets, kof, count,
+                               (T*)scratch, phi_out, rot_e_out, feat_out, flag);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    };
+    return dispatch_exact(n, f);
 }
 
 }  // namespace tcw

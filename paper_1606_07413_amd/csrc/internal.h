@@ -91,6 +91,17 @@ hipError_t exact_claw_check(const ExactDev& S, int k, const uint64_t* u0, const 
                             void* scratch, size_t scratch_bytes, int32_t* ok, int32_t* perm, int8_t* sign,
                             hipStream_t s);
 size_t exact_claw_scratch_bytes(int n);
+// canonical FP32 features (n <= 3)
+hipError_t exact_features(const ExactDev& m, float* out_dev, hipStream_t s);
+// many targets from words: phi (n <= 3 int8 layout), rot_e, features; flag |= 2 / 4 / 8 on range errors
+size_t build_batch_scratch_bytes(int n, int blocks);
+hipError_t build_batch(int n, const uint16_t* words, const int32_t* offsets, const int32_t* kof, int count,
+                       void* scratch, int blocks, uint32_t* phi_out, int32_t* rot_e_out, float* feat_out, int* flag,
+                       hipStream_t s);
+// meet-in-the-middle level table and probes (walk.hip)
+hipError_t mitm_levels(int n, const SpaceDev& sp, int h, uint64_t* table, int log2_table, hipStream_t s);
+hipError_t mitm_probe(int n, const SpaceDev& sp, const uint32_t* phi_all, const int32_t* rot_e_all, int count,
+                      int h_max, const uint64_t* table, int log2_table, int32_t* best_out, hipStream_t s);
 
 // ---- launchers (walk.hip) ----
 hipError_t keys_fill(int n, uint64_t seed, uint64_t* keys_dev, hipStream_t s);
@@ -110,5 +121,18 @@ hipError_t launch_table_clear(uint64_t* table, int log2_table, hipStream_t s);
 int walk_grid_blocks(int n, int device);
 hipError_t pack_phi_i32(int n, const int32_t* a, const int32_t* b, int64_t count, uint32_t* phi_out,
                         int* flag_dev, hipStream_t s);
+
+// ---- depth-order network (mlp.hip) ----
+// mode: 0 plain, 1 bias+gelu (C = Z, H = gelu bf16), 2 bias, 3 A transposed, 4 B transposed with
+// gelu'(Z) (C fp32 and H bf16), 5 B transposed, 6 both transposed
+hipError_t mlp_gemm(int mode, const void* A, const void* B, int M, int N, int K, int lda, int ldb, float* C, int ldc,
+                    const float* bias, const float* Z, void* H, hipStream_t s);
+hipError_t mlp_softmax_ce(const float* logits, const int32_t* labels, int batch, int classes, float* probs, float* g,
+                          void* gb, float* loss_sum, hipStream_t s);
+hipError_t mlp_colsum(const float* g, int rows, int cols, float* out, hipStream_t s);
+hipError_t mlp_to_bf16(const float* x, void* y, int64_t count, hipStream_t s);
+hipError_t mlp_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1, float b2,
+                    float eps, int step, hipStream_t s);
+hipError_t mlp_init(float* w, int64_t count, int64_t index0, int fan_in, uint64_t seed, hipStream_t s);
 
 }  // namespace tcw

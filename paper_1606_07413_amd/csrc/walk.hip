@@ -834,6 +834,93 @@ __global__ void k_table_clear(uint64_t* table, uint64_t slots) {
     }
 }
 
+// ---- meet-in-the-middle labels for the depth-order network ----
+// Level table: key = matrix hash H (one salt for every h), value = 255 - (least h that reaches it).
+__device__ inline int level_lookup(const uint64_t* table, int log2_table, uint64_t key) {
+    const uint64_t mask = (1ull << log2_table) - 1;
+    uint64_t s = mix64(key ^ 0x5bd1e9955bd1e995ull) & mask;
+    for (int probe = 0; probe < 64; ++probe) {
+        const uint64_t k = __hip_atomic_load(&table[2 * s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == key) {
+            const uint64_t v = __hip_atomic_load(&table[2 * s + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return v ? 255 - (int)v : -1;
+        }
+        if (k == EMPTY_KEY) return -1;
+        s = (s + 1) & mask;
+    }
+    return -1;
+}
+
+template <int NQ, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_mitm_levels(SpaceDev sp, int h, uint64_t* table, int log2_table) {
+    using Gm = Geo<NQ>;
+    __shared__ Lds<NQ, WAVES> L;
+    load_lds(L, sp);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int gi = lane / Gm::G, gl = lane % Gm::G, gbase = gi * Gm::G;
+    uint32_t* limbs = L.limbs[wave * Gm::WPW + gi];
+    sp.h = h;
+    const int64_t stride = (int64_t)gridDim.x * WAVES * Gm::WPW;
+    for (int64_t base = ((int64_t)blockIdx.x * WAVES + wave) * Gm::WPW; base < (int64_t)sp.n_half; base += stride) {
+        const int64_t x = base + gi;
+        if (x >= (int64_t)sp.n_half) continue;
+        uint64_t o, H;
+        walk_step<NQ, WAVES>(sp, L, limbs, (uint64_t)x, gl, gbase, o, H);
+        if (gl == 0) {
+            const uint64_t key = H == EMPTY_KEY ? (H ^ 1) : H;
+            uint64_t slot = 0;
+            WalkDev wd{};
+            wd.table = table;
+            wd.log2_table = log2_table;
+            if (table_claim(wd, key, slot) != 3) atomicMax(&table[2 * slot + 1], (uint64_t)(255 - h));
+        }
+    }
+}
+
+// Per target (block): least i + j over side-1 products of j <= h_max rotations from U whose hash is
+// in the level table at level i; stops once j reaches the best total.  best_out = -1 if none.
+template <int NQ, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_mitm_probe(SpaceDev sp0, const uint32_t* phi_all,
+                                                           const int32_t* rot_e_all, int count, int h_max,
+                                                           const uint64_t* table, int log2_table, int32_t* best_out) {
+    using Gm = Geo<NQ>;
+    constexpr int NPHI = Gm::Q4 * Gm::R;
+    __shared__ Lds<NQ, WAVES> L;
+    __shared__ int best;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int gi = lane / Gm::G, gl = lane % Gm::G, gbase = gi * Gm::G;
+    uint32_t* limbs = L.limbs[wave * Gm::WPW + gi];
+    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+        SpaceDev sp = sp0;
+        sp.phi = phi_all + (size_t)t * 2 * NPHI;
+        sp.rot_e = rot_e_all[t];
+        __syncthreads();
+        load_lds(L, sp);
+        if (threadIdx.x == 0) best = 1 << 20;
+        __syncthreads();
+        uint32_t nh = 1;
+        for (int j = 0; j <= h_max; ++j) {
+            if (j >= best) break;
+            sp.h = j;
+            sp.n_half = nh;
+            for (int64_t base = (int64_t)wave * Gm::WPW; base < (int64_t)nh; base += WAVES * Gm::WPW) {
+                const int64_t x = base + gi;
+                if (x >= (int64_t)nh) continue;
+                uint64_t o, H;
+                walk_step<NQ, WAVES>(sp, L, limbs, (uint64_t)x | (1ull << 32), gl, gbase, o, H);
+                if (gl == 0) {
+                    const int lvl = level_lookup(table, log2_table, H == EMPTY_KEY ? (H ^ 1) : H);
+                    if (lvl >= 0) atomicMin(&best, j + lvl);
+                }
+            }
+            nh *= Gm::XI;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) best_out[t] = best < (1 << 20) ? best : -1;
+    }
+}
+
 template <typename F>
 hipError_t dispatch_n(int n, F&& f) {
     switch (n) {
@@ -971,6 +1058,43 @@ hipError_t launch_table_clear(uint64_t* table, int log2_table, hipStream_t s) {
     if (blocks > 65535) blocks = 65535;
     hipLaunchKernelGGL(k_table_clear, dim3((unsigned)blocks), dim3(256), 0, s, table, slots);
     return hipGetLastError();
+}
+
+}  // namespace tcw
+
+namespace tcw {
+
+hipError_t mitm_levels(int n, const SpaceDev& sp, int h, uint64_t* table, int log2_table, hipStream_t s) {
+    auto f = [&]<int NQ>() -> hipError_t {
+        constexpr int W = WalkWaves<NQ>::value;
+        if constexpr (NQ <= 3) {
+            int64_t blocks = ((int64_t)sp.n_half + W * Geo<NQ>::WPW - 1) / (W * Geo<NQ>::WPW);
+            if (blocks > 4096) blocks = 4096;
+            if (blocks < 1) blocks = 1;
+            hipLaunchKernelGGL((k_mitm_levels<NQ, W>), dim3((unsigned)blocks), dim3(W * 64), 0, s, sp, h, table,
+                               log2_table);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    };
+    return dispatch_n(n, f);
+}
+
+hipError_t mitm_probe(int n, const SpaceDev& sp, const uint32_t* phi_all, const int32_t* rot_e_all, int count,
+                      int h_max, const uint64_t* table, int log2_table, int32_t* best_out, hipStream_t s) {
+    auto f = [&]<int NQ>() -> hipError_t {
+        constexpr int W = WalkWaves<NQ>::value;
+        if constexpr (NQ <= 3) {
+            const int blocks = count < 4096 ? count : 4096;
+            hipLaunchKernelGGL((k_mitm_probe<NQ, W>), dim3(blocks), dim3(W * 64), 0, s, sp, phi_all, rot_e_all, count,
+                               h_max, table, log2_table, best_out);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    };
+    return dispatch_n(n, f);
 }
 
 }  // namespace tcw

@@ -99,6 +99,18 @@ _SIGS = {
                                    C.POINTER(C.c_double)]),
     "tcw_autotune": (C.c_int, [_P, _P, C.c_int, C.c_int, C.c_int, C.c_uint64, C.POINTER(C.c_int64),
                                C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "tcw_features": (C.c_int, [_P, _P, _P]),
+    "tcw_label_batch": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_uint16), C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int32), C.c_int, C.c_uint64, _P, _P]),
+    "tcw_mlp_create": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, _P, C.c_uint64, C.POINTER(_P)]),
+    "tcw_mlp_free": (C.c_int, [_P]),
+    "tcw_mlp_param_count": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+    "tcw_mlp_get_params": (C.c_int, [_P, _P]),
+    "tcw_mlp_set_params": (C.c_int, [_P, _P]),
+    "tcw_mlp_forward": (C.c_int, [_P, _P, C.c_int, _P]),
+    "tcw_mlp_gradients": (C.c_int, [_P, _P, _P, C.c_int, _P, C.POINTER(C.c_float)]),
+    "tcw_mlp_train_step": (C.c_int, [_P, _P, _P, C.c_int, C.c_float, C.POINTER(C.c_float)]),
+    "tcw_mlp_depth_order": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
 }
 
 EXPORTED = sorted(_SIGS)
@@ -354,3 +366,100 @@ class Walk:
             self.end()
         except Exception:
             pass
+
+
+def _features(self, target, out):
+    self._check(self.lib.tcw_features(self.h, target.h, _ptr(out)))
+
+
+def _label_batch(self, n, words_list, h_max, seed, features_out, labels_out):
+    """words_list: [(paulis, clifford), ...]; fills device tensors features_out, labels_out."""
+    flat, offs, ks = [], [0], []
+    for paulis, clifford in words_list:
+        flat.extend(paulis)
+        flat.extend(clifford)
+        offs.append(len(flat))
+        ks.append(len(paulis))
+    w = (C.c_uint16 * max(1, len(flat)))(*flat)
+    o = (C.c_int32 * len(offs))(*offs)
+    k = (C.c_int32 * len(ks))(*ks)
+    self._check(self.lib.tcw_label_batch(self.h, n, len(ks), w, o, k, h_max, seed, _ptr(features_out),
+                                         _ptr(labels_out)))
+
+
+Context.features = _features
+Context.label_batch = _label_batch
+
+
+class Network:
+    """The depth-order network (parameters W_0, b_0, W_1, b_1, ... as one float32 vector)."""
+
+    def __init__(self, ctx: Context, inp: int, hidden: int, depth: int, classes: int, init=None, seed: int = 42):
+        import numpy as np
+        self.ctx = ctx
+        self.dims = (inp, hidden, depth, classes)
+        h = _P()
+        buf = None
+        if init is not None:
+            buf = np.ascontiguousarray(init, dtype=np.float32)
+        ctx._check(ctx.lib.tcw_mlp_create(ctx.h, inp, hidden, depth, classes,
+                                          None if buf is None else buf.ctypes.data, seed, C.byref(h)))
+        self.h = h
+        cnt = C.c_int64(0)
+        ctx._check(ctx.lib.tcw_mlp_param_count(self.h, C.byref(cnt)))
+        self.count = cnt.value
+
+    def params(self):
+        import numpy as np
+        out = np.zeros(self.count, dtype=np.float32)
+        self.ctx._check(self.ctx.lib.tcw_mlp_get_params(self.h, out.ctypes.data))
+        return out
+
+    def set_params(self, flat):
+        import numpy as np
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        self.ctx._check(self.ctx.lib.tcw_mlp_set_params(self.h, flat.ctypes.data))
+
+    def forward(self, x, probs_out):
+        self.ctx._check(self.ctx.lib.tcw_mlp_forward(self.h, _ptr(x), x.shape[0], _ptr(probs_out)))
+
+    def gradients(self, x, labels):
+        import numpy as np
+        g = np.zeros(self.count, dtype=np.float32)
+        loss = C.c_float(0)
+        self.ctx._check(self.ctx.lib.tcw_mlp_gradients(self.h, _ptr(x), _ptr(labels), x.shape[0], g.ctypes.data,
+                                                       C.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, x, labels, lr):
+        loss = C.c_float(0)
+        self.ctx._check(self.ctx.lib.tcw_mlp_train_step(self.h, _ptr(x), _ptr(labels), x.shape[0], lr,
+                                                        C.byref(loss)))
+        return loss.value
+
+    def depth_order(self, target, k_max):
+        order = (C.c_int32 * (k_max + 1))()
+        probs = (C.c_float * self.dims[3])()
+        self.ctx._check(self.ctx.lib.tcw_mlp_depth_order(self.h, target.h, k_max, order, probs))
+        return list(order), list(probs)
+
+    def free(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.tcw_mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def flatten_params(params: dict, depth: int):
+    """W_0, b_0, W_1, b_1, ... concatenated (the library's parameter order)."""
+    import numpy as np
+    parts = []
+    for l in range(depth + 1):
+        parts.append(np.asarray(params[f"W{l}"], dtype=np.float32).reshape(-1))
+        parts.append(np.asarray(params[f"b{l}"], dtype=np.float32).reshape(-1))
+    return np.concatenate(parts)

@@ -107,3 +107,27 @@ def batch_targets(count: int = 64, batch_seed: int = 7, seed_base: int = 100):
         k = 3 + uniform_below(batch_seed, 2 * i + 1, 5)
         out.append(target_words(n, k, seed_base + i))
     return out
+
+
+def mlp_init(inp: int, hidden: int, depth: int, classes: int, seed: int):
+    """Seeded initial weights of the depth-order network, float32: W_l uniform in
+    [-1/sqrt(fan_in), 1/sqrt(fan_in)] (row-major in x out), biases zero.  Values come from the
+    SplitMix64 stream of `seed`, 24 bits each: u = (r >> 40) / 2^24."""
+    import numpy as np
+    sizes = [inp] + [hidden] * depth + [classes]
+    params = {}
+    idx = 0
+    for l in range(depth + 1):
+        fi, fo = sizes[l], sizes[l + 1]
+        count = fi * fo
+        i = np.arange(idx, idx + count, dtype=np.uint64)
+        z = (np.uint64(seed) + (i + np.uint64(1)) * np.uint64(GAMMA))
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+        u = (z >> np.uint64(40)).astype(np.float64) / float(1 << 24)
+        bound = 1.0 / np.sqrt(fi)
+        params[f"W{l}"] = ((2.0 * u - 1.0) * bound).astype(np.float32).reshape(fi, fo)
+        params[f"b{l}"] = np.zeros(fo, dtype=np.float32)
+        idx += count
+    return params

@@ -1,0 +1,191 @@
+"""GPU parity of the depth-order network's pieces against the CPU oracle: canonical features
+(bit-exact), meet-in-the-middle labels (against brute force), parameter init (bit-exact),
+gradients of the BF16/MFMA path (tolerance from BF16 rounding), training and the depth order."""
+
+import numpy as np
+import pytest
+
+import seeded_inputs
+from oracle import bfs
+from oracle import mlp as omlp
+from oracle import zmat
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1606_07413_amd import tcw
+    assert torch.cuda.is_available()
+    return tcw.Context(0)
+
+
+def oracle_target(n, k, seed, clifford=None):
+    tw = seeded_inputs.target_words(n, k, seed)
+    cl = tw.clifford if clifford is None else clifford
+    return tw, zmat.target_from_words(n, tw.paulis, cl)
+
+
+@pytest.mark.parametrize("n,k,seed", [(1, 4, 1), (2, 3, 2), (2, 6, 3), (3, 5, 4), (3, 7, 5)])
+def test_features_bit_exact(ctx, n, k, seed):
+    import torch
+    print("features", n, k, seed, flush=True)
+    tw, u = oracle_target(n, k, seed)
+    tgt = ctx.target_from_words(n, tw.paulis, tw.clifford)
+    out = torch.empty(16 ** n, dtype=torch.float32, device="cuda:0")
+    ctx.features(tgt, out)
+    want = omlp.features(u)
+    got = out.cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def test_features_left_clifford_invariant(ctx):
+    import torch
+    tw, u = oracle_target(3, 5, 9)
+    other = seeded_inputs.random_clifford_word(3, 77)
+    t1 = ctx.target_from_words(3, tw.paulis, tw.clifford)
+    t2 = ctx.target_from_words(3, tw.paulis, other)
+    a = torch.empty(4096, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    ctx.features(t1, a)
+    ctx.features(t2, b)
+    assert torch.equal(a, b)
+
+
+def _label(ctx, n, words, h_max, seed=11):
+    import torch
+    feats = torch.empty((len(words), 16 ** n), dtype=torch.float32, device="cuda:0")
+    labels = torch.empty(len(words), dtype=torch.int32, device="cuda:0")
+    ctx.label_batch(n, words, h_max, seed, feats, labels)
+    return feats, labels.cpu().tolist()
+
+
+def test_labels_match_brute_force_n1(ctx):
+    print("labels n1", flush=True)
+    _, seen, _ = bfs.cosets_by_tcount(1, 6)
+    words, us = [], []
+    for seed in range(40):
+        k = 1 + seed % 8
+        tw, u = oracle_target(1, k, seed)
+        words.append((tw.paulis, tw.clifford))
+        us.append(u)
+    feats, labels = _label(ctx, 1, words, 3)
+    for u, lab in zip(us, labels):
+        t = bfs.min_tcount(u, seen)
+        assert lab == (t if t is not None else -1)
+    # features from the batch kernel equal the single-target ones
+    assert np.array_equal(feats[0].cpu().numpy(), omlp.features(us[0]))
+
+
+def test_labels_match_brute_force_n2(ctx):
+    print("labels n2", flush=True)
+    _, seen, _ = bfs.cosets_by_tcount(2, 3)
+    words, us = [], []
+    for seed in range(24):
+        k = 1 + seed % 4
+        tw, u = oracle_target(2, k, 50 + seed)
+        words.append((tw.paulis, tw.clifford))
+        us.append(u)
+    _, labels = _label(ctx, 2, words, 2)
+    for u, lab in zip(us, labels):
+        t = bfs.min_tcount(u, seen)
+        if t is not None:
+            assert lab == t
+        else:
+            assert lab == 4   # T-count 4 (<= generating k = 4, not in levels 0..3)
+
+
+def test_labels_n3_consistent(ctx):
+    """n = 3: labels are at most the generating k, equal across left Cliffords, and match the
+    exhaustive search for T-count <= 5 (depths <= 5 are enumerated)."""
+    from paper_1606_07413_amd import tcw
+    print("labels n3", flush=True)
+    words, specs = [], []
+    for seed in range(8):
+        k = 2 + seed % 5
+        tw = seeded_inputs.target_words(3, k, 400 + seed)
+        words.append((tw.paulis, tw.clifford))
+        words.append((tw.paulis, seeded_inputs.random_clifford_word(3, 900 + seed)))
+        specs.append((k, tw))
+    _, labels = _label(ctx, 3, words, 3)
+    for i, (k, tw) in enumerate(specs):
+        a, b = labels[2 * i], labels[2 * i + 1]
+        assert a == b and 0 <= a <= k
+        if k <= 5:
+            tgt = ctx.target_from_words(3, tw.paulis, tw.clifford)
+            p = ctx.default_params(3)
+            p.k_max = 5
+            res = ctx.search(tgt, p)
+            assert res.status == 1 and res.t == a
+
+
+def test_init_bit_exact(ctx):
+    from paper_1606_07413_amd import tcw
+    net = tcw.Network(ctx, 256, 64, 3, 11, seed=42)
+    want = tcw.flatten_params(seeded_inputs.mlp_init(256, 64, 3, 11, 42), 3)
+    assert np.array_equal(net.params(), want)
+
+
+@pytest.mark.parametrize("batch", [37, 256])
+def test_gradients_against_oracle(ctx, batch):
+    import torch
+    from paper_1606_07413_amd import tcw
+    print("gradients", batch, flush=True)
+    inp, hidden, depth, classes = 256, 64, 3, 11
+    params = seeded_inputs.mlp_init(inp, hidden, depth, classes, 7)
+    rng = np.random.default_rng(batch)
+    for l in range(depth + 1):
+        params[f"b{l}"] = (rng.normal(size=params[f"b{l}"].shape) * 0.05).astype(np.float32)
+    x = rng.normal(size=(batch, inp)).astype(np.float32) * 0.5
+    y = rng.integers(0, classes, batch).astype(np.int32)
+    net = tcw.Network(ctx, inp, hidden, depth, classes, init=tcw.flatten_params(params, depth))
+    g, loss = net.gradients(torch.tensor(x, device="cuda:0"), torch.tensor(y, device="cuda:0"))
+    # oracle on the BF16-rounded weights and inputs the GPU multiplies
+    pr = {k: (omlp.bf16_round(v) if k.startswith("W") else v) for k, v in params.items()}
+    ref = omlp.gradients(pr, omlp.bf16_round(x), y, depth)
+    ref_loss = omlp.loss(pr, omlp.bf16_round(x), y, depth)
+    assert abs(loss - ref_loss) < 1e-2 * abs(ref_loss)
+    off = 0
+    for l in range(depth + 1):
+        for name in (f"W{l}", f"b{l}"):
+            size = params[name].size
+            got = g[off:off + size].reshape(params[name].shape)
+            want = ref[name]
+            off += size
+            rel = np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-12)
+            assert rel < 3e-2, (name, rel)
+
+
+def test_forward_probs(ctx):
+    import torch
+    from paper_1606_07413_amd import tcw
+    net = tcw.Network(ctx, 256, 64, 3, 11, seed=5)
+    x = torch.randn((50, 256), device="cuda:0")
+    p = torch.empty((50, 11), device="cuda:0")
+    net.forward(x, p)
+    assert torch.allclose(p.sum(dim=1), torch.ones(50, device="cuda:0"), atol=1e-5)
+
+
+def test_training_reduces_loss_and_orders_depths(ctx):
+    """n = 2 targets with k uniform in 1..6, labelled exactly (h_max = 3): training lowers the
+    loss; the depth order is a permutation led by the most probable T-count."""
+    import torch
+    from paper_1606_07413_amd import tcw
+    print("train n2", flush=True)
+    words = []
+    for seed in range(2048):
+        tw = seeded_inputs.target_words(2, 1 + seed % 6, 10_000 + seed)
+        words.append((tw.paulis, tw.clifford))
+    feats, labels = _label(ctx, 2, words, 3)
+    lab = torch.tensor(labels, dtype=torch.int32, device="cuda:0")
+    assert (lab >= 0).all()
+    net = tcw.Network(ctx, 256, 128, 3, 11, seed=42)
+    first = net.train_step(feats, lab, 1e-3)
+    for _ in range(60):
+        last = net.train_step(feats, lab, 1e-3)
+    assert last < 0.7 * first
+    tw = seeded_inputs.target_words(2, 5, 77)
+    order, probs = net.depth_order(ctx.target_from_words(2, tw.paulis, tw.clifford), 6)
+    assert sorted(order) == list(range(7))
+    assert probs[order[0]] == max(probs[:7])
