@@ -111,6 +111,96 @@ def batch_leg(ctx, cap: float):
             "aggregate_walk_steps_per_s": agg, "per_target_cap_s": cap, "per_target": per}
 
 
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def mlp_leg(ctx, train_count: int, epochs: int, eval_count: int, cap: float):
+    """Learned depth order at n = 3: train on seeded circuits (k uniform in 1..10) labelled by exact
+    meet-in-the-middle search, then search held-out targets with the plain and the learned order."""
+    import numpy as np
+    import torch
+
+    import seeded_inputs
+    from paper_1606_07413_amd import tcw
+    spec = seeded_inputs.WORKLOADS["mlp_n3"]
+    n, classes = spec["n"], spec["classes"]
+    h_max = 3
+
+    def dataset(words):
+        feats = torch.empty((len(words), 16 ** n), dtype=torch.float32, device="cuda:0")
+        labels = torch.empty(len(words), dtype=torch.int32, device="cuda:0")
+        ctx.label_batch(n, [(w.paulis, w.clifford) for w in words], h_max, 777, feats, labels)
+        return feats, labels
+
+    t0 = time.perf_counter()
+    train = seeded_inputs.mlp_targets(spec["train_seeds"][0], spec["train_seeds"][0] + train_count)
+    feats, labels = dataset(train)
+    torch.cuda.synchronize()
+    t_label = time.perf_counter() - t0
+    gen_k = torch.tensor([w.k for w in train], dtype=torch.int32, device="cuda:0")
+    unknown = labels < 0
+    labels = torch.where(unknown, gen_k, labels)       # T-count > 2 h_max: the generating k (an upper bound)
+    _log(f"labelled {train_count} circuits in {t_label:.1f} s ({int(unknown.sum())} above {2 * h_max})")
+    net = tcw.Network(ctx, 16 ** n, spec["hidden"], spec["depth"], classes, seed=spec["init_seed"])
+    t1 = time.perf_counter()
+    loss = net.train(feats, labels, spec["batch"], epochs, 1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    _log(f"trained {epochs} epochs in {t_train:.1f} s, loss {loss:.3f}")
+    flops = 6.0 * train_count * epochs * sum(a * b for a, b in [(16 ** n, 512), (512, 512), (512, 512), (512, classes)])
+    del feats
+
+    ev = seeded_inputs.mlp_targets(spec["eval_seeds"][0], spec["eval_seeds"][0] + eval_count)
+    ef, el = dataset(ev)
+    probs = torch.empty((eval_count, classes), dtype=torch.float32, device="cuda:0")
+    net.forward(ef, probs)
+    pred = probs.argmax(dim=1).to(torch.int32)
+    known = el >= 0
+    acc = float((pred[known] == el[known]).float().mean()) if bool(known.any()) else None
+
+    targets = [ctx.target_from_words(n, w.paulis, w.clifford) for w in ev]
+    results = {}
+    for name in ("plain", "learned"):
+        params = []
+        for i, (w, tgt) in enumerate(zip(ev, targets)):
+            p = ctx.default_params(n)
+            p.k_max = spec["k_range"][1]
+            p.seed = 9000 + i
+            p.walks = 0
+            p.log2_table = 0
+            p.iters_per_launch = 0
+            p.max_seconds = cap
+            if name == "learned":
+                order, _ = net.depth_order(tgt, p.k_max)
+                p.depth_order_kind = tcw.ORDER_GIVEN
+                p.depth_order_len = len(order)
+                for j, kk in enumerate(order):
+                    p.depth_order[j] = kk
+            params.append(p)
+        ts = time.perf_counter()
+        res, agg = ctx.search_batch(targets, params)
+        results[name] = (res, time.perf_counter() - ts)
+        _log(f"{name} order: {sum(r.status for r in res)}/{eval_count} solved in {results[name][1]:.1f} s")
+    pr, lr_ = results["plain"][0], results["learned"][0]
+    both = [i for i in range(eval_count) if pr[i].status and lr_[i].status]
+    tts = {name: [r.seconds if r.status else cap for r in results[name][0]] for name in results}
+    return {
+        "train_circuits": train_count, "label_seconds": t_label, "unknown_labels": int(unknown.sum()),
+        "epochs": epochs, "train_seconds": t_train, "final_loss": loss,
+        "train_tflops": flops / t_train / 1e12, "mfma_bf16_frac": flops / t_train / 2.5e15,
+        "eval_circuits": eval_count, "eval_accuracy_exact_labels": acc, "cap_s": cap,
+        "plain": {"solved": sum(r.status for r in pr), "mean_tts_s_censored_at_cap": float(np.mean(tts["plain"])),
+                  "wall_s": results["plain"][1]},
+        "learned": {"solved": sum(r.status for r in lr_), "mean_tts_s_censored_at_cap": float(np.mean(tts["learned"])),
+                    "wall_s": results["learned"][1]},
+        "solved_by_both": len(both),
+        "mean_tts_both_s": {"plain": float(np.mean([pr[i].seconds for i in both])) if both else None,
+                            "learned": float(np.mean([lr_[i].seconds for i in both])) if both else None},
+        "learned_larger_t": sum(1 for i in both if lr_[i].t > pr[i].t),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +213,11 @@ def main():
     ap.add_argument("--no-tts", action="store_true")
     ap.add_argument("--batch", action="store_true", help="also run the 64-target mixed batch")
     ap.add_argument("--batch-cap", type=float, default=30.0, help="per-target wall-clock cap (s)")
+    ap.add_argument("--mlp", action="store_true", help="also train the depth-order network and compare orders")
+    ap.add_argument("--mlp-train", type=int, default=1 << 16, help="training circuits")
+    ap.add_argument("--mlp-epochs", type=int, default=8)
+    ap.add_argument("--mlp-eval", type=int, default=256, help="held-out circuits")
+    ap.add_argument("--mlp-cap", type=float, default=20.0, help="per-target wall-clock cap (s) in the comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -209,6 +304,8 @@ def main():
     out.update(extra)
     if args.batch:
         out["batch64"] = batch_leg(ctx, args.batch_cap)
+    if args.mlp:
+        out["learned_order"] = mlp_leg(ctx, args.mlp_train, args.mlp_epochs, args.mlp_eval, args.mlp_cap)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, k, chunk, seed, delta, args.cpu_seconds)
     print(json.dumps(out), flush=True)

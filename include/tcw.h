@@ -259,6 +259,11 @@ int tcw_mlp_gradients(tcw_mlp* m, const float* x_dev, const int32_t* labels_dev,
                       float* loss);
 int tcw_mlp_train_step(tcw_mlp* m, const float* x_dev, const int32_t* labels_dev, int batch, float lr, float* loss);
 int tcw_mlp_depth_order(tcw_mlp* m, const tcw_target* t, int k_max, int32_t* order_out, float* probs_out);
+/* tcw_mlp_train: `epochs` passes over count samples (x_dev count x in, labels_dev count) in fixed
+ * consecutive batches of `batch` (the last one ragged), one Adam step each; *last_epoch_loss = mean
+ * loss over the final pass. */
+int tcw_mlp_train(tcw_mlp* m, const float* x_dev, const int32_t* labels_dev, int64_t count, int batch, int epochs,
+                  float lr, float* last_epoch_loss);
 
 #ifdef __cplusplus
 }

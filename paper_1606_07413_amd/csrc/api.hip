@@ -1756,3 +1756,24 @@ extern "C" int tcw_label_batch(tcw_ctx* c, int n, int count, const uint16_t* wor
     if (flag) return fail(c, TCW_EOVERFLOW, "target outside the int8 / int32 range or word too long");
     return TCW_OK;
 }
+
+extern "C" int tcw_mlp_train(tcw_mlp* m, const float* x, const int32_t* labels, int64_t count, int batch, int epochs,
+                             float lr, float* last_epoch_loss) {
+    if (!m || !x || !labels || count < 1 || batch < 1 || epochs < 1 || !(lr > 0)) return TCW_EINVAL;
+    double tot = 0;
+    int64_t nb = 0;
+    for (int ep = 0; ep < epochs; ++ep) {
+        tot = 0;
+        nb = 0;
+        for (int64_t first = 0; first < count; first += batch) {
+            const int b = (int)std::min<int64_t>(batch, count - first);
+            float ls = 0;
+            int rc = tcw_mlp_train_step(m, x + first * m->inp, labels + first, b, lr, &ls);
+            if (rc) return rc;
+            tot += ls * b;
+            nb += b;
+        }
+    }
+    if (last_epoch_loss) *last_epoch_loss = (float)(tot / (double)nb);
+    return TCW_OK;
+}

@@ -111,6 +111,7 @@ _SIGS = {
     "tcw_mlp_gradients": (C.c_int, [_P, _P, _P, C.c_int, _P, C.POINTER(C.c_float)]),
     "tcw_mlp_train_step": (C.c_int, [_P, _P, _P, C.c_int, C.c_float, C.POINTER(C.c_float)]),
     "tcw_mlp_depth_order": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+    "tcw_mlp_train": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int, C.c_int, C.c_float, C.POINTER(C.c_float)]),
 }
 
 EXPORTED = sorted(_SIGS)
@@ -435,6 +436,12 @@ class Network:
         loss = C.c_float(0)
         self.ctx._check(self.ctx.lib.tcw_mlp_train_step(self.h, _ptr(x), _ptr(labels), x.shape[0], lr,
                                                         C.byref(loss)))
+        return loss.value
+
+    def train(self, x, labels, batch, epochs, lr):
+        loss = C.c_float(0)
+        self.ctx._check(self.ctx.lib.tcw_mlp_train(self.h, _ptr(x), _ptr(labels), x.shape[0], batch, epochs, lr,
+                                                   C.byref(loss)))
         return loss.value
 
     def depth_order(self, target, k_max):

@@ -131,3 +131,13 @@ def mlp_init(inp: int, hidden: int, depth: int, classes: int, seed: int):
         params[f"b{l}"] = np.zeros(fo, dtype=np.float32)
         idx += count
     return params
+
+
+def mlp_targets(seed_lo: int, seed_hi: int, n: int = 3, k_lo: int = 1, k_hi: int = 10):
+    """Seeded circuits for the depth-order network: seed s gives k = k_lo + uniform_below(s', 0,
+    k_hi - k_lo + 1) (s' = s xor 0x6B) rotations times a seeded Clifford."""
+    out = []
+    for s in range(seed_lo, seed_hi):
+        k = k_lo + uniform_below(s ^ 0x6B, 0, k_hi - k_lo + 1)
+        out.append(target_words(n, k, s))
+    return out

@@ -189,3 +189,46 @@ def test_training_reduces_loss_and_orders_depths(ctx):
     order, probs = net.depth_order(ctx.target_from_words(2, tw.paulis, tw.clifford), 6)
     assert sorted(order) == list(range(7))
     assert probs[order[0]] == max(probs[:7])
+
+
+def test_learned_order_gains_over_plain(ctx):
+    """A network trained on n = 3 circuits with k in 1..6 (exact labels) orders depths so that the
+    search visits fewer spaces than the plain increasing order; answers stay exact and minimal."""
+    import torch
+    from oracle import search as osearch
+    from paper_1606_07413_amd import tcw
+    print("learned gain", flush=True)
+    train = seeded_inputs.mlp_targets(20_000, 20_000 + 4096, k_lo=1, k_hi=6)
+    feats, labels = _label(ctx, 3, [(w.paulis, w.clifford) for w in train], 3)
+    assert (labels.__class__ is list)
+    lab = torch.tensor(labels, dtype=torch.int32, device="cuda:0")
+    assert (lab >= 0).all()
+    net = tcw.Network(ctx, 4096, 256, 3, 11, seed=42)
+    net.train(feats, lab, 512, 6, 1e-3)
+    held = seeded_inputs.mlp_targets(30_000, 30_012, k_lo=5, k_hi=6)
+    spaces = {"plain": 0, "learned": 0}
+    for i, w in enumerate(held):
+        tgt = ctx.target_from_words(3, w.paulis, w.clifford)
+        found = {}
+        for name in ("plain", "learned"):
+            p = ctx.default_params(3)
+            p.k_max = 6
+            p.seed = 40 + i
+            p.max_seconds = 60
+            if name == "learned":
+                order, _ = net.depth_order(tgt, 6)
+                p.depth_order_kind = tcw.ORDER_GIVEN
+                p.depth_order_len = len(order)
+                for j, kk in enumerate(order):
+                    p.depth_order[j] = kk
+            r = ctx.search(tgt, p)
+            assert r.status == 1
+            spaces[name] += r.spaces
+            found[name] = r
+        u = zmat.target_from_words(3, w.paulis, w.clifford)
+        d = tcw.decomposition_of(found["learned"])
+        assert osearch.reconstruct(3, osearch.Decomposition(t=d.t, paulis_desc=d.paulis_desc, perm=d.perm,
+                                                            sign=d.sign)).equals(u)
+        assert found["learned"].t >= found["plain"].t
+    print("spaces searched", spaces, flush=True)
+    assert spaces["learned"] < spaces["plain"]
