@@ -213,6 +213,8 @@ def main():
     ap.add_argument("--no-tts", action="store_true")
     ap.add_argument("--batch", action="store_true", help="also run the 64-target mixed batch")
     ap.add_argument("--batch-cap", type=float, default=30.0, help="per-target wall-clock cap (s)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration for profiles)")
     ap.add_argument("--mlp", action="store_true", help="also train the depth-order network and compare orders")
     ap.add_argument("--mlp-train", type=int, default=1 << 16, help="training circuits")
     ap.add_argument("--mlp-epochs", type=int, default=8)
@@ -259,6 +261,11 @@ def main():
     peak = VALU_PEAK_OPS / 1e12
     mfma_achieved = mfma_ops_per_step(n) * per_launch_steps / (avg_ms * 1e-3)
     w.end()
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
     extra = {}
     if not args.no_tts:

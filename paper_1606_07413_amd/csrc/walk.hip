@@ -62,6 +62,14 @@ struct Lds<4, WAVES> {
     uint32_t limbs[WAVES][NLIMB * N4_ROW];
 };
 
+// A value every lane of the wavefront holds (the walk of a whole wavefront), made explicitly uniform.
+__device__ inline uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline uint32_t uniform32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -85,12 +93,6 @@ __device__ void load_lds(Lds<NQ, WAVES>& L, const SpaceDev& sp) {
         L.K[i] = sp.keys[i];
         L.K2[i] = sp.keys[Gm::R + i];
     }
-}
-
-__device__ inline uint64_t pick4(const uint64_t* u, int i) {
-    const uint64_t lo = (i & 1) ? u[1] : u[0];
-    const uint64_t hi = (i & 1) ? u[3] : u[2];
-    return (i & 2) ? hi : lo;
 }
 
 // Lane exchange with the partner lane ^ X (X a compile-time power of two below 64): DPP quad
@@ -256,8 +258,11 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
         }
         wave_sync();
 #pragma unroll
-        for (int kq = 0; kq < 4; ++kq)
-            afr[set * 4 + kq] = *reinterpret_cast<const v4i*>(&limbs[mr * N4_ROW + kq * 16 + g * 4]);
+        for (int kq = 0; kq < 4; ++kq) {
+            const v4i f = *reinterpret_cast<const v4i*>(&limbs[mr * N4_ROW + kq * 16 + g * 4]);
+            // A-operand rows 9..15 are zero, so those accumulator rows stay exactly zero
+            afr[set * 4 + kq] = n16 < NLIMB ? f : v4i{0, 0, 0, 0};
+        }
         wave_sync();
     }
     v4i acc[N4_NT];
@@ -265,21 +270,25 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
     for (int nt = 0; nt < N4_NT; ++nt) acc[nt] = v4i{0, 0, 0, 0};
 #pragma unroll
     for (int kk = 0; kk < N4_KK; ++kk) {
+        // issue the 16 fragment reads of this K step first, then the MFMAs consume them in order
+        v4i bf[N4_NT];
+#pragma unroll
+        for (int nt = 0; nt < N4_NT; ++nt) bf[nt] = L.frag[(nt * N4_KK + kk) * 64 + lane];
 #pragma unroll
         for (int nt = 0; nt < N4_NT; ++nt)
-            acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(afr[kk], L.frag[(nt * N4_KK + kk) * 64 + lane], acc[nt],
-                                                            0, 0, 0);
+            acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(afr[kk], bf[nt], acc[nt], 0, 0, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, N4_NT, 0);  // DS reads
+        __builtin_amdgcn_sched_group_barrier(0x008, N4_NT, 0);  // MFMA
     }
-    // this lane's partial sums: limbs m = 4g + j <= 8, weight 2^(7m) = 2^(28g) 2^(7j)
-    const bool v0 = 4 * g <= 8, v1 = 4 * g + 1 <= 8, v2 = 4 * g + 2 <= 8, v3 = 4 * g + 3 <= 8;
+    // this lane's partial sums over limbs m = 4g + j (rows m >= 9 are zero): weight 2^(7m) = 2^(28g) 2^(7j).
+    // |acc| < 2^23, so acc_0 + 2^7 acc_1 and acc_2 + 2^7 acc_3 fit in 31 bits.
     const uint32_t sh = (uint32_t)((28 * g) % 61);
     uint64_t P[N4_NT];
 #pragma unroll
     for (int nt = 0; nt < N4_NT; ++nt) {
-        uint64_t x = v0 ? (uint64_t)(int64_t)acc[nt][0] : 0;
-        x += v1 ? ((uint64_t)(int64_t)acc[nt][1] << 7) : 0;
-        x += v2 ? ((uint64_t)(int64_t)acc[nt][2] << 14) : 0;
-        x += v3 ? ((uint64_t)(int64_t)acc[nt][3] << 21) : 0;
+        const int32_t lo = acc[nt][0] + acc[nt][1] * 128;
+        const int32_t hi = acc[nt][2] + acc[nt][3] * 128;
+        const uint64_t x = (uint64_t)(int64_t)lo + ((uint64_t)(int64_t)hi << 14);
         P[nt] = m61_rotv(m61_fold(x + 4 * P61), sh);
     }
     // reduce-scatter over the four limb groups: lanes l^32, then l^16
@@ -305,6 +314,7 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
                           int gbase, uint64_t& out_pt, uint64_t& out_h) {
     using Gm = Geo<NQ>;
     constexpr int R = Gm::R, RPL = Gm::RPL, Q4 = Gm::Q4, HMAX = Gm::HMAX;
+    if constexpr (Gm::G == 64) pt = uniform64(pt);  // one walk per wavefront: decode on the scalar unit
     const uint32_t x = (uint32_t)pt;
     const int side = (int)((pt >> 32) & 1);
     const int h = sp.h;
@@ -332,9 +342,14 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
             if constexpr (RPL == 1) {
                 w[0] = u[0];
             } else {
-                const int jx = (int)(p & (RPL - 1));
-#pragma unroll
-                for (int j = 0; j < RPL; ++j) w[j] = pick4(u, j ^ jx);
+                // w[j] = u[j ^ (p & 3)] with constant register indices (no indexed private memory)
+                const bool s1 = (p & 1) != 0, s2 = (p & 2) != 0;
+                const uint64_t b0 = s1 ? u[1] : u[0], b1 = s1 ? u[0] : u[1];
+                const uint64_t b2 = s1 ? u[3] : u[2], b3 = s1 ? u[2] : u[3];
+                w[0] = s2 ? b2 : b0;
+                w[1] = s2 ? b3 : b1;
+                w[2] = s2 ? b0 : b2;
+                w[3] = s2 ? b1 : b3;
             }
             const int src = gbase + (gl ^ (int)(p >> Gm::LRPL));
 #pragma unroll
@@ -592,6 +607,18 @@ __device__ void walk_block(const SpaceDev& sp, const WalkDev& wd, int iters, Lds
         const int64_t w = base + gi;
         if (w >= wd.walks) continue;
         WalkState st = wd.states[w];
+        if constexpr (Gm::G == 64) {
+            st.start = uniform64(st.start);
+            st.cur = uniform64(st.cur);
+            st.pa = uniform64(st.pa);
+            st.pb = uniform64(st.pb);
+            st.na = uniform64(st.na);
+            st.ha = uniform64(st.ha);
+            st.len = uniform32(st.len);
+            st.trail = uniform32(st.trail);
+            st.mode = uniform32(st.mode);
+            st.rem = uniform32(st.rem);
+        }
         for (int it = 0; it < iters; ++it) {
             const uint32_t mode = st.mode & 0xff;
             if (mode == MODE_DONE) break;
