@@ -13,9 +13,11 @@ host on a bounded sample of the same workload, and time-to-solution figures.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import multiprocessing as mp
 import os
+import re
 import sys
 import time
 
@@ -26,6 +28,41 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # dense int8 MFMA peak (MI355X): 5.0e15 ops/s
 MFMA_I8_PEAK_OPS = 5.0e15
+
+
+# Files the walk kernel is built from; the counter summary below records their digest.
+WALK_KERNEL_SOURCES = ("paper_1606_07413_amd/csrc/walk.hip", "paper_1606_07413_amd/csrc/common.h",
+                       "paper_1606_07413_amd/csrc/internal.h", "paper_1606_07413_amd/build.py")
+TRAFFIC_SUMMARY = "profiles/k_walk_n4k7_traffic.md"
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for p in WALK_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(walks: int, iters: int):
+    """HBM bytes per launch of the walk kernel from the committed FETCH_SIZE / WRITE_SIZE summary,
+    each counter scaled by what it reads for a plain copy of known size.  None when the summary is
+    missing, was taken for another launch shape, or the kernel sources changed since."""
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        fields = dict(re.findall(r"^- (\w+): (\S+)$", f.read(), re.M))
+    try:
+        if fields["source_sha256"] != kernel_source_digest():
+            return None
+        if int(fields["walks"]) != walks or int(fields["iters_per_launch"]) != iters:
+            return None
+        kib = (float(fields["fetch_kib_per_launch"]) * float(fields["fetch_scale"])
+               + float(fields["write_kib_per_launch"]) * float(fields["write_scale"]))
+    except (KeyError, ValueError):
+        return None
+    return kib * 1024.0
 
 
 def valu_ops_per_step(n: int, h: int) -> float:
@@ -303,7 +340,8 @@ def main():
         "config": {"workload": "n4k7", "n": n, "k": k, "chunk": chunk, "walks": args.walks, "delta": delta,
                    "log2_table": log2_table, "iters_per_launch": args.iters, "parallelism": "1 GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s", "frac": achieved / peak,
-                     "traffic": None, "kernel": "k_walk<4,8>", "kernel_ms": avg_ms,
+                     "traffic": measured_traffic(args.walks, args.iters), "traffic_unit": "HBM bytes per launch",
+                     "kernel": "k_walk<4,8>", "kernel_ms": avg_ms, "kernel_source_sha256": kernel_source_digest(),
                      "mfma_i8": {"achieved": mfma_achieved / 1e12, "peak": MFMA_I8_PEAK_OPS / 1e12, "unit": "Tops/s",
                                  "frac": mfma_achieved / MFMA_I8_PEAK_OPS}},
         "walk_stats": st.as_dict(),
