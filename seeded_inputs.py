@@ -141,3 +141,38 @@ def mlp_targets(seed_lo: int, seed_hi: int, n: int = 3, k_lo: int = 1, k_hi: int
         k = k_lo + uniform_below(s ^ 0x6B, 0, k_hi - k_lo + 1)
         out.append(target_words(n, k, s))
     return out
+
+
+# Named 3-qubit reversible gates (Sec. 6, benchmarking known circuits), from their textbook
+# definitions as permutations of the computational basis.  Qubit 0 is the leftmost Kronecker
+# factor, so a basis index is 4 q0 + 2 q1 + q2.  perm[i] is the image of basis state i.
+def _perm3(f):
+    out = []
+    for i in range(8):
+        q0, q1, q2 = (i >> 2) & 1, (i >> 1) & 1, i & 1
+        a, b, c = f(q0, q1, q2)
+        out.append(4 * a + 2 * b + c)
+    return out
+
+
+NAMED_GATES = {
+    # Toffoli: q2 ^= q0 q1
+    "toffoli": _perm3(lambda a, b, c: (a, b, c ^ (a & b))),
+    # Fredkin: controlled swap of q1 and q2, control q0
+    "fredkin": _perm3(lambda a, b, c: (a, c, b) if a else (a, b, c)),
+    # Peres: (a, b, c) -> (a, a ^ b, c ^ a b), a Toffoli followed by CNOT q0 -> q1
+    "peres": _perm3(lambda a, b, c: (a, a ^ b, c ^ (a & b))),
+}
+
+
+def permutation_unitary(perm):
+    """d x d x 4 int64 array of the permutation matrix U|i> = |perm[i]> over Z[omega]: entry
+    [r, c] = (c0, c1, c2, c3) for c0 + c1 w + c2 w^2 + c3 w^3; exponent 0."""
+    import numpy as np
+    d = len(perm)
+    if sorted(perm) != list(range(d)):
+        raise ValueError("not a permutation")
+    v = np.zeros((d, d, 4), dtype=np.int64)
+    for c, r in enumerate(perm):
+        v[r, c, 0] = 1
+    return v
