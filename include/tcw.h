@@ -69,6 +69,14 @@ int tcw_target_from_words(tcw_ctx* ctx, int n, const uint16_t* paulis, int k, co
                           int m, tcw_target** out);
 int tcw_target_from_channel(tcw_ctx* ctx, int n, const int32_t* a, const int32_t* b, int32_t e,
                             tcw_target** out);
+/* tcw_target_from_unitary: the target given as a unitary U = V / sqrt2^e (Sec. 4.1), V a d x d
+ * host array (d = 2^n, row-major) of elements of Z[w], w = e^{i pi/4}, each as four int64
+ * coefficients (c0, c1, c2, c3) = c0 + c1 w + c2 w^2 + c3 w^3, so v[(r d + c) 4 + j] = c_j of U's
+ * entry (r, c); qubit 0 is the most significant bit of a basis index.  The channel rep
+ * U_hat_ij = 2^-n Tr(P_i U P_j U^dag) (Sec. 4.1) is evaluated on the GPU entry by entry, exactly.
+ * TCW_EINVAL if n is not in 1..4, e < 0 or n + e > 29, a coefficient lies outside [-2^20, 2^20],
+ * or V V^dag != 2^e I; the input is copied. */
+int tcw_target_from_unitary(tcw_ctx* ctx, int n, const int64_t* v, int32_t e, tcw_target** out);
 int tcw_target_free(tcw_target* t);
 /* Copy the reduced exact channel rep to host arrays a, b (R*R each) and *e.  Blocking. */
 int tcw_target_channel(tcw_ctx* ctx, const tcw_target* t, int32_t* a, int32_t* b, int32_t* e);
@@ -223,6 +231,14 @@ int tcw_search_batch(tcw_ctx* ctx, const tcw_target* const* targets, int count, 
 int tcw_autotune(tcw_ctx* ctx, const tcw_target* t, int k, int chunk, int delta, uint64_t seed, int64_t* walks,
                  int* iters, int* log2_table, double* steps_per_s);
 
+/* tcw_min_tcount: minimal T-count of a target (n <= 3) by meet in the middle (Sec. 3, the split
+ * of the synthesis equation into two halves): every left-Clifford coset of T-count <= h_max
+ * reached from the identity is tabled by its matrix hash (keyed by seed), then every product U R(P_1)^T ... R(P_j)^T, j <= h_max, is looked up.  *t_out
+ * is the least i + j over matches, which is the T-count whenever that is at most 2 h_max, else -1
+ * (no decomposition with T-count <= 2 h_max exists).  A 64-bit hash collision could only lower the
+ * answer, never hide a match.  TCW_EOVERFLOW if U's entries do not fit int8 at its exponent.
+ * Blocking. */
+int tcw_min_tcount(tcw_ctx* ctx, const tcw_target* t, int h_max, uint64_t seed, int32_t* t_out);
 /* ---- learned depth order (the network that orders which depths k are searched first) ---------
  * Input: the target's canonical channel rep (rows sign-normalised by their first nonzero entry,
  * sorted lexicographically as integer sequences, minimal exponent e), entries

@@ -341,6 +341,52 @@ int tcw_target_from_channel(tcw_ctx* c, int n, const int32_t* a, const int32_t* 
     return TCW_OK;
 }
 
+int tcw_target_from_unitary(tcw_ctx* c, int n, const int64_t* v, int32_t e, tcw_target** out) {
+    if (!c || !out || !v) return TCW_EINVAL;
+    *out = nullptr;
+    if (n < 1 || n > 4) return fail(c, TCW_EINVAL, "n must be in 1..4");
+    if (e < 0 || n + e > 29) return fail(c, TCW_EINVAL, "need 0 <= e and n + e <= 29");
+    const size_t d = (size_t)1 << n, rr = (size_t)1 << (4 * n);
+    for (size_t x = 0; x < d * d * 4; ++x)
+        if (v[x] > (1 << 20) || v[x] < -(1 << 20)) return fail(c, TCW_EINVAL, "coefficients must lie in [-2^20, 2^20]");
+    tcw_target* t = new (std::nothrow) tcw_target();
+    if (!t) return TCW_ENOMEM;
+    t->ctx = c;
+    t->n = n;
+    int64_t* dv = nullptr;
+    int32_t *da = nullptr, *db = nullptr;
+    hipError_t err = tcw::exact_alloc(t->U, n);
+    if (err == hipSuccess) err = hipMalloc(&dv, d * d * 4 * sizeof(int64_t));
+    if (err == hipSuccess) err = hipMalloc(&da, rr * 4);
+    if (err == hipSuccess) err = hipMalloc(&db, rr * 4);
+    if (err == hipSuccess) err = hipMemcpyAsync(dv, v, d * d * 4 * sizeof(int64_t), hipMemcpyHostToDevice, c->stream);
+    if (err == hipSuccess) err = hipMemsetAsync(c->flag, 0, sizeof(int), c->stream);
+    if (err == hipSuccess) err = tcw::exact_from_unitary(t->U, dv, e, da, db, c->flag, c->stream);
+    int flag = 0;
+    int rc = TCW_OK;
+    // the orthogonality check only runs on values that passed the unitary and range checks
+    if (err == hipSuccess) rc = read_flag(c, &flag);
+    else rc = hip_fail(c, err, "unitary upload");
+    if (rc == TCW_OK && flag == 0) {
+        err = tcw::exact_check_orthogonal(t->U, c->flag, c->stream);
+        if (err == hipSuccess) rc = read_flag(c, &flag);
+        else rc = hip_fail(c, err, "orthogonality check");
+    }
+    if (dv) (void)hipFree(dv);
+    if (da) (void)hipFree(da);
+    if (db) (void)hipFree(db);
+    if (rc == TCW_OK && (flag & 8)) rc = fail(c, TCW_EINVAL, "U is not unitary (V V^dag != 2^e I)");
+    if (rc == TCW_OK && (flag & 1)) rc = fail(c, TCW_EINVAL, "channel rep is not real orthogonal");
+    if (rc == TCW_OK && (flag & 4)) rc = fail(c, TCW_EOVERFLOW, "channel rep entry out of range");
+    if (rc) {
+        tcw::exact_free(t->U);
+        delete t;
+        return rc;
+    }
+    *out = t;
+    return TCW_OK;
+}
+
 int tcw_target_free(tcw_target* t) {
     if (!t) return TCW_EINVAL;
     tcw::exact_free(t->U);
@@ -1681,23 +1727,71 @@ extern "C" int tcw_mlp_depth_order(tcw_mlp* m, const tcw_target* t, int k_max, i
     return TCW_OK;
 }
 
+namespace {
+
+// Hash table of every left-Clifford coset reached by <= h_max rotations from the identity, keyed by
+// matrix hash, value 255 - (least number of rotations); shared by the labelling and certificate calls.
+struct LevelTable {
+    uint64_t* table = nullptr;
+    uint64_t* keys = nullptr;
+    uint32_t* zero_phi = nullptr;
+    int lg = 0;
+    tcw::SpaceDev sp{};
+    ~LevelTable() {
+        for (void* q : {(void*)table, (void*)keys, (void*)zero_phi})
+            if (q) (void)hipFree(q);
+    }
+};
+
+int build_level_table(tcw_ctx* c, int n, int h_max, uint64_t seed, LevelTable& lt) {
+    const int R = 1 << (2 * n);
+    HIP_TRY(c, hipMalloc(&lt.zero_phi, (size_t)R * R / 2 * 4));
+    HIP_TRY(c, hipMemsetAsync(lt.zero_phi, 0, (size_t)R * R / 2 * 4, c->stream));
+    HIP_TRY(c, hipMalloc(&lt.keys, 2 * (size_t)R * 8));
+    HIP_TRY(c, tcw::keys_fill(n, seed, lt.keys, c->stream));
+    uint64_t entries = 0;
+    for (int h = 0; h <= h_max; ++h) entries += n_half_of(n, h);
+    lt.lg = 10;
+    while ((1ull << lt.lg) < 4 * entries && lt.lg < 30) ++lt.lg;
+    HIP_TRY(c, hipMalloc(&lt.table, ((size_t)1 << lt.lg) * 16));
+    HIP_TRY(c, tcw::launch_table_clear(lt.table, lt.lg, c->stream));
+    lt.sp.delta = 0;
+    lt.sp.salt_h = tcw::sm64(tcw::sm64(seed, 2), 0x4C4142454Cull);
+    lt.sp.keys = lt.keys;
+    lt.sp.phi = lt.zero_phi;
+    for (int h = 0; h <= h_max; ++h) {
+        lt.sp.h = h;
+        lt.sp.n_half = (uint32_t)n_half_of(n, h);
+        HIP_TRY(c, tcw::mitm_levels(n, lt.sp, h, lt.table, lt.lg, c->stream));
+    }
+    return TCW_OK;
+}
+
+int check_mitm_args(tcw_ctx* c, int n, int h_max) {
+    if (n < 1 || n > 3) return fail(c, TCW_EINVAL, "meet in the middle runs for n <= 3");
+    if (h_max < 0 || n_half_of(n, h_max) == 0) return fail(c, TCW_EINVAL, "h_max too large");
+    uint64_t entries = 0;
+    for (int h = 0; h <= h_max; ++h) entries += n_half_of(n, h);
+    if (entries > (1ull << 28)) return fail(c, TCW_EINVAL, "h_max too large for the level table");
+    return TCW_OK;
+}
+
+}  // namespace
+
 extern "C" int tcw_label_batch(tcw_ctx* c, int n, int count, const uint16_t* words, const int32_t* offsets,
                                const int32_t* kof, int h_max, uint64_t seed, float* features_dev, int32_t* labels_dev) {
     if (!c || !words || !offsets || !kof || !features_dev || !labels_dev || count < 1) return TCW_EINVAL;
-    if (n < 1 || n > 3) return fail(c, TCW_EINVAL, "labels are built for n <= 3");
-    if (h_max < 0 || n_half_of(n, h_max) == 0) return fail(c, TCW_EINVAL, "h_max too large");
+    int rc = check_mitm_args(c, n, h_max);
+    if (rc) return rc;
     const int R = 1 << (2 * n);
     const int64_t nw = offsets[count];
     uint16_t* dwords = nullptr;
     int32_t *doff = nullptr, *dk = nullptr, *rot = nullptr;
-    uint32_t *phi = nullptr, *zero_phi = nullptr;
-    uint64_t *keys = nullptr, *table = nullptr;
+    uint32_t* phi = nullptr;
     void* scratch = nullptr;
     const int chunk = 1024, blocks = 256;
-    int rc = TCW_OK;
     auto cleanup = [&]() {
-        for (void* q : {(void*)dwords, (void*)doff, (void*)dk, (void*)rot, (void*)phi, (void*)zero_phi, (void*)keys,
-                        (void*)table, scratch})
+        for (void* q : {(void*)dwords, (void*)doff, (void*)dk, (void*)rot, (void*)phi, scratch})
             if (q) (void)hipFree(q);
     };
 #define LB_TRY(expr)                         \
@@ -1716,29 +1810,9 @@ extern "C" int tcw_label_batch(tcw_ctx* c, int n, int count, const uint16_t* wor
     LB_TRY(hipMemcpyAsync(dk, kof, count * 4, hipMemcpyHostToDevice, c->stream));
     LB_TRY(hipMalloc(&rot, chunk * 4));
     LB_TRY(hipMalloc(&phi, (size_t)chunk * R * R / 2 * 4));
-    LB_TRY(hipMalloc(&zero_phi, (size_t)R * R / 2 * 4));
-    LB_TRY(hipMemsetAsync(zero_phi, 0, (size_t)R * R / 2 * 4, c->stream));
-    LB_TRY(hipMalloc(&keys, 2 * (size_t)R * 8));
-    LB_TRY(tcw::keys_fill(n, seed, keys, c->stream));
     LB_TRY(hipMalloc(&scratch, tcw::build_batch_scratch_bytes(n, blocks)));
-    // level table of every coset reached by <= h_max rotations from the identity
-    uint64_t entries = 0;
-    for (int h = 0; h <= h_max; ++h) entries += n_half_of(n, h);
-    int lg = 10;
-    while ((1ull << lg) < 4 * entries && lg < 30) ++lg;
-    LB_TRY(hipMalloc(&table, ((size_t)1 << lg) * 16));
-    LB_TRY(tcw::launch_table_clear(table, lg, c->stream));
-    tcw::SpaceDev sp{};
-    sp.delta = 0;
-    sp.salt_h = tcw::sm64(tcw::sm64(seed, 2), 0x4C4142454Cull);
-    sp.keys = keys;
-    sp.phi = zero_phi;
-    for (int h = 0; h <= h_max; ++h) {
-        sp.h = h;
-        sp.n_half = (uint32_t)n_half_of(n, h);
-        LB_TRY(tcw::mitm_levels(n, sp, h, table, lg, c->stream));
-    }
-    if ((rc = clear_flag(c))) {
+    LevelTable lt;
+    if ((rc = build_level_table(c, n, h_max, seed, lt)) || (rc = clear_flag(c))) {
         cleanup();
         return rc;
     }
@@ -1746,7 +1820,7 @@ extern "C" int tcw_label_batch(tcw_ctx* c, int n, int count, const uint16_t* wor
         const int cnt = std::min(chunk, count - first);
         LB_TRY(tcw::build_batch(n, dwords, doff + first, dk + first, cnt, scratch, blocks, phi, rot,
                                 features_dev + (size_t)first * R * R, c->flag, c->stream));
-        LB_TRY(tcw::mitm_probe(n, sp, phi, rot, cnt, h_max, table, lg, labels_dev + first, c->stream));
+        LB_TRY(tcw::mitm_probe(n, lt.sp, phi, rot, cnt, h_max, lt.table, lt.lg, labels_dev + first, c->stream));
     }
     int flag = 0;
     rc = read_flag(c, &flag);
@@ -1754,6 +1828,56 @@ extern "C" int tcw_label_batch(tcw_ctx* c, int n, int count, const uint16_t* wor
 #undef LB_TRY
     if (rc) return rc;
     if (flag) return fail(c, TCW_EOVERFLOW, "target outside the int8 / int32 range or word too long");
+    return TCW_OK;
+}
+
+extern "C" int tcw_min_tcount(tcw_ctx* c, const tcw_target* t, int h_max, uint64_t seed, int32_t* t_out) {
+    if (!c || !t || !t_out) return TCW_EINVAL;
+    int rc = check_mitm_args(c, t->n, h_max);
+    if (rc) return rc;
+    const int n = t->n;
+    const int R = 1 << (2 * n);
+    uint32_t* phi = nullptr;
+    int32_t* dev_i32 = nullptr;  // [0] rot_e, [1] result
+    auto cleanup = [&]() {
+        if (phi) (void)hipFree(phi);
+        if (dev_i32) (void)hipFree(dev_i32);
+    };
+    LevelTable lt;
+    int32_t e_u = 0;
+    int flag = 0;
+    hipError_t err = hipMalloc(&phi, (size_t)R * R / 2 * 4 + 16);
+    if (err == hipSuccess) err = hipMalloc(&dev_i32, 2 * sizeof(int32_t));
+    if (err == hipSuccess) err = hipMemsetAsync(c->flag, 0, sizeof(int), c->stream);
+    if (err == hipSuccess) err = tcw::exact_pack_phi(t->U, phi, c->flag, c->stream);
+    if (err == hipSuccess) err = hipMemcpyAsync(&e_u, t->U.e, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+    if (err != hipSuccess) {
+        cleanup();
+        return hip_fail(c, err, "target packing");
+    }
+    if ((rc = read_flag(c, &flag))) {
+        cleanup();
+        return rc;
+    }
+    if (flag) {
+        cleanup();
+        return fail(c, TCW_EOVERFLOW, "target entry outside the int8 range (exponent too large)");
+    }
+    const int32_t rot_e = (int32_t)((30ll * e_u) % 61);
+    err = hipMemcpyAsync(dev_i32, &rot_e, sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
+    if (err != hipSuccess) {
+        cleanup();
+        return hip_fail(c, err, "rot_e upload");
+    }
+    if ((rc = build_level_table(c, n, h_max, seed, lt))) {
+        cleanup();
+        return rc;
+    }
+    err = tcw::mitm_probe(n, lt.sp, phi, dev_i32, 1, h_max, lt.table, lt.lg, dev_i32 + 1, c->stream);
+    if (err == hipSuccess) err = hipMemcpyAsync(t_out, dev_i32 + 1, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
+    cleanup();
+    if (err != hipSuccess) return hip_fail(c, err, "meet-in-the-middle probe");
     return TCW_OK;
 }
 

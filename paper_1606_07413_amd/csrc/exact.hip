@@ -174,6 +174,108 @@ __global__ void k_orthogonal(const T* a, const T* b, const int32_t* e_p, int* fl
     if (rat != want || irr != 0) atomicOr(flag, 1);
 }
 
+// ---- channel rep of an exact unitary (Sec. 4.1: U_hat_ij = 2^-n Tr(P_i U P_j U^dag)) ----
+//
+// U = V / sqrt2^e with V over Z[w], w = e^{i pi/4}, each entry four int64 coefficients of
+// w^0..w^3 (w^4 = -1).  On the basis |c> (qubit 0 = most significant bit of c), the Pauli
+// P_q = (x) sigma(x_j, z_j), sigma(x, z) = i^{xz} X^x Z^z, acts as
+//   P_q |c> = i^{|x & z|} (-1)^{|z' & c|} |c ^ x'>,
+// with x', z' the bit-reversed masks (qubit j on bit n-1-j).  Hence
+//   Tr(P_i V P_j V^dag) = sum_{r,t} w^{k(r,t)} V[r ^ x_i'][t] conj(V[r][t ^ x_j'])
+// with k = 2|x_i & z_i| + 4|z_i' & (r ^ x_i')| + 2|x_j & z_j| + 4|z_j' & (t ^ x_j')| (mod 8).
+// The trace is real, t0 + t1 w + t2 w^2 + t3 w^3 with t2 = 0 and t3 = -t1, i.e. t0 + t1 sqrt2,
+// and U_hat_ij = (t0 + t1 sqrt2) / sqrt2^(2(n + e)).
+
+struct Zw {
+    int64_t c[4];
+};
+
+__device__ inline Zw zw_load(const int64_t* p) { return Zw{{p[0], p[1], p[2], p[3]}}; }
+
+__device__ inline Zw zw_mul_conj(const Zw& x, const Zw& y) {
+    // x * conj(y), conj(y) = y0 - y3 w - y2 w^2 - y1 w^3
+    const int64_t yc[4] = {y.c[0], -y.c[3], -y.c[2], -y.c[1]};
+    Zw r{{0, 0, 0, 0}};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t v = x.c[i] * yc[j];
+            if (i + j < 4) r.c[i + j] += v;
+            else r.c[i + j - 4] -= v;
+        }
+    return r;
+}
+
+// acc += w^k x, k in 0..7
+__device__ inline void zw_acc_rot(Zw& acc, const Zw& x, int k) {
+    const int64_t sg = k >= 4 ? -1 : 1;
+    const int kk = k & 3;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = i + kk;
+        if (j < 4) acc.c[j] += sg * x.c[i];
+        else acc.c[j - 4] -= sg * x.c[i];
+    }
+}
+
+template <int NQ>
+__device__ inline uint32_t bit_reverse_n(uint32_t v) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) r |= ((v >> j) & 1u) << (NQ - 1 - j);
+    return r;
+}
+
+// One thread per channel-rep entry (i, j).  flag |= 1 if an entry is not real, 4 if t0 or t1 leaves int32.
+template <int NQ>
+__global__ __launch_bounds__(256) void k_unitary_channel(const int64_t* v, int32_t* oa, int32_t* ob, int* flag) {
+    constexpr int D = 1 << NQ;
+    constexpr int R = D * D;
+    __shared__ int64_t sv[D * D * 4];
+    for (int x = threadIdx.x; x < D * D * 4; x += blockDim.x) sv[x] = v[x];
+    __syncthreads();
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= R * R) return;
+    const uint32_t i = (uint32_t)idx / R, j = (uint32_t)idx % R;
+    const uint32_t xi = i & (D - 1), zi = i >> NQ, xj = j & (D - 1), zj = j >> NQ;
+    const uint32_t xir = bit_reverse_n<NQ>(xi), zir = bit_reverse_n<NQ>(zi);
+    const uint32_t xjr = bit_reverse_n<NQ>(xj), zjr = bit_reverse_n<NQ>(zj);
+    const int k0 = 2 * __builtin_popcount(xi & zi) + 2 * __builtin_popcount(xj & zj);
+    Zw acc{{0, 0, 0, 0}};
+    for (uint32_t r = 0; r < (uint32_t)D; ++r) {
+        const uint32_t s = r ^ xir;
+        const int ks = k0 + 4 * __builtin_popcount(zir & s);
+        for (uint32_t t = 0; t < (uint32_t)D; ++t) {
+            const uint32_t u = t ^ xjr;
+            const int k = (ks + 4 * __builtin_popcount(zjr & u)) & 7;
+            const Zw prod = zw_mul_conj(zw_load(&sv[(s * D + t) * 4]), zw_load(&sv[(r * D + u) * 4]));
+            zw_acc_rot(acc, prod, k);
+        }
+    }
+    if (acc.c[2] != 0 || acc.c[3] != -acc.c[1]) atomicOr(flag, 1);
+    if (acc.c[0] > INT32_MAX || acc.c[0] < INT32_MIN || acc.c[1] > INT32_MAX || acc.c[1] < INT32_MIN)
+        atomicOr(flag, 4);
+    oa[idx] = (int32_t)acc.c[0];
+    ob[idx] = (int32_t)acc.c[1];
+}
+
+// V V^dag = 2^e I over Z[w], one thread per entry (r, c); flag |= 8 otherwise.
+template <int NQ>
+__global__ __launch_bounds__(256) void k_unitary_check(const int64_t* v, int32_t e, int* flag) {
+    constexpr int D = 1 << NQ;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= D * D) return;
+    const int r = idx / D, c = idx % D;
+    Zw acc{{0, 0, 0, 0}};
+    for (int t = 0; t < D; ++t) {
+        const Zw prod = zw_mul_conj(zw_load(&v[(r * D + t) * 4]), zw_load(&v[(c * D + t) * 4]));
+        zw_acc_rot(acc, prod, 0);
+    }
+    const int64_t want = r == c ? ((int64_t)1 << e) : 0;
+    if (acc.c[0] != want || acc.c[1] != 0 || acc.c[2] != 0 || acc.c[3] != 0) atomicOr(flag, 8);
+}
+
 // Signed permutation test on a reduced matrix: e = 0, B = 0, each column one +-1.
 template <int NQ, typename T>
 __global__ __launch_bounds__(256) void k_signed_perm(const T* a, const T* b, const int32_t* e_p, int32_t* ok,
@@ -551,6 +653,22 @@ hipError_t exact_from_i32(ExactDev& m, const int32_t* a, const int32_t* b, int32
         return hipGetLastError();
     };
     return dispatch_exact(m.n, f);
+}
+
+hipError_t exact_from_unitary(ExactDev& m, const int64_t* v, int32_t e, int32_t* a_tmp, int32_t* b_tmp, int* flag,
+                              hipStream_t s) {
+    const int n = m.n;
+    auto f = [&]<int NQ, typename T>() -> hipError_t {
+        constexpr int D = 1 << NQ;
+        constexpr int R = D * D;
+        hipLaunchKernelGGL((k_unitary_check<NQ>), dim3((D * D + 255) / 256), dim3(256), 0, s, v, e, flag);
+        hipLaunchKernelGGL((k_unitary_channel<NQ>), dim3((R * R + 255) / 256), dim3(256), 0, s, v, a_tmp, b_tmp,
+                           flag);
+        return hipGetLastError();
+    };
+    hipError_t err = dispatch_exact(n, f);
+    if (err != hipSuccess) return err;
+    return exact_from_i32(m, a_tmp, b_tmp, 2 * (n + e), flag, s);
 }
 
 hipError_t exact_to_i32(const ExactDev& m, int32_t* a, int32_t* b, int* flag, hipStream_t s) {

@@ -80,6 +80,11 @@ hipError_t exact_apply(ExactDev& dst, const ExactDev& src, const uint16_t* seq_d
 hipError_t exact_from_i32(ExactDev& m, const int32_t* a_dev, const int32_t* b_dev, int32_t e, int* flag_dev,
                           hipStream_t s);
 hipError_t exact_to_i32(const ExactDev& m, int32_t* a_dev, int32_t* b_dev, int* flag_dev, hipStream_t s);
+// m = channel rep of U = V / sqrt2^e (V: d x d entries of Z[w], 4 int64 coefficients each, device),
+// reduced.  a_tmp, b_tmp: R*R int32 each.  flag bits: 8 V V^dag != 2^e I, 1 an entry not real,
+// 4 an entry out of range.  Needs n + e <= 29 and |coefficients| <= 2^20 (checked by the caller).
+hipError_t exact_from_unitary(ExactDev& m, const int64_t* v_dev, int32_t e, int32_t* a_tmp, int32_t* b_tmp,
+                              int* flag_dev, hipStream_t s);
 // flag |= 1 if X X^T != 2^e I
 hipError_t exact_check_orthogonal(const ExactDev& m, int* flag_dev, hipStream_t s);
 // ok/perm/sign of a reduced matrix being a signed permutation

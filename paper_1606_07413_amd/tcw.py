@@ -72,6 +72,7 @@ _SIGS = {
                                         C.c_int, C.POINTER(_P)]),
     "tcw_target_from_channel": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
                                           C.POINTER(_P)]),
+    "tcw_target_from_unitary": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int64), C.c_int32, C.POINTER(_P)]),
     "tcw_target_free": (C.c_int, [_P]),
     "tcw_target_channel": (C.c_int, [_P, _P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "tcw_target_n": (C.c_int, [_P]),
@@ -102,6 +103,7 @@ _SIGS = {
     "tcw_features": (C.c_int, [_P, _P, _P]),
     "tcw_label_batch": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_uint16), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int32), C.c_int, C.c_uint64, _P, _P]),
+    "tcw_min_tcount": (C.c_int, [_P, _P, C.c_int, C.c_uint64, C.POINTER(C.c_int32)]),
     "tcw_mlp_create": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, _P, C.c_uint64, C.POINTER(_P)]),
     "tcw_mlp_free": (C.c_int, [_P]),
     "tcw_mlp_param_count": (C.c_int, [_P, C.POINTER(C.c_int64)]),
@@ -203,6 +205,23 @@ class Context:
         self._check(self.lib.tcw_target_from_channel(self.h, n, a.ctypes.data_as(C.POINTER(C.c_int32)),
                                                      b.ctypes.data_as(C.POINTER(C.c_int32)), int(e), C.byref(out)))
         return Target(self, out, n)
+
+    def target_from_unitary(self, n: int, v, e: int) -> "Target":
+        """U = V / sqrt2^e, V a 2^n x 2^n x 4 integer array (coefficients of w^0..w^3, w = e^{i pi/4})."""
+        import numpy as np
+        v = np.ascontiguousarray(v, dtype=np.int64)
+        if v.shape != (2 ** n, 2 ** n, 4):
+            raise ValueError("V must have shape (2^n, 2^n, 4)")
+        out = _P()
+        self._check(self.lib.tcw_target_from_unitary(self.h, n, v.ctypes.data_as(C.POINTER(C.c_int64)), int(e),
+                                                     C.byref(out)))
+        return Target(self, out, n)
+
+    def min_tcount(self, target, h_max: int, seed: int = 1) -> int:
+        """Minimal T-count by meet in the middle when it is at most 2 h_max, else -1."""
+        out = C.c_int32(0)
+        self._check(self.lib.tcw_min_tcount(self.h, target.h, h_max, seed, C.byref(out)))
+        return out.value
 
     # ---- parity entry points ----
     def step(self, target, k, chunk, seed, delta, pts_in, pts_out, hash_out=None, version=0):

@@ -143,7 +143,7 @@ def mlp_targets(seed_lo: int, seed_hi: int, n: int = 3, k_lo: int = 1, k_hi: int
     return out
 
 
-# Named 3-qubit reversible gates (Sec. 6, benchmarking known circuits), from their textbook
+# Named 3-qubit reversible gates (Sec. 5.2, benchmarking known circuits), from their textbook
 # definitions as permutations of the computational basis.  Qubit 0 is the leftmost Kronecker
 # factor, so a basis index is 4 q0 + 2 q1 + q2.  perm[i] is the image of basis state i.
 def _perm3(f):

@@ -1,0 +1,204 @@
+"""Named 3-qubit targets of Sec. 5.2 (Toffoli, Fredkin, Peres) through the C ABI: the channel
+rep of an exact unitary built on the GPU against the oracle, input validation, the
+meet-in-the-middle T-count certificate, and full searches that must find T-count 7 with a
+decomposition the oracle reconstructs exactly."""
+
+import numpy as np
+import pytest
+
+import seeded_inputs
+from oracle import bfs
+from oracle import search as osearch
+from oracle import unitary as ounitary
+from oracle import zmat
+from oracle.cyclotomic import CycMat, rotation
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1606_07413_amd import tcw
+    assert torch.cuda.is_available()
+    return tcw.Context(0)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def coeffs_of(m: CycMat):
+    v = np.zeros(m.shape + (4,), dtype=np.int64)
+    for a in range(4):
+        v[:, :, a] = np.array(m.c[a], dtype=np.int64)
+    return v
+
+
+def times_sqrt2(v):
+    """V sqrt2 = V (w - w^3), coefficient-wise on w^0..w^3 with w^4 = -1."""
+    out = np.zeros_like(v)
+    # (c0 + c1 w + c2 w^2 + c3 w^3)(w - w^3)
+    out[..., 0] = v[..., 1] - v[..., 3]
+    out[..., 1] = v[..., 0] + v[..., 2]
+    out[..., 2] = v[..., 1] + v[..., 3]
+    out[..., 3] = v[..., 2] - v[..., 0]
+    return out
+
+
+def word_unitary(n, paulis, clifford):
+    """U = D R(P_k) ... R(P_1) as an exact matrix (the oracle's literal products), as V / sqrt2^e
+    with e minimal (divide by sqrt2 while V sqrt2 / 2 stays integral)."""
+    def halve(m):
+        while m.d > 0 and all(not (x % 2).any() for x in m.c):
+            m = CycMat([x // 2 for x in m.c], m.d - 1)
+        return m
+
+    u = CycMat.identity(n)
+    for c in clifford:
+        u = halve(u @ rotation(c, n) @ rotation(c, n))
+    for p in reversed(paulis):
+        u = halve(u @ rotation(p, n))
+    v, e = coeffs_of(u), 2 * u.d
+    while e > 0 and not (times_sqrt2(v) % 2).any():
+        v, e = times_sqrt2(v) // 2, e - 1
+    return v, e
+
+
+def assert_channel(tgt, m: zmat.ZMat):
+    a, b, e = tgt.channel()
+    assert e == m.e
+    assert np.array_equal(a, np.array(m.A, dtype=np.int64)) and np.array_equal(b, np.array(m.B, dtype=np.int64))
+
+
+def named_v(name):
+    return seeded_inputs.permutation_unitary(seeded_inputs.NAMED_GATES[name])
+
+
+@pytest.mark.parametrize("name", ["toffoli", "fredkin", "peres"])
+def test_named_channel_matches_oracle(ctx, name):
+    say("named channel", name)
+    v = named_v(name)
+    assert_channel(ctx.target_from_unitary(3, v, 0), ounitary.channel_of_unitary(3, v, 0))
+
+
+@pytest.mark.parametrize("n,k,seed,clen", [(1, 5, 1, 4), (2, 4, 2, 6), (3, 3, 3, 6), (4, 3, 4, 4)])
+def test_word_unitary_matches_oracle(ctx, n, k, seed, clen):
+    say("word unitary", n, k, seed)
+    tw = seeded_inputs.target_words(n, k, seed, clifford_len=clen)
+    v, e = word_unitary(n, tw.paulis, tw.clifford)
+    want = zmat.target_from_words(n, tw.paulis, tw.clifford)
+    assert_channel(ctx.target_from_unitary(n, v, e), want)
+
+
+def test_odd_exponent_hadamards(ctx):
+    say("odd exponent")
+    h = np.array([[1, 1], [1, -1]], dtype=np.int64)
+    for n, pos in [(1, 0), (4, 0), (4, 3)]:
+        m = np.array([[1]], dtype=np.int64)
+        for j in range(n):
+            m = np.kron(m, h if j == pos else np.eye(2, dtype=np.int64))
+        v = np.zeros(m.shape + (4,), dtype=np.int64)
+        v[:, :, 0] = m
+        got = ctx.target_from_unitary(n, v, 1)
+        if n == 1:
+            assert_channel(got, ounitary.channel_of_unitary(1, v, 1))
+        else:
+            # a Clifford: reduced exponent 0, a signed permutation that fixes every Pauli with
+            # identity on the Hadamard's qubit and swaps X <-> Z there
+            a, b, e = got.channel()
+            assert e == 0 and not b.any()
+            assert np.array_equal(np.abs(a) @ np.abs(a).T, np.eye(256, dtype=np.int64))
+            bit = 1 << pos
+            for q in range(256):
+                x, z = q & 15, q >> 4
+                xq, zq = (x >> pos) & 1, (z >> pos) & 1
+                x2 = (x & ~bit) | (zq << pos)
+                z2 = (z & ~bit) | (xq << pos)
+                col = a[:, q]
+                assert col[x2 | (z2 << 4)] == (-1 if (xq and zq) else 1)
+
+
+def test_from_unitary_validates(ctx):
+    from paper_1606_07413_amd import tcw
+    say("unitary validation")
+    v = named_v("toffoli")
+    bad = v.copy()
+    bad[0, 1, 0] = 1                       # two ones in row 0: not unitary
+    with pytest.raises(tcw.TcwError):
+        ctx.target_from_unitary(3, bad, 0)
+    with pytest.raises(tcw.TcwError):
+        ctx.target_from_unitary(3, v, 1)   # V V^dag = I != 2 I
+    big = v.copy()
+    big[0, 0, 1] = 1 << 21
+    with pytest.raises(tcw.TcwError):
+        ctx.target_from_unitary(3, big, 0)
+    with pytest.raises(tcw.TcwError):
+        ctx.target_from_unitary(3, v, 27)  # n + e > 29
+    # the context still works after the errors
+    assert_channel(ctx.target_from_unitary(3, v, 0), ounitary.channel_of_unitary(3, v, 0))
+
+
+def test_min_tcount_matches_bfs_n1(ctx):
+    say("min tcount n1")
+    _, seen, _ = bfs.cosets_by_tcount(1, 6)
+    for seed in range(24):
+        k = 1 + seed % 8
+        tw = seeded_inputs.target_words(1, k, 700 + seed)
+        u = zmat.target_from_words(1, tw.paulis, tw.clifford)
+        tgt = ctx.target_from_words(1, tw.paulis, tw.clifford)
+        t = bfs.min_tcount(u, seen)
+        assert ctx.min_tcount(tgt, 3) == (t if t is not None else -1)
+
+
+def test_min_tcount_n2_matches_bfs(ctx):
+    say("min tcount n2")
+    _, seen, _ = bfs.cosets_by_tcount(2, 3)
+    for seed in range(12):
+        k = 1 + seed % 3
+        tw = seeded_inputs.target_words(2, k, 800 + seed)
+        u = zmat.target_from_words(2, tw.paulis, tw.clifford)
+        tgt = ctx.target_from_words(2, tw.paulis, tw.clifford)
+        assert ctx.min_tcount(tgt, 2) == bfs.min_tcount(u, seen)
+
+
+def test_named_tcount_exceeds_six(ctx):
+    """No decomposition of T-count <= 6 exists for the three named gates (meet in the middle over
+    every coset of T-count <= 3 on each side), while a T-count-3 word is found at 3."""
+    say("named certificate")
+    for name in ("toffoli", "fredkin", "peres"):
+        assert ctx.min_tcount(ctx.target_from_unitary(3, named_v(name), 0), 3) == -1, name
+    tw = seeded_inputs.target_words(3, 3, 5)
+    v, e = word_unitary(3, tw.paulis, tw.clifford)
+    t3 = ctx.min_tcount(ctx.target_from_unitary(3, v, e), 3)
+    assert 0 <= t3 <= 3
+    assert t3 == ctx.min_tcount(ctx.target_from_words(3, tw.paulis, tw.clifford), 3)
+
+
+def _search_named(ctx, name, delta, seed):
+    from paper_1606_07413_amd import tcw
+    v = named_v(name)
+    tgt = ctx.target_from_unitary(3, v, 0)
+    p = ctx.default_params(3)
+    p.k_max = 7
+    p.delta = delta
+    p.seed = seed
+    p.max_seconds = 100
+    res = ctx.search(tgt, p)
+    dec = tcw.decomposition_of(res)
+    say(name, "delta", delta, "status", res.status, "t", res.t, "chunk", res.chunk, "seconds", round(res.seconds, 3),
+        "steps", res.stats.steps, "versions", res.versions)
+    assert dec is not None and dec.t == 7
+    d = osearch.Decomposition(t=dec.t, paulis_desc=dec.paulis_desc, perm=dec.perm, sign=dec.sign)
+    assert osearch.reconstruct(3, d).equals(ounitary.channel_of_unitary(3, v, 0))
+    return res
+
+
+@pytest.mark.parametrize("name", ["toffoli", "fredkin", "peres"])
+def test_named_search_finds_tcount_7(ctx, name):
+    # theta = 1/2 as in the paper's runs on these circuits
+    _search_named(ctx, name, 1, 11)
+
+
+def test_toffoli_search_default_theta(ctx):
+    _search_named(ctx, "toffoli", 8, 12)

@@ -1,5 +1,5 @@
 """Pins of the oracle's unitary -> channel rep route (Sec. 4.1 trace formula) and of the named
-3-qubit gates of Sec. 6, against closed forms and textbook identities."""
+3-qubit gates of Sec. 5.2 (benchmarking known circuits), against closed forms and textbook identities."""
 
 import numpy as np
 import pytest
