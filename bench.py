@@ -152,6 +152,54 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# Sec. 5.2, Table 1: mean synthesis time of the T-count-7 three-qubit gates over 100 trials on
+# 4096 Blue Gene/Q cores with half of the points distinguished (another machine: context only).
+PAPER_TABLE1_SECONDS = {"toffoli": 25.9870, "fredkin": 25.0031, "peres": 25.4931}
+
+
+def named_leg(ctx, reps: int, reps_default_theta: int):
+    """Optimal T-count synthesis of the named gates: the whole depth loop k = 0..7 (chunks in
+    ascending order at odd k) until a verified decomposition, repeated over walk seeds; plus the
+    meet-in-the-middle certificate that no decomposition of T-count <= 6 exists."""
+    import statistics
+
+    import seeded_inputs
+    from paper_1606_07413_amd import tcw
+    out = {}
+    for name in ("toffoli", "fredkin", "peres"):
+        v = seeded_inputs.permutation_unitary(seeded_inputs.NAMED_GATES[name])
+        tgt = ctx.target_from_unitary(3, v, 0)
+        t0 = time.perf_counter()
+        cert = ctx.min_tcount(tgt, 3)
+        cert_s = time.perf_counter() - t0
+        entry = {"certificate_tcount_gt_6": cert == -1, "certificate_seconds": cert_s}
+        for label, delta, cpar, count in (("theta_2^-1", 1, 1, reps), ("theta_2^-1_all_chunks", 1, 0, reps),
+                                          ("theta_2^-8", 8, 1, reps_default_theta)):
+            secs, steps, ts = [], [], []
+            for r in range(count):
+                p = ctx.default_params(3)
+                p.k_max = 7
+                p.delta = delta
+                p.seed = 5000 + 97 * r
+                p.chunk_parallel = cpar
+                p.max_seconds = 120
+                res = ctx.search(tgt, p)
+                dec = tcw.decomposition_of(res)
+                ts.append(dec.t if dec else None)
+                secs.append(res.seconds)
+                steps.append(res.stats.steps)
+            print(f"named {name} {label}: t={ts[0]} mean {statistics.mean(secs):.3f} s over {count}",
+                  file=sys.stderr, flush=True)
+            entry[label] = {
+                "reps": count, "found_t": sorted(set(t for t in ts if t is not None)),
+                "not_found": sum(1 for t in ts if t is None),
+                "mean_s": statistics.mean(secs), "std_s": statistics.stdev(secs) if count > 1 else 0.0,
+                "mean_steps": statistics.mean(steps)}
+        entry["paper_mean_s_4096_bgq_cores"] = PAPER_TABLE1_SECONDS[name]
+        out[name] = entry
+    return out
+
+
 def mlp_leg(ctx, train_count: int, epochs: int, eval_count: int, cap: float):
     """Learned depth order at n = 3: train on seeded circuits (k uniform in 1..10) labelled by exact
     meet-in-the-middle search, then search held-out targets with the plain and the learned order."""
@@ -252,6 +300,10 @@ def main():
     ap.add_argument("--batch-cap", type=float, default=30.0, help="per-target wall-clock cap (s)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration for profiles)")
+    ap.add_argument("--named", action="store_true",
+                    help="also synthesise Toffoli, Fredkin and Peres (n = 3, T-count 7) repeatedly")
+    ap.add_argument("--named-reps", type=int, default=20)
+    ap.add_argument("--named-reps-default-theta", type=int, default=3)
     ap.add_argument("--mlp", action="store_true", help="also train the depth-order network and compare orders")
     ap.add_argument("--mlp-train", type=int, default=1 << 16, help="training circuits")
     ap.add_argument("--mlp-epochs", type=int, default=8)
@@ -316,6 +368,28 @@ def main():
         r3 = ctx.search(t3, p3)
         extra["tts_n3k6"] = {"seconds": r3.seconds, "found_t": r3.t if r3.status else None,
                              "steps": r3.stats.steps, "versions": r3.versions, "measured": True}
+        # n = 4: the whole optimal-T-count search (depths 0..7, every chunk of an odd depth searched
+        # concurrently) at theta = 1/2, the paper's choice when the table holds the whole space
+        # (2^27 slots >> N = 3.3e7 per chunk), for the four seeded n = 4, k = 7 targets
+        runs = []
+        for ts in range(1, 5):
+            twn = seeded_inputs.target_words(4, 7, ts)
+            tn = ctx.target_from_words(4, twn.paulis, twn.clifford)
+            p4 = ctx.default_params(4)
+            p4.k_max = 7
+            p4.delta = 1
+            p4.log2_table = 27
+            p4.seed = 3100 + ts
+            p4.chunk_parallel = 0
+            p4.max_seconds = 150
+            r4 = ctx.search(tn, p4)
+            runs.append({"target_seed": ts, "seconds": r4.seconds, "found_t": r4.t if r4.status else None,
+                         "chunk": r4.chunk if r4.status else None, "steps": r4.stats.steps,
+                         "spaces": r4.spaces, "versions": r4.versions})
+            print(f"tts n4k7 target {ts}: t={runs[-1]['found_t']} in {r4.seconds:.2f} s", file=sys.stderr,
+                  flush=True)
+            tn.free()
+        extra["tts_n4k7_theta_half"] = {"measured": True, "theta": 0.5, "chunk_parallel": "all", "runs": runs}
         n_pts = 2 * 255 ** 3
         steps_chunk = n_pts * (1 << delta)          # Appendix: about N / theta steps for the chunk with the claw
         budget = 16 * steps_chunk                   # each earlier chunk fails after its full budget
@@ -349,6 +423,8 @@ def main():
     out.update(extra)
     if args.batch:
         out["batch64"] = batch_leg(ctx, args.batch_cap)
+    if args.named:
+        out["named_n3_t7"] = named_leg(ctx, args.named_reps, args.named_reps_default_theta)
     if args.mlp:
         out["learned_order"] = mlp_leg(ctx, args.mlp_train, args.mlp_epochs, args.mlp_eval, args.mlp_cap)
     if not args.no_cpu_baseline:

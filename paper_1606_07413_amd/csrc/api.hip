@@ -676,6 +676,7 @@ void tcw_default_params(tcw_walk_params* p, int n) {
     p->chunk_first = 0;
     p->chunk_last = 0;
     p->max_seconds = 0.0;
+    p->chunk_parallel = 1;
 }
 
 }  // extern "C"
@@ -881,11 +882,19 @@ int search_enum(tcw_ctx* c, const tcw_target* t, const tcw_walk_params* p, int k
     return TCW_OK;
 }
 
-uint64_t version_steps(const tcw_walk_params* p, uint64_t npts, int delta, int64_t walks) {
+// Steps per function version: max(factor * N, 2 walks / theta), but no more than the table holds
+// at half load (slots / 2 distinguished points, i.e. slots / (2 theta) steps).
+uint64_t version_steps(const tcw_walk_params* p, uint64_t npts, int delta, int64_t walks, int log2_table) {
     uint64_t per_version = (uint64_t)p->version_factor * npts;
     const uint64_t floor_v = 2ull * (uint64_t)walks << delta;
-    return per_version < floor_v ? floor_v : per_version;
+    if (per_version < floor_v) per_version = floor_v;
+    const uint64_t table_v = (1ull << (log2_table - 1)) << delta;
+    return per_version < table_v ? per_version : table_v;
 }
+
+struct BatchTarget;
+int search_chunks_concurrent(tcw_ctx* c, const tcw_target* t, const tcw_walk_params* p, int k, int c_first,
+                             int c_last, int delta, tcw_result* res, int* found, double t0);
 
 }  // namespace
 
@@ -924,7 +933,16 @@ extern "C" int tcw_search(tcw_ctx* c, const tcw_target* t, const tcw_walk_params
         }
         const bool enumerate = (int64_t)npts <= p->enum_max;
         const int delta = p->delta >= 0 ? p->delta : default_delta(n);
-        for (int chunk = cf; chunk <= cl && !found; ++chunk) {
+        if (k % 2 && !enumerate && p->chunk_parallel != 1) {
+            // chunks in groups of G searched concurrently, one batch member each
+            const int G = p->chunk_parallel <= 0 ? cl - cf + 1 : p->chunk_parallel;
+            for (int first = cf; first <= cl && !found; first += G) {
+                if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) break;
+                rc = search_chunks_concurrent(c, t, p, k, first, std::min(cl, first + G - 1), delta, res, &found, t0);
+                if (rc) return rc;
+            }
+        }
+        for (int chunk = cf; chunk <= cl && !found && (k % 2 == 0 || enumerate || p->chunk_parallel == 1); ++chunk) {
             if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) break;
             if (enumerate) {
                 if ((rc = search_enum(c, t, p, k, chunk, iters, res, &found, t0))) return rc;
@@ -933,7 +951,7 @@ extern "C" int tcw_search(tcw_ctx* c, const tcw_target* t, const tcw_walk_params
             tcw_space sp{k, chunk, p->seed, p->version, delta};
             res->spaces++;
             const uint64_t budget = (uint64_t)p->budget_beta * npts << delta;
-            const uint64_t per_version = version_steps(p, npts, delta, p->walks);
+            const uint64_t per_version = version_steps(p, npts, delta, p->walks, p->log2_table);
             const uint32_t cap = (uint32_t)p->trail_cap_factor << delta;
             // a launch must not overrun a function version
             int iters_v = iters;
@@ -1171,7 +1189,7 @@ int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStr
         b.res->versions++;
         b.version = b.p.version;
         b.budget = (uint64_t)b.p.budget_beta * npts << delta;
-        b.per_version = version_steps(&b.p, npts, delta, b.walks);
+        b.per_version = version_steps(&b.p, npts, delta, b.walks, b.log2);
         const uint64_t fit = b.per_version / (uint64_t)b.walks;
         if ((uint64_t)b.iters > fit) b.iters = fit > 0 ? (int)fit : 1;
         b.used = b.used_v = 0;
@@ -1224,12 +1242,28 @@ extern "C" int tcw_autotune(tcw_ctx* c, const tcw_target* t, int k, int chunk, i
     return TCW_OK;
 }
 
-extern "C" int tcw_search_batch(tcw_ctx* c, const tcw_target* const* targets, int count, const tcw_walk_params* params,
-                                tcw_result* results, double* aggregate_steps_per_s) {
-    if (!c || !targets || !params || !results || count < 1) return TCW_EINVAL;
-    for (int i = 0; i < count; ++i)
-        if (!targets[i]) return fail(c, TCW_EINVAL, "NULL target in batch");
-    const double t0 = now_s();
+namespace {
+
+tcw_walk_stats stats_of(const unsigned long long* st) {
+    tcw_walk_stats ws{};
+    ws.steps = (int64_t)st[tcw::ST_STEPS];
+    ws.dps = (int64_t)st[tcw::ST_DPS];
+    ws.inserts = (int64_t)st[tcw::ST_INSERTS];
+    ws.abandoned = (int64_t)st[tcw::ST_ABANDONED];
+    ws.robin_hood = (int64_t)st[tcw::ST_ROBIN];
+    ws.same_side = (int64_t)st[tcw::ST_SAME];
+    ws.reduction = (int64_t)st[tcw::ST_REDUCTION];
+    ws.claws = (int64_t)st[tcw::ST_CLAWS];
+    ws.table_full = (int64_t)st[tcw::ST_FULL];
+    ws.spin_timeouts = (int64_t)st[tcw::ST_SPIN];
+    return ws;
+}
+
+// Runs every member search of bt (each with its own depth order, chunk range, walks and table)
+// in graph-captured rounds until all are done, or, with stop_on_first, until one member holds a
+// verified decomposition.  *agg: walk steps per second of walk-kernel time.
+int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, double t0, double* agg) {
+    const int count = (int)bt.size();
     BatchBuffers bb;
     HIP_TRY(c, hipMalloc(&bb.stats, (size_t)count * tcw::ST_COUNT * 8));
     HIP_TRY(c, hipMalloc(&bb.claw_count, (size_t)count * 8));
@@ -1240,18 +1274,7 @@ extern "C" int tcw_search_batch(tcw_ctx* c, const tcw_target* const* targets, in
     HIP_TRY(c, hipMalloc(&bb.tgt_blocks, (size_t)count * 4));
     HIP_TRY(c, hipMemsetAsync(bb.stats, 0, (size_t)count * tcw::ST_COUNT * 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(bb.claw_count, 0, (size_t)count * 8, c->stream));
-    std::vector<BatchTarget> bt(count);
     int rc = TCW_OK;
-    for (int i = 0; i < count && !rc; ++i) {
-        BatchTarget& b = bt[i];
-        b.t = targets[i];
-        b.p = params[i];
-        b.res = &results[i];
-        std::memset(b.res, 0, sizeof(tcw_result));
-        b.res->n = b.t->n;
-        rc = depth_order_of(c, &b.p, b.order);
-    }
-    if (rc) return rc;
     for (int i = 0; i < count && !rc; ++i) {
         rc = batch_advance(c, bt[i], i, bb, c->stream, t0);
         if (bt[i].done) bt[i].res->seconds = now_s() - t0;
@@ -1298,6 +1321,7 @@ extern "C" int tcw_search_batch(tcw_ctx* c, const tcw_target* const* targets, in
             return hip_fail(c, _e, #expr);   \
         }                                    \
     } while (0)
+    bool stop = false;
     for (;;) {
         bool any = false;
         for (auto& b : bt) any |= b.walking;
@@ -1391,17 +1415,7 @@ extern "C" int tcw_search_batch(tcw_ctx* c, const tcw_target* const* targets, in
                 }
                 b.seen = avail;
             }
-            tcw_walk_stats ws{};
-            ws.steps = (int64_t)st[tcw::ST_STEPS];
-            ws.dps = (int64_t)st[tcw::ST_DPS];
-            ws.inserts = (int64_t)st[tcw::ST_INSERTS];
-            ws.abandoned = (int64_t)st[tcw::ST_ABANDONED];
-            ws.robin_hood = (int64_t)st[tcw::ST_ROBIN];
-            ws.same_side = (int64_t)st[tcw::ST_SAME];
-            ws.reduction = (int64_t)st[tcw::ST_REDUCTION];
-            ws.claws = (int64_t)st[tcw::ST_CLAWS];
-            ws.table_full = (int64_t)st[tcw::ST_FULL];
-            ws.spin_timeouts = (int64_t)st[tcw::ST_SPIN];
+            const tcw_walk_stats ws = stats_of(st);
             const bool over_time = b.p.max_seconds > 0 && now_s() - t0 > b.p.max_seconds;
             if (found || over_time || b.used >= b.budget) {
                 add_stats(b.res->stats, ws);
@@ -1432,15 +1446,107 @@ extern "C" int tcw_search_batch(tcw_ctx* c, const tcw_target* const* targets, in
                     return rc;
                 }
             }
+            if (stop_on_first && b.res->status == 1) stop = true;
         }
         BATCH_TRY(hipStreamSynchronize(gs[0]));
+        if (stop) {
+            // one member found a verified decomposition: end the others with their counts so far
+            for (int i = 0; i < count; ++i) {
+                BatchTarget& b = bt[i];
+                if (!b.walking) continue;
+                add_stats(b.res->stats, stats_of(&stats[(size_t)i * tcw::ST_COUNT]));
+                b.walking = false;
+                b.done = true;
+                b.res->seconds = now_s() - t0;
+            }
+            break;
+        }
     }
 #undef BATCH_TRY
     cleanup();
     for (auto& b : bt)
         if (b.res->seconds == 0) b.res->seconds = now_s() - t0;
-    if (aggregate_steps_per_s) *aggregate_steps_per_s = walk_seconds > 0 ? (double)total_steps / walk_seconds : 0.0;
+    if (agg) *agg = walk_seconds > 0 ? (double)total_steps / walk_seconds : 0.0;
     return TCW_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Total bytes of distinguished-point tables a concurrent chunk group may hold (2^35 = 32 GiB).
+constexpr int CHUNK_TABLE_POOL_LOG2 = 35;
+
+int search_chunks_concurrent(tcw_ctx* c, const tcw_target* t, const tcw_walk_params* p, int k, int c_first,
+                             int c_last, int delta, tcw_result* res, int* found, double t0) {
+    const int n = t->n;
+    const int G = c_last - c_first + 1;
+    int lg_g = 0;
+    while ((1 << lg_g) < G) ++lg_g;
+    const int64_t walks_c = std::max<int64_t>(64, p->walks / G);
+    const int log2_c = std::max(10, std::min(p->log2_table, CHUNK_TABLE_POOL_LOG2 - 4 - lg_g));
+    const int iters = p->iters_per_launch > 0 ? p->iters_per_launch : default_iters(n);
+    std::vector<BatchTarget> bt(G);
+    std::vector<tcw_result> rs(G);
+    for (int i = 0; i < G; ++i) {
+        BatchTarget& b = bt[i];
+        b.t = t;
+        b.p = *p;
+        b.p.walks = walks_c;
+        b.p.log2_table = log2_c;
+        b.p.iters_per_launch = iters;
+        b.p.delta = delta;
+        b.p.chunk_first = b.p.chunk_last = c_first + i;
+        b.order.assign(1, k);
+        std::memset(&rs[i], 0, sizeof(tcw_result));
+        rs[i].n = n;
+        b.res = &rs[i];
+    }
+    const int rc = batch_run(c, bt, true, t0, nullptr);
+    if (rc) return rc;
+    int64_t launches = 0;
+    for (int i = 0; i < G; ++i) {
+        const tcw_result& r = rs[i];
+        add_stats(res->stats, r.stats);
+        res->spaces += r.spaces;
+        res->versions += r.versions;
+        res->false_claws += r.false_claws;
+        launches = std::max(launches, r.launches);
+        if (r.status == 1 && !*found) {
+            *found = 1;
+            res->status = 1;
+            res->t = r.t;
+            res->chunk = r.chunk;
+            std::memcpy(res->paulis, r.paulis, sizeof(res->paulis));
+            std::memcpy(res->clifford_perm, r.clifford_perm, sizeof(res->clifford_perm));
+            std::memcpy(res->clifford_sign, r.clifford_sign, sizeof(res->clifford_sign));
+        }
+    }
+    res->launches += launches;
+    return TCW_OK;
+}
+
+}  // namespace
+
+extern "C" int tcw_search_batch(tcw_ctx* c, const tcw_target* const* targets, int count, const tcw_walk_params* params,
+                                tcw_result* results, double* aggregate_steps_per_s) {
+    if (!c || !targets || !params || !results || count < 1) return TCW_EINVAL;
+    for (int i = 0; i < count; ++i)
+        if (!targets[i]) return fail(c, TCW_EINVAL, "NULL target in batch");
+    const double t0 = now_s();
+    std::vector<BatchTarget> bt(count);
+    int rc = TCW_OK;
+    for (int i = 0; i < count && !rc; ++i) {
+        BatchTarget& b = bt[i];
+        b.t = targets[i];
+        b.p = params[i];
+        b.res = &results[i];
+        std::memset(b.res, 0, sizeof(tcw_result));
+        b.res->n = b.t->n;
+        rc = depth_order_of(c, &b.p, b.order);
+    }
+    if (rc) return rc;
+    return batch_run(c, bt, false, t0, aggregate_steps_per_s);
 }
 
 // ---------------------------------------------------------------------------------------------

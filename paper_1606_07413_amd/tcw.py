@@ -49,7 +49,7 @@ class WalkParams(C.Structure):
         ("budget_beta", C.c_int32), ("version_factor", C.c_int32), ("enum_max", C.c_int64),
         ("iters_per_launch", C.c_int32), ("depth_order_kind", C.c_int32), ("depth_order_len", C.c_int32),
         ("depth_order", C.c_int32 * 16), ("chunk_first", C.c_int32), ("chunk_last", C.c_int32),
-        ("max_seconds", C.c_double),
+        ("max_seconds", C.c_double), ("chunk_parallel", C.c_int32),
     ]
 
 

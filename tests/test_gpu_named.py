@@ -175,7 +175,7 @@ def test_named_tcount_exceeds_six(ctx):
     assert t3 == ctx.min_tcount(ctx.target_from_words(3, tw.paulis, tw.clifford), 3)
 
 
-def _search_named(ctx, name, delta, seed):
+def _search_named(ctx, name, delta, seed, chunk_parallel=1):
     from paper_1606_07413_amd import tcw
     v = named_v(name)
     tgt = ctx.target_from_unitary(3, v, 0)
@@ -184,9 +184,10 @@ def _search_named(ctx, name, delta, seed):
     p.delta = delta
     p.seed = seed
     p.max_seconds = 100
+    p.chunk_parallel = chunk_parallel
     res = ctx.search(tgt, p)
     dec = tcw.decomposition_of(res)
-    say(name, "delta", delta, "status", res.status, "t", res.t, "chunk", res.chunk, "seconds", round(res.seconds, 3),
+    say(name, "delta", delta, "chunk_parallel", chunk_parallel, "status", res.status, "t", res.t, "chunk", res.chunk, "seconds", round(res.seconds, 3),
         "steps", res.stats.steps, "versions", res.versions)
     assert dec is not None and dec.t == 7
     d = osearch.Decomposition(t=dec.t, paulis_desc=dec.paulis_desc, perm=dec.perm, sign=dec.sign)
@@ -202,3 +203,36 @@ def test_named_search_finds_tcount_7(ctx, name):
 
 def test_toffoli_search_default_theta(ctx):
     _search_named(ctx, "toffoli", 8, 12)
+
+
+@pytest.mark.parametrize("name,group", [("toffoli", 0), ("fredkin", 0), ("peres", 16)])
+def test_named_search_concurrent_chunks(ctx, name, group):
+    """Odd-depth chunks searched concurrently (all 63, or groups of 16) give the same T-count and
+    an exact decomposition."""
+    _search_named(ctx, name, 1, 21, chunk_parallel=group)
+
+
+def test_n4k7_all_chunks_concurrent(ctx):
+    """n = 4, k = 7: all 255 chunks concurrently at theta = 1/2 find a verified decomposition of the
+    seeded target (depth 7 only)."""
+    from paper_1606_07413_amd import tcw
+    say("n4k7 concurrent chunks")
+    tw = seeded_inputs.target_words(4, 7, 1)
+    tgt = ctx.target_from_words(4, tw.paulis, tw.clifford)
+    p = ctx.default_params(4)
+    p.k_max = 7
+    p.depth_order_kind = 1
+    p.depth_order_len = 1
+    p.depth_order[0] = 7
+    p.delta = 1
+    p.log2_table = 27
+    p.seed = 31
+    p.chunk_parallel = 0
+    p.max_seconds = 100
+    res = ctx.search(tgt, p)
+    dec = tcw.decomposition_of(res)
+    say("n4k7 concurrent: status", res.status, "chunk", res.chunk, "seconds", round(res.seconds, 3), "steps",
+        res.stats.steps, "spaces", res.spaces, "versions", res.versions)
+    assert dec is not None and dec.t == 7 and res.spaces == 255
+    d = osearch.Decomposition(t=dec.t, paulis_desc=dec.paulis_desc, perm=dec.perm, sign=dec.sign)
+    assert osearch.reconstruct(4, d).equals(zmat.target_from_words(4, tw.paulis, tw.clifford))

@@ -70,3 +70,4 @@ def test_default_params_per_n():
         p = tcw.WalkParams()
         lib.tcw_default_params(ctypes.byref(p), n)
         assert p.walks == walks and p.log2_table == lg and p.trail_cap_factor == 20 and p.budget_beta == 16
+        assert p.chunk_parallel == 1
