@@ -152,6 +152,52 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def tts_n4_leg(ctx, cap: float, slice_s: float = 60.0):
+    """The whole optimal-T-count search for the four seeded n = 4, k = 7 targets at theta = 1/2 (the
+    paper's choice when the table holds the whole space: 2^27 slots >> N = 3.3e7 per chunk), every
+    chunk of an odd depth searched concurrently.  Depths 0..6 run as one call; depth 7 runs in calls
+    of at most slice_s seconds, each starting a fresh range of function versions (a version starts
+    from an empty table anyway), until a verified decomposition or the cap."""
+    import seeded_inputs
+    runs = []
+    for ts in range(1, 5):
+        twn = seeded_inputs.target_words(4, 7, ts)
+        tn = ctx.target_from_words(4, twn.paulis, twn.clifford)
+
+        def params(k_max, version, seconds, only=None):
+            p4 = ctx.default_params(4)
+            p4.k_max = k_max
+            p4.delta = 1
+            p4.log2_table = 27
+            p4.seed = 3100 + ts
+            p4.version = version
+            p4.chunk_parallel = 0
+            p4.max_seconds = seconds
+            if only is not None:
+                p4.depth_order_kind = 1
+                p4.depth_order_len = 1
+                p4.depth_order[0] = only
+            return p4
+
+        t0 = time.perf_counter()
+        r = ctx.search(tn, params(6, 0, cap))
+        steps, slices = r.stats.steps, 0
+        print(f"tts n4k7 target {ts}: depths 0..6 done in {time.perf_counter() - t0:.1f} s, "
+              f"t={r.t if r.status else None}", file=sys.stderr, flush=True)
+        while not r.status and time.perf_counter() - t0 < cap:
+            left = cap - (time.perf_counter() - t0)
+            r = ctx.search(tn, params(7, (slices + 1) << 20, min(slice_s, left), only=7))
+            steps += r.stats.steps
+            slices += 1
+            print(f"tts n4k7 target {ts}: depth 7 slice {slices} ended at {time.perf_counter() - t0:.1f} s, "
+                  f"found={bool(r.status)}", file=sys.stderr, flush=True)
+        runs.append({"target_seed": ts, "seconds": time.perf_counter() - t0,
+                     "found_t": r.t if r.status else None, "chunk": r.chunk if r.status else None,
+                     "steps": steps, "depth7_slices": slices})
+        tn.free()
+    return {"measured": True, "theta": 0.5, "chunk_parallel": "all", "cap_s": cap, "runs": runs}
+
+
 # Sec. 5.2, Table 1: mean synthesis time of the T-count-7 three-qubit gates over 100 trials on
 # 4096 Blue Gene/Q cores with half of the points distinguished (another machine: context only).
 PAPER_TABLE1_SECONDS = {"toffoli": 25.9870, "fredkin": 25.0031, "peres": 25.4931}
@@ -300,6 +346,9 @@ def main():
     ap.add_argument("--batch-cap", type=float, default=30.0, help="per-target wall-clock cap (s)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration for profiles)")
+    ap.add_argument("--tts-n4", action="store_true",
+                    help="also run the whole optimal-T-count search for the four n = 4, k = 7 targets")
+    ap.add_argument("--tts-n4-cap", type=float, default=150.0, help="wall-clock cap per n = 4 target (s)")
     ap.add_argument("--named", action="store_true",
                     help="also synthesise Toffoli, Fredkin and Peres (n = 3, T-count 7) repeatedly")
     ap.add_argument("--named-reps", type=int, default=20)
@@ -368,28 +417,9 @@ def main():
         r3 = ctx.search(t3, p3)
         extra["tts_n3k6"] = {"seconds": r3.seconds, "found_t": r3.t if r3.status else None,
                              "steps": r3.stats.steps, "versions": r3.versions, "measured": True}
-        # n = 4: the whole optimal-T-count search (depths 0..7, every chunk of an odd depth searched
-        # concurrently) at theta = 1/2, the paper's choice when the table holds the whole space
-        # (2^27 slots >> N = 3.3e7 per chunk), for the four seeded n = 4, k = 7 targets
-        runs = []
-        for ts in range(1, 5):
-            twn = seeded_inputs.target_words(4, 7, ts)
-            tn = ctx.target_from_words(4, twn.paulis, twn.clifford)
-            p4 = ctx.default_params(4)
-            p4.k_max = 7
-            p4.delta = 1
-            p4.log2_table = 27
-            p4.seed = 3100 + ts
-            p4.chunk_parallel = 0
-            p4.max_seconds = 150
-            r4 = ctx.search(tn, p4)
-            runs.append({"target_seed": ts, "seconds": r4.seconds, "found_t": r4.t if r4.status else None,
-                         "chunk": r4.chunk if r4.status else None, "steps": r4.stats.steps,
-                         "spaces": r4.spaces, "versions": r4.versions})
-            print(f"tts n4k7 target {ts}: t={runs[-1]['found_t']} in {r4.seconds:.2f} s", file=sys.stderr,
-                  flush=True)
-            tn.free()
-        extra["tts_n4k7_theta_half"] = {"measured": True, "theta": 0.5, "chunk_parallel": "all", "runs": runs}
+    if args.tts_n4:
+        extra["tts_n4k7_theta_half"] = tts_n4_leg(ctx, args.tts_n4_cap)
+    if not args.no_tts:
         n_pts = 2 * 255 ** 3
         steps_chunk = n_pts * (1 << delta)          # Appendix: about N / theta steps for the chunk with the claw
         budget = 16 * steps_chunk                   # each earlier chunk fails after its full budget
