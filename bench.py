@@ -69,14 +69,14 @@ def valu_ops_per_step(n: int, h: int) -> float:
     """32-bit VALU lane-operations the n = 4 walk step needs per evaluation of f (mean over sides).
 
     both sides: h R/2 butterflies x 12 (64-bit modular add + 61-bit rotation + sign), R x 6 (fold),
-                bitonic sort log2R(log2R+1)/2 stages x R keys x 5 (exchange, compare, select),
-                R x 6 (position-keyed sum) + log2(64) x 4 (wave reduction, per lane)
+                R x 27 (multiset hash: salt xor 2, SplitMix64 finaliser 23 -- three 64-bit
+                xor-shifts and two 64-bit products by constants -- and the 64-bit add 2),
+                log2(64) x 4 x 64 (wave reduction of the sum)
     side 1:     limb packing 2 sets x 9 limbs x R x 3, limb recombination R x 9 x 4 plus the
                 reduce-scatter (12 values x 64 lanes x 8) -- the S_c product itself runs on MFMA
     """
     r = 4 ** n
-    lg = 2 * n
-    common = h * (r // 2) * 12 + r * 6 + (lg * (lg + 1) // 2) * r * 5 + r * 6 + 6 * 4 * 64
+    common = h * (r // 2) * 12 + r * 6 + r * 27 + 6 * 4 * 64
     side1 = 2 * 9 * r * 3 + r * 9 * 4 + 12 * 64 * 8
     return common + 0.5 * side1
 
@@ -445,7 +445,7 @@ def main():
                    "log2_table": log2_table, "iters_per_launch": args.iters, "parallelism": "1 GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s", "frac": achieved / peak,
                      "traffic": measured_traffic(args.walks, args.iters), "traffic_unit": "HBM bytes per launch",
-                     "kernel": "k_walk<4,8>", "kernel_ms": avg_ms, "kernel_source_sha256": kernel_source_digest(),
+                     "kernel": "k_walk<4,12>", "kernel_ms": avg_ms, "kernel_source_sha256": kernel_source_digest(),
                      "mfma_i8": {"achieved": mfma_achieved / 1e12, "peak": MFMA_I8_PEAK_OPS / 1e12, "unit": "Tops/s",
                                  "frac": mfma_achieved / MFMA_I8_PEAK_OPS}},
         "walk_stats": st.as_dict(),

@@ -22,8 +22,11 @@ hash function" applied to information about every matrix element):
 * Row digest.  phi: Z[1/sqrt2] -> Z/p, p = 2^61 - 1, sends sqrt2 to 2^31 (a
   square root of 2 mod p), hence 1/sqrt2 to 2^30.  S_r = sum_q K[q] phi(M_rq)
   mod p; D_r = min(S_r, p - S_r) (invariant under negating the row).
-* Matrix hash.  D sorted ascending; H = mix(salt_h + sum_i K2[i] D_(i) mod 2^64)
-  where mix is SplitMix64's finaliser.
+* Matrix hash.  An additive multiset hash of the digests (MSet-Add-Hash of Clarke,
+  Devadas, van Dijk, Gassend, Suh, "Incremental multiset hash functions and their
+  application to memory integrity checking", ASIACRYPT 2003):
+  H = mix(sum_r mix(D_r xor salt_h) mod 2^64), mix being SplitMix64's finaliser.  A sum
+  does not depend on the order of the rows, so no canonical sort is needed.
 * Reduction.  x' = floor(H N_half / 2^64), b' = H mod 2.
 * Distinguished points (Sec. 3, fraction theta = 2^-delta): the top delta bits
   of mix(((x << 1) | b) xor salt_d) are zero.
@@ -31,7 +34,7 @@ hash function" applied to information about every matrix element):
   x_0 = floor(g N_half / 2^64), b_0 = g mod 2.  The start is not tested.
 * Keys: sm64(s, i) = mix(s + (i+1) GAMMA) is the i-th SplitMix64 output from
   seed s.  From the search seed sigma: s_t = sm64(sigma, t) for t = 0..4;
-  K[q] = (sm64(s_0, q) >> 3) mod p; K2[i] = sm64(s_1, i) | 1; with
+  K[q] = (sm64(s_0, q) >> 3) mod p (s_1 is not used); with
   ctx = (version << 16) | (k << 8) | c: salt_h = sm64(s_2, ctx),
   salt_d = sm64(s_3, ctx), salt_s = sm64(s_4, ctx).
 """
@@ -79,7 +82,6 @@ def unpack(pt: int) -> Tuple[int, int]:
 @dataclass
 class Keys:
     K: List[int]
-    K2: List[int]
     salt_h: int
     salt_d: int
     salt_s: int
@@ -91,7 +93,6 @@ def make_keys(n: int, k: int, chunk: int, seed: int, version: int = 0) -> Keys:
     ctx = (version << 16) | (k << 8) | chunk
     return Keys(
         K=[(sm64(s[0], q) >> 3) % P61 for q in range(r)],
-        K2=[sm64(s[1], i) | 1 for i in range(r)],
         salt_h=sm64(s[2], ctx),
         salt_d=sm64(s[3], ctx),
         salt_s=sm64(s[4], ctx),
@@ -119,10 +120,11 @@ def row_digests(m: zmat.ZMat, K: List[int]) -> List[int]:
 
 
 def matrix_hash(m: zmat.ZMat, keys: Keys) -> int:
-    d = sorted(row_digests(m, keys.K))
-    acc = keys.salt_h
-    for i, v in enumerate(d):
-        acc += keys.K2[i] * v
+    """H = mix(sum over rows of mix(D_r xor salt_h), mod 2^64): a function of the multiset of
+    sign-normalised row digests, i.e. of the left-Clifford coset."""
+    acc = 0
+    for v in row_digests(m, keys.K):
+        acc += mix64(v ^ keys.salt_h)
     return mix64(acc & MASK64)
 
 

@@ -140,7 +140,7 @@ int prepare_space(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, Space& o
     out.seed = sp->seed;
     HIP_TRY(c, tcw::exact_alloc(out.S, n));
     HIP_TRY(c, hipMalloc(&out.phi, (size_t)R * R / 2 * sizeof(uint32_t) + 16));
-    HIP_TRY(c, hipMalloc(&out.keys, 2 * (size_t)R * sizeof(uint64_t)));
+    HIP_TRY(c, hipMalloc(&out.keys, (size_t)R * sizeof(uint64_t)));
     if ((rc = clear_flag(c))) return rc;
     // S_c = U R(c)^T for odd k, U for even k
     uint16_t* seq = nullptr;
@@ -463,7 +463,7 @@ int tcw_canon_hash(tcw_ctx* c, int n, const tcw_space* sp, const int32_t* a, con
     uint32_t* phi = nullptr;
     uint64_t* keys = nullptr;
     HIP_TRY(c, hipMalloc(&phi, (size_t)count * R * R / 2 * sizeof(uint32_t)));
-    HIP_TRY(c, hipMalloc(&keys, 2 * (size_t)R * sizeof(uint64_t)));
+    HIP_TRY(c, hipMalloc(&keys, (size_t)R * sizeof(uint64_t)));
     int rc = clear_flag(c);
     Space s;
     s.k = sp->k;
@@ -1853,7 +1853,7 @@ int build_level_table(tcw_ctx* c, int n, int h_max, uint64_t seed, LevelTable& l
     const int R = 1 << (2 * n);
     HIP_TRY(c, hipMalloc(&lt.zero_phi, (size_t)R * R / 2 * 4));
     HIP_TRY(c, hipMemsetAsync(lt.zero_phi, 0, (size_t)R * R / 2 * 4, c->stream));
-    HIP_TRY(c, hipMalloc(&lt.keys, 2 * (size_t)R * 8));
+    HIP_TRY(c, hipMalloc(&lt.keys, (size_t)R * 8));
     HIP_TRY(c, tcw::keys_fill(n, seed, lt.keys, c->stream));
     uint64_t entries = 0;
     for (int h = 0; h <= h_max; ++h) entries += n_half_of(n, h);

@@ -18,7 +18,7 @@ struct SpaceDev {
     uint64_t salt_d;    // distinguished-point salt
     uint64_t salt_s;    // trail-start salt
     const uint32_t* phi;   // S_c as int8: A packed [q4][r] dwords, then B packed the same way
-    const uint64_t* keys;  // K[R] (row-digest keys, < p) then K2[R] (odd position keys)
+    const uint64_t* keys;  // K[R] (row-digest keys, < p)
 };
 
 enum : uint32_t { MODE_WALK = 0, MODE_ALIGN = 1, MODE_LOCK = 2, MODE_DONE = 3 };

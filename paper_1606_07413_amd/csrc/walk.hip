@@ -13,8 +13,8 @@
 // fixed chunk matrix S_c = (A + B sqrt2)/sqrt2^e runs as int8 dot products (v_dot4_i32_i8) of A
 // and B against 7-bit limbs of u, A and B resident in LDS.  Then (nu + h of Sec. 2):
 //   D_r = min(S_r, p - S_r)   (sign-normalised row: negating a row negates S_r)
-//   sort D ascending with a wavefront bitonic network            (left-Clifford canonical order)
-//   H = mix64(salt_h + sum_i K2[i] D_(i))                          (mod 2^64: order-independent)
+//   H = mix64(sum_r mix64(D_r ^ salt_h))   (mod 2^64: an additive multiset hash, so the order of
+//                                           the rows -- a left signed permutation -- drops out)
 //   f(x, b) = (floor(H * xi^h / 2^64), H mod 2)                    (reduction back to a point)
 #include "common.h"
 #include "internal.h"
@@ -44,7 +44,6 @@ struct Lds {
     uint32_t phiA[Geo<NQ>::Q4 * Geo<NQ>::R];
     uint32_t phiB[Geo<NQ>::Q4 * Geo<NQ>::R];
     uint64_t K[Geo<NQ>::R];
-    uint64_t K2[Geo<NQ>::R];
     uint32_t limbs[WAVES * Geo<NQ>::WPW][Geo<NQ>::Q4 * LIMB_STRIDE];
 };
 
@@ -58,7 +57,6 @@ template <int WAVES>
 struct Lds<4, WAVES> {
     v4i frag[N4_NT * N4_KK * 64];
     uint64_t K[256];
-    uint64_t K2[256];
     uint32_t limbs[WAVES][NLIMB * N4_ROW];
 };
 
@@ -89,10 +87,7 @@ __device__ void load_lds(Lds<NQ, WAVES>& L, const SpaceDev& sp) {
             L.phiB[i] = sp.phi[NPHI + i];
         }
     }
-    for (int i = threadIdx.x; i < Gm::R; i += blockDim.x) {
-        L.K[i] = sp.keys[i];
-        L.K2[i] = sp.keys[Gm::R + i];
-    }
+    for (int i = threadIdx.x; i < Gm::R; i += blockDim.x) L.K[i] = sp.keys[i];
 }
 
 // Lane exchange with the partner lane ^ X (X a compile-time power of two below 64): DPP quad
@@ -123,43 +118,6 @@ __device__ inline uint64_t xchg64_dyn(uint64_t v, int x, int lane) {
         case 8: return xchg64<8>(v, lane);
         case 16: return xchg64<16>(v, lane);
         default: return xchg64<32>(v, lane);
-    }
-}
-
-// Sort RPL keys per lane across the G lanes of a group, ascending in index i = gl * RPL + j
-// (bitonic network; the group is aligned in the wave, so lane ^ x stays inside it for x < G).
-template <int NQ>
-__device__ inline void bitonic_sort(uint64_t* d, int gl, int lane) {
-    using Gm = Geo<NQ>;
-    constexpr int R = Gm::R, RPL = Gm::RPL;
-#pragma unroll
-    for (int k = 2; k <= R; k <<= 1) {
-#pragma unroll
-        for (int s = k >> 1; s > 0; s >>= 1) {
-            if (s >= RPL) {
-                // s, k >= RPL: the direction depends on the lane only
-                const int i0 = gl * RPL;
-                const bool keep_min = ((i0 & s) == 0) == ((i0 & k) == 0);
-#pragma unroll
-                for (int j = 0; j < RPL; ++j) {
-                    const uint64_t o = xchg64_dyn(d[j], s / RPL, lane);
-                    const bool take_own = (d[j] < o) == keep_min;
-                    d[j] = take_own ? d[j] : o;
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < RPL; ++j) {
-                    if ((j & s) == 0) {
-                        const int i = gl * RPL + j;
-                        const bool asc = (i & k) == 0;
-                        const uint64_t a = d[j], b = d[j | s];
-                        const bool sw = (a > b) == asc;
-                        d[j] = sw ? b : a;
-                        d[j | s] = sw ? a : b;
-                    }
-                }
-            }
-        }
     }
 }
 
@@ -265,31 +223,36 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
         }
         wave_sync();
     }
-    v4i acc[N4_NT];
-#pragma unroll
-    for (int nt = 0; nt < N4_NT; ++nt) acc[nt] = v4i{0, 0, 0, 0};
-#pragma unroll
-    for (int kk = 0; kk < N4_KK; ++kk) {
-        // issue the 16 fragment reads of this K step first, then the MFMAs consume them in order
-        v4i bf[N4_NT];
-#pragma unroll
-        for (int nt = 0; nt < N4_NT; ++nt) bf[nt] = L.frag[(nt * N4_KK + kk) * 64 + lane];
-#pragma unroll
-        for (int nt = 0; nt < N4_NT; ++nt)
-            acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(afr[kk], bf[nt], acc[nt], 0, 0, 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, N4_NT, 0);  // DS reads
-        __builtin_amdgcn_sched_group_barrier(0x008, N4_NT, 0);  // MFMA
-    }
-    // this lane's partial sums over limbs m = 4g + j (rows m >= 9 are zero): weight 2^(7m) = 2^(28g) 2^(7j).
-    // |acc| < 2^23, so acc_0 + 2^7 acc_1 and acc_2 + 2^7 acc_3 fit in 31 bits.
+    // N tiles in groups of NG: NG independent accumulation chains over the 8 K steps, then each
+    // finished tile is combined at once, so only NG accumulators and NG fragments are live.
+    // This lane's partial sums are over limbs m = 4g + j (rows m >= 9 are zero), weight
+    // 2^(7m) = 2^(28g) 2^(7j); |acc| < 2^23, so acc_0 + 2^7 acc_1 and acc_2 + 2^7 acc_3 fit in 31 bits.
+    constexpr int NG = 4;
     const uint32_t sh = (uint32_t)((28 * g) % 61);
     uint64_t P[N4_NT];
 #pragma unroll
-    for (int nt = 0; nt < N4_NT; ++nt) {
-        const int32_t lo = acc[nt][0] + acc[nt][1] * 128;
-        const int32_t hi = acc[nt][2] + acc[nt][3] * 128;
-        const uint64_t x = (uint64_t)(int64_t)lo + ((uint64_t)(int64_t)hi << 14);
-        P[nt] = m61_rotv(m61_fold(x + 4 * P61), sh);
+    for (int n0 = 0; n0 < N4_NT; n0 += NG) {
+        v4i acc[NG];
+#pragma unroll
+        for (int i = 0; i < NG; ++i) acc[i] = v4i{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < N4_KK; ++kk) {
+            v4i bf[NG];
+#pragma unroll
+            for (int i = 0; i < NG; ++i) bf[i] = L.frag[((n0 + i) * N4_KK + kk) * 64 + lane];
+#pragma unroll
+            for (int i = 0; i < NG; ++i)
+                acc[i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(afr[kk], bf[i], acc[i], 0, 0, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, NG, 0);  // DS reads
+            __builtin_amdgcn_sched_group_barrier(0x008, NG, 0);  // MFMA
+        }
+#pragma unroll
+        for (int i = 0; i < NG; ++i) {
+            const int32_t lo = acc[i][0] + acc[i][1] * 128;
+            const int32_t hi = acc[i][2] + acc[i][3] * 128;
+            const uint64_t x = (uint64_t)(int64_t)lo + ((uint64_t)(int64_t)hi << 14);
+            P[n0 + i] = m61_rotv(m61_fold(x + 4 * P61), sh);
+        }
     }
     // reduce-scatter over the four limb groups: lanes l^32, then l^16
     const bool lowpair = g < 2, even = (g & 1) == 0;
@@ -379,21 +342,17 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
         for (int j = 0; j < RPL; ++j) S[j] = u[j];
     }
 
-    // sign-normalised row digests, canonical order, matrix hash
-    uint64_t d[RPL];
+    // sign-normalised row digests and the multiset hash of the walk group's rows
+    uint64_t acc = 0;
 #pragma unroll
     for (int j = 0; j < RPL; ++j) {
         const uint64_t c = m61_canon(S[j]);
         const uint64_t c2 = P61 - c;
-        d[j] = c < c2 ? c : c2;
+        acc += mix64((c < c2 ? c : c2) ^ sp.salt_h);
     }
-    bitonic_sort<NQ>(d, gl, gbase + gl);
-    uint64_t acc = 0;
-#pragma unroll
-    for (int j = 0; j < RPL; ++j) acc += L.K2[gl * RPL + j] * d[j];
 #pragma unroll
     for (int off = 1; off < Gm::G; off <<= 1) acc += xchg64_dyn(acc, off, gbase + gl);
-    const uint64_t H = mix64(sp.salt_h + acc);
+    const uint64_t H = mix64(acc);
     out_h = H;
     out_pt = mulhi64(H, sp.n_half) | ((H & 1) << 32);
 }
@@ -412,7 +371,7 @@ __device__ inline uint64_t start_point(const SpaceDev& sp, uint64_t w, uint32_t 
 constexpr int WAVES_SMALL = 4;
 template <int NQ>
 struct WalkWaves {
-    static constexpr int value = NQ == 4 ? 8 : WAVES_SMALL;
+    static constexpr int value = NQ == 4 ? 12 : WAVES_SMALL;
 };
 
 // ---- parity kernels ----
@@ -553,15 +512,14 @@ __global__ void k_starts(SpaceDev sp, int64_t w0, uint32_t j, int64_t count, uin
         out[i] = start_point(sp, (uint64_t)(w0 + i), j);
 }
 
-// K[q] = (sm64(s_0, q) >> 3) mod p, K2[i] = sm64(s_1, i) | 1, s_t = sm64(seed, t)
+// K[q] = (sm64(s_0, q) >> 3) mod p, s_0 = sm64(seed, 0)
 __global__ void k_keys(int r, uint64_t seed, uint64_t* keys) {
     const int i = threadIdx.x + blockIdx.x * blockDim.x;
     if (i >= r) return;
-    const uint64_t s0 = sm64(seed, 0), s1 = sm64(seed, 1);
+    const uint64_t s0 = sm64(seed, 0);
     uint64_t k = sm64(s0, (uint64_t)i) >> 3;
     if (k >= P61) k -= P61;
     keys[i] = k;
-    keys[r + i] = sm64(s1, (uint64_t)i) | 1ull;
 }
 
 // ---- the walk kernel: trails, distinguished-point table, backtracking (Sec. 3) ----
