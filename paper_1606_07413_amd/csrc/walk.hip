@@ -58,6 +58,7 @@ struct Lds<4, WAVES> {
     v4i frag[N4_NT * N4_KK * 64];
     uint64_t K[256];
     uint32_t limbs[WAVES][NLIMB * N4_ROW];
+    alignas(16) uint32_t zero_row[N4_ROW];  // A-operand rows 9..15 (no limb) read this
 };
 
 // A value every lane of the wavefront holds (the walk of a whole wavefront), made explicitly uniform.
@@ -81,6 +82,7 @@ __device__ void load_lds(Lds<NQ, WAVES>& L, const SpaceDev& sp) {
     if constexpr (NQ == 4) {
         const v4i* src = reinterpret_cast<const v4i*>(sp.phi);
         for (int i = threadIdx.x; i < N4_NT * N4_KK * 64; i += blockDim.x) L.frag[i] = src[i];
+        for (int i = threadIdx.x; i < N4_ROW; i += blockDim.x) L.zero_row[i] = 0;
     } else {
         for (int i = threadIdx.x; i < NPHI; i += blockDim.x) {
             L.phiA[i] = sp.phi[i];
@@ -200,13 +202,16 @@ template <int WAVES>
 __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const uint64_t* u, int lane, int rot_e,
                                   uint64_t* S) {
     const int g = lane >> 4, n16 = lane & 15;
-    const int mr = n16 < NLIMB ? n16 : NLIMB - 1;  // limb rows 9..15 of the A operand are unused
+    // A-operand row n16: limb n16 of the key vector, or zeros for the unused rows 9..15, so those
+    // accumulator rows stay exactly zero
+    const uint32_t* arow = n16 < NLIMB ? limbs + n16 * N4_ROW : L.zero_row;
     v4i afr[N4_KK];
 #pragma unroll
     for (int set = 0; set < 2; ++set) {
         uint64_t w[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) w[j] = set ? m61_rot(u[j], 31) : u[j];
+        // u is lazily reduced (< 2^61 + 2^32); so is its image 2^31 u = (u >> 30) + (u mod 2^30) 2^31
+        for (int j = 0; j < 4; ++j) w[j] = set ? (u[j] >> 30) + ((u[j] & 0x3fffffffull) << 31) : u[j];
 #pragma unroll
         for (int m = 0; m < NLIMB; ++m) {
             uint32_t dw = 0;
@@ -216,11 +221,7 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
         }
         wave_sync();
 #pragma unroll
-        for (int kq = 0; kq < 4; ++kq) {
-            const v4i f = *reinterpret_cast<const v4i*>(&limbs[mr * N4_ROW + kq * 16 + g * 4]);
-            // A-operand rows 9..15 are zero, so those accumulator rows stay exactly zero
-            afr[set * 4 + kq] = n16 < NLIMB ? f : v4i{0, 0, 0, 0};
-        }
+        for (int kq = 0; kq < 4; ++kq) afr[set * 4 + kq] = *reinterpret_cast<const v4i*>(&arow[kq * 16 + g * 4]);
         wave_sync();
     }
     // N tiles in groups of NG: NG independent accumulation chains over the 8 K steps, then each
@@ -271,6 +272,59 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
     }
 }
 
+// n = 4: the h rotations applied to the key vector, branch-free.  Lane l holds rows r_j = 4 l + j,
+// so x_r = j | (l & 3) << 2 and z_r = l >> 2.  Each popcount in the commutation test and in the
+// phase c(p, r) of P_p P_r = i^c P_{p^r} splits into a lane term, a row term and uniform terms;
+// the four rows' bits are formed at once, one row per byte:
+//   anticommute_j = parity(x_p & z_r) ^ parity((z_p >> 2) & (l & 3)) ^ parity(z_p & 3 & j)
+//   c_j = |x_p & z_p| + |x_r & z_r| - |(x_p ^ x_r) & (z_p ^ z_r)| + 2 |z_p & x_r|   (mod 4)
+// and the butterfly of R (side 0) or R^T (side 1) adds the partner value when side ^ bit1(c_j) is
+// set, else subtracts it.  Values stay lazily reduced below 2^61 + 2^32: u + (2p - part) < 2^63,
+// and for s = a 2^31 + b, s 2^30 = a 2^61 + b 2^30 = a + b 2^30 (mod p).
+__device__ inline void rotate4(uint64_t* u, const uint32_t* dig, int h, int side, int gl, int gbase) {
+    const uint32_t lx = (uint32_t)gl & 3, zr = (uint32_t)gl >> 2;
+    uint32_t A = 0;  // bytes j: |x_r & z_r|
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        A |= (uint32_t)(__builtin_popcount((uint32_t)j & (zr & 3)) + __builtin_popcount(lx & (zr >> 2))) << (8 * j);
+    const uint32_t side_b = side ? 0x01010101u : 0u;
+#pragma unroll
+    for (int t = Geo<4>::HMAX - 1; t >= 0; --t) {
+        if (t >= h) continue;
+        const uint32_t p = dig[t];
+        // partner rows r ^ p: lane l ^ (p >> 2), register j ^ (p & 3) (constant register indices)
+        const bool s1 = (p & 1) != 0, s2 = (p & 2) != 0;
+        const uint64_t b0 = s1 ? u[1] : u[0], b1 = s1 ? u[0] : u[1];
+        const uint64_t b2 = s1 ? u[3] : u[2], b3 = s1 ? u[2] : u[3];
+        const uint64_t w[4] = {s2 ? b2 : b0, s2 ? b3 : b1, s2 ? b0 : b2, s2 ? b1 : b3};
+        const int src = gbase + (gl ^ (int)(p >> 2));
+        const uint32_t xp = p & 15, zp = p >> 4, z2 = zp & 3;
+        // uniform parts
+        const uint32_t ja = ((z2 & 1) << 8) | (((z2 >> 1) & 1) << 16) | ((uint32_t)(__builtin_popcount(z2) & 1) << 24);
+        const uint32_t zu = ((z2 & 1) << 8) | (((z2 >> 1) & 1) << 16) | ((uint32_t)__builtin_popcount(z2) << 24);
+        const uint32_t uni = (uint32_t)__builtin_popcount(xp & zp) * 0x01010101u + 2 * zu + 0x04040404u;
+        const uint32_t xj = ((xp & 3) * 0x01010101u) ^ 0x03020100u;
+        // lane parts
+        const uint32_t la = (uint32_t)__builtin_popcount((xp & zr) ^ ((zp >> 2) & lx)) & 1;
+        const uint32_t acb = (la ? 0x01010101u : 0u) ^ ja;
+        const uint32_t d = zp ^ zr;
+        const uint32_t t_hi = (uint32_t)__builtin_popcount(((xp >> 2) ^ lx) & (d >> 2));
+        const uint32_t zl = (uint32_t)__builtin_popcount((zp >> 2) & lx);
+        const uint32_t m = xj & ((d & 3) * 0x01010101u);
+        const uint32_t tlo = (m & 0x01010101u) + ((m >> 1) & 0x01010101u);
+        const uint32_t cb = uni + A + ((2 * zl - t_hi) & 3) * 0x01010101u - tlo;
+        const uint32_t plus_b = ((cb >> 1) & 0x01010101u) ^ side_b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t part = shfl64(w[j], src);
+            const uint64_t q = ((plus_b >> (8 * j)) & 1) ? part : (2 * P61 - part);
+            const uint64_t sum = u[j] + q;
+            const uint64_t r = (sum >> 31) + ((sum & 0x7fffffffull) << 30);
+            u[j] = ((acb >> (8 * j)) & 1) ? r : u[j];
+        }
+    }
+}
+
 // One evaluation of f on `pt` by the walk group; every lane of the group returns the same values.
 template <int NQ, int WAVES>
 __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t* limbs, uint64_t pt, int gl,
@@ -297,6 +351,9 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
     uint64_t u[RPL];
 #pragma unroll
     for (int j = 0; j < RPL; ++j) u[j] = L.K[gl * RPL + j];
+    if constexpr (NQ == 4) {
+        rotate4(u, dig, h, side, gl, gbase);
+    } else {
 #pragma unroll
     for (int t = HMAX - 1; t >= 0; --t) {
         if (t < h) {
@@ -329,6 +386,7 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
             }
         }
     }
+    }
 
     uint64_t S[RPL];
     if (side) {
@@ -339,7 +397,7 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < RPL; ++j) S[j] = u[j];
+        for (int j = 0; j < RPL; ++j) S[j] = m61_fold(u[j]);  // n = 4 keeps u lazily reduced
     }
 
     // sign-normalised row digests and the multiset hash of the walk group's rows
