@@ -50,15 +50,16 @@ struct Lds {
 // n = 4: S_c as MFMA B-operand fragments.  With K stacked as [A | B] (512 columns), fragment
 // (nt, kk) holds, for lane l, the 16 bytes S''[nt*16 + l%16][kk*64 + (l/16)*16 + 0..15] where
 // S''[r][q] = A[r][q] for q < 256 and B[r][q - 256] otherwise; one ds_read_b128 per lane per MFMA.
-// Per walk: limb rows [9][68] (7-bit limbs of the rotated key vector, 4 columns per dword; the row
-// stride of 68 dwords keeps the MFMA A-operand reads free of bank conflicts).
+// Per walk: digit rows [8][68] (signed base-256 digits of the rotated key vector, 4 columns per
+// dword; the row stride of 68 dwords keeps the MFMA A-operand reads free of bank conflicts).
 constexpr int N4_NT = 16, N4_KK = 8, N4_ROW = 68;
+constexpr int N4_DIG = 8;  // signed base-256 digits of a residue below 2^62
 template <int WAVES>
 struct Lds<4, WAVES> {
     v4i frag[N4_NT * N4_KK * 64];
     uint64_t K[256];
-    uint32_t limbs[WAVES][NLIMB * N4_ROW];
-    alignas(16) uint32_t zero_row[N4_ROW];  // A-operand rows 9..15 (no limb) read this
+    uint32_t limbs[WAVES][N4_DIG * N4_ROW];
+    alignas(16) uint32_t zero_row[N4_ROW];  // A-operand rows 8..15 (no digit) read this
 };
 
 // A value every lane of the wavefront holds (the walk of a whole wavefront), made explicitly uniform.
@@ -198,38 +199,65 @@ __device__ inline void side1_dot4(const Lds<NQ, WAVES>& L, uint32_t* limbs, cons
 // tile, 16 tiles; 8 K steps), so sum_m 2^(7m) D[m][r] = A u + 2^31 B u = 2^(-30 e) S_r (mod p).  Lane l
 // holds limbs 4g..4g+3 (g = l/16) of row l%16 of every tile; the limb groups are combined by a
 // reduce-scatter over lanes l^32, l^16, leaving each lane the rows (4g + j)*16 + l%16, j = 0..3.
+// out[m] = bytes m of x[0..3] (byte j of out[m] = byte m of x[j]): two rounds of v_perm_b32.
+__device__ inline void transpose_bytes4(const uint32_t* x, uint32_t* out) {
+    const uint32_t t0 = __builtin_amdgcn_perm(x[1], x[0], 0x05010400u);
+    const uint32_t t1 = __builtin_amdgcn_perm(x[1], x[0], 0x07030602u);
+    const uint32_t t2 = __builtin_amdgcn_perm(x[3], x[2], 0x05010400u);
+    const uint32_t t3 = __builtin_amdgcn_perm(x[3], x[2], 0x07030602u);
+    out[0] = __builtin_amdgcn_perm(t2, t0, 0x05040100u);
+    out[1] = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
+    out[2] = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
+    out[3] = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
+}
+
 template <int WAVES>
 __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const uint64_t* u, int lane, int rot_e,
                                   uint64_t* S) {
     const int g = lane >> 4, n16 = lane & 15;
-    // A-operand row n16: limb n16 of the key vector, or zeros for the unused rows 9..15, so those
-    // accumulator rows stay exactly zero
-    const uint32_t* arow = n16 < NLIMB ? limbs + n16 * N4_ROW : L.zero_row;
+    // A operand (16 rows x K = 512): rows 0..7 hold the digits of u on the A half of K (columns
+    // q < 256) and are zero on the B half; rows 8..15 hold the digits of 2^31 u on the B half and
+    // are zero on the A half.  Both sets go through the same 8-row LDS buffer, one after the other.
+    const uint32_t* arow0 = n16 < N4_DIG ? limbs + n16 * N4_ROW : L.zero_row;
+    const uint32_t* arow1 = n16 >= N4_DIG ? limbs + (n16 - N4_DIG) * N4_ROW : L.zero_row;
     v4i afr[N4_KK];
 #pragma unroll
     for (int set = 0; set < 2; ++set) {
-        uint64_t w[4];
+        // Signed base-256 digits: for v < 2^62, b = v + C0 with C0 = 0x8080808080808080 stays below
+        // 2^64 and v = sum_m (byte_m(b) - 128) 256^m, each digit in [-128, 127]; as an int8 the digit
+        // is byte_m(b) xor 0x80.  u is lazily reduced (< 2^61 + 2^32), and so is its image
+        // 2^31 u = (u >> 30) + (u mod 2^30) 2^31 (mod p).
+        uint32_t lo[4], hi[4];
 #pragma unroll
-        // u is lazily reduced (< 2^61 + 2^32); so is its image 2^31 u = (u >> 30) + (u mod 2^30) 2^31
-        for (int j = 0; j < 4; ++j) w[j] = set ? (u[j] >> 30) + ((u[j] & 0x3fffffffull) << 31) : u[j];
-#pragma unroll
-        for (int m = 0; m < NLIMB; ++m) {
-            uint32_t dw = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) dw |= (uint32_t)((w[j] >> (7 * m)) & 127) << (8 * j);
-            limbs[m * N4_ROW + lane] = dw;  // columns q = 4 lane .. 4 lane + 3
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t w = set ? (u[j] >> 30) + ((u[j] & 0x3fffffffull) << 31) : u[j];
+            const uint64_t b = w + 0x8080808080808080ull;
+            lo[j] = (uint32_t)b;
+            hi[j] = (uint32_t)(b >> 32);
         }
+        // 4 x 4 byte transposes: digit row m gets byte m of the lane's four values (columns 4 lane + j)
+        uint32_t dg[N4_DIG];
+        transpose_bytes4(lo, dg);
+        transpose_bytes4(hi, dg + 4);
+#pragma unroll
+        for (int m = 0; m < N4_DIG; ++m) limbs[m * N4_ROW + lane] = dg[m] ^ 0x80808080u;
         wave_sync();
+        const uint32_t* arow = set ? arow1 : arow0;
 #pragma unroll
         for (int kq = 0; kq < 4; ++kq) afr[set * 4 + kq] = *reinterpret_cast<const v4i*>(&arow[kq * 16 + g * 4]);
         wave_sync();
     }
     // N tiles in groups of NG: NG independent accumulation chains over the 8 K steps, then each
     // finished tile is combined at once, so only NG accumulators and NG fragments are live.
-    // This lane's partial sums are over limbs m = 4g + j (rows m >= 9 are zero), weight
-    // 2^(7m) = 2^(28g) 2^(7j); |acc| < 2^23, so acc_0 + 2^7 acc_1 and acc_2 + 2^7 acc_3 fit in 31 bits.
+    // Accumulator row m = 4g + j of this lane is digit m % 8 of set g >> 1 (u, or 2^31 u), weight
+    // 2^(8 (m % 8)) = 2^(32 (g & 1)) 2^(8j).  Each row sums 256 products, |acc| <= 256 * 128 * 127
+    // < 2^22, so x = acc_0 + 2^8 acc_1 + 2^16 acc_2 + 2^24 acc_3 lies in (-2^46, 2^46).  Its weighted
+    // residue, kept lazily in [0, 2^62): with s = 61 - 32 (g & 1),
+    //   2^(61 - s) x = (x >> s) 2^61 + (x mod 2^s) 2^(61 - s) = (x >> s) + (x mod 2^s) 2^(61 - s)  (mod p)
+    // and y = p + (x >> s) + (x mod 2^s) 2^(61 - s).  Four such values sum below 2^64.
     constexpr int NG = 4;
-    const uint32_t sh = (uint32_t)((28 * g) % 61);
+    const uint32_t s_g = 61 - 32 * (uint32_t)(g & 1);
+    const uint64_t m_g = (1ull << s_g) - 1;
     uint64_t P[N4_NT];
 #pragma unroll
     for (int n0 = 0; n0 < N4_NT; n0 += NG) {
@@ -249,26 +277,27 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
         }
 #pragma unroll
         for (int i = 0; i < NG; ++i) {
-            const int32_t lo = acc[i][0] + acc[i][1] * 128;
-            const int32_t hi = acc[i][2] + acc[i][3] * 128;
-            const uint64_t x = (uint64_t)(int64_t)lo + ((uint64_t)(int64_t)hi << 14);
-            P[n0 + i] = m61_rotv(m61_fold(x + 4 * P61), sh);
+            const int32_t lo = acc[i][0] + acc[i][1] * 256;
+            const int32_t hi = acc[i][2] + acc[i][3] * 256;
+            const int64_t x = (int64_t)lo + (int64_t)hi * 65536;
+            P[n0 + i] = P61 + (uint64_t)(x >> s_g) + (((uint64_t)x & m_g) << (61 - s_g));
         }
     }
-    // reduce-scatter over the four limb groups: lanes l^32, then l^16
+    // reduce-scatter over the four lane groups (lanes l^32, then l^16): plain 64-bit sums of the
+    // lazy residues, one fold at the end
     const bool lowpair = g < 2, even = (g & 1) == 0;
     uint64_t Q[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const uint64_t send = lowpair ? P[8 + i] : P[i];
         const uint64_t mine = lowpair ? P[i] : P[8 + i];
-        Q[i] = m61_add(mine, xchg64<32>(send, lane));
+        Q[i] = mine + xchg64<32>(send, lane);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const uint64_t send = even ? Q[4 + i] : Q[i];
         const uint64_t mine = even ? Q[i] : Q[4 + i];
-        S[i] = m61_rot(m61_add(mine, xchg64<16>(send, lane)), rot_e);
+        S[i] = m61_rot(m61_fold(mine + xchg64<16>(send, lane)), rot_e);
     }
 }
 
