@@ -439,6 +439,8 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
     }
 #pragma unroll
     for (int off = 1; off < Gm::G; off <<= 1) acc += xchg64_dyn(acc, off, gbase + gl);
+    // one walk per wavefront: the sum is the same in every lane; finish on the scalar unit
+    if constexpr (Gm::G == 64) acc = uniform64(acc);
     const uint64_t H = mix64(acc);
     out_h = H;
     out_pt = mulhi64(H, sp.n_half) | ((H & 1) << 32);
