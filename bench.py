@@ -241,6 +241,11 @@ def named_leg(ctx, reps: int, reps_default_theta: int):
                 "not_found": sum(1 for t in ts if t is None),
                 "mean_s": statistics.mean(secs), "std_s": statistics.stdev(secs) if count > 1 else 0.0,
                 "mean_steps": statistics.mean(steps)}
+        # the last search's decomposition as gates (Sec. 5.3)
+        if res.status == 1:
+            gates = tcw.circuit_of(res)
+            entry["circuit"] = {"gates": len(gates), "t": sum(1 for g, _ in gates if g in ("t", "tdg")),
+                                "cnot": sum(1 for g, _ in gates if g == "cx")}
         entry["paper_mean_s_4096_bgq_cores"] = PAPER_TABLE1_SECONDS[name]
         out[name] = entry
     return out

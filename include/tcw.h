@@ -241,6 +241,33 @@ int tcw_autotune(tcw_ctx* ctx, const tcw_target* t, int k, int chunk, int delta,
  * answer, never hide a match.  TCW_EOVERFLOW if U's entries do not fit int8 at its exponent.
  * Blocking. */
 int tcw_min_tcount(tcw_ctx* ctx, const tcw_target* t, int h_max, uint64_t seed, int32_t* t_out);
+/* ---- a decomposition as gates (Sec. 5.3: the rotations as Clifford-conjugated T gates, the
+ * Clifford D from its action on Paulis by a stabilizer-tableau reduction) ---------------------
+ * tcw_circuit: gates (application order, first gate applied first) whose product is U =
+ * D R(P_t) ... R(P_1) of a verified result, up to global phase.  R(P) = C^dag T C (or T^dag) with C
+ * mapping P to +-Z on one qubit; D = the inverse of the H / S / CNOT / Pauli sequence that reduces
+ * D's images of X_j and Z_j to the identity.  Adjacent inverse pairs are cancelled.  The T and
+ * T^dag gates number exactly res->t.  Qubit indices as in the Pauli codes (qubit 0 is the leftmost
+ * Kronecker factor).  *count = gates needed; TCW_EOVERFLOW if that exceeds cap (nothing past cap is
+ * written); TCW_EINVAL if res is not a verified decomposition.  Host only: needs no context or GPU. */
+enum {
+    TCW_GATE_H = 1,
+    TCW_GATE_S = 2,
+    TCW_GATE_SDG = 3,
+    TCW_GATE_CNOT = 4, /* q0 control, q1 target */
+    TCW_GATE_T = 5,
+    TCW_GATE_TDG = 6,
+    TCW_GATE_X = 7,
+    TCW_GATE_Y = 8,
+    TCW_GATE_Z = 9
+};
+typedef struct tcw_gate {
+    int32_t kind;
+    int32_t q0;
+    int32_t q1; /* CNOT target, else -1 */
+} tcw_gate;
+int tcw_circuit(const tcw_result* res, tcw_gate* gates, int32_t cap, int32_t* count);
+
 /* ---- learned depth order (the network that orders which depths k are searched first) ---------
  * Input: the target's canonical channel rep (rows sign-normalised by their first nonzero entry,
  * sorted lexicographically as integer sequences, minimal exponent e), entries

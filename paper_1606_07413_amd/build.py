@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["exact.hip", "walk.hip", "mlp.hip", "api.hip"]
+SOURCES = ["exact.hip", "walk.hip", "mlp.hip", "api.hip", "circuit.cpp"]
 LIB = os.path.join(HERE, "libtcw.so")
 
 HIPCC_FLAGS = [

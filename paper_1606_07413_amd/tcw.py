@@ -16,6 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtcw.so")
 
 TCW_OK = 0
+TCW_EINVAL = -1
+TCW_EOVERFLOW = -4
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW", -5: "ESTATE"}
 MAX_T = 64
 MAX_R = 256
@@ -51,6 +53,13 @@ class WalkParams(C.Structure):
         ("depth_order", C.c_int32 * 16), ("chunk_first", C.c_int32), ("chunk_last", C.c_int32),
         ("max_seconds", C.c_double), ("chunk_parallel", C.c_int32),
     ]
+
+
+class Gate(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("q0", C.c_int32), ("q1", C.c_int32)]
+
+
+GATE_NAMES = {1: "h", 2: "s", 3: "sdg", 4: "cx", 5: "t", 6: "tdg", 7: "x", 8: "y", 9: "z"}
 
 
 class Result(C.Structure):
@@ -103,6 +112,7 @@ _SIGS = {
     "tcw_features": (C.c_int, [_P, _P, _P]),
     "tcw_label_batch": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_uint16), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int32), C.c_int, C.c_uint64, _P, _P]),
+    "tcw_circuit": (C.c_int, [C.POINTER(Result), C.POINTER(Gate), C.c_int32, C.POINTER(C.c_int32)]),
     "tcw_min_tcount": (C.c_int, [_P, _P, C.c_int, C.c_uint64, C.POINTER(C.c_int32)]),
     "tcw_mlp_create": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, _P, C.c_uint64, C.POINTER(_P)]),
     "tcw_mlp_free": (C.c_int, [_P]),
@@ -287,6 +297,23 @@ def _autotune(self, target, k, chunk, delta, seed):
 
 Context.search_batch = _search_batch
 Context.autotune = _autotune
+
+
+def circuit_of(res: Result):
+    """The decomposition in `res` as gates in application order: [(name, qubits), ...]."""
+    lib = load()
+    count = C.c_int32(0)
+    rc = lib.tcw_circuit(C.byref(res), None, 0, C.byref(count))
+    if rc != TCW_OK:
+        raise TcwError(rc, "result is not a verified decomposition")
+    buf = (Gate * max(1, count.value))()
+    rc = lib.tcw_circuit(C.byref(res), buf, count.value, C.byref(count))
+    if rc != TCW_OK:
+        raise TcwError(rc, "circuit synthesis failed")
+    out = []
+    for g in buf[:count.value]:
+        out.append((GATE_NAMES[g.kind], (g.q0, g.q1) if g.kind == 4 else (g.q0,)))
+    return out
 
 
 def decomposition_of(res: Result) -> Optional[Decomposition]:

@@ -196,6 +196,19 @@ def _search_named(ctx, name, delta, seed, chunk_parallel=1):
 
 
 @pytest.mark.parametrize("name", ["toffoli", "fredkin", "peres"])
+def test_named_circuit(ctx, name):
+    """The found decomposition as gates: seven T / T^dag, and the gates' exact product has the
+    named gate's channel rep."""
+    from paper_1606_07413_amd import tcw
+    from oracle import circuit as ocircuit
+    res = _search_named(ctx, name, 1, 31)
+    gates = tcw.circuit_of(res)
+    say(name, "circuit:", len(gates), "gates,", sum(1 for g, _ in gates if g == "cx"), "CNOT")
+    assert sum(1 for g, _ in gates if g in ("t", "tdg")) == 7
+    assert ocircuit.circuit_channel(3, gates).equals(ounitary.channel_of_unitary(3, named_v(name), 0))
+
+
+@pytest.mark.parametrize("name", ["toffoli", "fredkin", "peres"])
 def test_named_search_finds_tcount_7(ctx, name):
     # theta = 1/2 as in the paper's runs on these circuits
     _search_named(ctx, name, 1, 11)
