@@ -152,6 +152,30 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def tts_n4_enum_leg(ctx, cap: float):
+    """The same n = 4 searches in the memory-rich limit: every space of up to 2^26 points (all of
+    depths <= 7 at n = 4) enumerated exhaustively, each point hashed once into a table of 4N slots
+    keyed by its full matrix hash (the meet-in-the-middle the walks replace when memory is short);
+    deterministic, and every depth below the answer is searched completely."""
+    import seeded_inputs
+    runs = []
+    for ts in range(1, 5):
+        twn = seeded_inputs.target_words(4, 7, ts)
+        tn = ctx.target_from_words(4, twn.paulis, twn.clifford)
+        p4 = ctx.default_params(4)
+        p4.k_max = 7
+        p4.enum_max = 1 << 26
+        p4.seed = 3200 + ts
+        p4.max_seconds = cap
+        r = ctx.search(tn, p4)
+        runs.append({"target_seed": ts, "seconds": r.seconds, "found_t": r.t if r.status else None,
+                     "chunk": r.chunk if r.status else None, "points": r.stats.steps, "spaces": r.spaces})
+        print(f"tts n4k7 (exhaustive) target {ts}: t={runs[-1]['found_t']} in {r.seconds:.2f} s", file=sys.stderr,
+              flush=True)
+        tn.free()
+    return {"measured": True, "mode": "exhaustive spaces (enum_max 2^26)", "cap_s": cap, "runs": runs}
+
+
 def tts_n4_leg(ctx, cap: float, slice_s: float = 60.0):
     """The whole optimal-T-count search for the four seeded n = 4, k = 7 targets at theta = 1/2 (the
     paper's choice when the table holds the whole space: 2^27 slots >> N = 3.3e7 per chunk), every
@@ -353,6 +377,8 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration for profiles)")
     ap.add_argument("--tts-n4", action="store_true",
                     help="also run the whole optimal-T-count search for the four n = 4, k = 7 targets")
+    ap.add_argument("--tts-n4-enum", action="store_true",
+                    help="also run the n = 4 searches with every space enumerated exhaustively")
     ap.add_argument("--tts-n4-cap", type=float, default=150.0, help="wall-clock cap per n = 4 target (s)")
     ap.add_argument("--named", action="store_true",
                     help="also synthesise Toffoli, Fredkin and Peres (n = 3, T-count 7) repeatedly")
@@ -424,6 +450,8 @@ def main():
                              "steps": r3.stats.steps, "versions": r3.versions, "measured": True}
     if args.tts_n4:
         extra["tts_n4k7_theta_half"] = tts_n4_leg(ctx, args.tts_n4_cap)
+    if args.tts_n4_enum:
+        extra["tts_n4k7_exhaustive"] = tts_n4_enum_leg(ctx, args.tts_n4_cap)
     if not args.no_tts:
         n_pts = 2 * 255 ** 3
         steps_chunk = n_pts * (1 << delta)          # Appendix: about N / theta steps for the chunk with the claw
