@@ -30,17 +30,20 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 MFMA_I8_PEAK_OPS = 5.0e15
 
 
-# Files the walk kernel is built from; the counter summary below records their digest.
+# Files the walk kernel is compiled from; the counter summary below records their digest together
+# with the hipcc flags.
 WALK_KERNEL_SOURCES = ("paper_1606_07413_amd/csrc/walk.hip", "paper_1606_07413_amd/csrc/common.h",
-                       "paper_1606_07413_amd/csrc/internal.h", "paper_1606_07413_amd/build.py")
+                       "paper_1606_07413_amd/csrc/internal.h")
 TRAFFIC_SUMMARY = "profiles/k_walk_n4k7_traffic.md"
 
 
 def kernel_source_digest() -> str:
+    from paper_1606_07413_amd import build
     h = hashlib.sha256()
     for p in WALK_KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
+    h.update(" ".join(build.HIPCC_FLAGS).encode())
     return h.hexdigest()
 
 
