@@ -310,6 +310,13 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
 // and the butterfly of R (side 0) or R^T (side 1) adds the partner value when side ^ bit1(c_j) is
 // set, else subtracts it.  Values stay lazily reduced below 2^61 + 2^32: u + (2p - part) < 2^63,
 // and for s = a 2^31 + b, s 2^30 = a 2^61 + b 2^30 = a + b 2^30 (mod p).
+// part[j] = u[j ^ C] of lane src (C a compile-time register permutation).
+template <int C>
+__device__ inline void fetch4(const uint64_t* u, int src, uint64_t* part) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) part[j] = shfl64(u[j ^ C], src);
+}
+
 __device__ inline void rotate4(uint64_t* u, const uint32_t* dig, int h, int side, int gl, int gbase) {
     const uint32_t lx = (uint32_t)gl & 3, zr = (uint32_t)gl >> 2;
     uint32_t A = 0;  // bytes j: |x_r & z_r|
@@ -321,12 +328,16 @@ __device__ inline void rotate4(uint64_t* u, const uint32_t* dig, int h, int side
     for (int t = Geo<4>::HMAX - 1; t >= 0; --t) {
         if (t >= h) continue;
         const uint32_t p = dig[t];
-        // partner rows r ^ p: lane l ^ (p >> 2), register j ^ (p & 3) (constant register indices)
-        const bool s1 = (p & 1) != 0, s2 = (p & 2) != 0;
-        const uint64_t b0 = s1 ? u[1] : u[0], b1 = s1 ? u[0] : u[1];
-        const uint64_t b2 = s1 ? u[3] : u[2], b3 = s1 ? u[2] : u[3];
-        const uint64_t w[4] = {s2 ? b2 : b0, s2 ? b3 : b1, s2 ? b0 : b2, s2 ? b1 : b3};
+        // partner rows r ^ p: lane l ^ (p >> 2), register j ^ (p & 3).  p is wave-uniform, so the
+        // register order is a uniform branch and all eight partner fetches are issued together.
         const int src = gbase + (gl ^ (int)(p >> 2));
+        uint64_t part[4];
+        switch (p & 3) {
+            case 0: fetch4<0>(u, src, part); break;
+            case 1: fetch4<1>(u, src, part); break;
+            case 2: fetch4<2>(u, src, part); break;
+            default: fetch4<3>(u, src, part); break;
+        }
         const uint32_t xp = p & 15, zp = p >> 4, z2 = zp & 3;
         // uniform parts
         const uint32_t ja = ((z2 & 1) << 8) | (((z2 >> 1) & 1) << 16) | ((uint32_t)(__builtin_popcount(z2) & 1) << 24);
@@ -345,11 +356,12 @@ __device__ inline void rotate4(uint64_t* u, const uint32_t* dig, int h, int side
         const uint32_t plus_b = ((cb >> 1) & 0x01010101u) ^ side_b;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const uint64_t part = shfl64(w[j], src);
-            const uint64_t q = ((plus_b >> (8 * j)) & 1) ? part : (2 * P61 - part);
+            const uint64_t q = ((plus_b >> (8 * j)) & 1) ? part[j] : (2 * P61 - part[j]);
             const uint64_t sum = u[j] + q;
             const uint64_t r = (sum >> 31) + ((sum & 0x7fffffffull) << 30);
-            u[j] = ((acb >> (8 * j)) & 1) ? r : u[j];
+            // every row computes its butterfly; commuting rows keep u (a select, not a branch: the
+            // condition differs from lane to lane)
+            u[j] = __builtin_unpredictable(((acb >> (8 * j)) & 1) != 0) ? r : u[j];
         }
     }
 }
