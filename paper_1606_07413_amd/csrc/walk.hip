@@ -194,11 +194,11 @@ __device__ inline void side1_dot4(const Lds<NQ, WAVES>& L, uint32_t* limbs, cons
     wave_sync();
 }
 
-// n = 4: phi(S_c) u on MFMA.  D[m][r] = sum_q A_rq limb_m(u_q) + sum_q B_rq limb_m(2^31 u_q) over the
-// stacked K = 512 columns (v_mfma_i32_16x16x64_i8: M = 16 limb rows, 9 used; N = 16 matrix rows per
-// tile, 16 tiles; 8 K steps), so sum_m 2^(7m) D[m][r] = A u + 2^31 B u = 2^(-30 e) S_r (mod p).  Lane l
-// holds limbs 4g..4g+3 (g = l/16) of row l%16 of every tile; the limb groups are combined by a
-// reduce-scatter over lanes l^32, l^16, leaving each lane the rows (4g + j)*16 + l%16, j = 0..3.
+// n = 4: phi(S_c) u on MFMA (v_mfma_i32_16x16x64_i8; N = 16 matrix rows per tile, 16 tiles; K = 512
+// = [A | B] in 8 steps).  A-operand row m < 8 is digit m of u on the A half of K, row 8 + m digit m
+// of 2^31 u on the B half, so sum_m 256^m (D[m][r] + D[8 + m][r]) = A u + 2^31 B u = 2^(-30 e) S_r
+// (mod p).  Lane l holds rows 4g..4g+3 (g = l/16) of column l%16 of every tile; the four lane groups
+// are combined by a reduce-scatter over lanes l^32, l^16, leaving each lane four finished rows.
 // out[m] = bytes m of x[0..3] (byte j of out[m] = byte m of x[j]): two rounds of v_perm_b32.
 __device__ inline void transpose_bytes4(const uint32_t* x, uint32_t* out) {
     const uint32_t t0 = __builtin_amdgcn_perm(x[1], x[0], 0x05010400u);
@@ -301,6 +301,24 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
     }
 }
 
+// n <= 3 (one row per lane, r = gl): the h rotations with the same lazy reduction as rotate4.
+template <int NQ>
+__device__ inline void rotate1(uint64_t& u, const uint32_t* dig, int h, int side, int gl, int gbase) {
+    const uint32_t r = (uint32_t)gl;
+#pragma unroll
+    for (int t = Geo<NQ>::HMAX - 1; t >= 0; --t) {
+        if (t >= h) continue;
+        const uint32_t p = dig[t];
+        const uint64_t part = shfl64(u, gbase + (gl ^ (int)p));
+        // side 0 (R u): (u_r - s u_{r^p}) / sqrt2;  side 1 (R^T u): (u_r + s u_{r^p}) / sqrt2
+        const bool plus = (side == 1) == (rotation_sign<NQ>(p, r) > 0);
+        const uint64_t q = plus ? part : (2 * P61 - part);
+        const uint64_t sum = u + q;
+        const uint64_t rot = (sum >> 31) + ((sum & 0x7fffffffull) << 30);
+        u = anticommutes<NQ>(p, r) ? rot : u;
+    }
+}
+
 // n = 4: the h rotations applied to the key vector, branch-free.  Lane l holds rows r_j = 4 l + j,
 // so x_r = j | (l & 3) << 2 and z_r = l >> 2.  Each popcount in the commutation test and in the
 // phase c(p, r) of P_p P_r = i^c P_{p^r} splits into a lane term, a row term and uniform terms;
@@ -395,38 +413,7 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
     if constexpr (NQ == 4) {
         rotate4(u, dig, h, side, gl, gbase);
     } else {
-#pragma unroll
-    for (int t = HMAX - 1; t >= 0; --t) {
-        if (t < h) {
-            const uint32_t p = dig[t];
-            uint64_t w[RPL];
-            if constexpr (RPL == 1) {
-                w[0] = u[0];
-            } else {
-                // w[j] = u[j ^ (p & 3)] with constant register indices (no indexed private memory)
-                const bool s1 = (p & 1) != 0, s2 = (p & 2) != 0;
-                const uint64_t b0 = s1 ? u[1] : u[0], b1 = s1 ? u[0] : u[1];
-                const uint64_t b2 = s1 ? u[3] : u[2], b3 = s1 ? u[2] : u[3];
-                w[0] = s2 ? b2 : b0;
-                w[1] = s2 ? b3 : b1;
-                w[2] = s2 ? b0 : b2;
-                w[3] = s2 ? b1 : b3;
-            }
-            const int src = gbase + (gl ^ (int)(p >> Gm::LRPL));
-#pragma unroll
-            for (int j = 0; j < RPL; ++j) {
-                const uint64_t part = shfl64(w[j], src);
-                const uint32_t r = (uint32_t)(gl * RPL + j);
-                if (anticommutes<NQ>(p, r)) {
-                    const int s = rotation_sign<NQ>(p, r);
-                    // side 0 (R u):   (u_r - s u_{r^p}) / sqrt2;  side 1 (R^T u): (u_r + s u_{r^p}) / sqrt2
-                    const bool plus = (side == 1) == (s > 0);
-                    const uint64_t v = plus ? m61_add(u[j], part) : m61_sub(u[j], part);
-                    u[j] = m61_rot(v, 30);
-                }
-            }
-        }
-    }
+        rotate1<NQ>(u[0], dig, h, side, gl, gbase);
     }
 
     uint64_t S[RPL];
