@@ -142,6 +142,23 @@ __device__ inline uint64_t limbs_to_m61(const int32_t* acc) {
     return m61_add(l, m61_rot(hh, 35));
 }
 
+// Cross-half exchanges without LDS (gfx950 v_permlane32_swap / v_permlane16_swap).  permlane32_swap
+// exchanges lanes 32..63 of its first operand with lanes 0..31 of its second; permlane16_swap the
+// odd 16-lane rows of the first with the even rows of the second.  So half_add32(x, y) leaves lanes
+// 0..31 with x + x(lane + 32) and lanes 32..63 with y(lane - 32) + y; half_add16 likewise within
+// each 32-lane half (rows 0, 2 get x + x(lane + 16), rows 1, 3 get y(lane - 16) + y).
+// half_addNN(v, v) is v + v(lane ^ NN) in every lane.
+__device__ inline uint64_t half_add32(uint64_t x, uint64_t y) {
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)x, (uint32_t)y, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(x >> 32), (uint32_t)(y >> 32), false, false);
+    return (((uint64_t)hi[0] << 32) | lo[0]) + (((uint64_t)hi[1] << 32) | lo[1]);
+}
+__device__ inline uint64_t half_add16(uint64_t x, uint64_t y) {
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)x, (uint32_t)y, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(x >> 32), (uint32_t)(y >> 32), false, false);
+    return (((uint64_t)hi[0] << 32) | lo[0]) + (((uint64_t)hi[1] << 32) | lo[1]);
+}
+
 // n <= 3: phi(S_c) u with v_dot4_i32_i8 on A, B (int8, LDS) and 7-bit limbs of u.
 template <int NQ, int WAVES>
 __device__ inline void side1_dot4(const Lds<NQ, WAVES>& L, uint32_t* limbs, const uint64_t* u, int gl, int rot_e,
@@ -283,22 +300,15 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
             P[n0 + i] = P61 + (uint64_t)(x >> s_g) + (((uint64_t)x & m_g) << (61 - s_g));
         }
     }
-    // reduce-scatter over the four lane groups (lanes l^32, then l^16): plain 64-bit sums of the
-    // lazy residues, one fold at the end
-    const bool lowpair = g < 2, even = (g & 1) == 0;
+    // reduce-scatter over the four lane groups: lanes g < 2 keep tiles 0..7 and add their l^32
+    // partner's, lanes g >= 2 keep tiles 8..15; then within each half, even groups keep Q[0..3] and
+    // odd groups Q[4..7], adding the l^16 partner's.  Plain 64-bit sums of the lazy residues, one
+    // fold at the end.
     uint64_t Q[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const uint64_t send = lowpair ? P[8 + i] : P[i];
-        const uint64_t mine = lowpair ? P[i] : P[8 + i];
-        Q[i] = mine + xchg64<32>(send, lane);
-    }
+    for (int i = 0; i < 8; ++i) Q[i] = half_add32(P[i], P[8 + i]);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint64_t send = even ? Q[4 + i] : Q[i];
-        const uint64_t mine = even ? Q[i] : Q[4 + i];
-        S[i] = m61_rot(m61_fold(mine + xchg64<16>(send, lane)), rot_e);
-    }
+    for (int i = 0; i < 4; ++i) S[i] = m61_rot(m61_fold(half_add16(Q[i], Q[4 + i])), rot_e);
 }
 
 // n <= 3 (one row per lane, r = gl): the h rotations with the same lazy reduction as rotate4.
@@ -436,10 +446,17 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
         const uint64_t c2 = P61 - c;
         acc += mix64((c < c2 ? c : c2) ^ sp.salt_h);
     }
+    if constexpr (Gm::G == 64) {
 #pragma unroll
-    for (int off = 1; off < Gm::G; off <<= 1) acc += xchg64_dyn(acc, off, gbase + gl);
-    // one walk per wavefront: the sum is the same in every lane; finish on the scalar unit
-    if constexpr (Gm::G == 64) acc = uniform64(acc);
+        for (int off = 1; off < 16; off <<= 1) acc += xchg64_dyn(acc, off, gl);
+        acc = half_add16(acc, acc);
+        acc = half_add32(acc, acc);
+        // one walk per wavefront: the sum is the same in every lane; finish on the scalar unit
+        acc = uniform64(acc);
+    } else {
+#pragma unroll
+        for (int off = 1; off < Gm::G; off <<= 1) acc += xchg64_dyn(acc, off, gbase + gl);
+    }
     const uint64_t H = mix64(acc);
     out_h = H;
     out_pt = mulhi64(H, sp.n_half) | ((H & 1) << 32);
