@@ -268,8 +268,9 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
     // finished tile is combined at once, so only NG accumulators and NG fragments are live.
     // Accumulator row m = 4g + j of this lane is digit m % 8 of set g >> 1 (u, or 2^31 u), weight
     // 2^(8 (m % 8)) = 2^(32 (g & 1)) 2^(8j).  Each row sums 256 products, |acc| <= 256 * 128 * 127
-    // < 2^22, so x = acc_0 + 2^8 acc_1 + 2^16 acc_2 + 2^24 acc_3 lies in (-2^46, 2^46).  Its weighted
-    // residue, kept lazily in [0, 2^62): with s = 61 - 32 (g & 1),
+    // < 2^22, so x = acc_0 + 2^8 acc_1 + 2^16 acc_2 + 2^24 acc_3 lies in (-2^45, 2^45) and the sum of
+    // two such in (-2^46, 2^46).  Its weighted residue, kept lazily in [0, 2^62): with
+    // s = 61 - 32 (g & 1),
     //   2^(61 - s) x = (x >> s) 2^61 + (x mod 2^s) 2^(61 - s) = (x >> s) + (x mod 2^s) 2^(61 - s)  (mod p)
     // and y = p + (x >> s) + (x mod 2^s) 2^(61 - s).  Four such values sum below 2^64.
     constexpr int NG = 4;
@@ -296,17 +297,20 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
         for (int i = 0; i < NG; ++i) {
             const int32_t lo = acc[i][0] + acc[i][1] * 256;
             const int32_t hi = acc[i][2] + acc[i][3] * 256;
-            const int64_t x = (int64_t)lo + (int64_t)hi * 65536;
-            P[n0 + i] = P61 + (uint64_t)(x >> s_g) + (((uint64_t)x & m_g) << (61 - s_g));
+            P[n0 + i] = (uint64_t)((int64_t)lo + (int64_t)hi * 65536);
         }
     }
-    // reduce-scatter over the four lane groups: lanes g < 2 keep tiles 0..7 and add their l^32
-    // partner's, lanes g >= 2 keep tiles 8..15; then within each half, even groups keep Q[0..3] and
-    // odd groups Q[4..7], adding the l^16 partner's.  Plain 64-bit sums of the lazy residues, one
-    // fold at the end.
+    // reduce-scatter over the four lane groups.  Groups g and g ^ 2 carry the same digit weights, so
+    // their raw sums x add exactly first (|x| < 2^46): lanes g < 2 keep tiles 0..7 plus their l^32
+    // partner's, lanes g >= 2 keep tiles 8..15.  Then each x becomes its lazy weighted residue and
+    // within each half the even groups keep Q[0..3], the odd groups Q[4..7], adding the l^16
+    // partner's: plain 64-bit sums below 2^63, one fold at the end.
     uint64_t Q[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) Q[i] = half_add32(P[i], P[8 + i]);
+    for (int i = 0; i < 8; ++i) {
+        const int64_t x = (int64_t)half_add32(P[i], P[8 + i]);
+        Q[i] = P61 + (uint64_t)(x >> s_g) + (((uint64_t)x & m_g) << (61 - s_g));
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) S[i] = m61_rot(m61_fold(half_add16(Q[i], Q[4 + i])), rot_e);
 }
@@ -438,13 +442,15 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
         for (int j = 0; j < RPL; ++j) S[j] = m61_fold(u[j]);  // n = 4 keeps u lazily reduced
     }
 
-    // sign-normalised row digests and the multiset hash of the walk group's rows
+    // sign-normalised row digests and the multiset hash of the walk group's rows.  For c in
+    // [0, p]: p - c = c ^ p, and of c and p - c the smaller is the one with bit 60 clear, so
+    // min(c mod p, p - c mod p) = c ^ (bit 60 of c ? p : 0) (which also sends p to 0).
     uint64_t acc = 0;
 #pragma unroll
     for (int j = 0; j < RPL; ++j) {
-        const uint64_t c = m61_canon(S[j]);
-        const uint64_t c2 = P61 - c;
-        acc += mix64((c < c2 ? c : c2) ^ sp.salt_h);
+        const uint64_t c = S[j];
+        const uint64_t d = c ^ (P61 & (0ull - ((c >> 60) & 1)));
+        acc += mix64(d ^ sp.salt_h);
     }
     if constexpr (Gm::G == 64) {
 #pragma unroll
