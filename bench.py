@@ -75,12 +75,13 @@ def valu_ops_per_step(n: int, h: int) -> float:
                 R x 27 (multiset hash: salt xor 2, SplitMix64 finaliser 23 -- three 64-bit
                 xor-shifts and two 64-bit products by constants -- and the 64-bit add 2),
                 log2(64) x 4 x 64 (wave reduction of the sum)
-    side 1:     limb packing 2 sets x 9 limbs x R x 3, limb recombination R x 9 x 4 plus the
-                reduce-scatter (12 values x 64 lanes x 8) -- the S_c product itself runs on MFMA
+    side 1:     digit packing 2 sets x 8 signed base-256 digits x R x 3, digit recombination
+                R x 16 x 4 (16 partial sums per row, digits of both sets) plus the reduce-scatter
+                (12 values x 64 lanes x 8) -- the S_c product itself runs on MFMA
     """
     r = 4 ** n
     common = h * (r // 2) * 12 + r * 6 + r * 27 + 6 * 4 * 64
-    side1 = 2 * 9 * r * 3 + r * 9 * 4 + 12 * 64 * 8
+    side1 = 2 * 8 * r * 3 + r * 16 * 4 + 12 * 64 * 8
     return common + 0.5 * side1
 
 
