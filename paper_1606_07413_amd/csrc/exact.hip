@@ -304,18 +304,20 @@ __global__ __launch_bounds__(256) void k_signed_perm(const T* a, const T* b, con
 }
 
 // int8 packing of S for the walk kernels: phi[q4 * R + r] = bytes A[r][4 q4 .. 4 q4 + 3] (then B).
-// n = 4 uses the MFMA fragment layout instead: dword idx = ((nt * 8 + kk) * 64 + l) * 4 + w holds the
-// bytes S''[nt*16 + l%16][kk*64 + (l/16)*16 + 4w + c], c = 0..3, with S'' = [A | B] (256 x 512).
+// n >= 3 uses the MFMA fragment layout instead: with KK = 2R / 64 K steps and NT = R / 16 tiles,
+// dword idx = ((nt * KK + kk) * 64 + l) * 4 + w holds the bytes S''[nt*16 + l%16][kk*64 + (l/16)*16 +
+// 4w + c], c = 0..3, with S'' = [A | B] (R x 2R).
 template <int NQ, typename T>
 __global__ void k_pack_phi(const T* a, const T* b, uint32_t* phi, int* flag) {
     constexpr int R = EGeo<NQ>::R;
     constexpr int Q4 = R / 4;
     const int idx = threadIdx.x + blockIdx.x * blockDim.x;
-    if constexpr (NQ == 4) {
+    if constexpr (NQ >= 3) {
+        constexpr int KK = 2 * R / 64;
         if (idx >= 2 * Q4 * R) return;
         const int fi = idx >> 2, w = idx & 3;
         const int l = fi & 63, fk = fi >> 6;
-        const int nt = fk >> 3, kk = fk & 7;
+        const int nt = fk / KK, kk = fk % KK;
         const int r = nt * 16 + (l & 15);
         uint32_t word = 0;
         for (int c = 0; c < 4; ++c) {
@@ -551,17 +553,36 @@ __global__ __launch_bounds__(1024) void k_build_batch(const uint16_t* words, con
         __syncthreads();
         int e = 0;
         block_apply<NQ, T>(a, b, ta, tb, e, seq, nullptr, nseq, flag);
-        for (int i = threadIdx.x; i < Q4 * R; i += blockDim.x) {
-            const int q4 = i / R, r = i % R;
-            uint32_t wa = 0, wb = 0;
-            for (int c = 0; c < 4; ++c) {
-                const T va = a[r * R + 4 * q4 + c], vb = b[r * R + 4 * q4 + c];
-                if (va > 127 || va < -127 || vb > 127 || vb < -127) atomicOr(flag, 2);
-                wa |= ((uint32_t)(uint8_t)(int8_t)va) << (8 * c);
-                wb |= ((uint32_t)(uint8_t)(int8_t)vb) << (8 * c);
+        if constexpr (NQ == 3) {
+            // MFMA fragment layout (as k_pack_phi for n >= 3)
+            constexpr int KK = 2 * R / 64;
+            for (int i = threadIdx.x; i < 2 * Q4 * R; i += blockDim.x) {
+                const int fi = i >> 2, w = i & 3;
+                const int l = fi & 63, fk = fi >> 6;
+                const int nt = fk / KK, kk = fk % KK;
+                const int r = nt * 16 + (l & 15);
+                uint32_t word = 0;
+                for (int c = 0; c < 4; ++c) {
+                    const int qq = kk * 64 + (l >> 4) * 16 + 4 * w + c;
+                    const T v = qq < R ? a[r * R + qq] : b[r * R + qq - R];
+                    if (v > 127 || v < -127) atomicOr(flag, 2);
+                    word |= ((uint32_t)(uint8_t)(int8_t)v) << (8 * c);
+                }
+                phi_out[(size_t)t * 2 * Q4 * R + i] = word;
             }
-            phi_out[(size_t)t * 2 * Q4 * R + i] = wa;
-            phi_out[(size_t)t * 2 * Q4 * R + Q4 * R + i] = wb;
+        } else {
+            for (int i = threadIdx.x; i < Q4 * R; i += blockDim.x) {
+                const int q4 = i / R, r = i % R;
+                uint32_t wa = 0, wb = 0;
+                for (int c = 0; c < 4; ++c) {
+                    const T va = a[r * R + 4 * q4 + c], vb = b[r * R + 4 * q4 + c];
+                    if (va > 127 || va < -127 || vb > 127 || vb < -127) atomicOr(flag, 2);
+                    wa |= ((uint32_t)(uint8_t)(int8_t)va) << (8 * c);
+                    wb |= ((uint32_t)(uint8_t)(int8_t)vb) << (8 * c);
+                }
+                phi_out[(size_t)t * 2 * Q4 * R + i] = wa;
+                phi_out[(size_t)t * 2 * Q4 * R + Q4 * R + i] = wb;
+            }
         }
         if (threadIdx.x == 0) rot_e_out[t] = (int32_t)((30ll * e) % 61);
         block_features<NQ, T>(a, b, e, rows, idx, feat_out + (size_t)t * R * R);
@@ -702,7 +723,7 @@ hipError_t exact_signed_perm(const ExactDev& m, int32_t* ok, int32_t* perm, int8
 hipError_t exact_pack_phi(const ExactDev& m, uint32_t* phi, int* flag, hipStream_t s) {
     auto f = [&]<int NQ, typename T>() -> hipError_t {
         constexpr int R = 1 << (2 * NQ);
-        const int nthr = NQ == 4 ? R / 2 * R : R / 4 * R;
+        const int nthr = NQ >= 3 ? R / 2 * R : R / 4 * R;
         hipLaunchKernelGGL((k_pack_phi<NQ, T>), dim3((nthr + 255) / 256), dim3(256), 0, s, (const T*)m.a,
                            (const T*)m.b, phi, flag);
         return hipGetLastError();

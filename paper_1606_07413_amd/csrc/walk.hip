@@ -62,6 +62,18 @@ struct Lds<4, WAVES> {
     alignas(16) uint32_t zero_row[N4_ROW];  // A-operand rows 8..15 (no digit) read this
 };
 
+// n = 3: S_c as MFMA B-operand fragments in the same layout with KK = 2 K steps and NT = 4 tiles;
+// per walk (one per wavefront, lane l holds row l): digit rows [8][20] (64 bytes, one per column,
+// plus padding).
+constexpr int N3_NT = 4, N3_KK = 2, N3_ROW = 20;
+template <int WAVES>
+struct Lds<3, WAVES> {
+    v4i frag[N3_NT * N3_KK * 64];
+    uint64_t K[64];
+    uint32_t limbs[WAVES][N4_DIG * N3_ROW];
+    alignas(16) uint32_t zero_row[N3_ROW];
+};
+
 // A value every lane of the wavefront holds (the walk of a whole wavefront), made explicitly uniform.
 __device__ inline uint64_t uniform64(uint64_t v) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
@@ -84,6 +96,10 @@ __device__ void load_lds(Lds<NQ, WAVES>& L, const SpaceDev& sp) {
         const v4i* src = reinterpret_cast<const v4i*>(sp.phi);
         for (int i = threadIdx.x; i < N4_NT * N4_KK * 64; i += blockDim.x) L.frag[i] = src[i];
         for (int i = threadIdx.x; i < N4_ROW; i += blockDim.x) L.zero_row[i] = 0;
+    } else if constexpr (NQ == 3) {
+        const v4i* src = reinterpret_cast<const v4i*>(sp.phi);
+        for (int i = threadIdx.x; i < N3_NT * N3_KK * 64; i += blockDim.x) L.frag[i] = src[i];
+        for (int i = threadIdx.x; i < N3_ROW; i += blockDim.x) L.zero_row[i] = 0;
     } else {
         for (int i = threadIdx.x; i < NPHI; i += blockDim.x) {
             L.phiA[i] = sp.phi[i];
@@ -315,6 +331,54 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
     for (int i = 0; i < 4; ++i) S[i] = m61_rot(m61_fold(half_add16(Q[i], Q[4 + i])), rot_e);
 }
 
+// n = 3: phi(S_c) u on MFMA, the n = 4 scheme at R = 64 with one row per lane: A-operand rows 0..7
+// are the signed base-256 digits of u on the A half of K = 128, rows 8..15 those of 2^31 u on the
+// B half; 4 N tiles x 2 K steps.  Lane l holds accumulator rows 4g..4g+3 (g = l/16) of column l%16
+// of each tile; groups g and g ^ 2 have equal digit weights, so their raw sums add first (l^32),
+// then as lazy weighted residues within each half (l^16), leaving each lane one finished row.
+template <int WAVES>
+__device__ inline void side1_mfma3(const Lds<3, WAVES>& L, uint32_t* limbs, const uint64_t* u, int lane, int rot_e,
+                                   uint64_t* S) {
+    const int g = lane >> 4, n16 = lane & 15;
+    const uint32_t* arow0 = n16 < N4_DIG ? limbs + n16 * N3_ROW : L.zero_row;
+    const uint32_t* arow1 = n16 >= N4_DIG ? limbs + (n16 - N4_DIG) * N3_ROW : L.zero_row;
+    uint8_t* lb = reinterpret_cast<uint8_t*>(limbs);
+    v4i afr[N3_KK];
+#pragma unroll
+    for (int set = 0; set < 2; ++set) {
+        // digits as for n = 4 (bytes of v + 0x8080808080808080, each minus 128); column = lane
+        const uint64_t w = set ? (u[0] >> 30) + ((u[0] & 0x3fffffffull) << 31) : u[0];
+        const uint64_t b = w + 0x8080808080808080ull;
+#pragma unroll
+        for (int m = 0; m < N4_DIG; ++m) lb[m * N3_ROW * 4 + lane] = (uint8_t)((b >> (8 * m)) ^ 0x80);
+        wave_sync();
+        const uint32_t* arow = set ? arow1 : arow0;
+        afr[set] = *reinterpret_cast<const v4i*>(&arow[g * 4]);
+        wave_sync();
+    }
+    const uint32_t s_g = 61 - 32 * (uint32_t)(g & 1);
+    const uint64_t m_g = (1ull << s_g) - 1;
+    uint64_t P[N3_NT];
+#pragma unroll
+    for (int nt = 0; nt < N3_NT; ++nt) {
+        v4i acc = v4i{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < N3_KK; ++kk)
+            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(afr[kk], L.frag[(nt * N3_KK + kk) * 64 + lane], acc, 0, 0, 0);
+        // |acc| <= 64 * 128 * 127 < 2^20
+        const int32_t lo = acc[0] + acc[1] * 256;
+        const int32_t hi = acc[2] + acc[3] * 256;
+        P[nt] = (uint64_t)((int64_t)lo + (int64_t)hi * 65536);
+    }
+    uint64_t Q[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int64_t x = (int64_t)half_add32(P[i], P[2 + i]);
+        Q[i] = P61 + (uint64_t)(x >> s_g) + (((uint64_t)x & m_g) << (61 - s_g));
+    }
+    S[0] = m61_rot(m61_fold(half_add16(Q[0], Q[1])), rot_e);
+}
+
 // n <= 3 (one row per lane, r = gl): the h rotations with the same lazy reduction as rotate4.
 template <int NQ>
 __device__ inline void rotate1(uint64_t& u, const uint32_t* dig, int h, int side, int gl, int gbase) {
@@ -434,6 +498,8 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
     if (side) {
         if constexpr (NQ == 4) {
             side1_mfma<WAVES>(L, limbs, u, gl, sp.rot_e, S);
+        } else if constexpr (NQ == 3) {
+            side1_mfma3<WAVES>(L, limbs, u, gl, sp.rot_e, S);
         } else {
             side1_dot4<NQ, WAVES>(L, limbs, u, gl, sp.rot_e, S);
         }
@@ -574,8 +640,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_canon(SpaceDev sp, const uint32_
 template <int NQ>
 __global__ void k_pack_i32(const int32_t* a, const int32_t* b, int64_t count, uint32_t* phi, int* flag) {
     constexpr int R = Geo<NQ>::R, Q4 = Geo<NQ>::Q4;
-    if constexpr (NQ == 4) {
-        // MFMA fragment layout (see Lds<4>): 2 * Q4 * R dwords per matrix
+    if constexpr (NQ >= 3) {
+        // MFMA fragment layout (see Lds<4>, Lds<3>): 2 * Q4 * R dwords per matrix, KK = 2R / 64 K steps
+        constexpr int KK = 2 * R / 64;
         const int64_t total4 = count * 2 * Q4 * R;
         for (int64_t idx = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; idx < total4;
              idx += (int64_t)blockDim.x * gridDim.x) {
@@ -583,7 +650,7 @@ __global__ void k_pack_i32(const int32_t* a, const int32_t* b, int64_t count, ui
             const int rem = (int)(idx % (2 * Q4 * R));
             const int fi = rem >> 2, w = rem & 3;
             const int l = fi & 63, fk = fi >> 6;
-            const int nt = fk >> 3, kk = fk & 7;
+            const int nt = fk / KK, kk = fk % KK;
             const int r = nt * 16 + (l & 15);
             const int32_t* am = a + m * R * R;
             const int32_t* bm = b + m * R * R;
