@@ -10,8 +10,9 @@
 //   side 1: S = phi(S_c) u,  u = R(p_0)^T ( ... (R(p_{h-1})^T K))
 // Each factor touches the vector by the channel rep's column rule (one butterfly per
 // anticommuting row; the 1/sqrt2 is a 61-bit rotation by 30), and the side-1 product with the
-// fixed chunk matrix S_c = (A + B sqrt2)/sqrt2^e runs as int8 dot products (v_dot4_i32_i8) of A
-// and B against 7-bit limbs of u, A and B resident in LDS.  Then (nu + h of Sec. 2):
+// fixed chunk matrix S_c = (A + B sqrt2)/sqrt2^e runs on int8 MFMA for n >= 3 (A and B resident in
+// LDS as B-operand fragments, against signed base-256 digits of u and 2^31 u) and on int8 dot
+// products (v_dot4_i32_i8) against 7-bit limbs of u for n <= 2.  Then (nu + h of Sec. 2):
 //   D_r = min(S_r, p - S_r)   (sign-normalised row: negating a row negates S_r)
 //   H = mix64(sum_r mix64(D_r ^ salt_h))   (mod 2^64: an additive multiset hash, so the order of
 //                                           the rows -- a left signed permutation -- drops out)
@@ -38,7 +39,7 @@ struct Geo {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-// n <= 3: S_c as int8 dwords [q/4][r] for v_dot4; per-walk limb buffer [q/4][limb].
+// n <= 2: S_c as int8 dwords [q/4][r] for v_dot4; per-walk limb buffer [q/4][limb].
 template <int NQ, int WAVES>
 struct Lds {
     uint32_t phiA[Geo<NQ>::Q4 * Geo<NQ>::R];
@@ -175,7 +176,7 @@ __device__ inline uint64_t half_add16(uint64_t x, uint64_t y) {
     return (((uint64_t)hi[0] << 32) | lo[0]) + (((uint64_t)hi[1] << 32) | lo[1]);
 }
 
-// n <= 3: phi(S_c) u with v_dot4_i32_i8 on A, B (int8, LDS) and 7-bit limbs of u.
+// n <= 2: phi(S_c) u with v_dot4_i32_i8 on A, B (int8, LDS) and 7-bit limbs of u.
 template <int NQ, int WAVES>
 __device__ inline void side1_dot4(const Lds<NQ, WAVES>& L, uint32_t* limbs, const uint64_t* u, int gl, int rot_e,
                                   uint64_t* S) {
