@@ -1336,7 +1336,7 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
                     blocks_n[n] = 0;
                     continue;
                 }
-                const int cap_blocks = std::max(1, (n == 4 ? cus : 4 * cus) / active);
+                const int cap_blocks = std::max(1, tcw::walk_grid_blocks(n, c->device) / active);
                 iters_n[n] = 1 << 30;
                 for (int i = 0; i < count; ++i) {
                     BatchTarget& b = bt[i];
