@@ -123,6 +123,140 @@ def cpu_baseline(n, k, chunk, seed, delta, seconds: float):
                       f"{per_proc} per process over {cores} processes, {wall:.1f} s wall"}
 
 
+def _oracle_search_worker(args):
+    n, k, target_seed, walk_seed, delta, walks, beta, enum_max = args
+    import seeded_inputs
+    from oracle import search as osearch
+    from oracle import zmat
+    tw = seeded_inputs.target_words(n, k, target_seed)
+    u = zmat.target_from_words(n, tw.paulis, tw.clifford)
+    r = osearch.search(u, n, k, walk_seed, lambda kk: delta, walks=walks, beta=beta, enum_max=enum_max)
+    return target_seed, (r.decomposition.t if r.found else None), r.seconds, r.stats.steps
+
+
+def cpu_configs(seconds: float):
+    """The oracle on the host cores at every configuration: walk steps/s in one process and in a
+    pool of one process per core (bounded samples of about `seconds` each), and the measured
+    time-to-solution of the n = 2, k = 4 searches (16 targets, the same walk parameters as the GPU
+    leg), one target per process."""
+    import seeded_inputs
+    cores = min(os.cpu_count() or 1, 16)
+    rates = {}
+    for name, n, k in (("n2k4", 2, 4), ("n3k6", 3, 6), ("n4k7", 4, 7)):
+        spec = seeded_inputs.WORKLOADS[name]
+        tw = seeded_inputs.target_words(n, k, spec["target_seeds"][0])
+        chunk = tw.paulis[0] if k % 2 else 0
+        n_half = (4 ** n - 1) ** (k // 2)
+        _, dt = _oracle_worker((n, k, chunk, 5, spec["delta"], seeded_inputs.random_points(n_half, 2, 5)))
+        per = max(1, int(seconds / max(dt / 2, 1e-4)))
+        cnt, t1 = _oracle_worker((n, k, chunk, 5, spec["delta"], seeded_inputs.random_points(n_half, per, 7)))
+        per_proc = max(1, per // 2)
+        jobs = [(n, k, chunk, 5, spec["delta"], seeded_inputs.random_points(n_half, per_proc, 100 + i))
+                for i in range(cores)]
+        with mp.get_context("spawn").Pool(cores) as pool:
+            res = pool.map(_oracle_worker, jobs)
+        # the processes run side by side: the pool's rate is the sum of each one's own rate
+        rates[name] = {"single_process": cnt / t1, "pool": sum(c / dt for c, dt in res), "cores": cores}
+        _log(f"oracle {name}: {cnt / t1:.1f} steps/s single, {rates[name]['pool']:.1f} pool")
+    spec = seeded_inputs.WORKLOADS["n2k4"]
+    jobs = [(2, 4, s, spec["walk_seed_base"] + s, spec["delta"], spec["walks"], 16, 64) for s in spec["target_seeds"]]
+    per_target = {}
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        for seed_t, t, secs, steps in pool.imap_unordered(_oracle_search_worker, jobs):
+            per_target[seed_t] = {"found_t": t, "seconds": secs, "steps": steps}
+            _log(f"oracle n2k4 target {seed_t}: t={t} {secs:.2f} s")
+    wall = time.perf_counter() - t0
+    secs = [v["seconds"] for v in per_target.values()]
+    return {"walk_steps_per_s": rates,
+            "tts_n2k4": {"targets": len(jobs), "found": sum(1 for v in per_target.values() if v["found_t"] is not None),
+                         "mean_s": sum(secs) / len(secs), "max_s": max(secs), "wall_s": wall, "processes": cores,
+                         "per_target": [per_target[s] | {"target_seed": s} for s in sorted(per_target)]}}
+
+
+def config_legs(ctx):
+    """The two smaller configurations on the GPU: time-to-solution of the n = 2, k = 4 searches
+    (16 targets, 64 walks, theta = 2^-4, 2^10 slots; depths below 4 enumerated) and of the n = 3,
+    k = 6 searches (8 targets x 20 walk seeds, 2^16 walks, theta = 2^-8, 2^20 slots), plus the
+    walk-kernel rate at n = 2 and n = 3 for the configured and for 2^20 walks."""
+    import statistics
+
+    import seeded_inputs
+    from paper_1606_07413_amd import tcw
+    out = {}
+    spec = seeded_inputs.WORKLOADS["n2k4"]
+    per = []
+    for s in spec["target_seeds"]:
+        tw = seeded_inputs.target_words(2, 4, s)
+        tgt = ctx.target_from_words(2, tw.paulis, tw.clifford)
+        p = ctx.default_params(2)
+        p.k_max = 4
+        p.seed = spec["walk_seed_base"] + s
+        p.delta = spec["delta"]
+        p.walks = spec["walks"]
+        p.log2_table = spec["log2_table"]
+        p.enum_max = 64
+        p.budget_beta = 16
+        r = ctx.search(tgt, p)
+        per.append({"target_seed": s, "found_t": r.t if r.status else None, "seconds": r.seconds,
+                    "steps": r.stats.steps})
+    _log(f"n2k4: {sum(1 for v in per if v['found_t'] is not None)}/{len(per)} found")
+    out["tts_n2k4"] = {"targets": len(per), "found": sum(1 for v in per if v["found_t"] is not None),
+                       "mean_s": statistics.mean(v["seconds"] for v in per),
+                       "max_s": max(v["seconds"] for v in per), "per_target": per}
+    spec = seeded_inputs.WORKLOADS["n3k6"]
+    # the configured theta = 2^-8, then the library's default (theta from the table size)
+    for label, delta in (("tts_n3k6", spec["delta"]), ("tts_n3k6_default_theta", -1)):
+        rows = []
+        for s in spec["target_seeds"]:
+            tw = seeded_inputs.target_words(3, 6, s)
+            tgt = ctx.target_from_words(3, tw.paulis, tw.clifford)
+            secs, steps, ts = [], [], []
+            for rep in range(20):
+                p = ctx.default_params(3)
+                p.k_max = 6
+                p.seed = spec["walk_seed_base"] + 100 * s + rep
+                p.delta = delta
+                p.walks = spec["walks"]
+                p.log2_table = spec["log2_table"]
+                p.max_seconds = 60
+                r = ctx.search(tgt, p)
+                ts.append(r.t if r.status else None)
+                secs.append(r.seconds)
+                steps.append(r.stats.steps)
+            rows.append({"target_seed": s, "found_t": sorted(set(t for t in ts if t is not None)),
+                         "not_found": sum(1 for t in ts if t is None), "mean_s": statistics.mean(secs),
+                         "median_s": statistics.median(secs), "max_s": max(secs),
+                         "mean_steps": statistics.mean(steps)})
+            _log(f"{label} target {s}: t={rows[-1]['found_t']} not found {rows[-1]['not_found']} "
+                 f"mean {rows[-1]['mean_s']:.3f} s over 20 walk seeds")
+        out[label] = {"targets": len(rows), "reps": 20, "delta": delta, "per_target": rows,
+                      "not_found": sum(r["not_found"] for r in rows),
+                      "mean_s": statistics.mean(r["mean_s"] for r in rows)}
+    rates = {}
+    for name, n, k, walks_list in (("n2k4", 2, 4, (64, 1 << 20)), ("n3k6", 3, 6, (1 << 16, 1 << 20))):
+        spec = seeded_inputs.WORKLOADS[name]
+        tw = seeded_inputs.target_words(n, k, spec["target_seeds"][0])
+        tgt = ctx.target_from_words(n, tw.paulis, tw.clifford)
+        for walks in walks_list:
+            w = ctx.walk(tgt, k, 0, 77, spec["delta"], walks=walks, log2_table=spec["log2_table"],
+                         cap=20 << spec["delta"])
+            iters = 64 if walks < 4096 else 8
+            w.run(iters)
+            ms = []
+            before = w.stats().steps
+            for _ in range(10):
+                w.run(iters)
+                ms.append(w.last_ms())
+            steps = w.stats().steps - before
+            w.end()
+            rates[f"{name}_walks{walks}"] = {"walk_steps_per_s": steps / (sum(ms) * 1e-3),
+                                             "kernel_ms": sum(ms) / len(ms), "iters_per_launch": iters}
+            _log(f"walk {name} {walks} walks: {steps / (sum(ms) * 1e-3):.3g} steps/s")
+    out["walk_rates"] = rates
+    return out
+
+
 def batch_leg(ctx, cap: float):
     """64 seeded targets, n in {2,3,4}, k in {3..7}, searched together (autotuned walks and tables)."""
     import seeded_inputs
@@ -388,6 +522,10 @@ def main():
                     help="also synthesise Toffoli, Fredkin and Peres (n = 3, T-count 7) repeatedly")
     ap.add_argument("--named-reps", type=int, default=20)
     ap.add_argument("--named-reps-default-theta", type=int, default=3)
+    ap.add_argument("--configs", action="store_true",
+                    help="also run the n = 2, k = 4 and n = 3, k = 6 searches and walk rates")
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="with the CPU baseline, also time the oracle at every configuration")
     ap.add_argument("--mlp", action="store_true", help="also train the depth-order network and compare orders")
     ap.add_argument("--mlp-train", type=int, default=1 << 16, help="training circuits")
     ap.add_argument("--mlp-epochs", type=int, default=8)
@@ -447,6 +585,7 @@ def main():
         t3 = ctx.target_from_words(3, tw3.paulis, tw3.clifford)
         p3 = ctx.default_params(3)
         p3.k_max = 6
+        p3.delta = seeded_inputs.WORKLOADS["n3k6"]["delta"]
         p3.seed = 2001
         p3.max_seconds = 120
         r3 = ctx.search(t3, p3)
@@ -488,6 +627,8 @@ def main():
         "walk_stats": st.as_dict(),
     }
     out.update(extra)
+    if args.configs:
+        out["configs"] = config_legs(ctx)
     if args.batch:
         out["batch64"] = batch_leg(ctx, args.batch_cap)
     if args.named:
@@ -496,6 +637,8 @@ def main():
         out["learned_order"] = mlp_leg(ctx, args.mlp_train, args.mlp_epochs, args.mlp_eval, args.mlp_cap)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, k, chunk, seed, delta, args.cpu_seconds)
+        if args.cpu_configs:
+            out["cpu_baseline"]["configs"] = cpu_configs(5.0)
     print(json.dumps(out), flush=True)
 
 

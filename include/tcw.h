@@ -174,7 +174,9 @@ int tcw_walk_end(tcw_walk* w);
 
 typedef struct tcw_walk_params {
     int32_t k_max;            /* deepest depth searched (plain order 0..k_max) */
-    int32_t delta;            /* theta = 2^-delta for walk spaces; < 0: 4, 8 or 12 by n = 2, 3, 4 */
+    int32_t delta;            /* theta = 2^-delta for walk spaces; < 0 (default): per space, the largest theta
+                                 (delta >= 1) whose 2 N theta distinguished points per version fill at most a
+                                 quarter of the table (Sec. 5.1: larger theta is faster while memory holds them) */
     int64_t walks;            /* concurrent walks */
     int32_t log2_table;       /* table slots 2^log2_table */
     uint64_t seed;            /* search seed */

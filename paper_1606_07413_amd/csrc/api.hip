@@ -177,7 +177,17 @@ int prepare_space(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, Space& o
     return TCW_OK;
 }
 
-int default_delta(int n) { return n <= 2 ? 4 : (n == 3 ? 8 : 12); }
+int default_log2_table(int n) { return n <= 2 ? 12 : (n == 3 ? 20 : 26); }
+
+// theta of a walk space when the caller leaves it open.  The time to a golden collision falls as
+// theta rises for as long as memory holds the distinguished points (Sec. 5.1), so take the largest
+// theta = 2^-delta, delta >= 1, whose 2 N theta distinguished points per function version fill at
+// most a quarter of the table: 8 N <= 2^(log2_table + delta).
+int auto_delta(uint64_t npts, int log2_table) {
+    int d = 1;
+    while (d < 30 && (npts << 3) > (1ull << (log2_table + d))) ++d;
+    return d;
+}
 int default_iters(int n) { return n <= 2 ? 64 : (n == 3 ? 32 : 8); }
 
 }  // namespace
@@ -664,7 +674,7 @@ void tcw_default_params(tcw_walk_params* p, int n) {
     p->k_max = 7;
     p->delta = -1;
     p->walks = n <= 2 ? 64 : (n == 3 ? (1 << 16) : (1 << 20));
-    p->log2_table = n <= 2 ? 12 : (n == 3 ? 20 : 26);
+    p->log2_table = default_log2_table(n);
     p->seed = 1;
     p->version = 0;
     p->trail_cap_factor = 20;
@@ -932,13 +942,15 @@ extern "C" int tcw_search(tcw_ctx* c, const tcw_target* t, const tcw_walk_params
             if (cl > (int)xi) cl = (int)xi;
         }
         const bool enumerate = (int64_t)npts <= p->enum_max;
-        const int delta = p->delta >= 0 ? p->delta : default_delta(n);
+        const int delta = p->delta >= 0 ? p->delta : auto_delta(npts, p->log2_table);
         if (k % 2 && !enumerate && p->chunk_parallel != 1) {
             // chunks in groups of G searched concurrently, one batch member each
             const int G = p->chunk_parallel <= 0 ? cl - cf + 1 : p->chunk_parallel;
             for (int first = cf; first <= cl && !found; first += G) {
                 if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) break;
-                rc = search_chunks_concurrent(c, t, p, k, first, std::min(cl, first + G - 1), delta, res, &found, t0);
+                // each member resolves an open delta against its own (smaller) table
+                rc = search_chunks_concurrent(c, t, p, k, first, std::min(cl, first + G - 1), p->delta, res, &found,
+                                              t0);
                 if (rc) return rc;
             }
         }
@@ -1174,7 +1186,8 @@ int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStr
             continue;
         }
         // a walk space
-        const int delta = b.p.delta >= 0 ? b.p.delta : default_delta(n);
+        const int delta =
+            b.p.delta >= 0 ? b.p.delta : auto_delta(npts, b.p.log2_table > 0 ? b.p.log2_table : default_log2_table(n));
         TunedCfg cfg;
         if (b.p.walks <= 0 || b.p.log2_table <= 0 || b.p.iters_per_launch <= 0) {
             if ((rc = autotune(c, b.t, b.k, b.chunk, delta, b.p.seed, &cfg))) return rc;

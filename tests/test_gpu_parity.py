@@ -257,7 +257,7 @@ def test_checkpoint_resume_continues_trails(ctx):
     w2.end()
 
 
-@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+@pytest.mark.parametrize("seed", list(range(1, 17)))
 def test_search_n2_cfg1(ctx, seed):
     """n = 2, k = 4 targets; depths 0..3 are enumerated exhaustively, k = 4 by 64 walks at
     theta = 2^-4 (budget 16 N / theta).  The T-count found equals the brute-force minimum (targets
@@ -319,6 +319,27 @@ def test_search_n3_cfg2(ctx):
     d = osearch.Decomposition(t=dec.t, paulis_desc=dec.paulis_desc, perm=dec.perm, sign=dec.sign)
     assert osearch.reconstruct(3, d).equals(u)
     say("n3 k6 search", res.seconds, "s", res.stats.steps, "steps", res.versions, "versions")
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_search_n3_default_theta(ctx, seed):
+    """n = 3, k = 6 targets of T-count 6 (depths <= 5 are enumerated exhaustively, so 6 is the
+    minimum) with the default theta, chosen from the table size: the search reaches depth 6 by walks
+    and returns an exact decomposition of T-count 6."""
+    from paper_1606_07413_amd import tcw
+    say("search n3 k6 default theta", seed)
+    tw, u = oracle_target(3, 6, seed)
+    tgt = ctx.target_from_words(3, tw.paulis, tw.clifford)
+    p = ctx.default_params(3)
+    p.k_max = 6
+    p.seed = 2100 + seed
+    p.max_seconds = 60
+    res = ctx.search(tgt, p)
+    dec = tcw.decomposition_of(res)
+    assert dec is not None and dec.t == 6
+    d = osearch.Decomposition(t=dec.t, paulis_desc=dec.paulis_desc, perm=dec.perm, sign=dec.sign)
+    assert osearch.reconstruct(3, d).equals(u)
+    say("n3 k6 default theta", res.seconds, "s", res.stats.steps, "steps", res.versions, "versions")
 
 
 def test_autotune_choices(ctx):
