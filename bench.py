@@ -257,8 +257,9 @@ def config_legs(ctx):
     return out
 
 
-def batch_leg(ctx, cap: float):
-    """64 seeded targets, n in {2,3,4}, k in {3..7}, searched together (autotuned walks and tables)."""
+def batch_leg(ctx, cap: float, configured_theta: bool = True):
+    """64 seeded targets, n in {2,3,4}, k in {3..7}, searched together (autotuned walks and tables);
+    theta = 2^-4, 2^-8, 2^-12 by n as configured, or the library's default (from the table size)."""
     import seeded_inputs
     from paper_1606_07413_amd import tcw
     spec = seeded_inputs.WORKLOADS["batch64"]
@@ -269,7 +270,7 @@ def batch_leg(ctx, cap: float):
         p = ctx.default_params(tw.n)
         p.k_max = tw.k
         p.seed = 5000 + i
-        p.delta = spec["delta_by_n"][tw.n]
+        p.delta = spec["delta_by_n"][tw.n] if configured_theta else -1
         p.walks = 0
         p.log2_table = 0
         p.iters_per_launch = 0
@@ -282,6 +283,8 @@ def batch_leg(ctx, cap: float):
     for tw, r in zip(words, results):
         per.append({"n": tw.n, "k": tw.k, "found_t": r.t if r.status else None, "seconds": round(r.seconds, 4),
                     "censored": not r.status, "steps": r.stats.steps})
+    _log(f"batch64 ({'configured' if configured_theta else 'default'} theta): "
+         f"{sum(1 for r in results if r.status)}/{len(words)} found in {wall:.1f} s")
     return {"targets": len(words), "found": sum(1 for r in results if r.status), "wall_seconds": wall,
             "aggregate_walk_steps_per_s": agg, "per_target_cap_s": cap, "per_target": per}
 
@@ -631,6 +634,7 @@ def main():
         out["configs"] = config_legs(ctx)
     if args.batch:
         out["batch64"] = batch_leg(ctx, args.batch_cap)
+        out["batch64_default_theta"] = batch_leg(ctx, args.batch_cap, configured_theta=False)
     if args.named:
         out["named_n3_t7"] = named_leg(ctx, args.named_reps, args.named_reps_default_theta)
     if args.mlp:
