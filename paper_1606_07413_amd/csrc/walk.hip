@@ -165,15 +165,27 @@ __device__ inline uint64_t limbs_to_m61(const int32_t* acc) {
 // 0..31 with x + x(lane + 32) and lanes 32..63 with y(lane - 32) + y; half_add16 likewise within
 // each 32-lane half (rows 0, 2 get x + x(lane + 16), rows 1, 3 get y(lane - 16) + y).
 // half_addNN(v, v) is v + v(lane ^ NN) in every lane.
+// The halves are joined into a register pair before the add (an empty asm the compiler cannot see
+// through), so the sum is one 64-bit add rather than a split low add, carry and high add.
+__device__ inline uint64_t join64(uint32_t lo, uint32_t hi) {
+    uint64_t v = ((uint64_t)hi << 32) | lo;
+    asm("" : "+v"(v));
+    return v;
+}
 __device__ inline uint64_t half_add32(uint64_t x, uint64_t y) {
     const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)x, (uint32_t)y, false, false);
     const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(x >> 32), (uint32_t)(y >> 32), false, false);
-    return (((uint64_t)hi[0] << 32) | lo[0]) + (((uint64_t)hi[1] << 32) | lo[1]);
+    return join64(lo[0], hi[0]) + join64(lo[1], hi[1]);
 }
 __device__ inline uint64_t half_add16(uint64_t x, uint64_t y) {
     const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)x, (uint32_t)y, false, false);
     const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(x >> 32), (uint32_t)(y >> 32), false, false);
-    return (((uint64_t)hi[0] << 32) | lo[0]) + (((uint64_t)hi[1] << 32) | lo[1]);
+    return join64(lo[0], hi[0]) + join64(lo[1], hi[1]);
+}
+// 32-bit version: x + x(lane + 32) in lanes 0..31, y(lane - 32) + y in lanes 32..63.
+__device__ inline int32_t half_add32_i32(int32_t x, int32_t y) {
+    const auto v = __builtin_amdgcn_permlane32_swap((uint32_t)x, (uint32_t)y, false, false);
+    return (int32_t)(v[0] + v[1]);
 }
 
 // n <= 2: phi(S_c) u with v_dot4_i32_i8 on A, B (int8, LDS) and 7-bit limbs of u.
@@ -293,9 +305,20 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
     constexpr int NG = 4;
     const uint32_t s_g = 61 - 32 * (uint32_t)(g & 1);
     const uint64_t m_g = (1ull << s_g) - 1;
-    uint64_t P[N4_NT];
+    // Fragments of tiles 8..15 lie beyond the 64 KiB reach of a DS immediate offset: they are read
+    // through a second base address (kept opaque, so it is formed once instead of per read).
+    uint32_t hi_base = 8 * N4_KK * 64;
+    asm("" : "+v"(hi_base));
+    const v4i* frag_hi = L.frag + hi_base;
+    // Per tile, the two 32-bit halves of the raw sum: lo = acc_0 + 2^8 acc_1, hi = acc_2 + 2^8 acc_3,
+    // |lo|, |hi| <= 257 * 256 * 128 * 127 < 2^30.
+    int32_t lo[N4_NT], hi[N4_NT];
+    uint64_t Q[8];
+    // tile groups in the order 0..3, 8..11, 4..7, 12..15: after the second and the fourth group the
+    // tile pairs (i, 8 + i) are complete and reduce at once, which keeps few halves live
 #pragma unroll
-    for (int n0 = 0; n0 < N4_NT; n0 += NG) {
+    for (int gi = 0; gi < 4; ++gi) {
+        const int n0 = (gi & 1) * 8 + (gi >> 1) * NG;
         v4i acc[NG];
 #pragma unroll
         for (int i = 0; i < NG; ++i) acc[i] = v4i{0, 0, 0, 0};
@@ -303,7 +326,10 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
         for (int kk = 0; kk < N4_KK; ++kk) {
             v4i bf[NG];
 #pragma unroll
-            for (int i = 0; i < NG; ++i) bf[i] = L.frag[((n0 + i) * N4_KK + kk) * 64 + lane];
+            for (int i = 0; i < NG; ++i) {
+                const int t = n0 + i;
+                bf[i] = t < 8 ? L.frag[(t * N4_KK + kk) * 64 + lane] : frag_hi[((t - 8) * N4_KK + kk) * 64 + lane];
+            }
 #pragma unroll
             for (int i = 0; i < NG; ++i)
                 acc[i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(afr[kk], bf[i], acc[i], 0, 0, 0);
@@ -312,22 +338,24 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
         }
 #pragma unroll
         for (int i = 0; i < NG; ++i) {
-            const int32_t lo = acc[i][0] + acc[i][1] * 256;
-            const int32_t hi = acc[i][2] + acc[i][3] * 256;
-            P[n0 + i] = (uint64_t)((int64_t)lo + (int64_t)hi * 65536);
+            lo[n0 + i] = acc[i][0] + acc[i][1] * 256;
+            hi[n0 + i] = acc[i][2] + acc[i][3] * 256;
+        }
+        // reduce-scatter over the four lane groups.  Groups g and g ^ 2 carry the same digit weights,
+        // so their halves add exactly first, still in 32 bits (|lo + lo'| < 2^31): lanes g < 2 keep
+        // tiles 0..7 plus their l^32 partner's, lanes g >= 2 keep tiles 8..15.  The raw sum
+        // x = lo + 2^16 hi (|x| < 2^47) then becomes its lazy weighted residue.
+        if (gi & 1) {
+#pragma unroll
+            for (int i = n0 - 8; i < n0 - 8 + NG; ++i) {
+                const int64_t x =
+                    (int64_t)half_add32_i32(lo[i], lo[8 + i]) + (int64_t)half_add32_i32(hi[i], hi[8 + i]) * 65536;
+                Q[i] = P61 + (uint64_t)(x >> s_g) + (((uint64_t)x & m_g) << (61 - s_g));
+            }
         }
     }
-    // reduce-scatter over the four lane groups.  Groups g and g ^ 2 carry the same digit weights, so
-    // their raw sums x add exactly first (|x| < 2^46): lanes g < 2 keep tiles 0..7 plus their l^32
-    // partner's, lanes g >= 2 keep tiles 8..15.  Then each x becomes its lazy weighted residue and
     // within each half the even groups keep Q[0..3], the odd groups Q[4..7], adding the l^16
     // partner's: plain 64-bit sums below 2^63, one fold at the end.
-    uint64_t Q[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int64_t x = (int64_t)half_add32(P[i], P[8 + i]);
-        Q[i] = P61 + (uint64_t)(x >> s_g) + (((uint64_t)x & m_g) << (61 - s_g));
-    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) S[i] = m61_rot(m61_fold(half_add16(Q[i], Q[4 + i])), rot_e);
 }
@@ -398,15 +426,38 @@ __device__ inline void rotate1(uint64_t& u, const uint32_t* dig, int h, int side
     }
 }
 
-// n = 4: the h rotations applied to the key vector, branch-free.  Lane l holds rows r_j = 4 l + j,
-// so x_r = j | (l & 3) << 2 and z_r = l >> 2.  Each popcount in the commutation test and in the
-// phase c(p, r) of P_p P_r = i^c P_{p^r} splits into a lane term, a row term and uniform terms;
-// the four rows' bits are formed at once, one row per byte:
-//   anticommute_j = parity(x_p & z_r) ^ parity((z_p >> 2) & (l & 3)) ^ parity(z_p & 3 & j)
-//   c_j = |x_p & z_p| + |x_r & z_r| - |(x_p ^ x_r) & (z_p ^ z_r)| + 2 |z_p & x_r|   (mod 4)
-// and the butterfly of R (side 0) or R^T (side 1) adds the partner value when side ^ bit1(c_j) is
-// set, else subtracts it.  Values stay lazily reduced below 2^61 + 2^32: u + (2p - part) < 2^63,
-// and for s = a 2^31 + b, s 2^30 = a 2^61 + b 2^30 = a + b 2^30 (mod p).
+// n = 4: the h rotations applied to the key vector.  Lane l holds rows r_j = 4 l + j (j = 0..3).
+// Rotation p touches row r when P_p and P_r anticommute (<p, r> = |x_p & z_r| + |z_p & x_r| odd);
+// with P_p P_r = i^c P_{p^r}, c = |x_p & z_p| + |x_r & z_r| - |(x_p ^ x_r) & (z_p ^ z_r)| +
+// 2 |z_p & x_r| (mod 4), the butterfly of R (side 0) adds the partner value u_{r^p} when c = 3
+// and subtracts it when c = 1; R^T (side 1) the other way round.  Both bits depend only on (p, l, j)
+// and sit in a compile-time table, one byte per (p, lane): bit j = anticommutes, bit 4 + j = c is 3.
+struct Rot4Tab {
+    uint8_t v[256 * 64];
+};
+constexpr Rot4Tab make_rot4_tab() {
+    Rot4Tab t{};
+    for (uint32_t p = 1; p < 256; ++p) {
+        const uint32_t xp = p & 15, zp = p >> 4;
+        for (uint32_t l = 0; l < 64; ++l) {
+            uint32_t b = 0;
+            for (uint32_t j = 0; j < 4; ++j) {
+                const uint32_t r = 4 * l + j, xr = r & 15, zr = r >> 4;
+                const uint32_t anti = (uint32_t)(__builtin_popcount(xp & zr) + __builtin_popcount(zp & xr)) & 1;
+                const uint32_t c = (uint32_t)(__builtin_popcount(xp & zp) + __builtin_popcount(xr & zr) + 4 -
+                                              __builtin_popcount((xp ^ xr) & (zp ^ zr)) +
+                                              2 * __builtin_popcount(zp & xr)) & 3;
+                b |= (anti << j) | ((uint32_t)(c == 3) << (4 + j));
+            }
+            t.v[p * 64 + l] = (uint8_t)b;
+        }
+    }
+    return t;
+}
+__device__ constexpr Rot4Tab ROT4_TAB = make_rot4_tab();
+
+// Values stay lazily reduced below 2^61 + 2^32: u + (2p - part) < 2^63, and for s = a 2^31 + b,
+// s 2^30 = a 2^61 + b 2^30 = a + b 2^30 (mod p).
 // part[j] = u[j ^ C] of lane src (C a compile-time register permutation).
 template <int C>
 __device__ inline void fetch4(const uint64_t* u, int src, uint64_t* part) {
@@ -415,12 +466,12 @@ __device__ inline void fetch4(const uint64_t* u, int src, uint64_t* part) {
 }
 
 __device__ inline void rotate4(uint64_t* u, const uint32_t* dig, int h, int side, int gl, int gbase) {
-    const uint32_t lx = (uint32_t)gl & 3, zr = (uint32_t)gl >> 2;
-    uint32_t A = 0;  // bytes j: |x_r & z_r|
+    // the table bytes of every rotation first (p is a valid code in every digit slot, so all loads
+    // stay in the table), so their latency overlaps the partner fetches
+    uint32_t tb[Geo<4>::HMAX];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-        A |= (uint32_t)(__builtin_popcount((uint32_t)j & (zr & 3)) + __builtin_popcount(lx & (zr >> 2))) << (8 * j);
-    const uint32_t side_b = side ? 0x01010101u : 0u;
+    for (int t = 0; t < Geo<4>::HMAX; ++t) tb[t] = ROT4_TAB.v[dig[t] * 64 + gl];
+    const uint32_t side_b = side ? 0xf0u : 0u;
 #pragma unroll
     for (int t = Geo<4>::HMAX - 1; t >= 0; --t) {
         if (t >= h) continue;
@@ -435,30 +486,14 @@ __device__ inline void rotate4(uint64_t* u, const uint32_t* dig, int h, int side
             case 2: fetch4<2>(u, src, part); break;
             default: fetch4<3>(u, src, part); break;
         }
-        const uint32_t xp = p & 15, zp = p >> 4, z2 = zp & 3;
-        // uniform parts
-        const uint32_t ja = ((z2 & 1) << 8) | (((z2 >> 1) & 1) << 16) | ((uint32_t)(__builtin_popcount(z2) & 1) << 24);
-        const uint32_t zu = ((z2 & 1) << 8) | (((z2 >> 1) & 1) << 16) | ((uint32_t)__builtin_popcount(z2) << 24);
-        const uint32_t uni = (uint32_t)__builtin_popcount(xp & zp) * 0x01010101u + 2 * zu + 0x04040404u;
-        const uint32_t xj = ((xp & 3) * 0x01010101u) ^ 0x03020100u;
-        // lane parts
-        const uint32_t la = (uint32_t)__builtin_popcount((xp & zr) ^ ((zp >> 2) & lx)) & 1;
-        const uint32_t acb = (la ? 0x01010101u : 0u) ^ ja;
-        const uint32_t d = zp ^ zr;
-        const uint32_t t_hi = (uint32_t)__builtin_popcount(((xp >> 2) ^ lx) & (d >> 2));
-        const uint32_t zl = (uint32_t)__builtin_popcount((zp >> 2) & lx);
-        const uint32_t m = xj & ((d & 3) * 0x01010101u);
-        const uint32_t tlo = (m & 0x01010101u) + ((m >> 1) & 0x01010101u);
-        const uint32_t cb = uni + A + ((2 * zl - t_hi) & 3) * 0x01010101u - tlo;
-        const uint32_t plus_b = ((cb >> 1) & 0x01010101u) ^ side_b;
+        // bit j: anticommutes; bit 4 + j: the butterfly adds the partner (side 0: c = 3, side 1: c = 1)
+        const uint32_t b = tb[t] ^ side_b;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const uint64_t q = ((plus_b >> (8 * j)) & 1) ? part[j] : (2 * P61 - part[j]);
+            const uint64_t q = ((b >> (4 + j)) & 1) ? part[j] : (2 * P61 - part[j]);
             const uint64_t sum = u[j] + q;
             const uint64_t r = (sum >> 31) + ((sum & 0x7fffffffull) << 30);
-            // every row computes its butterfly; commuting rows keep u (a select, not a branch: the
-            // condition differs from lane to lane)
-            u[j] = __builtin_unpredictable(((acb >> (8 * j)) & 1) != 0) ? r : u[j];
+            u[j] = ((b >> j) & 1) ? r : u[j];
         }
     }
 }
