@@ -25,8 +25,11 @@ hash function" applied to information about every matrix element):
 * Matrix hash.  An additive multiset hash of the digests (MSet-Add-Hash of Clarke,
   Devadas, van Dijk, Gassend, Suh, "Incremental multiset hash functions and their
   application to memory integrity checking", ASIACRYPT 2003):
-  H = mix(sum_r mix(D_r xor salt_h) mod 2^64), mix being SplitMix64's finaliser.  A sum
-  does not depend on the order of the rows, so no canonical sort is needed.
+  H = mix(sum_r g(D_r) mod 2^64), mix being SplitMix64's finaliser and g the element map
+  g(D) = ((D mod 2^32 + a) mod 2^32) * ((floor(D / 2^32) + b) mod 2^32), with a and b the low
+  and high 32 bits of salt_h: NH of Black, Halevi, Krawczyk, Krovetz and Rogaway (UMAC,
+  CRYPTO 1999) on the digest's two 32-bit words.  A sum does not depend on the order of the
+  rows, so no canonical sort is needed.
 * Reduction.  x' = floor(H N_half / 2^64), b' = H mod 2.
 * Distinguished points (Sec. 3, fraction theta = 2^-delta): the top delta bits
   of mix(((x << 1) | b) xor salt_d) are zero.
@@ -119,12 +122,19 @@ def row_digests(m: zmat.ZMat, K: List[int]) -> List[int]:
     return out
 
 
+def nh_element(d: int, salt: int) -> int:
+    """NH on the two 32-bit words of d, keyed by the two words of salt: a 64-bit product."""
+    m32 = 0xFFFFFFFF
+    a, b = salt & m32, salt >> 32
+    return (((d & m32) + a) & m32) * (((d >> 32) + b) & m32)
+
+
 def matrix_hash(m: zmat.ZMat, keys: Keys) -> int:
-    """H = mix(sum over rows of mix(D_r xor salt_h), mod 2^64): a function of the multiset of
-    sign-normalised row digests, i.e. of the left-Clifford coset."""
+    """H = mix(sum over rows of g(D_r), mod 2^64), g the NH element map: a function of the
+    multiset of sign-normalised row digests, i.e. of the left-Clifford coset."""
     acc = 0
     for v in row_digests(m, keys.K):
-        acc += mix64(v ^ keys.salt_h)
+        acc += nh_element(v, keys.salt_h)
     return mix64(acc & MASK64)
 
 

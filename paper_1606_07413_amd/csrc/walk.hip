@@ -14,8 +14,11 @@
 // LDS as B-operand fragments, against signed base-256 digits of u and 2^31 u) and on int8 dot
 // products (v_dot4_i32_i8) against 7-bit limbs of u for n <= 2.  Then (nu + h of Sec. 2):
 //   D_r = min(S_r, p - S_r)   (sign-normalised row: negating a row negates S_r)
-//   H = mix64(sum_r mix64(D_r ^ salt_h))   (mod 2^64: an additive multiset hash, so the order of
-//                                           the rows -- a left signed permutation -- drops out)
+//   H = mix64(sum_r g(D_r))   (mod 2^64: an additive multiset hash, so the order of the rows -- a
+//                               left signed permutation -- drops out), with the element map
+//   g(D) = ((D mod 2^32 + a) mod 2^32) ((D div 2^32 + b) mod 2^32),  a, b the halves of salt_h
+//   (NH of Black, Halevi, Krawczyk, Krovetz and Rogaway, UMAC, CRYPTO 1999, on the digest's two
+//   32-bit words: one 32 x 32 -> 64-bit product per row)
 //   f(x, b) = (floor(H * xi^h / 2^64), H mod 2)                    (reduction back to a point)
 #include "common.h"
 #include "internal.h"
@@ -548,11 +551,12 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
     // [0, p]: p - c = c ^ p, and of c and p - c the smaller is the one with bit 60 clear, so
     // min(c mod p, p - c mod p) = c ^ (bit 60 of c ? p : 0) (which also sends p to 0).
     uint64_t acc = 0;
+    const uint32_t ka = (uint32_t)sp.salt_h, kb = (uint32_t)(sp.salt_h >> 32);
 #pragma unroll
     for (int j = 0; j < RPL; ++j) {
         const uint64_t c = S[j];
         const uint64_t d = c ^ (P61 & (0ull - ((c >> 60) & 1)));
-        acc += mix64(d ^ sp.salt_h);
+        acc += (uint64_t)((uint32_t)d + ka) * (uint64_t)((uint32_t)(d >> 32) + kb);
     }
     if constexpr (Gm::G == 64) {
 #pragma unroll
