@@ -133,6 +133,14 @@ __device__ inline uint64_t xchg64(uint64_t v, int lane) {
     const uint32_t hi = xchg32<X>((uint32_t)(v >> 32), lane);
     return ((uint64_t)hi << 32) | lo;
 }
+// a 64-bit value moved by one DPP pattern (every source lane inside the wave: quad permutes, row
+// rotations)
+template <int CTRL>
+__device__ inline uint64_t dpp64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, 0xF, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, true);
+    return ((uint64_t)hi << 32) | lo;
+}
 __device__ inline uint64_t xchg64_dyn(uint64_t v, int x, int lane) {
     switch (x) {
         case 1: return xchg64<1>(v, lane);
@@ -559,8 +567,12 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
         acc += (uint64_t)((uint32_t)d + ka) * (uint64_t)((uint32_t)(d >> 32) + kb);
     }
     if constexpr (Gm::G == 64) {
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) acc += xchg64_dyn(acc, off, gl);
+        // within each 16-lane row by DPP (quad permutes, then row rotations by 4 and 8, which add the
+        // other quads' sums), then across rows by the cross-half swaps: no LDS round trip
+        acc += dpp64<0xB1>(acc);   // quad_perm [1,0,3,2]
+        acc += dpp64<0x4E>(acc);   // quad_perm [2,3,0,1]
+        acc += dpp64<0x124>(acc);  // row_ror:4
+        acc += dpp64<0x128>(acc);  // row_ror:8
         acc = half_add16(acc, acc);
         acc = half_add32(acc, acc);
         // one walk per wavefront: the sum is the same in every lane; finish on the scalar unit
