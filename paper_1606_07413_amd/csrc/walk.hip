@@ -419,21 +419,56 @@ __device__ inline void side1_mfma3(const Lds<3, WAVES>& L, uint32_t* limbs, cons
     S[0] = m61_rot(m61_fold(half_add16(Q[0], Q[1])), rot_e);
 }
 
+// n = 3: for each (p, row r) bit 0 = P_p and P_r anticommute, bit 1 = their product's phase c is 3
+// (the butterfly of R adds the partner), one byte each, computed at compile time.
+struct Rot3Tab {
+    uint8_t v[64 * 64];
+};
+constexpr Rot3Tab make_rot3_tab() {
+    Rot3Tab t{};
+    for (uint32_t p = 1; p < 64; ++p) {
+        const uint32_t xp = p & 7, zp = p >> 3;
+        for (uint32_t r = 0; r < 64; ++r) {
+            const uint32_t xr = r & 7, zr = r >> 3;
+            const uint32_t anti = (uint32_t)(__builtin_popcount(xp & zr) + __builtin_popcount(zp & xr)) & 1;
+            const uint32_t c = (uint32_t)(__builtin_popcount(xp & zp) + __builtin_popcount(xr & zr) + 4 -
+                                          __builtin_popcount((xp ^ xr) & (zp ^ zr)) + 2 * __builtin_popcount(zp & xr)) &
+                               3;
+            t.v[p * 64 + r] = (uint8_t)(anti | ((uint32_t)(c == 3) << 1));
+        }
+    }
+    return t;
+}
+__device__ constexpr Rot3Tab ROT3_TAB = make_rot3_tab();
+
 // n <= 3 (one row per lane, r = gl): the h rotations with the same lazy reduction as rotate4.
 template <int NQ>
 __device__ inline void rotate1(uint64_t& u, const uint32_t* dig, int h, int side, int gl, int gbase) {
     const uint32_t r = (uint32_t)gl;
+    uint32_t tb[Geo<NQ>::HMAX];
+    if constexpr (NQ == 3) {
+        // every digit slot holds a valid code, so all loads stay in the table
+#pragma unroll
+        for (int t = 0; t < Geo<NQ>::HMAX; ++t) tb[t] = ROT3_TAB.v[dig[t] * 64 + r];
+    }
 #pragma unroll
     for (int t = Geo<NQ>::HMAX - 1; t >= 0; --t) {
         if (t >= h) continue;
         const uint32_t p = dig[t];
         const uint64_t part = shfl64(u, gbase + (gl ^ (int)p));
         // side 0 (R u): (u_r - s u_{r^p}) / sqrt2;  side 1 (R^T u): (u_r + s u_{r^p}) / sqrt2
-        const bool plus = (side == 1) == (rotation_sign<NQ>(p, r) > 0);
+        bool plus, anti;
+        if constexpr (NQ == 3) {
+            plus = (((tb[t] >> 1) ^ (uint32_t)side) & 1) != 0;
+            anti = (tb[t] & 1) != 0;
+        } else {
+            plus = (side == 1) == (rotation_sign<NQ>(p, r) > 0);
+            anti = anticommutes<NQ>(p, r) != 0;
+        }
         const uint64_t q = plus ? part : (2 * P61 - part);
         const uint64_t sum = u + q;
         const uint64_t rot = (sum >> 31) + ((sum & 0x7fffffffull) << 30);
-        u = anticommutes<NQ>(p, r) ? rot : u;
+        u = anti ? rot : u;
     }
 }
 
