@@ -362,6 +362,49 @@ def tts_n4_leg(ctx, cap: float, slice_s: float = 60.0):
     return {"measured": True, "theta": 0.5, "chunk_parallel": "all", "cap_s": cap, "runs": runs}
 
 
+def tts_n4_planted_leg(ctx, cap: float, slice_s: float = 120.0, seeds=(2, 3, 4)):
+    """The configured n = 4, k = 7 search (theta = 2^-12, 2^20 walks, 2^26 slots) on the planted
+    chunk alone (P_1 of the generating word), one target at a time: the time until the exact check
+    accepts a decomposition, in calls of at most slice_s seconds (each a fresh range of function
+    versions) with a line of progress after each, until the cap."""
+    import seeded_inputs
+    runs = []
+    for ts in seeds:
+        twn = seeded_inputs.target_words(4, 7, ts)
+        tn = ctx.target_from_words(4, twn.paulis, twn.clifford)
+        chunk = twn.paulis[0]
+        t0 = time.perf_counter()
+        steps, slices, r = 0, 0, None
+        while time.perf_counter() - t0 < cap:
+            p4 = ctx.default_params(4)
+            p4.k_max = 7
+            p4.delta = 12
+            p4.walks = 1 << 20
+            p4.log2_table = 26
+            p4.seed = 3200 + ts
+            p4.version = slices << 20
+            p4.chunk_first = p4.chunk_last = chunk
+            p4.depth_order_kind = 1
+            p4.depth_order_len = 1
+            p4.depth_order[0] = 7
+            p4.max_seconds = min(slice_s, cap - (time.perf_counter() - t0))
+            r = ctx.search(tn, p4)
+            steps += r.stats.steps
+            slices += 1
+            print(f"planted chunk {chunk} of n4k7 target {ts}: slice {slices} ended at "
+                  f"{time.perf_counter() - t0:.1f} s, {steps:.3g} steps, found={bool(r.status)}",
+                  file=sys.stderr, flush=True)
+            if r.status:
+                break
+        n_pts = 2 * 255 ** 3
+        runs.append({"target_seed": ts, "chunk": chunk, "seconds": time.perf_counter() - t0,
+                     "found_t": r.t if r is not None and r.status else None, "steps": steps,
+                     "steps_over_N_per_theta": steps / (n_pts * 4096.0), "slices": slices})
+        tn.free()
+    return {"measured": True, "theta": 2.0 ** -12, "walks": 1 << 20, "log2_table": 26, "cap_s": cap,
+            "runs": runs}
+
+
 # Sec. 5.2, Table 1: mean synthesis time of the T-count-7 three-qubit gates over 100 trials on
 # 4096 Blue Gene/Q cores with half of the points distinguished (another machine: context only).
 PAPER_TABLE1_SECONDS = {"toffoli": 25.9870, "fredkin": 25.0031, "peres": 25.4931}
@@ -520,6 +563,10 @@ def main():
     ap.add_argument("--tts-n4-enum", action="store_true",
                     help="also run the n = 4 searches with every space enumerated exhaustively")
     ap.add_argument("--tts-n4-cap", type=float, default=150.0, help="wall-clock cap per n = 4 target (s)")
+    ap.add_argument("--tts-n4-planted", action="store_true",
+                    help="also search the planted depth-7 chunk of n = 4 targets 2..4 at theta = 2^-12")
+    ap.add_argument("--tts-n4-planted-cap", type=float, default=600.0, help="wall-clock cap per target (s)")
+    ap.add_argument("--tts-n4-planted-seeds", default="2,3,4", help="target seeds (comma-separated)")
     ap.add_argument("--named", action="store_true",
                     help="also synthesise Toffoli, Fredkin and Peres (n = 3, T-count 7) repeatedly")
     ap.add_argument("--named-reps", type=int, default=20)
@@ -597,6 +644,9 @@ def main():
         extra["tts_n4k7_theta_half"] = tts_n4_leg(ctx, args.tts_n4_cap)
     if args.tts_n4_enum:
         extra["tts_n4k7_exhaustive"] = tts_n4_enum_leg(ctx, args.tts_n4_cap)
+    if args.tts_n4_planted:
+        extra["tts_n4k7_planted_chunk"] = tts_n4_planted_leg(
+            ctx, args.tts_n4_planted_cap, seeds=tuple(int(v) for v in args.tts_n4_planted_seeds.split(",")))
     if not args.no_tts:
         n_pts = 2 * 255 ** 3
         steps_chunk = n_pts * (1 << delta)          # Appendix: about N / theta steps for the chunk with the claw
