@@ -96,12 +96,14 @@ struct Space {
     int32_t e_s = 0;
     uint32_t* phi = nullptr;
     uint64_t* keys = nullptr;
+    uint64_t* rkeys = nullptr;  // n = 4: rotated keys (SpaceDev::rkeys)
     SpaceDev dev{};
 
     ~Space() {
         tcw::exact_free(S);
         if (phi) (void)hipFree(phi);
         if (keys) (void)hipFree(keys);
+        if (rkeys) (void)hipFree(rkeys);
     }
 
     void set_version(uint32_t v) {
@@ -161,6 +163,10 @@ int prepare_space(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, Space& o
     if (e != hipSuccess) return hip_fail(c, e, "chunk matrix");
     HIP_TRY(c, tcw::exact_pack_phi(out.S, out.phi, c->flag, c->stream));
     HIP_TRY(c, tcw::keys_fill(n, sp->seed, out.keys, c->stream));
+    if (n == 4) {
+        HIP_TRY(c, hipMalloc(&out.rkeys, (size_t)2 * 256 * 256 * sizeof(uint64_t)));
+        HIP_TRY(c, tcw::rot_keys_fill(out.keys, out.rkeys, c->stream));
+    }
     HIP_TRY(c, hipMemcpyAsync(&out.e_s, out.S.e, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     int flag = 0;
     if ((rc = read_flag(c, &flag))) return rc;
@@ -173,6 +179,7 @@ int prepare_space(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, Space& o
     out.dev.rot_e = (int32_t)((30ll * out.e_s) % 61);
     out.dev.phi = out.phi;
     out.dev.keys = out.keys;
+    out.dev.rkeys = out.rkeys;
     out.set_version(sp->version);
     return TCW_OK;
 }

@@ -568,11 +568,22 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
 
     // key vector through the rotations, p_{h-1} first
     uint64_t u[RPL];
-#pragma unroll
-    for (int j = 0; j < RPL; ++j) u[j] = L.K[gl * RPL + j];
     if constexpr (NQ == 4) {
-        rotate4(u, dig, h, side, gl, gbase);
+        // the first rotation, R(p_{h-1}) K or its transpose's, comes precomputed for every Pauli (an
+        // L2-resident 1 MiB table, 32 contiguous bytes per lane); the other h - 1 are applied here
+        int h_left = h;
+        if (sp.rkeys != nullptr && h > 0) {
+            const uint64_t* tp = sp.rkeys + ((uint32_t)side * 256u + dig[h - 1]) * 256u + 4u * (uint32_t)gl;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) u[j] = tp[j];
+            h_left = h - 1;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) u[j] = L.K[gl * 4 + j];
+        }
+        rotate4(u, dig, h_left, side, gl, gbase);
     } else {
+        u[0] = L.K[gl];
         rotate1<NQ>(u[0], dig, h, side, gl, gbase);
     }
 
@@ -775,6 +786,24 @@ __global__ void k_pack_i32(const int32_t* a, const int32_t* b, int64_t count, ui
 __global__ void k_starts(SpaceDev sp, int64_t w0, uint32_t j, int64_t count, uint64_t* out) {
     for (int64_t i = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; i < count; i += (int64_t)blockDim.x * gridDim.x)
         out[i] = start_point(sp, (uint64_t)(w0 + i), j);
+}
+
+// n = 4: out[side][p][q] = the first rotation of the walk step applied to K, by rotate4's butterfly
+// (so the values are the ones the step would compute): side 0 R(p) K, side 1 R(p)^T K.  One block
+// per (side, p), one thread per row q; p = 0 (no rotation) copies K.
+__global__ void k_rot_keys(const uint64_t* keys, uint64_t* out) {
+    const uint32_t q = threadIdx.x, p = blockIdx.x & 255u, side = blockIdx.x >> 8;
+    uint64_t v = keys[q];
+    if (p != 0) {
+        const uint32_t b = ROT4_TAB.v[p * 64 + (q >> 2)], j = q & 3;
+        if ((b >> j) & 1) {
+            const uint64_t part = keys[q ^ p];
+            const uint64_t w = (((b >> (4 + j)) ^ side) & 1) ? part : (2 * P61 - part);
+            const uint64_t sum = v + w;
+            v = (sum >> 31) + ((sum & 0x7fffffffull) << 30);
+        }
+    }
+    out[(size_t)blockIdx.x * 256 + q] = v;
 }
 
 // K[q] = (sm64(s_0, q) >> 3) mod p, s_0 = sm64(seed, 0)
@@ -1201,6 +1230,11 @@ int walk_grid_blocks(int n, int device) {
 hipError_t keys_fill(int n, uint64_t seed, uint64_t* keys, hipStream_t s) {
     const int r = 1 << (2 * n);
     hipLaunchKernelGGL(k_keys, dim3((r + 255) / 256), dim3(256), 0, s, r, seed, keys);
+    return hipGetLastError();
+}
+
+hipError_t rot_keys_fill(const uint64_t* keys, uint64_t* rkeys, hipStream_t s) {
+    hipLaunchKernelGGL(k_rot_keys, dim3(512), dim3(256), 0, s, keys, rkeys);
     return hipGetLastError();
 }
 
