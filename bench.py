@@ -71,7 +71,8 @@ def measured_traffic(walks: int, iters: int):
 def valu_ops_per_step(n: int, h: int) -> float:
     """32-bit VALU lane-operations the n = 4 walk step needs per evaluation of f (mean over sides).
 
-    both sides: h R/2 butterflies x 12 (64-bit modular add + 61-bit rotation + sign), R x 6 (fold),
+    both sides: (h - 2) R/2 butterflies x 12 (64-bit modular add + 61-bit rotation + sign; the first two
+                rotations of a step come from the table of rotated keys), R x 6 (fold),
                 R x 6 (multiset hash: the NH element map's two 32-bit key adds and 32 x 32 -> 64-bit
                 product 2, and the 64-bit add 2), log2(64) x 4 x 64 (wave reduction of the sum)
     side 1:     digit packing 2 sets x 8 signed base-256 digits x R x 3, digit recombination
@@ -79,7 +80,7 @@ def valu_ops_per_step(n: int, h: int) -> float:
                 (12 values x 64 lanes x 8) -- the S_c product itself runs on MFMA
     """
     r = 4 ** n
-    common = h * (r // 2) * 12 + r * 6 + r * 6 + 6 * 4 * 64
+    common = max(h - 2, 0) * (r // 2) * 12 + r * 6 + r * 6 + 6 * 4 * 64
     side1 = 2 * 8 * r * 3 + r * 16 * 4 + 12 * 64 * 8
     return common + 0.5 * side1
 

@@ -25,8 +25,21 @@ struct TunedCfg {
     double rate = 0;
 };
 
+namespace tcw {
+// n = 4: rotated key vectors (SpaceDev::rkeys, rkeys2), shared by the spaces of one search seed.
+struct RotKeys {
+    uint64_t* t1 = nullptr;  // 1 MiB
+    uint64_t* t2 = nullptr;  // 256 MiB, or null when the allocation failed
+    ~RotKeys() {
+        if (t1) (void)hipFree(t1);
+        if (t2) (void)hipFree(t2);
+    }
+};
+}  // namespace tcw
+
 struct tcw_ctx {
     std::map<uint64_t, TunedCfg> tuned;  // autotuner results by (n, k, delta)
+    std::map<uint64_t, std::weak_ptr<tcw::RotKeys>> rot_keys;  // n = 4, by search seed
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
@@ -96,14 +109,13 @@ struct Space {
     int32_t e_s = 0;
     uint32_t* phi = nullptr;
     uint64_t* keys = nullptr;
-    uint64_t* rkeys = nullptr;  // n = 4: rotated keys (SpaceDev::rkeys)
+    std::shared_ptr<tcw::RotKeys> rk;  // n = 4: rotated keys (SpaceDev::rkeys, rkeys2)
     SpaceDev dev{};
 
     ~Space() {
         tcw::exact_free(S);
         if (phi) (void)hipFree(phi);
         if (keys) (void)hipFree(keys);
-        if (rkeys) (void)hipFree(rkeys);
     }
 
     void set_version(uint32_t v) {
@@ -164,8 +176,24 @@ int prepare_space(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, Space& o
     HIP_TRY(c, tcw::exact_pack_phi(out.S, out.phi, c->flag, c->stream));
     HIP_TRY(c, tcw::keys_fill(n, sp->seed, out.keys, c->stream));
     if (n == 4) {
-        HIP_TRY(c, hipMalloc(&out.rkeys, (size_t)2 * 256 * 256 * sizeof(uint64_t)));
-        HIP_TRY(c, tcw::rot_keys_fill(out.keys, out.rkeys, c->stream));
+        // the keys depend on the seed only: one set of rotated keys per seed and context, kept while
+        // a space uses it
+        for (auto it = c->rot_keys.begin(); it != c->rot_keys.end();)
+            it = it->second.expired() ? c->rot_keys.erase(it) : std::next(it);
+        std::shared_ptr<tcw::RotKeys> rk = c->rot_keys[sp->seed].lock();
+        if (!rk) {
+            rk = std::make_shared<tcw::RotKeys>();
+            HIP_TRY(c, hipMalloc(&rk->t1, (size_t)2 * 256 * 256 * sizeof(uint64_t)));
+            HIP_TRY(c, tcw::rot_keys_fill(out.keys, rk->t1, c->stream));
+            if (hipMalloc(&rk->t2, (size_t)2 * 256 * 256 * 256 * sizeof(uint64_t)) == hipSuccess) {
+                HIP_TRY(c, tcw::rot_keys2_fill(rk->t1, rk->t2, c->stream));
+            } else {
+                rk->t2 = nullptr;  // without the 256 MiB table the step applies one more rotation
+                (void)hipGetLastError();
+            }
+            c->rot_keys[sp->seed] = rk;
+        }
+        out.rk = rk;
     }
     HIP_TRY(c, hipMemcpyAsync(&out.e_s, out.S.e, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     int flag = 0;
@@ -179,7 +207,8 @@ int prepare_space(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, Space& o
     out.dev.rot_e = (int32_t)((30ll * out.e_s) % 61);
     out.dev.phi = out.phi;
     out.dev.keys = out.keys;
-    out.dev.rkeys = out.rkeys;
+    out.dev.rkeys = out.rk ? out.rk->t1 : nullptr;
+    out.dev.rkeys2 = out.rk ? out.rk->t2 : nullptr;
     out.set_version(sp->version);
     return TCW_OK;
 }

@@ -21,6 +21,8 @@ struct SpaceDev {
     const uint64_t* keys;  // K[R] (row-digest keys, < p)
     const uint64_t* rkeys; // n = 4, or null: the first rotation of a step applied to K for every Pauli,
                            // [side][p][q] = (R(p) K)_q (side 0), (R(p)^T K)_q (side 1); 2 x 256 x 256
+    const uint64_t* rkeys2;  // n = 4, or null: the first two, [side][p][p'][q] = (R(p') R(p) K)_q
+                             // (side 0; transposes for side 1), p applied first; 2 x 256^3 values
 };
 
 enum : uint32_t { MODE_WALK = 0, MODE_ALIGN = 1, MODE_LOCK = 2, MODE_DONE = 3 };
@@ -114,6 +116,8 @@ hipError_t mitm_probe(int n, const SpaceDev& sp, const uint32_t* phi_all, const 
 hipError_t keys_fill(int n, uint64_t seed, uint64_t* keys_dev, hipStream_t s);
 // n = 4: the rotated keys of SpaceDev::rkeys (2 x 256 x 256 values) from K.
 hipError_t rot_keys_fill(const uint64_t* keys, uint64_t* rkeys, hipStream_t s);
+// n = 4: SpaceDev::rkeys2 (2 x 256^3 values) from SpaceDev::rkeys.
+hipError_t rot_keys2_fill(const uint64_t* rkeys, uint64_t* rkeys2, hipStream_t s);
 hipError_t launch_step(int n, const SpaceDev& sp, const uint64_t* in, uint64_t* out, uint64_t* hash, int64_t count,
                        hipStream_t s);
 hipError_t launch_trails(int n, const SpaceDev& sp, const uint64_t* starts, int64_t count, uint32_t cap,

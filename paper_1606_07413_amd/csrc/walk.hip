@@ -569,10 +569,17 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
     // key vector through the rotations, p_{h-1} first
     uint64_t u[RPL];
     if constexpr (NQ == 4) {
-        // the first rotation, R(p_{h-1}) K or its transpose's, comes precomputed for every Pauli (an
-        // L2-resident 1 MiB table, 32 contiguous bytes per lane); the other h - 1 are applied here
+        // the first two rotations, R(p_{h-2}) R(p_{h-1}) K or the transposes', come precomputed for
+        // every pair of Paulis (a 256 MiB table in HBM, 2 KiB per step in 32 contiguous bytes per
+        // lane); with one rotation only, from a 1 MiB table; the others are applied here
         int h_left = h;
-        if (sp.rkeys != nullptr && h > 0) {
+        if (sp.rkeys2 != nullptr && h >= 2) {
+            const uint64_t* tp =
+                sp.rkeys2 + ((((uint32_t)side * 256u + dig[h - 1]) * 256u + dig[h - 2]) * 256u + 4u * (uint32_t)gl);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) u[j] = tp[j];
+            h_left = h - 2;
+        } else if (sp.rkeys != nullptr && h >= 1) {
             const uint64_t* tp = sp.rkeys + ((uint32_t)side * 256u + dig[h - 1]) * 256u + 4u * (uint32_t)gl;
 #pragma unroll
             for (int j = 0; j < 4; ++j) u[j] = tp[j];
@@ -798,6 +805,24 @@ __global__ void k_rot_keys(const uint64_t* keys, uint64_t* out) {
         const uint32_t b = ROT4_TAB.v[p * 64 + (q >> 2)], j = q & 3;
         if ((b >> j) & 1) {
             const uint64_t part = keys[q ^ p];
+            const uint64_t w = (((b >> (4 + j)) ^ side) & 1) ? part : (2 * P61 - part);
+            const uint64_t sum = v + w;
+            v = (sum >> 31) + ((sum & 0x7fffffffull) << 30);
+        }
+    }
+    out[(size_t)blockIdx.x * 256 + q] = v;
+}
+
+// n = 4: out[side][p][p'][q] = rotation p' (rotate4's butterfly) applied to rkeys[side][p]; one block
+// per (side, p, p'), one thread per row q; p' = 0 copies.
+__global__ void k_rot_keys2(const uint64_t* rkeys, uint64_t* out) {
+    const uint32_t q = threadIdx.x, p2 = blockIdx.x & 255u, sp1 = blockIdx.x >> 8, side = sp1 >> 8;
+    const uint64_t* in = rkeys + (size_t)sp1 * 256;
+    uint64_t v = in[q];
+    if (p2 != 0) {
+        const uint32_t b = ROT4_TAB.v[p2 * 64 + (q >> 2)], j = q & 3;
+        if ((b >> j) & 1) {
+            const uint64_t part = in[q ^ p2];
             const uint64_t w = (((b >> (4 + j)) ^ side) & 1) ? part : (2 * P61 - part);
             const uint64_t sum = v + w;
             v = (sum >> 31) + ((sum & 0x7fffffffull) << 30);
@@ -1235,6 +1260,11 @@ hipError_t keys_fill(int n, uint64_t seed, uint64_t* keys, hipStream_t s) {
 
 hipError_t rot_keys_fill(const uint64_t* keys, uint64_t* rkeys, hipStream_t s) {
     hipLaunchKernelGGL(k_rot_keys, dim3(512), dim3(256), 0, s, keys, rkeys);
+    return hipGetLastError();
+}
+
+hipError_t rot_keys2_fill(const uint64_t* rkeys, uint64_t* rkeys2, hipStream_t s) {
+    hipLaunchKernelGGL(k_rot_keys2, dim3(2 * 256 * 256), dim3(256), 0, s, rkeys, rkeys2);
     return hipGetLastError();
 }
 
