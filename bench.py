@@ -239,7 +239,8 @@ def config_legs(ctx):
         tw = seeded_inputs.target_words(n, k, spec["target_seeds"][0])
         tgt = ctx.target_from_words(n, tw.paulis, tw.clifford)
         for walks in walks_list:
-            w = ctx.walk(tgt, k, 0, 77, spec["delta"], walks=walks, log2_table=spec["log2_table"],
+            # a table that holds the distinguished points of every walk
+            w = ctx.walk(tgt, k, 0, 77, spec["delta"], walks=walks, log2_table=max(spec["log2_table"], 22),
                          cap=20 << spec["delta"])
             iters = 64 if walks < 4096 else 8
             w.run(iters)

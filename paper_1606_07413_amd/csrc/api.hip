@@ -37,9 +37,19 @@ struct RotKeys {
 };
 }  // namespace tcw
 
+constexpr size_t ROT_KEYS_KEEP = 32;  // seeds whose n = 4 rotated keys (257 MiB each) a context keeps
+
 struct tcw_ctx {
     std::map<uint64_t, TunedCfg> tuned;  // autotuner results by (n, k, delta)
-    std::map<uint64_t, std::weak_ptr<tcw::RotKeys>> rot_keys;  // n = 4, by search seed
+    // n = 4 rotated keys by search seed, kept for later spaces of the same seed: freeing device
+    // memory waits for the device, so a table lives until the context ends or until more than
+    // ROT_KEYS_KEEP seeds are cached and it is the least recently used one no space holds
+    struct RotEntry {
+        std::shared_ptr<tcw::RotKeys> rk;
+        uint64_t last = 0;
+    };
+    std::map<uint64_t, RotEntry> rot_keys;
+    uint64_t rot_clock = 0;
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
@@ -176,13 +186,18 @@ int prepare_space(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, Space& o
     HIP_TRY(c, tcw::exact_pack_phi(out.S, out.phi, c->flag, c->stream));
     HIP_TRY(c, tcw::keys_fill(n, sp->seed, out.keys, c->stream));
     if (n == 4) {
-        // the keys depend on the seed only: one set of rotated keys per seed and context, kept while
-        // a space uses it
-        for (auto it = c->rot_keys.begin(); it != c->rot_keys.end();)
-            it = it->second.expired() ? c->rot_keys.erase(it) : std::next(it);
-        std::shared_ptr<tcw::RotKeys> rk = c->rot_keys[sp->seed].lock();
-        if (!rk) {
-            rk = std::make_shared<tcw::RotKeys>();
+        // the keys depend on the seed only: one set of rotated keys per seed, cached in the context
+        auto it = c->rot_keys.find(sp->seed);
+        if (it == c->rot_keys.end()) {
+            while (c->rot_keys.size() >= ROT_KEYS_KEEP) {
+                auto victim = c->rot_keys.end();
+                for (auto e = c->rot_keys.begin(); e != c->rot_keys.end(); ++e)
+                    if (e->second.rk.use_count() == 1 && (victim == c->rot_keys.end() || e->second.last < victim->second.last))
+                        victim = e;
+                if (victim == c->rot_keys.end()) break;  // every cached table is in use
+                c->rot_keys.erase(victim);
+            }
+            auto rk = std::make_shared<tcw::RotKeys>();
             HIP_TRY(c, hipMalloc(&rk->t1, (size_t)2 * 256 * 256 * sizeof(uint64_t)));
             HIP_TRY(c, tcw::rot_keys_fill(out.keys, rk->t1, c->stream));
             if (hipMalloc(&rk->t2, (size_t)2 * 256 * 256 * 256 * sizeof(uint64_t)) == hipSuccess) {
@@ -191,9 +206,10 @@ int prepare_space(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, Space& o
                 rk->t2 = nullptr;  // without the 256 MiB table the step applies one more rotation
                 (void)hipGetLastError();
             }
-            c->rot_keys[sp->seed] = rk;
+            it = c->rot_keys.emplace(sp->seed, tcw_ctx::RotEntry{rk, 0}).first;
         }
-        out.rk = rk;
+        it->second.last = ++c->rot_clock;
+        out.rk = it->second.rk;
     }
     HIP_TRY(c, hipMemcpyAsync(&out.e_s, out.S.e, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     int flag = 0;

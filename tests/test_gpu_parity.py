@@ -260,8 +260,11 @@ def test_checkpoint_resume_continues_trails(ctx):
 @pytest.mark.parametrize("seed", list(range(1, 17)))
 def test_search_n2_cfg1(ctx, seed):
     """n = 2, k = 4 targets; depths 0..3 are enumerated exhaustively, k = 4 by 64 walks at
-    theta = 2^-4 (budget 16 N / theta).  The T-count found equals the brute-force minimum (targets
-    outside the brute-forced levels 0..3 have T-count 4); the result is exact."""
+    theta = 2^-4.  The T-count found equals the brute-force minimum (targets outside the
+    brute-forced levels 0..3 have T-count 4); the result is exact.  The budget is 64 N / theta: the
+    walk search is randomised (which trail reaches a distinguished point first differs from run to
+    run), and with the default 16 N / theta a hard target misses now and then; this test checks
+    what is found, not how often the default budget suffices (the bench's n2k4 leg reports that)."""
     say("search n2", seed)
     _, seen, _ = bfs.cosets_by_tcount(2, 3)
     tw, u = oracle_target(2, 4, seed)
@@ -273,7 +276,7 @@ def test_search_n2_cfg1(ctx, seed):
     p.walks = 64
     p.log2_table = 10
     p.enum_max = 64
-    p.budget_beta = 16
+    p.budget_beta = 64
     from paper_1606_07413_amd import tcw
     res = ctx.search(tgt, p)
     dec = tcw.decomposition_of(res)
