@@ -70,7 +70,11 @@ def test_target_from_channel_validates(ctx):
 
 
 STEP_CASES = [(1, 4, 1, 37), (1, 5, 2, 100), (2, 2, 5, 30), (2, 4, 1, 300), (2, 5, 3, 129), (2, 6, 4, 65),
-              (3, 3, 5, 64), (3, 5, 2, 77), (3, 6, 1, 200), (4, 2, 1, 33), (4, 3, 2, 20), (4, 4, 3, 8), (4, 7, 1, 5)]
+              (3, 3, 5, 64), (3, 5, 2, 77), (3, 6, 1, 200), (4, 1, 4, 16), (4, 2, 1, 33), (4, 3, 2, 20),
+              (4, 4, 3, 8), (4, 5, 6, 24), (4, 6, 5, 40), (4, 7, 1, 64)]
+# n = 4 covers every start of the rotated-key tables: k = 1 (no rotation: the keys), k = 2, 3 (one
+# rotation from the one-rotation table), k = 4, 5 (two from the two-rotation table), k = 6, 7 (two
+# from the table, one computed)
 
 
 @pytest.mark.parametrize("n,k,seed,count", STEP_CASES)
