@@ -9,8 +9,10 @@
 //   side 0: S = R(p_0) (R(p_1) ( ... (R(p_{h-1}) K)))
 //   side 1: S = phi(S_c) u,  u = R(p_0)^T ( ... (R(p_{h-1})^T K))
 // Each factor touches the vector by the channel rep's column rule (one butterfly per
-// anticommuting row; the 1/sqrt2 is a 61-bit rotation by 30), and the side-1 product with the
-// fixed chunk matrix S_c = (A + B sqrt2)/sqrt2^e runs on int8 MFMA for n >= 3 (A and B resident in
+// anticommuting row; the 1/sqrt2 is a 61-bit rotation by 30); at n = 4 the first two factors
+// applied to K come from a table of rotated keys built once per search seed (2 x 256^2 vectors of
+// 256 values), so a step reads one row of it and applies the remaining h - 2.  The side-1 product
+// with the fixed chunk matrix S_c = (A + B sqrt2)/sqrt2^e runs on int8 MFMA for n >= 3 (A and B in
 // LDS as B-operand fragments, against signed base-256 digits of u and 2^31 u) and on int8 dot
 // products (v_dot4_i32_i8) against 7-bit limbs of u for n <= 2.  Then (nu + h of Sec. 2):
 //   D_r = min(S_r, p - S_r)   (sign-normalised row: negating a row negates S_r)

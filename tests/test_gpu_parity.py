@@ -98,6 +98,24 @@ def test_step_parity(ctx, n, k, seed, count):
     assert got_h == [w[1] for w in want]
 
 
+def test_rot_keys_cache_many_seeds(ctx):
+    """n = 4 steps under more search seeds than the context keeps rotated-key tables for (32), then
+    the first seeds again (their tables were evicted and are rebuilt): every step stays exact."""
+    import torch
+    n, k = 4, 4
+    say("rot keys cache")
+    tw, u = oracle_target(n, k, 9)
+    tgt = ctx.target_from_words(n, tw.paulis, tw.clifford)
+    seeds = list(range(5000, 5036)) + [5000, 5001, 5035]
+    for sseed in seeds:
+        spec = owalk.make_spec(u, n, k, 0, sseed, delta=4)
+        pts = seeded_inputs.random_points(spec.n_half, 2, sseed)
+        din = dev(pts)
+        dout = torch.empty_like(din)
+        ctx.step(tgt, k, 0, sseed, 4, din, dout)
+        assert host_u64(dout) == [owalk.f(spec, p) for p in pts], sseed
+
+
 @pytest.mark.parametrize("n,k,seed", [(1, 6, 3), (2, 4, 1), (2, 5, 6), (3, 6, 2), (3, 5, 7), (4, 7, 1), (4, 6, 2)])
 def test_planted_claw_on_gpu(ctx, n, k, seed):
     import torch
