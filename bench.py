@@ -28,6 +28,8 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # dense int8 MFMA peak (MI355X): 5.0e15 ops/s
 MFMA_I8_PEAK_OPS = 5.0e15
+# HBM3E (MI355X): 8 TB/s
+HBM_PEAK_BYTES = 8.0e12
 
 
 # Files the walk kernel is compiled from; the counter summary below records their digest together
@@ -658,6 +660,7 @@ def main():
                              "basis": f"{chunk - 1} chunks x budget {budget:.3g} steps + N/theta = {steps_chunk:.3g} "
                                       f"steps in the planted chunk, at the measured rate (projected)"}
 
+    traffic = measured_traffic(args.walks, args.iters)
     out = {
         "metric": "walk steps/s + time-to-solution at n=4,k=7; learned depth order vs plain",
         "value": value,
@@ -674,10 +677,14 @@ def main():
         "config": {"workload": "n4k7", "n": n, "k": k, "chunk": chunk, "walks": args.walks, "delta": delta,
                    "log2_table": log2_table, "iters_per_launch": args.iters, "parallelism": "1 GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(args.walks, args.iters), "traffic_unit": "HBM bytes per launch",
+                     "traffic": traffic, "traffic_unit": "HBM bytes per launch",
                      "kernel": "k_walk<4,12>", "kernel_ms": avg_ms, "kernel_source_sha256": kernel_source_digest(),
                      "mfma_i8": {"achieved": mfma_achieved / 1e12, "peak": MFMA_I8_PEAK_OPS / 1e12, "unit": "Tops/s",
-                                 "frac": mfma_achieved / MFMA_I8_PEAK_OPS}},
+                                 "frac": mfma_achieved / MFMA_I8_PEAK_OPS},
+                     # the measured HBM bytes per launch over the live kernel time
+                     "hbm": None if traffic is None else
+                     {"achieved": traffic / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_BYTES / 1e9, "unit": "GB/s",
+                      "frac": traffic / (avg_ms * 1e-3) / HBM_PEAK_BYTES}},
         "walk_stats": st.as_dict(),
     }
     out.update(extra)
