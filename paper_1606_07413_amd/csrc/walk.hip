@@ -916,12 +916,12 @@ __device__ void walk_block(const SpaceDev& sp, const WalkDev& wd, int iters, Lds
                 uint64_t slot = 0, other = 0;
                 if (leader) kind = table_claim(wd, key, slot);
                 if (leader && kind == 1)
-                    __hip_atomic_store(&wd.table[2 * slot + 1], pack_value(st.start, 1), __ATOMIC_RELEASE,
+                    __hip_atomic_store(&wd.table[2 * slot + 1], pack_value(st.start, 1), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                 if (leader && kind == 2) {
                     int spin = 0;
                     do {
-                        other = __hip_atomic_load(&wd.table[2 * slot + 1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                        other = __hip_atomic_load(&wd.table[2 * slot + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     } while (other == 0 && ++spin < (1 << 20));
                     if (other == 0) kind = 4;
                 }
@@ -954,14 +954,17 @@ __device__ void walk_block(const SpaceDev& sp, const WalkDev& wd, int iters, Lds
                     int kind = 0;
                     uint64_t slot = 0, other = 0;
                     if (leader) kind = table_claim(wd, nxt, slot);
+                    // The slot's writer publishes its value right after its claim.  The value word is
+                    // all a reader uses (start, length and a ready bit), so relaxed device-scope atomics
+                    // suffice; release and acquire would write back and invalidate the L2 of the
+                    // wavefront's XCD at every distinguished point.
                     if (leader && kind == 1)
-                        __hip_atomic_store(&wd.table[2 * slot + 1], pack_value(st.start, st.len), __ATOMIC_RELEASE,
+                        __hip_atomic_store(&wd.table[2 * slot + 1], pack_value(st.start, st.len), __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                     if (leader && kind == 2) {
-                        // the slot's writer publishes its value right after its claim
                         int spin = 0;
                         do {
-                            other = __hip_atomic_load(&wd.table[2 * slot + 1], __ATOMIC_ACQUIRE,
+                            other = __hip_atomic_load(&wd.table[2 * slot + 1], __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
                         } while (other == 0 && ++spin < (1 << 20));
                         if (other == 0) kind = 4;
