@@ -586,7 +586,7 @@ def main():
     ap.add_argument("--mlp-cap", type=float, default=20.0, help="per-target wall-clock cap (s) in the comparison")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the walk search here runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
