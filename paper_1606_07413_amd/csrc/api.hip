@@ -191,9 +191,10 @@ int prepare_space(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, Space& o
         if (it == c->rot_keys.end()) {
             while (c->rot_keys.size() >= ROT_KEYS_KEEP) {
                 auto victim = c->rot_keys.end();
-                for (auto e = c->rot_keys.begin(); e != c->rot_keys.end(); ++e)
-                    if (e->second.rk.use_count() == 1 && (victim == c->rot_keys.end() || e->second.last < victim->second.last))
-                        victim = e;
+                for (auto e = c->rot_keys.begin(); e != c->rot_keys.end(); ++e) {
+                    const bool unused = e->second.rk.use_count() == 1;
+                    if (unused && (victim == c->rot_keys.end() || e->second.last < victim->second.last)) victim = e;
+                }
                 if (victim == c->rot_keys.end()) break;  // every cached table is in use
                 c->rot_keys.erase(victim);
             }
