@@ -514,11 +514,10 @@ __device__ inline void fetch4(const uint64_t* u, int src, uint64_t* part) {
 }
 
 __device__ inline void rotate4(uint64_t* u, const uint32_t* dig, int h, int side, int gl, int gbase) {
-    // the table bytes of every rotation first (p is a valid code in every digit slot, so all loads
-    // stay in the table), so their latency overlaps the partner fetches
+    // the table bytes of the rotations to apply, first, so their latency overlaps the partner fetches
     uint32_t tb[Geo<4>::HMAX];
 #pragma unroll
-    for (int t = 0; t < Geo<4>::HMAX; ++t) tb[t] = ROT4_TAB.v[dig[t] * 64 + gl];
+    for (int t = 0; t < Geo<4>::HMAX; ++t) tb[t] = t < h ? ROT4_TAB.v[dig[t] * 64 + gl] : 0u;
     const uint32_t side_b = side ? 0xf0u : 0u;
 #pragma unroll
     for (int t = Geo<4>::HMAX - 1; t >= 0; --t) {
