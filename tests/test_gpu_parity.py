@@ -260,6 +260,38 @@ def test_walk_kernel_full_size_sampled_n4(ctx):
     w.end()
 
 
+@pytest.mark.parametrize("n,k,delta,walks,lg", [(2, 4, 3, 64, 10), (3, 6, 4, 256, 14)])
+def test_dp_table_entries(ctx, n, k, delta, walks, lg):
+    """The distinguished-point table after a few launches: every key is distinguished, keys are
+    unique, and each value (start, length, ready bit) is a trail the oracle walks from that start to
+    that key in exactly that many steps, with no distinguished point before."""
+    say("dp table", n, k, delta)
+    tw, u = oracle_target(n, k, 3)
+    tgt = ctx.target_from_words(n, tw.paulis, tw.clifford)
+    seed = 4200 + n
+    w = ctx.walk(tgt, k, 0, seed, delta, walks=walks, log2_table=lg, cap=20 << delta)
+    w.run(16)
+    w.run(16)
+    table = w.read_table(lg)
+    w.end()
+    empty = (1 << 64) - 1
+    keys = [int(key) for key, _ in table if int(key) != empty]
+    assert keys and len(keys) == len(set(keys))
+    spec = owalk.make_spec(u, n, k, 0, seed, delta=delta)
+    entries = [(int(key), int(val)) for key, val in table if int(key) != empty]
+    for key, val in entries[:24]:
+        assert owalk.distinguished(spec, key)
+        assert val >> 63 == 1
+        start, length = val & 0x1FFFFFFFF, (val >> 33) & 0x3FFFFFFF
+        assert length >= 1
+        pt = start
+        for i in range(length):
+            pt = owalk.f(spec, pt)
+            if i < length - 1:
+                assert not owalk.distinguished(spec, pt)
+        assert pt == key
+
+
 def test_checkpoint_resume_continues_trails(ctx):
     say("checkpoint")
     tw, u = oracle_target(3, 6, 2)
