@@ -955,6 +955,9 @@ uint64_t version_steps(const tcw_walk_params* p, uint64_t npts, int delta, int64
     return per_version < table_v ? per_version : table_v;
 }
 
+// the tables of one group of concurrently searched chunks stay within 2^35 bytes (32 GiB)
+constexpr int CHUNK_TABLE_POOL_LOG2 = 35;
+
 struct BatchTarget;
 int search_chunks_concurrent(tcw_ctx* c, const tcw_target* t, const tcw_walk_params* p, int k, int c_first,
                              int c_last, int delta, tcw_result* res, int* found, double t0);
@@ -996,7 +999,13 @@ extern "C" int tcw_search(tcw_ctx* c, const tcw_target* t, const tcw_walk_params
         }
         const bool enumerate = (int64_t)npts <= p->enum_max;
         const int delta = p->delta >= 0 ? p->delta : auto_delta(npts, p->log2_table);
-        if (k % 2 && !enumerate && p->chunk_parallel != 1) {
+        // odd depths with chunk_parallel != 1 run their chunks as concurrent batch members; for
+        // enumerated chunks only while their tables (4 npts slots of 16 B each) fit the chunk pool
+        const uint64_t n_chunks = (uint64_t)(cl - cf + 1);
+        const bool concurrent =
+            k % 2 && p->chunk_parallel != 1 &&
+            (!enumerate || n_chunks * 64 * npts <= (1ull << CHUNK_TABLE_POOL_LOG2));
+        if (concurrent) {
             // chunks in groups of G searched concurrently, one batch member each
             const int G = p->chunk_parallel <= 0 ? cl - cf + 1 : p->chunk_parallel;
             for (int first = cf; first <= cl && !found; first += G) {
@@ -1007,7 +1016,7 @@ extern "C" int tcw_search(tcw_ctx* c, const tcw_target* t, const tcw_walk_params
                 if (rc) return rc;
             }
         }
-        for (int chunk = cf; chunk <= cl && !found && (k % 2 == 0 || enumerate || p->chunk_parallel == 1); ++chunk) {
+        for (int chunk = cf; chunk <= cl && !found && !concurrent; ++chunk) {
             if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) break;
             if (enumerate) {
                 if ((rc = search_enum(c, t, p, k, chunk, iters, res, &found, t0))) return rc;
@@ -1232,32 +1241,44 @@ int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStr
             continue;
         }
         const uint64_t npts = 2 * nh;
-        if ((int64_t)npts <= b.p.enum_max) {
-            const int iters = default_iters(n);
-            if ((rc = search_enum(c, b.t, &b.p, b.k, b.chunk, iters, b.res, &found, t0))) return rc;
-            if (found) b.done = true;
-            continue;
+        // A small space is enumerated: every point evaluated once, keyed in the table by its full
+        // matrix hash, as one more member of the batch; it is done after npts steps.  Larger
+        // spaces are walked.
+        const bool enumerate = (int64_t)npts <= b.p.enum_max;
+        int delta = 0;
+        if (enumerate) {
+            const int64_t wmax = std::max<int64_t>(64, b.p.walks);
+            b.walks = (int64_t)npts < wmax ? (int64_t)npts : wmax;
+            int lg = 4;
+            while ((1ull << lg) < 4 * npts && lg < 30) ++lg;
+            b.log2 = lg;
+            b.iters = default_iters(n);
+        } else {
+            delta = b.p.delta >= 0 ? b.p.delta
+                                   : auto_delta(npts, b.p.log2_table > 0 ? b.p.log2_table : default_log2_table(n));
+            TunedCfg cfg;
+            if (b.p.walks <= 0 || b.p.log2_table <= 0 || b.p.iters_per_launch <= 0) {
+                if ((rc = autotune(c, b.t, b.k, b.chunk, delta, b.p.seed, &cfg))) return rc;
+            }
+            b.walks = b.p.walks > 0 ? b.p.walks : cfg.walks;
+            b.log2 = b.p.log2_table > 0 ? b.p.log2_table : cfg.log2_table;
+            b.iters = b.p.iters_per_launch > 0 ? b.p.iters_per_launch : cfg.iters;
         }
-        // a walk space
-        const int delta =
-            b.p.delta >= 0 ? b.p.delta : auto_delta(npts, b.p.log2_table > 0 ? b.p.log2_table : default_log2_table(n));
-        TunedCfg cfg;
-        if (b.p.walks <= 0 || b.p.log2_table <= 0 || b.p.iters_per_launch <= 0) {
-            if ((rc = autotune(c, b.t, b.k, b.chunk, delta, b.p.seed, &cfg))) return rc;
-        }
-        b.walks = b.p.walks > 0 ? b.p.walks : cfg.walks;
-        b.log2 = b.p.log2_table > 0 ? b.p.log2_table : cfg.log2_table;
-        b.iters = b.p.iters_per_launch > 0 ? b.p.iters_per_launch : cfg.iters;
         b.space.reset(new Space());
         tcw_space sp{b.k, b.chunk, b.p.seed, b.p.version, delta};
         if ((rc = prepare_space(c, b.t, &sp, *b.space))) return rc;
         b.res->spaces++;
         b.res->versions++;
         b.version = b.p.version;
-        b.budget = (uint64_t)b.p.budget_beta * npts << delta;
-        b.per_version = version_steps(&b.p, npts, delta, b.walks, b.log2);
-        const uint64_t fit = b.per_version / (uint64_t)b.walks;
-        if ((uint64_t)b.iters > fit) b.iters = fit > 0 ? (int)fit : 1;
+        if (enumerate) {
+            b.budget = npts;
+            b.per_version = ~0ull;  // no function versions: the enumeration is exhaustive
+        } else {
+            b.budget = (uint64_t)b.p.budget_beta * npts << delta;
+            b.per_version = version_steps(&b.p, npts, delta, b.walks, b.log2);
+            const uint64_t fit = b.per_version / (uint64_t)b.walks;
+            if ((uint64_t)b.iters > fit) b.iters = fit > 0 ? (int)fit : 1;
+        }
         b.used = b.used_v = 0;
         b.seen = 0;
         // walk buffers (kept across spaces when large enough)
@@ -1274,8 +1295,8 @@ int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStr
         }
         b.wd.walks = b.walks;
         b.wd.log2_table = b.log2;
-        b.wd.cap = (uint32_t)b.p.trail_cap_factor << delta;
-        b.wd.enumerate = 0;
+        b.wd.cap = enumerate ? 2u : (uint32_t)b.p.trail_cap_factor << delta;
+        b.wd.enumerate = enumerate ? 1 : 0;
         b.wd.n_points = npts;
         b.wd.stats = bb.stats + (size_t)slot * tcw::ST_COUNT;
         b.wd.claws = bb.claws + (size_t)slot * BATCH_CLAW_CAP * 2;
@@ -1539,9 +1560,6 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
 }  // namespace
 
 namespace {
-
-// Total bytes of distinguished-point tables a concurrent chunk group may hold (2^35 = 32 GiB).
-constexpr int CHUNK_TABLE_POOL_LOG2 = 35;
 
 int search_chunks_concurrent(tcw_ctx* c, const tcw_target* t, const tcw_walk_params* p, int k, int c_first,
                              int c_last, int delta, tcw_result* res, int* found, double t0) {
