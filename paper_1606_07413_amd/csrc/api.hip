@@ -1203,8 +1203,8 @@ int batch_restart(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStr
     return TCW_OK;
 }
 
-// Move a target to its next space: depth 0 and small spaces are searched on the spot, the first
-// walk space leaves the target `walking`.
+// Move a target to its next space: depth 0 is checked on the spot; the next space of a positive
+// depth, enumerated when small and walked otherwise, leaves the target `walking`.
 int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStream_t s, double t0) {
     const int n = b.t->n;
     const uint32_t xi = xi_of(n);
