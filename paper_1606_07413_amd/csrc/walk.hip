@@ -115,26 +115,6 @@ __device__ void load_lds(Lds<NQ, WAVES>& L, const SpaceDev& sp) {
     for (int i = threadIdx.x; i < Gm::R; i += blockDim.x) L.K[i] = sp.keys[i];
 }
 
-// Lane exchange with the partner lane ^ X (X a compile-time power of two below 64): DPP quad
-// permutes for 1 and 2, ds_swizzle's xor mode for 4..16 (within 32 lanes), ds_bpermute for 32.
-template <int X>
-__device__ inline uint32_t xchg32(uint32_t v, int lane) {
-    if constexpr (X == 1) {
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
-    } else if constexpr (X == 2) {
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
-    } else if constexpr (X == 4 || X == 8 || X == 16) {
-        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (X << 10));   // and 0x1f, xor X
-    } else {
-        return shfl32(v, lane ^ X);
-    }
-}
-template <int X>
-__device__ inline uint64_t xchg64(uint64_t v, int lane) {
-    const uint32_t lo = xchg32<X>((uint32_t)v, lane);
-    const uint32_t hi = xchg32<X>((uint32_t)(v >> 32), lane);
-    return ((uint64_t)hi << 32) | lo;
-}
 // a 64-bit value moved by one DPP pattern (every source lane inside the wave: quad permutes, row
 // rotations)
 template <int CTRL>
@@ -142,16 +122,6 @@ __device__ inline uint64_t dpp64(uint64_t v) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, 0xF, 0xF, true);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, true);
     return ((uint64_t)hi << 32) | lo;
-}
-__device__ inline uint64_t xchg64_dyn(uint64_t v, int x, int lane) {
-    switch (x) {
-        case 1: return xchg64<1>(v, lane);
-        case 2: return xchg64<2>(v, lane);
-        case 4: return xchg64<4>(v, lane);
-        case 8: return xchg64<8>(v, lane);
-        case 16: return xchg64<16>(v, lane);
-        default: return xchg64<32>(v, lane);
-    }
 }
 
 // x * 2^s mod p for a lane-dependent 0 <= s < 61 (x in [0, p])
@@ -632,8 +602,14 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
         // one walk per wavefront: the sum is the same in every lane; finish on the scalar unit
         acc = uniform64(acc);
     } else {
-#pragma unroll
-        for (int off = 1; off < Gm::G; off <<= 1) acc += xchg64_dyn(acc, off, gbase + gl);
+        // a walk group is a quad (n = 1) or a 16-lane row (n = 2): DPP within it, no LDS round trip
+        static_assert(Gm::G == 4 || Gm::G == 16, "walk groups below 64 lanes are quads or rows");
+        acc += dpp64<0xB1>(acc);  // quad_perm [1,0,3,2]
+        acc += dpp64<0x4E>(acc);  // quad_perm [2,3,0,1]
+        if constexpr (Gm::G == 16) {
+            acc += dpp64<0x124>(acc);  // row_ror:4
+            acc += dpp64<0x128>(acc);  // row_ror:8
+        }
     }
     const uint64_t H = mix64(acc);
     out_h = H;
