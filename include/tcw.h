@@ -194,7 +194,8 @@ typedef struct tcw_walk_params {
     int32_t chunk_last;       /* odd k: last chunk tried (default xi) */
     double max_seconds;       /* wall-clock cap for the whole search (0: none) */
     int32_t chunk_parallel;   /* odd k: chunks searched concurrently, each with walks / G walks and its
-                                 own table (1, the default: one at a time in ascending order; 0: all) */
+                                 own table; small (enumerated) chunks too while their tables fit 32 GiB
+                                 (1, the default: one at a time in ascending order; 0: all) */
 } tcw_walk_params;
 
 typedef struct tcw_result {
