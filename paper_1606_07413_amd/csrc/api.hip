@@ -86,6 +86,30 @@ int hip_fail(tcw_ctx* c, hipError_t e, const char* where) {
         if (_e != hipSuccess) return hip_fail(ctx, _e, #expr); \
     } while (0)
 
+// Device buffers local to one call, freed when the call returns on any path (an early HIP_TRY
+// return included).
+class DevScope {
+   public:
+    DevScope() = default;
+    DevScope(const DevScope&) = delete;
+    DevScope& operator=(const DevScope&) = delete;
+    ~DevScope() {
+        for (void* q : bufs_) (void)hipFree(q);
+    }
+    template <typename T>
+    hipError_t alloc(T** p, size_t bytes) {
+        void* q = nullptr;
+        const hipError_t e = hipMalloc(&q, bytes);
+        if (e != hipSuccess) return e;
+        bufs_.push_back(q);
+        *p = static_cast<T*>(q);
+        return hipSuccess;
+    }
+
+   private:
+    std::vector<void*> bufs_;
+};
+
 uint32_t xi_of(int n) { return (1u << (2 * n)) - 1; }
 
 // xi^h, or 0 if it does not fit in 32 bits
@@ -167,12 +191,13 @@ int prepare_space(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, Space& o
     HIP_TRY(c, hipMalloc(&out.keys, (size_t)R * sizeof(uint64_t)));
     if ((rc = clear_flag(c))) return rc;
     // S_c = U R(c)^T for odd k, U for even k
+    DevScope scope;
     uint16_t* seq = nullptr;
     uint8_t* tr = nullptr;
     int nseq = 0;
     if (sp->k % 2 == 1) {
-        HIP_TRY(c, hipMalloc(&seq, sizeof(uint16_t)));
-        HIP_TRY(c, hipMalloc(&tr, 1));
+        HIP_TRY(c, scope.alloc(&seq, sizeof(uint16_t)));
+        HIP_TRY(c, scope.alloc(&tr, 1));
         const uint16_t cc = (uint16_t)sp->chunk;
         const uint8_t one = 1;
         HIP_TRY(c, hipMemcpyAsync(seq, &cc, sizeof(cc), hipMemcpyHostToDevice, c->stream));
@@ -180,8 +205,6 @@ int prepare_space(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, Space& o
         nseq = 1;
     }
     hipError_t e = tcw::exact_apply(out.S, t->U, seq, tr, nseq, c->flag, c->stream);
-    if (seq) (void)hipFree(seq);
-    if (tr) (void)hipFree(tr);
     if (e != hipSuccess) return hip_fail(c, e, "chunk matrix");
     HIP_TRY(c, tcw::exact_pack_phi(out.S, out.phi, c->flag, c->stream));
     HIP_TRY(c, tcw::keys_fill(n, sp->seed, out.keys, c->stream));
@@ -461,8 +484,9 @@ int tcw_target_channel(tcw_ctx* c, const tcw_target* t, int32_t* a, int32_t* b, 
     if (!c || !t || !a || !b || !e) return TCW_EINVAL;
     const size_t rr = (size_t)1 << (4 * t->n);
     int32_t *da = nullptr, *db = nullptr;
-    HIP_TRY(c, hipMalloc(&da, rr * 4));
-    HIP_TRY(c, hipMalloc(&db, rr * 4));
+    DevScope scope;
+    HIP_TRY(c, scope.alloc(&da, rr * 4));
+    HIP_TRY(c, scope.alloc(&db, rr * 4));
     int rc = clear_flag(c);
     if (!rc) {
         hipError_t err = tcw::exact_to_i32(t->U, da, db, c->flag, c->stream);
@@ -473,8 +497,6 @@ int tcw_target_channel(tcw_ctx* c, const tcw_target* t, int32_t* a, int32_t* b, 
     }
     int flag = 0;
     if (!rc) rc = read_flag(c, &flag);
-    (void)hipFree(da);
-    (void)hipFree(db);
     if (!rc && flag) rc = fail(c, TCW_EOVERFLOW, "entry does not fit int32");
     return rc;
 }
@@ -523,10 +545,12 @@ int tcw_canon_hash(tcw_ctx* c, int n, const tcw_space* sp, const int32_t* a, con
     if (n < 1 || n > 4) return fail(c, TCW_EINVAL, "n must be in 1..4");
     if (count == 0) return TCW_OK;
     const int R = 1 << (2 * n);
+    if (count > (int64_t)1 << 31) return fail(c, TCW_EINVAL, "count above 2^31");  // keeps the byte count exact
     uint32_t* phi = nullptr;
     uint64_t* keys = nullptr;
-    HIP_TRY(c, hipMalloc(&phi, (size_t)count * R * R / 2 * sizeof(uint32_t)));
-    HIP_TRY(c, hipMalloc(&keys, (size_t)R * sizeof(uint64_t)));
+    DevScope scope;
+    HIP_TRY(c, scope.alloc(&phi, (size_t)count * R * R / 2 * sizeof(uint32_t)));
+    HIP_TRY(c, scope.alloc(&keys, (size_t)R * sizeof(uint64_t)));
     int rc = clear_flag(c);
     Space s;
     s.k = sp->k;
@@ -544,8 +568,6 @@ int tcw_canon_hash(tcw_ctx* c, int n, const tcw_space* sp, const int32_t* a, con
     if (!rc && err == hipSuccess) err = tcw::launch_canon_hash(n, s.dev, phi, e, count, h_out, c->stream);
     if (!rc && err == hipSuccess) err = hipStreamSynchronize(c->stream);
     if (!rc && err != hipSuccess) rc = hip_fail(c, err, "canon hash");
-    (void)hipFree(phi);
-    (void)hipFree(keys);
     return rc;
 }
 
@@ -778,11 +800,12 @@ int check_pairs(tcw_ctx* c, const Space& sp, const uint64_t* u0, const uint64_t*
     uint64_t *d0 = nullptr, *d1 = nullptr;
     int32_t *dok = nullptr, *dperm = nullptr;
     int8_t* dsign = nullptr;
-    HIP_TRY(c, hipMalloc(&d0, m * 8));
-    HIP_TRY(c, hipMalloc(&d1, m * 8));
-    HIP_TRY(c, hipMalloc(&dok, m * 4));
-    HIP_TRY(c, hipMalloc(&dperm, m * R * 4));
-    HIP_TRY(c, hipMalloc(&dsign, m * R));
+    DevScope scope;
+    HIP_TRY(c, scope.alloc(&d0, m * 8));
+    HIP_TRY(c, scope.alloc(&d1, m * 8));
+    HIP_TRY(c, scope.alloc(&dok, m * 4));
+    HIP_TRY(c, scope.alloc(&dperm, m * R * 4));
+    HIP_TRY(c, scope.alloc(&dsign, m * R));
     HIP_TRY(c, hipMemcpyAsync(d0, u0, m * 8, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d1, u1, m * 8, hipMemcpyHostToDevice, c->stream));
     const size_t need = tcw::exact_claw_scratch_bytes(n);
@@ -801,11 +824,6 @@ int check_pairs(tcw_ctx* c, const Space& sp, const uint64_t* u0, const uint64_t*
     HIP_TRY(c, hipMemcpyAsync(perm.data(), dperm, m * R * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(sign.data(), dsign, m * R, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    (void)hipFree(d0);
-    (void)hipFree(d1);
-    (void)hipFree(dok);
-    (void)hipFree(dperm);
-    (void)hipFree(dsign);
     for (int64_t i = 0; i < m; ++i) {
         if (!ok[i]) {
             res->false_claws++;
@@ -880,9 +898,10 @@ int search_k0(tcw_ctx* c, const tcw_target* t, tcw_result* res, int* found) {
     *found = 0;
     int32_t *dok = nullptr, *dperm = nullptr;
     int8_t* dsign = nullptr;
-    HIP_TRY(c, hipMalloc(&dok, 4));
-    HIP_TRY(c, hipMalloc(&dperm, R * 4));
-    HIP_TRY(c, hipMalloc(&dsign, R));
+    DevScope scope;
+    HIP_TRY(c, scope.alloc(&dok, 4));
+    HIP_TRY(c, scope.alloc(&dperm, R * 4));
+    HIP_TRY(c, scope.alloc(&dsign, R));
     HIP_TRY(c, tcw::exact_signed_perm(t->U, dok, dperm, dsign, c->stream));
     int32_t ok = 0;
     std::vector<int32_t> perm(R);
@@ -891,9 +910,6 @@ int search_k0(tcw_ctx* c, const tcw_target* t, tcw_result* res, int* found) {
     HIP_TRY(c, hipMemcpyAsync(perm.data(), dperm, R * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(sign.data(), dsign, R, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    (void)hipFree(dok);
-    (void)hipFree(dperm);
-    (void)hipFree(dsign);
     res->spaces++;
     if (ok) {
         res->status = 1;
