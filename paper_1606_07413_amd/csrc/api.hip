@@ -1477,7 +1477,7 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
             BATCH_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
             dirty = false;
         }
-        // descriptors of this round (salts change with versions)
+        // descriptors for the next graph replay (salts change with versions)
         for (int i = 0; i < count; ++i) {
             if (!bt[i].walking) continue;
             h_sps[i] = bt[i].space->dev;

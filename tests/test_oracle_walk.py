@@ -195,3 +195,9 @@ def test_input_generator_and_oracle_mixers_agree():
     for s in (0, 1, 0xDEADBEEF, (1 << 64) - 1):
         for i in range(5):
             assert seeded_inputs.splitmix64(s, i) == walk.sm64(s, i)
+
+
+def test_splitmix64_published_sequence():
+    """The mixer is SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): from state 0 its reference
+    generator's first three outputs are these published values."""
+    assert [walk.sm64(0, i) for i in range(3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
