@@ -296,14 +296,14 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def tts_n4_enum_leg(ctx, cap: float):
+def tts_n4_enum_leg(ctx, cap: float, seeds=(1, 2, 3, 4)):
     """The same n = 4 searches in the memory-rich limit: every space of up to 2^26 points (all of
     depths <= 7 at n = 4) enumerated exhaustively, each point hashed once into a table of 4N slots
     keyed by its full matrix hash (the meet-in-the-middle the walks replace when memory is short);
     deterministic, and every depth below the answer is searched completely."""
     import seeded_inputs
     runs = []
-    for ts in range(1, 5):
+    for ts in seeds:
         twn = seeded_inputs.target_words(4, 7, ts)
         tn = ctx.target_from_words(4, twn.paulis, twn.clifford)
         p4 = ctx.default_params(4)
@@ -320,7 +320,7 @@ def tts_n4_enum_leg(ctx, cap: float):
     return {"measured": True, "mode": "exhaustive spaces (enum_max 2^26)", "cap_s": cap, "runs": runs}
 
 
-def tts_n4_leg(ctx, cap: float, slice_s: float = 60.0):
+def tts_n4_leg(ctx, cap: float, slice_s: float = 60.0, seeds=(1, 2, 3, 4)):
     """The whole optimal-T-count search for the four seeded n = 4, k = 7 targets at theta = 1/2 (the
     paper's choice when the table holds the whole space: 2^27 slots >> N = 3.3e7 per chunk), every
     chunk of an odd depth searched concurrently.  Depths 0..6 run as one call; depth 7 runs in calls
@@ -328,7 +328,7 @@ def tts_n4_leg(ctx, cap: float, slice_s: float = 60.0):
     from an empty table anyway), until a verified decomposition or the cap."""
     import seeded_inputs
     runs = []
-    for ts in range(1, 5):
+    for ts in seeds:
         twn = seeded_inputs.target_words(4, 7, ts)
         tn = ctx.target_from_words(4, twn.paulis, twn.clifford)
 
@@ -633,7 +633,7 @@ def main():
 
     extra = {}
     if not args.no_tts:
-        # time-to-solution at n = 3, k = 6 (measured) and the n = 4, k = 7 projection
+        # time-to-solution at n = 3, k = 6 (measured); n = 4, k = 7 below
         tw3 = seeded_inputs.target_words(3, 6, 1)
         t3 = ctx.target_from_words(3, tw3.paulis, tw3.clifford)
         p3 = ctx.default_params(3)
@@ -652,13 +652,26 @@ def main():
         extra["tts_n4k7_planted_chunk"] = tts_n4_planted_leg(
             ctx, args.tts_n4_planted_cap, seeds=tuple(int(v) for v in args.tts_n4_planted_seeds.split(",")))
     if not args.no_tts:
+        # the whole optimal-T-count search of this target, measured two ways: the walks (theta = 1/2,
+        # chunks of each odd depth concurrent) and exhaustive enumeration of every space.  Its
+        # generating word has 7 rotations but its optimum is lower (two equal adjacent Paulis).
+        walks_run = tts_n4_leg(ctx, 60.0, seeds=(1,))["runs"][0]
+        enum_run = tts_n4_enum_leg(ctx, 60.0, seeds=(1,))["runs"][0]
+        # and a projection for the configured walk search (theta = 2^-12, chunks in ascending order)
+        # of a target of T-count 7 whose claw lies in this chunk
         n_pts = 2 * 255 ** 3
         steps_chunk = n_pts * (1 << delta)          # Appendix: about N / theta steps for the chunk with the claw
         budget = 16 * steps_chunk                   # each earlier chunk fails after its full budget
-        proj = (chunk - 1) * budget + steps_chunk   # chunks run in ascending order
-        extra["tts_n4k7"] = {"seconds": proj / value, "measured": False,
-                             "basis": f"{chunk - 1} chunks x budget {budget:.3g} steps + N/theta = {steps_chunk:.3g} "
-                                      f"steps in the planted chunk, at the measured rate (projected)"}
+        proj = (chunk - 1) * budget + steps_chunk
+        extra["tts_n4k7"] = {
+            "target_seed": 1, "measured": True,
+            "walks_theta_half": {**walks_run, "theta": 0.5, "chunk_parallel": "all", "cap_s": 60.0},
+            "exhaustive": {**enum_run, "enum_max": 1 << 26, "cap_s": 60.0},
+            "configured_theta_projection": {
+                "seconds": proj / value, "measured": False,
+                "basis": f"a T-count-7 target with its claw in chunk {chunk}, theta = 2^-{delta}, chunks in "
+                         f"ascending order: {chunk - 1} chunks x budget {budget:.3g} steps + N/theta = "
+                         f"{steps_chunk:.3g} steps in that chunk, at the measured rate"}}
 
     traffic = measured_traffic(args.walks, args.iters)
     out = {
