@@ -155,6 +155,21 @@ def _ptr(t) -> Optional[int]:
     return t.data_ptr()
 
 
+def _dev(t, esize: int, need: int, what: str, device: int) -> Optional[int]:
+    """Device pointer of a contiguous CUDA tensor on `device` whose elements are esize bytes wide and
+    which holds at least `need` of them: the library writes `need` elements through the pointer."""
+    if t is None:
+        return None
+    p = _ptr(t)
+    if t.device.index != device:
+        raise ValueError(f"{what}: tensor on cuda:{t.device.index}, context on cuda:{device}")
+    if t.element_size() != esize:
+        raise TypeError(f"{what}: elements of {esize} bytes expected, got {t.dtype}")
+    if t.numel() < need:
+        raise ValueError(f"{what}: at least {need} elements expected, got {t.numel()}")
+    return p
+
+
 def _u16_array(vals: Sequence[int]):
     arr = (C.c_uint16 * max(1, len(vals)))(*vals)
     return arr
@@ -236,27 +251,35 @@ class Context:
     # ---- parity entry points ----
     def step(self, target, k, chunk, seed, delta, pts_in, pts_out, hash_out=None, version=0):
         sp = Space(k, chunk, seed, version, delta)
-        self._check(self.lib.tcw_step(self.h, target.h, C.byref(sp), _ptr(pts_in), _ptr(pts_out), _ptr(hash_out),
-                                      pts_in.numel()))
+        count, d = pts_in.numel(), self.device
+        self._check(self.lib.tcw_step(self.h, target.h, C.byref(sp), _dev(pts_in, 8, count, "pts_in", d),
+                                      _dev(pts_out, 8, count, "pts_out", d), _dev(hash_out, 8, count, "hash_out", d),
+                                      count))
 
     def trails(self, target, k, chunk, seed, delta, starts, cap, dp_out, len_out, version=0):
         sp = Space(k, chunk, seed, version, delta)
-        self._check(self.lib.tcw_trails(self.h, target.h, C.byref(sp), _ptr(starts), starts.numel(), cap,
-                                        _ptr(dp_out), _ptr(len_out)))
+        count, d = starts.numel(), self.device
+        self._check(self.lib.tcw_trails(self.h, target.h, C.byref(sp), _dev(starts, 8, count, "starts", d), count,
+                                        cap, _dev(dp_out, 8, count, "dp_out", d), _dev(len_out, 4, count, "len_out", d)))
 
     def start_points(self, target, k, chunk, seed, w0, j, count, out, version=0):
         sp = Space(k, chunk, seed, version, 0)
-        self._check(self.lib.tcw_start_points(self.h, target.h, C.byref(sp), w0, j, count, _ptr(out)))
+        self._check(self.lib.tcw_start_points(self.h, target.h, C.byref(sp), w0, j, count,
+                                              _dev(out, 8, count, "out", self.device)))
 
     def canon_hash(self, n, k, chunk, seed, a, b, e, out, version=0):
         sp = Space(k, chunk, seed, version, 0)
-        self._check(self.lib.tcw_canon_hash(self.h, n, C.byref(sp), _ptr(a), _ptr(b), _ptr(e), e.numel(),
-                                            _ptr(out)))
+        count, rr, d = e.numel(), 16 ** n, self.device
+        self._check(self.lib.tcw_canon_hash(self.h, n, C.byref(sp), _dev(a, 4, count * rr, "a", d),
+                                            _dev(b, 4, count * rr, "b", d), _dev(e, 4, count, "e", d), count,
+                                            _dev(out, 8, count, "out", d)))
 
     def claw_check(self, target, k, chunk, seed, u0, u1, ok, perm, sign, version=0):
         sp = Space(k, chunk, seed, version, 0)
-        self._check(self.lib.tcw_claw_check(self.h, target.h, C.byref(sp), _ptr(u0), _ptr(u1), u0.numel(),
-                                            _ptr(ok), _ptr(perm), _ptr(sign)))
+        count, r, d = u0.numel(), 4 ** target.n, self.device
+        self._check(self.lib.tcw_claw_check(self.h, target.h, C.byref(sp), _dev(u0, 8, count, "u0", d),
+                                            _dev(u1, 8, count, "u1", d), count, _dev(ok, 4, count, "ok", d),
+                                            _dev(perm, 4, count * r, "perm", d), _dev(sign, 1, count * r, "sign", d)))
 
     # ---- walks and search ----
     def walk(self, target, k, chunk, seed, delta, walks, log2_table, cap, enumerate=False, version=0) -> "Walk":
@@ -416,7 +439,7 @@ class Walk:
 
 
 def _features(self, target, out):
-    self._check(self.lib.tcw_features(self.h, target.h, _ptr(out)))
+    self._check(self.lib.tcw_features(self.h, target.h, _dev(out, 4, 16 ** target.n, "out", self.device)))
 
 
 def _label_batch(self, n, words_list, h_max, seed, features_out, labels_out):
@@ -430,8 +453,10 @@ def _label_batch(self, n, words_list, h_max, seed, features_out, labels_out):
     w = (C.c_uint16 * max(1, len(flat)))(*flat)
     o = (C.c_int32 * len(offs))(*offs)
     k = (C.c_int32 * len(ks))(*ks)
-    self._check(self.lib.tcw_label_batch(self.h, n, len(ks), w, o, k, h_max, seed, _ptr(features_out),
-                                         _ptr(labels_out)))
+    d = self.device
+    self._check(self.lib.tcw_label_batch(self.h, n, len(ks), w, o, k, h_max, seed,
+                                         _dev(features_out, 4, len(ks) * 16 ** n, "features_out", d),
+                                         _dev(labels_out, 4, len(ks), "labels_out", d)))
 
 
 Context.features = _features
@@ -467,27 +492,40 @@ class Network:
         flat = np.ascontiguousarray(flat, dtype=np.float32)
         self.ctx._check(self.ctx.lib.tcw_mlp_set_params(self.h, flat.ctypes.data))
 
+    def _x(self, x):
+        # rows of `inp` float32 features
+        return _dev(x, 4, x.shape[0] * self.dims[0], "x", self.ctx.device)
+
+    def _labels(self, labels, b):
+        return _dev(labels, 4, b, "labels", self.ctx.device)
+
     def forward(self, x, probs_out):
-        self.ctx._check(self.ctx.lib.tcw_mlp_forward(self.h, _ptr(x), x.shape[0], _ptr(probs_out)))
+        b = x.shape[0]
+        self.ctx._check(self.ctx.lib.tcw_mlp_forward(self.h, self._x(x), b,
+                                                     _dev(probs_out, 4, b * self.dims[3], "probs_out",
+                                                          self.ctx.device)))
 
     def gradients(self, x, labels):
         import numpy as np
         g = np.zeros(self.count, dtype=np.float32)
         loss = C.c_float(0)
-        self.ctx._check(self.ctx.lib.tcw_mlp_gradients(self.h, _ptr(x), _ptr(labels), x.shape[0], g.ctypes.data,
-                                                       C.byref(loss)))
+        b = x.shape[0]
+        self.ctx._check(self.ctx.lib.tcw_mlp_gradients(self.h, self._x(x), self._labels(labels, b), b,
+                                                       g.ctypes.data, C.byref(loss)))
         return g, loss.value
 
     def train_step(self, x, labels, lr):
         loss = C.c_float(0)
-        self.ctx._check(self.ctx.lib.tcw_mlp_train_step(self.h, _ptr(x), _ptr(labels), x.shape[0], lr,
+        b = x.shape[0]
+        self.ctx._check(self.ctx.lib.tcw_mlp_train_step(self.h, self._x(x), self._labels(labels, b), b, lr,
                                                         C.byref(loss)))
         return loss.value
 
     def train(self, x, labels, batch, epochs, lr):
         loss = C.c_float(0)
-        self.ctx._check(self.ctx.lib.tcw_mlp_train(self.h, _ptr(x), _ptr(labels), x.shape[0], batch, epochs, lr,
-                                                   C.byref(loss)))
+        b = x.shape[0]
+        self.ctx._check(self.ctx.lib.tcw_mlp_train(self.h, self._x(x), self._labels(labels, b), b, batch, epochs,
+                                                   lr, C.byref(loss)))
         return loss.value
 
     def depth_order(self, target, k_max):

@@ -69,6 +69,29 @@ def test_target_from_channel_validates(ctx):
         ctx.target_from_channel(2, bad, np.array(u.B, dtype=np.int32), u.e)
 
 
+
+def test_binding_checks_device_arrays(ctx):
+    """The binding refuses output arrays that are too short or of the wrong element width before
+    anything is launched (the library writes `count` elements through the pointer it gets)."""
+    import torch
+    say("binding argument checks")
+    tw, u = oracle_target(2, 4, 1)
+    tgt = ctx.target_from_words(2, tw.paulis, tw.clifford)
+    din = dev([owalk.pack(0, 0), owalk.pack(1, 1), owalk.pack(2, 0)])
+    with pytest.raises(ValueError):
+        ctx.step(tgt, 4, 0, 1, 4, din, torch.empty(2, dtype=torch.int64, device="cuda:0"))
+    with pytest.raises(TypeError):
+        ctx.step(tgt, 4, 0, 1, 4, din, torch.empty(3, dtype=torch.int32, device="cuda:0"))
+    with pytest.raises(ValueError):
+        ctx.trails(tgt, 4, 0, 1, 4, din, 64, torch.empty_like(din), torch.empty(2, dtype=torch.int32, device="cuda:0"))
+    with pytest.raises(TypeError):
+        ctx.step(tgt, 4, 0, 1, 4, din, torch.empty_like(din)[::1].cpu())
+    # a correct call still works afterwards
+    out = torch.empty_like(din)
+    ctx.step(tgt, 4, 0, 1, 4, din, out)
+    spec = owalk.make_spec(u, 2, 4, 0, 1, delta=4)
+    assert host_u64(out) == [owalk.f(spec, p) for p in host_u64(din)]
+
 STEP_CASES = [(1, 4, 1, 37), (1, 5, 2, 100), (2, 2, 5, 30), (2, 4, 1, 300), (2, 5, 3, 129), (2, 6, 4, 65),
               (3, 3, 5, 64), (3, 5, 2, 77), (3, 6, 1, 200), (4, 1, 4, 16), (4, 2, 1, 33), (4, 3, 2, 20),
               (4, 4, 3, 8), (4, 5, 6, 24), (4, 6, 5, 40), (4, 7, 1, 64)]

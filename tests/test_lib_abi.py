@@ -71,3 +71,12 @@ def test_default_params_per_n():
         lib.tcw_default_params(ctypes.byref(p), n)
         assert p.walks == walks and p.log2_table == lg and p.trail_cap_factor == 20 and p.budget_beta == 16
         assert p.chunk_parallel == 1
+
+
+def test_binding_refuses_host_tensors():
+    """Device-array arguments must be CUDA tensors: a host tensor is refused before any call."""
+    import torch
+    from paper_1606_07413_amd import tcw
+    with pytest.raises(TypeError):
+        tcw._dev(torch.zeros(4, dtype=torch.int64), 8, 4, "x", 0)
+    assert tcw._dev(None, 8, 4, "x", 0) is None
