@@ -95,6 +95,10 @@ typedef struct tcw_space {
     int32_t delta;
 } tcw_space;
 
+/* The per-point calls below (tcw_step, tcw_trails, tcw_start_points, tcw_canon_hash,
+ * tcw_claw_check) take count = 0 as a no-op that still validates the space; their arrays may then
+ * be NULL.  Otherwise every array pointer must be valid for `count` entries (NULL: TCW_EINVAL). */
+
 /* tcw_step (parity): pts_out[i] = f(pts_in[i]) and, if hash_out_dev != NULL, the matrix hash H of
  * pts_in[i] (Sec. 3, f(x, b) = z_b(x); Sec. 2, h o nu o mu).  Device arrays of `count` entries. */
 int tcw_step(tcw_ctx* ctx, const tcw_target* t, const tcw_space* sp, const uint64_t* pts_in_dev,

@@ -503,7 +503,8 @@ int tcw_target_channel(tcw_ctx* c, const tcw_target* t, int32_t* a, int32_t* b, 
 
 int tcw_step(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, const uint64_t* in, uint64_t* out, uint64_t* hash,
              int64_t count) {
-    if (!c || !t || !in || !out || count < 0) return TCW_EINVAL;
+    if (!c || !t || count < 0 || (count > 0 && (!in || !out))) return TCW_EINVAL;
+    if (count == 0) return check_space(c, t->n, sp);
     Space s;
     int rc = prepare_space(c, t, sp, s);
     if (rc) return rc;
@@ -514,7 +515,8 @@ int tcw_step(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, const uint64_
 
 int tcw_trails(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, const uint64_t* starts, int64_t count,
                uint32_t cap, uint64_t* dp, uint32_t* len) {
-    if (!c || !t || !starts || !dp || !len || count < 0 || cap == 0) return TCW_EINVAL;
+    if (!c || !t || count < 0 || cap == 0 || (count > 0 && (!starts || !dp || !len))) return TCW_EINVAL;
+    if (count == 0) return check_space(c, t->n, sp);
     Space s;
     int rc = prepare_space(c, t, sp, s);
     if (rc) return rc;
@@ -525,9 +527,9 @@ int tcw_trails(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, const uint6
 
 int tcw_start_points(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, int64_t w0, uint32_t j, int64_t count,
                      uint64_t* out) {
-    if (!c || !t || !out || count < 0 || w0 < 0 || w0 + count > (1ll << 32)) return TCW_EINVAL;
+    if (!c || !t || count < 0 || (count > 0 && !out) || w0 < 0 || w0 + count > (1ll << 32)) return TCW_EINVAL;
     int rc = check_space(c, t->n, sp);
-    if (rc) return rc;
+    if (rc || count == 0) return rc;
     Space s;
     s.k = sp->k;
     s.chunk = sp->chunk;
@@ -541,7 +543,7 @@ int tcw_start_points(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, int64
 
 int tcw_canon_hash(tcw_ctx* c, int n, const tcw_space* sp, const int32_t* a, const int32_t* b, const int32_t* e,
                    int64_t count, uint64_t* h_out) {
-    if (!c || !sp || !a || !b || !e || !h_out || count < 0) return TCW_EINVAL;
+    if (!c || !sp || count < 0 || (count > 0 && (!a || !b || !e || !h_out))) return TCW_EINVAL;
     if (n < 1 || n > 4) return fail(c, TCW_EINVAL, "n must be in 1..4");
     if (count == 0) return TCW_OK;
     const int R = 1 << (2 * n);
@@ -573,7 +575,8 @@ int tcw_canon_hash(tcw_ctx* c, int n, const tcw_space* sp, const int32_t* a, con
 
 int tcw_claw_check(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, const uint64_t* u0, const uint64_t* u1,
                    int64_t count, int32_t* ok, int32_t* perm, int8_t* sign) {
-    if (!c || !t || !u0 || !u1 || !ok || !perm || !sign || count < 0) return TCW_EINVAL;
+    if (!c || !t || count < 0 || (count > 0 && (!u0 || !u1 || !ok || !perm || !sign))) return TCW_EINVAL;
+    if (count == 0) return check_space(c, t->n, sp);
     Space s;
     int rc = prepare_space(c, t, sp, s);
     if (rc) return rc;

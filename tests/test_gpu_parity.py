@@ -92,6 +92,29 @@ def test_binding_checks_device_arrays(ctx):
     spec = owalk.make_spec(u, 2, 4, 0, 1, delta=4)
     assert host_u64(out) == [owalk.f(spec, p) for p in host_u64(din)]
 
+
+def test_empty_inputs_are_no_ops(ctx):
+    """count = 0: every per-point call returns without error and writes nothing (an empty torch
+    tensor may have a null data pointer); the space is still validated."""
+    import torch
+    from paper_1606_07413_amd import tcw
+    say("empty inputs")
+    for n, k in ((2, 4), (3, 5), (4, 7)):
+        tw, u = oracle_target(n, k, 1)
+        tgt = ctx.target_from_words(n, tw.paulis, tw.clifford)
+        chunk = 0 if k % 2 == 0 else 1
+        e64 = torch.empty(0, dtype=torch.int64, device="cuda:0")
+        e32 = torch.empty(0, dtype=torch.int32, device="cuda:0")
+        e8 = torch.empty(0, dtype=torch.int8, device="cuda:0")
+        ctx.step(tgt, k, chunk, 1, 4, e64, e64, e64)
+        ctx.trails(tgt, k, chunk, 1, 4, e64, 64, e64, e32)
+        ctx.start_points(tgt, k, chunk, 1, 0, 0, 0, e64)
+        ctx.canon_hash(n, k, chunk, 1, e32, e32, e32, e64)
+        ctx.claw_check(tgt, k, chunk, 1, e64, e64, e32, e32, e8)
+        # an invalid space is still refused (odd k needs a chunk in 1..xi)
+        with pytest.raises(tcw.TcwError):
+            ctx.step(tgt, 5, 0, 1, 4, e64, e64)
+
 STEP_CASES = [(1, 4, 1, 37), (1, 5, 2, 100), (2, 2, 5, 30), (2, 4, 1, 300), (2, 5, 3, 129), (2, 6, 4, 65),
               (3, 3, 5, 64), (3, 5, 2, 77), (3, 6, 1, 200), (4, 1, 4, 16), (4, 2, 1, 33), (4, 3, 2, 20),
               (4, 4, 3, 8), (4, 5, 6, 24), (4, 6, 5, 40), (4, 7, 1, 64)]
