@@ -257,7 +257,9 @@ int tcw_min_tcount(tcw_ctx* ctx, const tcw_target* t, int h_max, uint64_t seed, 
  * D's images of X_j and Z_j to the identity.  Adjacent inverse pairs are cancelled.  The T and
  * T^dag gates number exactly res->t.  Qubit indices as in the Pauli codes (qubit 0 is the leftmost
  * Kronecker factor).  *count = gates needed; TCW_EOVERFLOW if that exceeds cap (nothing past cap is
- * written); TCW_EINVAL if res is not a verified decomposition.  Host only: needs no context or GPU. */
+ * written); TCW_EINVAL if res is not a verified decomposition.  Of clifford_perm / clifford_sign only
+ * the entries of the generators (codes 1 << j, j < 2n) are read: non-identity codes below 4^n with
+ * signs +-1 whose images reduce to the identity, else TCW_EINVAL.  Host only: needs no context or GPU. */
 enum {
     TCW_GATE_H = 1,
     TCW_GATE_S = 2,
