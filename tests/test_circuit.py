@@ -121,3 +121,45 @@ def test_circuit_errors():
     assert lib.tcw_circuit(ctypes.byref(res), buf, 2, ctypes.byref(count)) == tcw.TCW_EOVERFLOW
     res.clifford_perm[1] = 0   # the image of X_0 cannot be the identity
     assert lib.tcw_circuit(ctypes.byref(res), None, 0, ctypes.byref(count)) == tcw.TCW_EINVAL
+
+
+def _gates(tcw, lib, res):
+    count = ctypes.c_int32(0)
+    rc = lib.tcw_circuit(ctypes.byref(res), None, 0, ctypes.byref(count))
+    if rc:
+        return rc
+    buf = (tcw.Gate * max(1, count.value))()
+    assert lib.tcw_circuit(ctypes.byref(res), buf, count.value, ctypes.byref(count)) == 0
+    return [(g.kind, g.q0, g.q1) for g in buf[:count.value]]
+
+
+@pytest.mark.parametrize("n,seed", [(1, 2), (2, 3), (3, 4), (4, 5)])
+def test_circuit_validates_generator_images(n, seed):
+    """Only the images of the generators X_j, Z_j (codes 1 << j) are read: an invalid one (code out of
+    range or the identity, sign outside +-1) is refused; changing any other entry changes nothing."""
+    tcw, lib = lib_or_skip()
+    tw = seeded_inputs.target_words(n, 3, seed, clifford_len=6 * n)
+    base = _gates(tcw, lib, make_result(tcw, n, tw.paulis, tw.clifford))
+    assert isinstance(base, list)
+    r = 4 ** n
+    gens = [1 << j for j in range(2 * n)]
+    for g in gens:
+        for bad in (0, -7, r, r + 100):
+            res = make_result(tcw, n, tw.paulis, tw.clifford)
+            res.clifford_perm[g] = bad
+            assert _gates(tcw, lib, res) == tcw.TCW_EINVAL
+        for bad in (0, 2, -3):
+            res = make_result(tcw, n, tw.paulis, tw.clifford)
+            res.clifford_sign[g] = bad
+            assert _gates(tcw, lib, res) == tcw.TCW_EINVAL
+    others = [q for q in range(r) if q not in gens][:20]
+    for q in others:
+        res = make_result(tcw, n, tw.paulis, tw.clifford)
+        res.clifford_perm[q] = r + 5
+        res.clifford_sign[q] = 0
+        assert _gates(tcw, lib, res) == base
+    # Pauli codes outside 1 .. 4^n - 1 are refused
+    for bad in (0, r, 65535):
+        res = make_result(tcw, n, tw.paulis, tw.clifford)
+        res.paulis[0] = bad
+        assert _gates(tcw, lib, res) == tcw.TCW_EINVAL
