@@ -354,7 +354,7 @@ def tts_n4_leg(ctx, cap: float, slice_s: float = 60.0, seeds=(1, 2, 3, 4)):
               f"t={r.t if r.status else None}", file=sys.stderr, flush=True)
         while not r.status and time.perf_counter() - t0 < cap:
             left = cap - (time.perf_counter() - t0)
-            r = ctx.search(tn, params(7, (slices + 1) << 20, min(slice_s, left), only=7))
+            r = ctx.search(tn, params(7, (slices + 1) << 20, max(1e-3, min(slice_s, left)), only=7))
             steps += r.stats.steps
             slices += 1
             print(f"tts n4k7 target {ts}: depth 7 slice {slices} ended at {time.perf_counter() - t0:.1f} s, "
@@ -391,7 +391,7 @@ def tts_n4_planted_leg(ctx, cap: float, slice_s: float = 120.0, seeds=(2, 3, 4))
             p4.depth_order_kind = 1
             p4.depth_order_len = 1
             p4.depth_order[0] = 7
-            p4.max_seconds = min(slice_s, cap - (time.perf_counter() - t0))
+            p4.max_seconds = max(1e-3, min(slice_s, cap - (time.perf_counter() - t0)))
             r = ctx.search(tn, p4)
             steps += r.stats.steps
             slices += 1

@@ -201,6 +201,10 @@ typedef struct tcw_walk_params {
                                  own table; small (enumerated) chunks too while their tables fit 32 GiB
                                  (1, the default: one at a time in ascending order; 0: all) */
 } tcw_walk_params;
+/* Ranges (else TCW_EINVAL, before any device work): delta <= 32; walks in 1..2^31 and log2_table in
+ * 4..32 (in a batch, <= 0 takes the autotuner's choice); trail_cap_factor, budget_beta and
+ * version_factor >= 1; enum_max >= 0; chunk_first, chunk_last in 0..xi; max_seconds >= 0;
+ * k_max in 0..64; a GIVEN depth order of at most 16 depths in 0..k_max. */
 
 typedef struct tcw_result {
     int32_t status;                 /* 1: decomposition found and verified exactly; 0: not found */

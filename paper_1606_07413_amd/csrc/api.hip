@@ -966,6 +966,23 @@ int search_enum(tcw_ctx* c, const tcw_target* t, const tcw_walk_params* p, int k
 
 // Steps per function version: max(factor * N, 2 walks / theta), but no more than the table holds
 // at half load (slots / 2 distinguished points, i.e. slots / (2 theta) steps).
+// Ranges of the search parameters, checked before any of them enters a shift or a launch.  In a
+// batch, walks and log2_table <= 0 take the autotuner's choice.
+int check_params(tcw_ctx* c, const tcw_walk_params* p, int n, bool batch) {
+    if (p->delta > 32) return fail(c, TCW_EINVAL, "delta must be at most 32 (negative: automatic)");
+    if ((!batch && p->walks < 1) || p->walks > (1ll << 31)) return fail(c, TCW_EINVAL, "walks must be in 1..2^31");
+    if ((!batch || p->log2_table > 0) && (p->log2_table < 4 || p->log2_table > 32))
+        return fail(c, TCW_EINVAL, "log2_table must be in 4..32");
+    if (p->trail_cap_factor < 1 || p->budget_beta < 1 || p->version_factor < 1)
+        return fail(c, TCW_EINVAL, "trail_cap_factor, budget_beta and version_factor must be positive");
+    if (p->enum_max < 0) return fail(c, TCW_EINVAL, "enum_max must be non-negative");
+    const int32_t xi = (int32_t)xi_of(n);
+    if (p->chunk_first < 0 || p->chunk_first > xi || p->chunk_last < 0 || p->chunk_last > xi)
+        return fail(c, TCW_EINVAL, "chunk_first and chunk_last must lie in 1..xi (0: default)");
+    if (!(p->max_seconds >= 0)) return fail(c, TCW_EINVAL, "max_seconds must be non-negative");
+    return TCW_OK;
+}
+
 uint64_t version_steps(const tcw_walk_params* p, uint64_t npts, int delta, int64_t walks, int log2_table) {
     uint64_t per_version = (uint64_t)p->version_factor * npts;
     const uint64_t floor_v = 2ull * (uint64_t)walks << delta;
@@ -989,9 +1006,10 @@ extern "C" int tcw_search(tcw_ctx* c, const tcw_target* t, const tcw_walk_params
     const double t0 = now_s();
     const int n = t->n;
     res->n = n;
-    if (p->walks < 1) return fail(c, TCW_EINVAL, "walks must be positive");
+    int rc = check_params(c, p, n, false);
+    if (rc) return rc;
     std::vector<int> order;
-    int rc = depth_order_of(c, p, order);
+    rc = depth_order_of(c, p, order);
     if (rc) return rc;
     const uint32_t xi = xi_of(n);
     const int iters = p->iters_per_launch > 0 ? p->iters_per_launch : default_iters(n);
@@ -1646,7 +1664,8 @@ extern "C" int tcw_search_batch(tcw_ctx* c, const tcw_target* const* targets, in
         b.res = &results[i];
         std::memset(b.res, 0, sizeof(tcw_result));
         b.res->n = b.t->n;
-        rc = depth_order_of(c, &b.p, b.order);
+        rc = check_params(c, &b.p, b.t->n, true);
+        if (!rc) rc = depth_order_of(c, &b.p, b.order);
     }
     if (rc) return rc;
     return batch_run(c, bt, false, t0, aggregate_steps_per_s);

@@ -391,6 +391,32 @@ def test_search_n2_cfg1(ctx, seed):
     assert osearch.reconstruct(2, d).equals(u)
 
 
+
+def test_search_rejects_out_of_range_params(ctx):
+    """Parameters outside their documented ranges are refused before any device work, in a single
+    search and in a batch; a batch still takes walks = log2_table = 0 as the autotuner's choice."""
+    from paper_1606_07413_amd import tcw
+    say("search parameter ranges")
+    tw, u = oracle_target(2, 3, 4)
+    tgt = ctx.target_from_words(2, tw.paulis, tw.clifford)
+    bad = [("delta", 40), ("walks", 0), ("walks", 1 << 32), ("log2_table", 0), ("log2_table", 40),
+           ("trail_cap_factor", 0), ("budget_beta", -1), ("version_factor", 0), ("enum_max", -5),
+           ("chunk_first", 16), ("chunk_last", -1), ("max_seconds", -1.0), ("k_max", 65)]
+    for name, value in bad:
+        p = ctx.default_params(2)
+        setattr(p, name, value)
+        with pytest.raises(tcw.TcwError):
+            ctx.search(tgt, p)
+        if name not in ("walks", "log2_table") or value > 0:
+            with pytest.raises(tcw.TcwError):
+                ctx.search_batch([tgt], [p])
+    p = ctx.default_params(2)
+    p.k_max = 3
+    p.walks = 0
+    p.log2_table = 0
+    results, _ = ctx.search_batch([tgt], [p])
+    assert results[0].status == 1 and results[0].t <= 3
+
 def test_search_n1_matches_bfs(ctx):
     from paper_1606_07413_amd import tcw
     say("search n1")
