@@ -294,7 +294,9 @@ int tcw_circuit(const tcw_result* res, tcw_gate* gates, int32_t cap, int32_t* co
  * C_1..C_m, k = kof[i]) are built exactly on the GPU; features_dev[i] gets their features and
  * labels_dev[i] their minimal T-count when it is at most 2 h_max (meet in the middle: every coset
  * of T-count <= h_max from the identity side against every product of <= h_max rotations on the
- * target side, by matrix hash), else -1.
+ * target side, by matrix hash), else -1.  Host arrays: offsets[0] = 0 and non-decreasing,
+ * 0 <= kof[i] <= word length, 2 m + k <= 256 rotations per word, codes in 1..4^n - 1, else
+ * TCW_EINVAL before any device work.
  * tcw_mlp_create: parameters are W_0, b_0, W_1, b_1, ... (W_l row-major in x out); init (host,
  * optional) gives them, else W_l uniform in [-1/sqrt(in), 1/sqrt(in)] from SplitMix64(seed) of the
  * running weight index (u = (r >> 40) / 2^24) and b_l = 0.

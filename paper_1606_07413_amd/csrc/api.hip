@@ -2011,6 +2011,16 @@ extern "C" int tcw_label_batch(tcw_ctx* c, int n, int count, const uint16_t* wor
     if (!c || !words || !offsets || !kof || !features_dev || !labels_dev || count < 1) return TCW_EINVAL;
     int rc = check_mitm_args(c, n, h_max);
     if (rc) return rc;
+    // the words are read on the device exactly as these arrays describe them: check them here
+    if (offsets[0] != 0) return fail(c, TCW_EINVAL, "offsets[0] must be 0");
+    const uint32_t xi = xi_of(n);
+    for (int i = 0; i < count; ++i) {
+        const int64_t len = (int64_t)offsets[i + 1] - offsets[i];
+        if (len < 0 || kof[i] < 0 || kof[i] > len) return fail(c, TCW_EINVAL, "offsets must not decrease and kof[i] <= word length");
+        if (2 * (len - kof[i]) + kof[i] > 256) return fail(c, TCW_EINVAL, "a word is longer than 256 rotations once expanded");
+    }
+    for (int64_t j = 0; j < offsets[count]; ++j)
+        if (words[j] < 1 || words[j] > xi) return fail(c, TCW_EINVAL, "Pauli code out of range 1..4^n - 1");
     const int R = 1 << (2 * n);
     const int64_t nw = offsets[count];
     uint16_t* dwords = nullptr;

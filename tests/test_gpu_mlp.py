@@ -233,3 +233,28 @@ def test_learned_order_gains_over_plain(ctx):
         assert found["learned"].t >= found["plain"].t
     print("spaces searched", spaces, flush=True)
     assert spaces["learned"] < spaces["plain"]
+
+
+def test_label_batch_validates_words(ctx):
+    """Word arrays that do not describe valid words are refused on the host, before the device reads
+    them: a Pauli code out of range, kof above the word length, decreasing offsets, an over-long word."""
+    import ctypes
+    import torch
+    from paper_1606_07413_amd import tcw
+    n = 2
+    feats = torch.empty((1, 16 ** n), dtype=torch.float32, device="cuda:0")
+    labels = torch.empty(1, dtype=torch.int32, device="cuda:0")
+
+    def call(words, offsets, kof):
+        w = (ctypes.c_uint16 * max(1, len(words)))(*words)
+        o = (ctypes.c_int32 * len(offsets))(*offsets)
+        k = (ctypes.c_int32 * len(kof))(*kof)
+        return ctx.lib.tcw_label_batch(ctx.h, n, len(kof), w, o, k, 2, 5, feats.data_ptr(), labels.data_ptr())
+
+    assert call([3, 5, 7], [0, 3], [2]) == 0
+    assert call([3, 16, 7], [0, 3], [2]) == tcw.TCW_EINVAL       # code above 4^n - 1
+    assert call([3, 0, 7], [0, 3], [2]) == tcw.TCW_EINVAL        # the identity
+    assert call([3, 5, 7], [0, 3], [4]) == tcw.TCW_EINVAL        # kof above the word length
+    assert call([3, 5, 7], [1, 3], [1]) == tcw.TCW_EINVAL        # offsets[0] != 0
+    assert call([3] * 200, [0, 200], [10]) == tcw.TCW_EINVAL     # 2 * 190 + 10 rotations
+
