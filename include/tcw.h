@@ -301,7 +301,8 @@ int tcw_circuit(const tcw_result* res, tcw_gate* gates, int32_t cap, int32_t* co
  * optional) gives them, else W_l uniform in [-1/sqrt(in), 1/sqrt(in)] from SplitMix64(seed) of the
  * running weight index (u = (r >> 40) / 2^24) and b_l = 0.
  * tcw_mlp_forward: probs_dev[batch x classes] from x_dev[batch x in].  tcw_mlp_gradients: gradients
- * of the mean cross-entropy (host array of param_count floats) and the loss, no update.
+ * of the mean cross-entropy (host array of param_count floats) and the loss, no update.  A label
+ * outside 0..classes-1 adds no loss term and no one-hot target (its probabilities are pushed down).
  * tcw_mlp_train_step: one Adam step on a batch.  tcw_mlp_depth_order: order_out[0..k_max] = depths
  * 0..k_max by descending predicted probability (ties: smaller first); probs_out (host, may be NULL).
  * All blocking except where noted; device pointers as elsewhere. */
