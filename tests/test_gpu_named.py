@@ -1,12 +1,14 @@
 """Named 3-qubit targets of Sec. 5.2 (Toffoli, Fredkin, Peres) through the C ABI: the channel
 rep of an exact unitary built on the GPU against the oracle, input validation, the
-meet-in-the-middle T-count certificate, and full searches that must find T-count 7 with a
-decomposition the oracle reconstructs exactly."""
+meet-in-the-middle T-count certificate, and full searches that must find the optimal T-count the
+paper reports (Table 1, read from tests/golden/table1_optimal_tcount.txt: 7) with a decomposition
+the oracle reconstructs exactly."""
 
 import numpy as np
 import pytest
 
 import seeded_inputs
+from golden_fixtures import table1
 from oracle import bfs
 from oracle import search as osearch
 from oracle import unitary as ounitary
@@ -14,6 +16,8 @@ from oracle import zmat
 from oracle.cyclotomic import CycMat, rotation
 
 pytestmark = pytest.mark.gpu
+
+TCOUNT = {name: t for name, (_, t) in table1().items()}   # Sec. 5.2, Table 1
 
 
 @pytest.fixture(scope="module")
@@ -167,6 +171,7 @@ def test_named_tcount_exceeds_six(ctx):
     every coset of T-count <= 3 on each side), while a T-count-3 word is found at 3."""
     say("named certificate")
     for name in ("toffoli", "fredkin", "peres"):
+        assert TCOUNT[name] - 1 == 2 * 3   # the certificate covers every T-count below the table's
         assert ctx.min_tcount(ctx.target_from_unitary(3, named_v(name), 0), 3) == -1, name
     tw = seeded_inputs.target_words(3, 3, 5)
     v, e = word_unitary(3, tw.paulis, tw.clifford)
@@ -189,7 +194,7 @@ def _search_named(ctx, name, delta, seed, chunk_parallel=1):
     dec = tcw.decomposition_of(res)
     say(name, "delta", delta, "chunk_parallel", chunk_parallel, "status", res.status, "t", res.t, "chunk", res.chunk, "seconds", round(res.seconds, 3),
         "steps", res.stats.steps, "versions", res.versions)
-    assert dec is not None and dec.t == 7
+    assert dec is not None and dec.t == TCOUNT[name]
     d = osearch.Decomposition(t=dec.t, paulis_desc=dec.paulis_desc, perm=dec.perm, sign=dec.sign)
     assert osearch.reconstruct(3, d).equals(ounitary.channel_of_unitary(3, v, 0))
     return res
@@ -204,7 +209,7 @@ def test_named_circuit(ctx, name):
     res = _search_named(ctx, name, 1, 31)
     gates = tcw.circuit_of(res)
     say(name, "circuit:", len(gates), "gates,", sum(1 for g, _ in gates if g == "cx"), "CNOT")
-    assert sum(1 for g, _ in gates if g in ("t", "tdg")) == 7
+    assert sum(1 for g, _ in gates if g in ("t", "tdg")) == TCOUNT[name]
     assert ocircuit.circuit_channel(3, gates).equals(ounitary.channel_of_unitary(3, named_v(name), 0))
 
 
