@@ -201,3 +201,28 @@ def test_splitmix64_published_sequence():
     """The mixer is SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): from state 0 its reference
     generator's first three outputs are these published values."""
     assert [walk.sm64(0, i) for i in range(3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_collisions_of_f_match_a_random_mapping():
+    """Appendix: in a space of N points a random mapping shows about N/2 colliding pairs (the `bad'
+    collisions met before the golden one).  f is a random mapping on cosets: points whose half
+    matrices lie in one left-Clifford coset collide by construction (grouped here by the exact
+    canonical form), and G distinct cosets collide as a random mapping of G points into N would,
+    G (G - 1) / (2 N) pairs in expectation (N (N - 1) / (2 N), about N/2, when every coset is
+    distinct)."""
+    from collections import Counter
+    n, k = 2, 6
+    _, u = target(n, k, 12)
+    spec = walk.make_spec(u, n, k, 0, 77, delta=4)
+    cosets = {}
+    for x in range(spec.n_half):
+        for b in (0, 1):
+            cosets.setdefault(zmat.canonical_form(walk.half_matrix(spec, x, b)), []).append(walk.pack(x, b))
+    big = max(cosets.values(), key=len)
+    assert len({walk.f(spec, p) for p in big}) == 1        # one coset, one image
+    reps = [v[0] for v in cosets.values()]
+    g, N = len(reps), 2 * spec.n_half
+    images = Counter(walk.f(spec, p) for p in reps)
+    pairs = sum(c * (c - 1) // 2 for c in images.values())
+    mean = g * (g - 1) / (2 * N)
+    assert abs(pairs - mean) < 5 * math.sqrt(mean), (pairs, mean, g, N)
