@@ -226,3 +226,24 @@ def test_collisions_of_f_match_a_random_mapping():
     pairs = sum(c * (c - 1) // 2 for c in images.values())
     mean = g * (g - 1) / (2 * N)
     assert abs(pairs - mean) < 5 * math.sqrt(mean), (pairs, mean, g, N)
+
+
+@pytest.mark.parametrize("delta", [1, 3])
+def test_mean_trail_length_is_one_over_theta(delta):
+    """Appendix: a trail runs 1/theta steps on average before it reaches a distinguished point (the
+    number of steps is geometric with parameter theta when f behaves as a random mapping).  Each
+    trail runs under its own function version (a re-salted f), so the trails are independent; under
+    one version they merge and share their distinguished points.  At theta = 1/2 a step counted
+    wrongly by one is 17 standard deviations out."""
+    n, k = 2, 8
+    _, u = target(n, k, 5)
+    lens = []
+    for v in range(600):
+        spec = walk.make_spec(u, n, k, 0, 91, delta=delta, version=v)
+        dp, d = walk.trail(spec, walk.start_point(spec, 0, 0))
+        if dp is not None:
+            lens.append(d)
+    theta = 1.0 / (1 << delta)
+    assert len(lens) >= 570   # a few trails fall into short cycles without distinguished points
+    sd = math.sqrt(1 - theta) / theta / math.sqrt(len(lens))
+    assert abs(sum(lens) / len(lens) - 1 / theta) < 5 * sd, (sum(lens) / len(lens), len(lens))
