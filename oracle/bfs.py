@@ -1,6 +1,9 @@
 """Brute-force minimal T-count by breadth-first search over left-Clifford cosets
 (the brute-force synthesis of Sec. 3, run at tiny n).
 
+Test infrastructure only: imported by the tests, smoke() and the benchmark's CPU baseline, never
+by the library.
+
 Level t holds the cosets {D M} whose minimal T-count is exactly t.  Right
 multiplication by R_hat(p) is well defined on left cosets, so level t is the set
 of new cosets among M R_hat(p) for M in level t-1 and p = 1..xi.  Cosets are

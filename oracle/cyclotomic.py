@@ -1,5 +1,8 @@
 """Exact matrices over Z[omega] / 2^d with omega = e^{i pi/4}.
 
+Test infrastructure only: imported by the tests, smoke() and the benchmark's CPU baseline, never
+by the library.
+
 Used only to evaluate the paper's definitions literally at small n:
 R(P) = (1 + omega)/2 I + (1 - omega)/2 P (Sec. 4.1) and the channel
 representation U_hat_ij = 2^-n Tr(P_i U P_j U^dag) (Sec. 4.1).

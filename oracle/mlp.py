@@ -1,5 +1,8 @@
 """Float64 reference of the depth-order network (forward, loss, backward).
 
+Test infrastructure only: imported by the tests, smoke() and the benchmark's CPU baseline, never
+by the library.
+
 The network predicts a target's minimal T-count from its canonical channel
 representation: x (4^n * 4^n features) -> [Linear -> GELU] x depth -> Linear ->
 softmax over T-counts 0..classes-1, trained with cross-entropy.  Weights and

@@ -1,6 +1,9 @@
 """n-qubit Paulis in binary symplectic form (Sec. 4.1: each R(P) is named by a Pauli,
 written as a binary string through the symplectic representation).
 
+Test infrastructure only: imported by the tests, smoke() and the benchmark's CPU baseline, never
+by the library.
+
 Code layout (this project's reading; the paper fixes only that the encoding is
 binary symplectic): a code q in [0, 4^n) has x = q mod 2^n (low n bits) and
 z = q >> n.  Qubit j carries bit j of x and of z; qubit 0 is the leftmost factor

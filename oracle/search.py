@@ -1,6 +1,9 @@
 """Distinguished-point storage, trail backtracking, claw checks and the search driver
 (Sec. 3 for the claw search, Sec. 4.1 for the T-count problem, Appendix for budgets).
 
+Test infrastructure only: imported by the tests, smoke() and the benchmark's CPU baseline, never
+by the library.
+
 Plain, sequential restatement:
 * Storage (Sec. 3): a dict from distinguished point to (start, length); the first
   writer stays; a second trail with a different start reaching the same point is

@@ -1,5 +1,8 @@
 """The walk function of the deterministic-walk claw search (Sec. 2, Sec. 3).
 
+Test infrastructure only: imported by the tests, smoke() and the benchmark's CPU baseline, never
+by the library.
+
 A point is (x, b): x in [0, N_half) names a half-circuit of h = floor(k/2)
 rotations, b in {0, 1} says which half (0: products from the identity, the
 paper's z_1 / V side; 1: products from the target side, z_2 / W side).

@@ -1,5 +1,8 @@
 """Exact channel representations over Z[1/sqrt2] (Sec. 4.1).
 
+Test infrastructure only: imported by the tests, smoke() and the benchmark's CPU baseline, never
+by the library.
+
 A matrix M is stored as two integer arrays A, B and one exponent e with
 M = (A + B sqrt2) / sqrt2^e.  The representation is canonical when e is
 minimal (reduce()).  Arithmetic is exact: object arrays of Python ints, or int64
