@@ -18,6 +18,15 @@
 #include "common.h"
 #include "internal.h"
 
+namespace tcw {
+// Depth-order network, weight gradient (mlp.hip): dW = H^T G (H: K x M, G: K x N, both bf16
+// row-major; dW: M x N fp32) with the batch K split over workgroups when that fills the GPU better;
+// `part` (mlp_dw_part_floats(M, N, K) floats, or null) holds the partial tiles, added in a fixed order.
+size_t mlp_dw_part_floats(int M, int N, int K);
+hipError_t mlp_gemm_dw(const void* H, const void* G, int M, int N, int K, float* dW, float* part, size_t part_floats,
+                       hipStream_t s);
+}  // namespace tcw
+
 struct TunedCfg {
     int64_t walks = 0;
     int iters = 0;
@@ -1687,10 +1696,14 @@ struct tcw_mlp {
     std::vector<float*> Z, Gf;
     std::vector<void*> Hb, Gb;
     float *logits = nullptr, *probs = nullptr, *loss = nullptr, *xdev = nullptr;
+    float* dw_part = nullptr;  // partial weight-gradient tiles of the batch split
+    size_t dw_part_floats = 0;
 
     void free_batch() {
-        for (void* q : {Xb, (void*)logits, (void*)probs})
+        for (void* q : {Xb, (void*)logits, (void*)probs, (void*)dw_part})
             if (q) (void)hipFree(q);
+        dw_part = nullptr;
+        dw_part_floats = 0;
         for (auto* q : Z)
             if (q) (void)hipFree(q);
         for (auto* q : Gf)
@@ -1737,6 +1750,12 @@ int mlp_ensure_batch(tcw_mlp* m, int b) {
     }
     HIP_TRY(c, hipMalloc(&m->logits, (size_t)b * m->classes * 4));
     HIP_TRY(c, hipMalloc(&m->probs, (size_t)b * m->classes * 4));
+    size_t part = 0;
+    for (int l = 0; l < m->L; ++l) part = std::max(part, tcw::mlp_dw_part_floats(m->sz[l], m->sz[l + 1], b));
+    if (part > 0) {
+        HIP_TRY(c, hipMalloc(&m->dw_part, part * 4));
+        m->dw_part_floats = part;
+    }
     m->cap_b = b;
     return TCW_OK;
 }
@@ -1776,8 +1795,8 @@ int mlp_backward(tcw_mlp* m, int b) {
         const void* Hin = l == 0 ? m->Xb : m->Hb[l - 1];
         const int in = m->sz[l], out = m->sz[l + 1];
         // dW_l = H_in^T G_l
-        HIP_TRY(c, tcw::mlp_gemm(3, Hin, m->Gb[l], in, out, b, in, out, m->G + m->w_off[l], out, nullptr, nullptr,
-                                 nullptr, c->stream));
+        HIP_TRY(c, tcw::mlp_gemm_dw(Hin, m->Gb[l], in, out, b, m->G + m->w_off[l], m->dw_part, m->dw_part_floats,
+                                    c->stream));
         HIP_TRY(c, tcw::mlp_colsum(m->Gf[l], b, out, m->G + m->b_off[l], c->stream));
         if (l > 0) {
             // G_{l-1} = (G_l W_l^T) * gelu'(Z_{l-1})

@@ -33,11 +33,13 @@ __device__ inline float gelu_grad_f(float z) {
 
 // C[M x N] = op(A)[M x K] op(B)[K x N].  TA: A element (m, k) at A[k * lda + m], else A[m * lda + k].
 // TB: B element (k, n) at B[n * ldb + k], else B[k * ldb + n].  256 threads, 64 x 64 tile, 4 waves of 32 x 32.
+// blockIdx.z = z takes the products k in [z kchunk, (z + 1) kchunk) (kchunk a multiple of TK) and, for
+// EPI_STORE, writes its partial tile to C + z M ldc; with gridDim.z = 1 it is the whole product.
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A, const __bf16* __restrict__ B, int M, int N,
                                               int K, int lda, int ldb, float* __restrict__ C, int ldc,
                                               const float* __restrict__ bias, const float* __restrict__ Zin,
-                                              __bf16* __restrict__ Hout) {
+                                              __bf16* __restrict__ Hout, int kchunk) {
     __shared__ __attribute__((aligned(16))) __bf16 As[TM][LDS_K];
     __shared__ __attribute__((aligned(16))) __bf16 Bs[TN][LDS_K];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -47,7 +49,9 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A, cons
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const __bf16 zero = (__bf16)0.0f;
-    for (int k0 = 0; k0 < K; k0 += TK) {
+    const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+    C += (size_t)blockIdx.z * M * ldc;
+    for (int k0 = kb; k0 < ke; k0 += TK) {
         // A tile -> As[m][k]
         if (!TA) {
             const int m = t >> 2, kk = (t & 3) * 8;
@@ -194,10 +198,31 @@ __global__ void k_init(float* w, int64_t count, int64_t index0, int fan_in, uint
 
 template <bool TA, bool TB, int EPI>
 hipError_t gemm_t(const __bf16* A, const __bf16* B, int M, int N, int K, int lda, int ldb, float* C, int ldc,
-                  const float* bias, const float* Z, __bf16* H, hipStream_t s) {
-    dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM);
-    hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, A, B, M, N, K, lda, ldb, C, ldc, bias, Z, H);
+                  const float* bias, const float* Z, __bf16* H, hipStream_t s, int splits = 1) {
+    dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM, splits);
+    const int kchunk = ((K + splits - 1) / splits + TK - 1) / TK * TK;
+    hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, A, B, M, N, K, lda, ldb, C, ldc, bias, Z, H,
+                       kchunk);
     return hipGetLastError();
+}
+
+// out[i] = sum over z of part[z * mn + i], in the order z = 0, 1, ... (the same sum on every run)
+__global__ void k_sum_parts(const float* __restrict__ part, int splits, int64_t mn, float* __restrict__ out) {
+    for (int64_t i = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; i < mn; i += (int64_t)blockDim.x * gridDim.x) {
+        float v = 0.f;
+        for (int z = 0; z < splits; ++z) v += part[(size_t)z * mn + i];
+        out[i] = v;
+    }
+}
+
+// The weight gradient dW = H^T G (M x N) reduces over the batch K.  With few output tiles one tile
+// per workgroup leaves most of the GPU idle while each runs the whole batch, so the batch is split
+// over up to 16 workgroups per tile (at least 256 samples each) until about 4096 workgroups run.
+int dw_splits(int M, int N, int K) {
+    const int tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
+    int splits = 1;
+    while (splits < 16 && tiles * splits < 4096 && K / (2 * splits) >= 256) splits *= 2;
+    return splits;
 }
 
 }  // namespace
@@ -217,6 +242,27 @@ hipError_t mlp_gemm(int mode, const void* A, const void* B, int M, int N, int K,
         case 6: return gemm_t<true, true, EPI_STORE>(a, b, M, N, K, lda, ldb, C, ldc, bias, Z, h, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+size_t mlp_dw_part_floats(int M, int N, int K) {
+    const int splits = dw_splits(M, N, K);
+    return splits > 1 ? (size_t)splits * M * N : 0;
+}
+
+hipError_t mlp_gemm_dw(const void* H, const void* G, int M, int N, int K, float* dW, float* part, size_t part_floats,
+                       hipStream_t s) {
+    const __bf16* a = (const __bf16*)H;
+    const __bf16* b = (const __bf16*)G;
+    const int splits = dw_splits(M, N, K);
+    if (splits == 1 || part == nullptr || part_floats < (size_t)splits * M * N)
+        return gemm_t<true, false, EPI_STORE>(a, b, M, N, K, M, N, dW, N, nullptr, nullptr, nullptr, s);
+    hipError_t e = gemm_t<true, false, EPI_STORE>(a, b, M, N, K, M, N, part, N, nullptr, nullptr, nullptr, s, splits);
+    if (e != hipSuccess) return e;
+    const int64_t mn = (int64_t)M * N;
+    int64_t blocks = (mn + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)blocks), dim3(256), 0, s, part, splits, mn, dW);
+    return hipGetLastError();
 }
 
 hipError_t mlp_softmax_ce(const float* logits, const int32_t* labels, int batch, int classes, float* probs, float* g,
