@@ -70,3 +70,31 @@ def test_init_is_seeded_and_bounded():
     assert np.abs(a["W0"]).max() <= 1 / math.sqrt(4096)
     assert abs(float(a["W1"].mean())) < 1e-3
     assert sum(v.size for v in a.values()) == 4096 * 512 + 512 + 2 * (512 * 512 + 512) + 512 * 11 + 11
+
+
+def _float_rows(m):
+    """Rows of the exact channel rep (A + B sqrt2) / sqrt2^e in float64, computed directly."""
+    a = np.array(m.A, dtype=np.float64)
+    b = np.array(m.B, dtype=np.float64)
+    return (a + b * math.sqrt(2.0)) / math.sqrt(2.0) ** m.e
+
+
+def test_features_pins():
+    """The canonical features: invariant under left Cliffords; as a 4^n x 4^n matrix orthogonal up to
+    float32 rounding (a signed row permutation of an orthogonal matrix); each row equal, up to sign,
+    to a row of the target evaluated directly; the identity gives a permutation matrix."""
+    from oracle import zmat
+    for n, k, seed in ((1, 4, 1), (2, 5, 2), (3, 4, 3)):
+        tw = seeded_inputs.target_words(n, k, seed)
+        u = zmat.target_from_words(n, tw.paulis, tw.clifford)
+        f = mlp.features(u)
+        d = zmat.clifford_from_word(n, seeded_inputs.random_clifford_word(n, 40 + seed))
+        assert np.array_equal(f, mlp.features(d @ u))
+        r = 4 ** n
+        fm = f.astype(np.float64).reshape(r, r)
+        assert np.allclose(fm @ fm.T, np.eye(r), atol=1e-5)
+        rows = _float_rows(u)
+        for i in range(r):
+            assert min(np.abs(rows - s * fm[i]).max(axis=1).min() for s in (1, -1)) < 1e-6
+    ident = mlp.features(zmat.ZMat.identity(2)).reshape(16, 16)
+    assert sorted(ident.sum(axis=0).tolist()) == [1.0] * 16 and set(np.unique(ident)) == {0.0, 1.0}
