@@ -78,6 +78,15 @@ int tcw_target_from_channel(tcw_ctx* ctx, int n, const int32_t* a, const int32_t
  * TCW_EINVAL if n is not in 1..4, e < 0 or n + e > 29, a coefficient lies outside [-2^20, 2^20],
  * or V V^dag != 2^e I; the input is copied. */
 int tcw_target_from_unitary(tcw_ctx* ctx, int n, const int64_t* v, int32_t e, tcw_target** out);
+/* tcw_target_random: a seeded synthetic target U_hat = D_hat R_hat(P_k) ... R_hat(P_1), D_hat =
+ * prod_{j=1}^{16 n} R_hat(C_j)^2 (R(C)^2 is a Clifford, Sec. 4.1), built exactly on the GPU.  The
+ * Paulis come from SplitMix64 (Steele, Lea and Flood, 2014) in counter form, r_i = mix64(seed +
+ * (i + 1) 0x9E3779B97F4A7C15): P_j = floor(r_{j-1} xi / 2^64) + 1 for j = 1..k, then C_j the same from
+ * r_{k + j - 1}, xi = 4^n - 1.  gen_paulis (host, k entries, may be NULL) receives P_1..P_k;
+ * gen_perm and gen_sign (host, 4^n entries each, may be NULL) receive D: D P_q D^dag =
+ * gen_sign[q] P_{gen_perm[q]}.  TCW_EINVAL if n is not in 1..4 or k is not in 0..TCW_MAX_T. */
+int tcw_target_random(tcw_ctx* ctx, int n, int k, uint64_t seed, tcw_target** out, uint16_t* gen_paulis,
+                      int32_t* gen_perm, int8_t* gen_sign);
 int tcw_target_free(tcw_target* t);
 /* Copy the reduced exact channel rep to host arrays a, b (R*R each) and *e.  Blocking. */
 int tcw_target_channel(tcw_ctx* ctx, const tcw_target* t, int32_t* a, int32_t* b, int32_t* e);
@@ -134,8 +143,10 @@ int tcw_claw_check(tcw_ctx* ctx, const tcw_target* t, const tcw_space* sp, const
  * (walking, inserting distinguished points, backtracking merged trails).  Claw candidates (equal
  * matrix hash, opposite sides) are queued on the device.  enumerate != 0 is the exhaustive mode for
  * small spaces: walk w takes the points w, w + walks, w + 2 walks, ... of the space once each and the
- * table is keyed by each point's full 64-bit matrix hash, so every pair of opposite-side points with
- * equal hash is reported (the first point of each hash class against every later one). */
+ * table is keyed by each point's full 64-bit matrix hash, keeping per side the least x that reached
+ * the key; once every point is done (active_walks = 0), tcw_walk_claws reads out one candidate per
+ * key reached from both sides (least side-0 x, least side-1 x), so the candidates do not depend on
+ * the order in which walks arrive. */
 typedef struct tcw_walk_stats {
     int64_t steps;          /* f evaluations, including backtracking */
     int64_t dps;            /* distinguished points reached */
@@ -148,6 +159,8 @@ typedef struct tcw_walk_stats {
     int64_t table_full;     /* inserts dropped for lack of a free slot */
     int64_t spin_timeouts;  /* table readers that gave up waiting for a slot's value */
     int64_t active_walks;   /* walks not yet finished (enumeration mode) */
+    int64_t claws_dropped;  /* claw candidates beyond the candidate buffer (4096 pairs per session, 1024 per
+                               batch member), counted but not checked */
 } tcw_walk_stats;
 
 int tcw_walk_begin(tcw_ctx* ctx, const tcw_target* t, const tcw_space* sp, int64_t walks, int log2_table,
@@ -156,7 +169,8 @@ int tcw_walk_run(tcw_walk* w, int iters);
 /* Blocking: synchronise the stream and read counters. */
 int tcw_walk_stats_get(tcw_walk* w, tcw_walk_stats* out);
 /* Blocking: copy up to max_pairs claw candidates (u0, u1) to host arrays; returns the count found
- * so far in *total. */
+ * so far in *total.  Enumeration mode: the candidates are formed by this call once every point is
+ * done (before that *total is 0), the first call after that forms them, later calls re-read them. */
 int tcw_walk_claws(tcw_walk* w, uint64_t* u0, uint64_t* u1, int64_t max_pairs, int64_t* total);
 /* Re-salt: switch to function version `version`, clear the table, restart every walk. */
 int tcw_walk_reset(tcw_walk* w, uint32_t version);
@@ -174,8 +188,18 @@ int tcw_walk_write_table(tcw_walk* w, const void* host_in);
 int tcw_walk_end(tcw_walk* w);
 
 /* ---- search driver (depth loop, chunk loop, budgets; Sec. 3 and Appendix) ------------------ */
-#define TCW_ORDER_PLAIN 0
-#define TCW_ORDER_GIVEN 1
+#define TCW_ORDER_PLAIN 0       /* depths 0, 1, ..., k_max */
+#define TCW_ORDER_GIVEN 1       /* depth_order first, then the remaining depths in increasing order; after a verified
+                                   decomposition at depth k, every depth below k not yet searched is searched in
+                                   increasing order and the lowest verified decomposition is returned */
+#define TCW_ORDER_GIVEN_FIRST 2 /* as TCW_ORDER_GIVEN, but the first verified decomposition is returned: its T-count may
+                                   exceed the minimum (tcw_result.minimal says whether the depths below were searched) */
+
+#define TCW_STATUS_NOT_FOUND 0  /* no decomposition within the budgets or the wall-clock cap */
+#define TCW_STATUS_FOUND 1      /* a decomposition was found and verified exactly */
+#define TCW_STATUS_STOPPED 2    /* the call ended at a launch boundary on tcw_search_stop or launch_limit */
+
+#define TCW_MAX_TRAIL_CAP ((1u << 30) - 1) /* longest trail a table entry can record */
 
 typedef struct tcw_walk_params {
     int32_t k_max;            /* deepest depth searched (plain order 0..k_max) */
@@ -200,14 +224,20 @@ typedef struct tcw_walk_params {
     int32_t chunk_parallel;   /* odd k: chunks searched concurrently, each with walks / G walks and its
                                  own table; small (enumerated) chunks too while their tables fit 32 GiB
                                  (1, the default: one at a time in ascending order; 0: all) */
+    int64_t launch_limit;     /* tcw_search / tcw_resume: end the call with TCW_STATUS_STOPPED after this many walk
+                                 launches in the call (0, the default: no limit); the stopped search can be
+                                 checkpointed */
 } tcw_walk_params;
 /* Ranges (else TCW_EINVAL, before any device work): delta <= 32; walks in 1..2^31 and log2_table in
  * 4..32 (in a batch, <= 0 takes the autotuner's choice); trail_cap_factor, budget_beta and
  * version_factor >= 1; enum_max >= 0; chunk_first, chunk_last in 0..xi; max_seconds >= 0;
- * k_max in 0..64; a GIVEN depth order of at most 16 depths in 0..k_max. */
+ * k_max in 0..64; depth_order_kind one of TCW_ORDER_*; a given depth order of at most 16 depths in
+ * 0..k_max; launch_limit >= 0.  The trail cap trail_cap_factor * 2^delta must not exceed
+ * TCW_MAX_TRAIL_CAP: checked up front for delta >= 0 and, for an automatic delta, when a walk space
+ * picks its delta (TCW_EINVAL then, before that space's first launch). */
 
 typedef struct tcw_result {
-    int32_t status;                 /* 1: decomposition found and verified exactly; 0: not found */
+    int32_t status;                 /* TCW_STATUS_*: 1 found and verified exactly, 0 not found, 2 stopped */
     int32_t t;                      /* its T-count (the depth k it was found at) */
     int32_t n;
     int32_t chunk;
@@ -220,11 +250,40 @@ typedef struct tcw_result {
     int64_t launches;
     int64_t false_claws;            /* candidates rejected by the exact check */
     double seconds;
+    uint64_t failed_depths;         /* bit k: depth k was searched to its full budget (every chunk; small spaces
+                                       exhaustively) without a verified decomposition */
+    int32_t minimal;                /* 1: found, and every depth below t is in failed_depths, so t is minimal up to
+                                       the per-depth budgets (exactly minimal where those depths were enumerated) */
+    int32_t reserved;
 } tcw_result;
 
 void tcw_default_params(tcw_walk_params* p, int n);
-/* Blocking.  Results written to *res (caller-allocated). */
+/* Blocking.  Results written to *res (caller-allocated).  The search runs one launch at a time: between
+ * launches it checks claw candidates exactly, switches function versions, chunks and depths, and ends
+ * early on a stop request or after launch_limit launches (status TCW_STATUS_STOPPED); the stopped
+ * search stays in the context for tcw_checkpoint until the next tcw_search / tcw_resume on it. */
 int tcw_search(tcw_ctx* ctx, const tcw_target* t, const tcw_walk_params* p, tcw_result* res);
+
+/* ---- stopping and resuming a search (a trail is fully described by its start, its current point
+ * and its length, Sec. 3, so a search resumes from its walk states and its table) ---------------
+ * tcw_search_stop: ask the search running on ctx (from another host thread) to stop at its next
+ * launch boundary; it then returns TCW_STATUS_STOPPED.  A request made while no search runs applies
+ * to the next one.  Thread-safe; the only call that may overlap another call on the same context.
+ * tcw_checkpoint: serialise the stopped search of ctx (parameters, depth-loop position, counters, the
+ * current space's walk states, its table and its counters) into host_buf.  *len is the buffer size on
+ * entry and the bytes written (or needed) on return; host_buf = NULL only reports the size.
+ * TCW_ESTATE if no stopped search is held (none stopped, or it stopped inside a group of concurrently
+ * searched chunks, chunk_parallel != 1, whose members are not serialised); TCW_EINVAL if *len is too
+ * small.  Blocking.
+ * tcw_resume: continue a checkpointed search of the same target t (checked by a fingerprint of its
+ * exact channel rep; TCW_EINVAL on a mismatch or a malformed buffer) in any context on any device of
+ * the same kind, with the checkpoint's parameters except launch_limit (this call's limit, 0: none).
+ * Walks continue their trails exactly: states, table, counters and the function version are restored.
+ * *res as for tcw_search, its counters and seconds including the work before the stop.  Blocking. */
+int tcw_search_stop(tcw_ctx* ctx);
+int tcw_checkpoint(tcw_ctx* ctx, void* host_buf, size_t* len);
+int tcw_resume(tcw_ctx* ctx, const tcw_target* t, const void* host_buf, size_t len, int64_t launch_limit,
+               tcw_result* res);
 
 /* ---- batching: many targets of mixed n and k in one graph-captured launch per round ----------
  * tcw_search_batch: targets[i] is searched with params[i] (its own k_max, seed, budgets, wall-clock

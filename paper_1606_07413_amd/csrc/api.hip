@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <memory>
 #include <new>
@@ -48,6 +49,9 @@ struct RotKeys {
 
 constexpr size_t ROT_KEYS_KEEP = 32;  // seeds whose n = 4 rotated keys (257 MiB each) a context keeps
 
+struct SearchRun;
+void free_search_run(SearchRun* r);
+
 struct tcw_ctx {
     std::map<uint64_t, TunedCfg> tuned;  // autotuner results by (n, k, delta)
     // n = 4 rotated keys by search seed, kept for later spaces of the same seed: freeing device
@@ -66,6 +70,8 @@ struct tcw_ctx {
     void* claw_scratch = nullptr;
     size_t claw_scratch_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::atomic<int> stop_req{0};   // tcw_search_stop: end the running search at its next launch boundary
+    SearchRun* stopped = nullptr;   // the last search that ended on a stop, for tcw_checkpoint
 };
 
 struct tcw_target {
@@ -283,6 +289,8 @@ struct tcw_walk {
     Space space;
     tcw::WalkDev wd{};
     bool ended = false;
+    bool pairs_formed = false;  // enumeration mode: candidates read out of the table
+    int64_t launches = 0;
 
     ~tcw_walk() {
         if (wd.states) (void)hipFree(wd.states);
@@ -297,7 +305,10 @@ namespace {
 
 int walk_restart(tcw_walk* w) {
     tcw_ctx* c = w->ctx;
-    HIP_TRY(c, tcw::launch_table_clear(w->wd.table, w->wd.log2_table, c->stream));
+    w->pairs_formed = false;
+    w->launches = 0;
+    HIP_TRY(c, tcw::launch_table_clear(w->wd.table, w->wd.log2_table, w->wd.enumerate ? tcw::ENUM_TABLE_INIT : 0,
+                                       c->stream));
     HIP_TRY(c, hipMemsetAsync(w->wd.stats, 0, tcw::ST_COUNT * sizeof(unsigned long long), c->stream));
     HIP_TRY(c, hipMemsetAsync(w->wd.claw_count, 0, sizeof(unsigned long long), c->stream));
     HIP_TRY(c, tcw::launch_walk_init(w->space.dev, w->wd, c->stream));
@@ -331,6 +342,8 @@ int tcw_create(tcw_ctx** out, int device, void* stream) {
 
 int tcw_destroy(tcw_ctx* c) {
     if (!c) return TCW_EINVAL;
+    if (c->stopped) free_search_run(c->stopped);
+    c->stopped = nullptr;
     if (c->flag) (void)hipFree(c->flag);
     if (c->claw_scratch) (void)hipFree(c->claw_scratch);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -482,6 +495,59 @@ int tcw_target_from_unitary(tcw_ctx* c, int n, const int64_t* v, int32_t e, tcw_
     return TCW_OK;
 }
 
+int tcw_target_random(tcw_ctx* c, int n, int k, uint64_t seed, tcw_target** out, uint16_t* gen_paulis,
+                      int32_t* gen_perm, int8_t* gen_sign) {
+    if (!c || !out) return TCW_EINVAL;
+    *out = nullptr;
+    if (n < 1 || n > 4) return fail(c, TCW_EINVAL, "n must be in 1..4");
+    if (k < 0 || k > TCW_MAX_T) return fail(c, TCW_EINVAL, "k must be in 0..TCW_MAX_T");
+    // SplitMix64 in counter form; each draw maps to a non-identity Pauli by a multiply-high by xi
+    const uint64_t xi = xi_of(n);
+    const int m = 16 * n;
+    auto draw = [&](int i) {
+        return (uint16_t)((uint64_t)(((unsigned __int128)tcw::sm64(seed, (uint64_t)i) * xi) >> 64) + 1);
+    };
+    std::vector<uint16_t> ps(k > 0 ? k : 1), cl(m);
+    for (int i = 0; i < k; ++i) ps[i] = draw(i);
+    for (int j = 0; j < m; ++j) cl[j] = draw(k + j);
+    if (gen_perm || gen_sign) {
+        // D alone, as the signed permutation of its channel rep
+        tcw_target* d = nullptr;
+        int rc = tcw_target_from_words(c, n, nullptr, 0, cl.data(), m, &d);
+        if (rc) return rc;
+        const int R = 1 << (2 * n);
+        int32_t *dok = nullptr, *dperm = nullptr;
+        int8_t* dsign = nullptr;
+        int32_t ok = 0;
+        std::vector<int32_t> perm(R);
+        std::vector<int8_t> sign(R);
+        {
+            DevScope scope;
+            hipError_t e = scope.alloc(&dok, 4);
+            if (e == hipSuccess) e = scope.alloc(&dperm, R * 4);
+            if (e == hipSuccess) e = scope.alloc(&dsign, R);
+            if (e == hipSuccess) e = tcw::exact_signed_perm(d->U, dok, dperm, dsign, c->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(&ok, dok, 4, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(perm.data(), dperm, R * 4, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(sign.data(), dsign, R, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) rc = hip_fail(c, e, "Clifford of a random target");
+        }
+        tcw_target_free(d);
+        if (rc) return rc;
+        if (!ok) return fail(c, TCW_EOVERFLOW, "the Clifford word did not give a signed permutation");
+        for (int q = 0; q < R; ++q) {
+            if (gen_perm) gen_perm[q] = perm[q];
+            if (gen_sign) gen_sign[q] = sign[q];
+        }
+    }
+    int rc = tcw_target_from_words(c, n, ps.data(), k, cl.data(), m, out);
+    if (rc) return rc;
+    if (gen_paulis)
+        for (int i = 0; i < k; ++i) gen_paulis[i] = ps[i];
+    return TCW_OK;
+}
+
 int tcw_target_free(tcw_target* t) {
     if (!t) return TCW_EINVAL;
     tcw::exact_free(t->U);
@@ -610,7 +676,7 @@ int tcw_walk_begin(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, int64_t
     *out = nullptr;
     if (walks < 1 || walks > (1ll << 31)) return fail(c, TCW_EINVAL, "walks must be in 1..2^31");
     if (log2_table < 4 || log2_table > 32) return fail(c, TCW_EINVAL, "log2_table must be in 4..32");
-    if (cap == 0) return fail(c, TCW_EINVAL, "cap must be positive");
+    if (cap == 0 || cap > TCW_MAX_TRAIL_CAP) return fail(c, TCW_EINVAL, "cap must be in 1..TCW_MAX_TRAIL_CAP");
     tcw_walk* w = new (std::nothrow) tcw_walk();
     if (!w) return TCW_ENOMEM;
     w->ctx = c;
@@ -653,6 +719,7 @@ int tcw_walk_run(tcw_walk* w, int iters) {
     HIP_TRY(c, tcw::launch_walk(w->space.n, w->space.dev, w->wd, iters, tcw::walk_grid_blocks(w->space.n, c->device),
                                 c->stream));
     HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+    w->launches++;
     return TCW_OK;
 }
 
@@ -660,8 +727,11 @@ int tcw_walk_stats_get(tcw_walk* w, tcw_walk_stats* out) {
     if (!w || !out) return TCW_EINVAL;
     tcw_ctx* c = w->ctx;
     unsigned long long v[tcw::ST_COUNT];
+    unsigned long long cc = 0;
     HIP_TRY(c, hipMemcpyAsync(v, w->wd.stats, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&cc, w->wd.claw_count, sizeof(cc), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    out->claws_dropped = cc > w->wd.claw_cap ? (int64_t)(cc - w->wd.claw_cap) : 0;
     out->steps = (int64_t)v[tcw::ST_STEPS];
     out->dps = (int64_t)v[tcw::ST_DPS];
     out->inserts = (int64_t)v[tcw::ST_INSERTS];
@@ -679,6 +749,21 @@ int tcw_walk_stats_get(tcw_walk* w, tcw_walk_stats* out) {
 int tcw_walk_claws(tcw_walk* w, uint64_t* u0, uint64_t* u1, int64_t max_pairs, int64_t* total) {
     if (!w || !total || max_pairs < 0 || (max_pairs > 0 && (!u0 || !u1))) return TCW_EINVAL;
     tcw_ctx* c = w->ctx;
+    if (w->wd.enumerate && !w->pairs_formed) {
+        // the candidates exist once every point is done
+        unsigned long long active = 1;
+        if (w->launches > 0) {
+            HIP_TRY(c, hipMemcpyAsync(&active, &w->wd.stats[tcw::ST_ACTIVE], sizeof(active), hipMemcpyDeviceToHost,
+                                      c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+        }
+        if (active != 0) {
+            *total = 0;
+            return TCW_OK;
+        }
+        HIP_TRY(c, tcw::launch_enum_pairs(w->wd, c->stream));
+        w->pairs_formed = true;
+    }
     unsigned long long cnt = 0;
     HIP_TRY(c, hipMemcpyAsync(&cnt, w->wd.claw_count, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -774,6 +859,7 @@ void tcw_default_params(tcw_walk_params* p, int n) {
     p->chunk_last = 0;
     p->max_seconds = 0.0;
     p->chunk_parallel = 1;
+    p->launch_limit = 0;
 }
 
 }  // extern "C"
@@ -800,9 +886,11 @@ void add_stats(tcw_walk_stats& a, const tcw_walk_stats& b) {
     a.claws += b.claws;
     a.table_full += b.table_full;
     a.spin_timeouts += b.spin_timeouts;
+    a.claws_dropped += b.claws_dropped;
 }
 
-// Exact check of claw candidate pairs (host arrays) of a space: the first that passes fills res.
+// Exact check of claw candidate pairs (host arrays) of a space: the first that passes, in the order
+// given, fills res.
 int check_pairs(tcw_ctx* c, const Space& sp, const uint64_t* u0, const uint64_t* u1, int64_t m, tcw_result* res,
                 int* found) {
     *found = 0;
@@ -850,9 +938,10 @@ int check_pairs(tcw_ctx* c, const Space& sp, const uint64_t* u0, const uint64_t*
         desc = dv;
         for (int t = h - 1; t >= 0; --t) desc.push_back(dw[t]);
         if (sp.k % 2) desc.push_back((uint16_t)sp.chunk);
-        res->status = 1;
+        res->status = TCW_STATUS_FOUND;
         res->t = sp.k;
         res->chunk = sp.chunk;
+        std::memset(res->paulis, 0, sizeof(res->paulis));
         for (size_t j = 0; j < desc.size() && j < TCW_MAX_T; ++j) res->paulis[j] = desc[j];
         for (int q = 0; q < R; ++q) {
             res->clifford_perm[q] = perm[i * R + q];
@@ -864,6 +953,18 @@ int check_pairs(tcw_ctx* c, const Space& sp, const uint64_t* u0, const uint64_t*
     return TCW_OK;
 }
 
+// Candidates of an enumerated space are checked in increasing (u0, u1) order, so the decomposition
+// returned does not depend on the order in which the candidates were written.
+void sort_pairs(uint64_t* u0, uint64_t* u1, int64_t m) {
+    std::vector<std::pair<uint64_t, uint64_t>> v(m);
+    for (int64_t i = 0; i < m; ++i) v[i] = {u0[i], u1[i]};
+    std::sort(v.begin(), v.end());
+    for (int64_t i = 0; i < m; ++i) {
+        u0[i] = v[i].first;
+        u1[i] = v[i].second;
+    }
+}
+
 // New claw candidates of a walk session; `seen` counts those already checked.
 int check_claws(tcw_ctx* c, tcw_walk* w, int64_t& seen, tcw_result* res, int* found) {
     *found = 0;
@@ -873,6 +974,7 @@ int check_claws(tcw_ctx* c, tcw_walk* w, int64_t& seen, tcw_result* res, int* fo
     if (rc) return rc;
     const int64_t avail = total < 4096 ? total : 4096;
     if (avail <= seen) return TCW_OK;
+    if (w->wd.enumerate) sort_pairs(u0.data() + seen, u1.data() + seen, avail - seen);
     rc = check_pairs(c, w->space, u0.data() + seen, u1.data() + seen, avail - seen, res, found);
     seen = avail;
     return rc;
@@ -885,7 +987,7 @@ double now_s() {
 int depth_order_of(tcw_ctx* c, const tcw_walk_params* p, std::vector<int>& order) {
     order.clear();
     if (p->k_max < 0 || p->k_max > TCW_MAX_T) return fail(c, TCW_EINVAL, "k_max out of range");
-    if (p->depth_order_kind == TCW_ORDER_GIVEN) {
+    if (p->depth_order_kind == TCW_ORDER_GIVEN || p->depth_order_kind == TCW_ORDER_GIVEN_FIRST) {
         if (p->depth_order_len < 0 || p->depth_order_len > 16) return fail(c, TCW_EINVAL, "bad depth order");
         for (int i = 0; i < p->depth_order_len; ++i) {
             const int k = p->depth_order[i];
@@ -894,6 +996,8 @@ int depth_order_of(tcw_ctx* c, const tcw_walk_params* p, std::vector<int>& order
             for (int o : order) dup |= (o == k);
             if (!dup) order.push_back(k);
         }
+    } else if (p->depth_order_kind != TCW_ORDER_PLAIN) {
+        return fail(c, TCW_EINVAL, "depth_order_kind must be one of TCW_ORDER_*");
     }
     // the plain increasing order is the fallback for depths the given order left out
     for (int k = 0; k <= p->k_max; ++k) {
@@ -924,8 +1028,10 @@ int search_k0(tcw_ctx* c, const tcw_target* t, tcw_result* res, int* found) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     res->spaces++;
     if (ok) {
-        res->status = 1;
+        res->status = TCW_STATUS_FOUND;
         res->t = 0;
+        res->chunk = 0;
+        std::memset(res->paulis, 0, sizeof(res->paulis));
         for (int q = 0; q < R; ++q) {
             res->clifford_perm[q] = perm[q];
             res->clifford_sign[q] = sign[q];
@@ -935,46 +1041,6 @@ int search_k0(tcw_ctx* c, const tcw_target* t, tcw_result* res, int* found) {
     return TCW_OK;
 }
 
-// A small space: every point once, keyed by the full matrix hash.
-int search_enum(tcw_ctx* c, const tcw_target* t, const tcw_walk_params* p, int k, int chunk, int iters,
-                tcw_result* res, int* found, double t0) {
-    *found = 0;
-    const uint64_t npts = 2 * n_half_of(t->n, k / 2);
-    tcw_space sp{k, chunk, p->seed, p->version, 0};
-    res->spaces++;
-    res->versions++;
-    int64_t walks = (int64_t)npts < p->walks ? (int64_t)npts : p->walks;
-    if (walks < 64) walks = (int64_t)npts < 64 ? (int64_t)npts : 64;
-    int lg = 4;
-    while ((1ull << lg) < 4 * npts && lg < 30) ++lg;
-    tcw_walk* w = nullptr;
-    int rc = tcw_walk_begin(c, t, &sp, walks, lg, 2, 1, &w);
-    if (rc) return rc;
-    int64_t seen = 0;
-    // each point costs one evaluation; a bounded number of launches covers them all
-    const int64_t max_launches = (int64_t)(npts / (uint64_t)walks + 2) / iters + 4;
-    for (int64_t launch = 0;; ++launch) {
-        rc = tcw_walk_run(w, iters);
-        res->launches++;
-        tcw_walk_stats st{};
-        if (!rc) rc = tcw_walk_stats_get(w, &st);
-        if (!rc) rc = check_claws(c, w, seen, res, found);
-        if (rc) {
-            tcw_walk_end(w);
-            return rc;
-        }
-        if (*found || st.active_walks == 0 || launch >= max_launches ||
-            (p->max_seconds > 0 && now_s() - t0 > p->max_seconds)) {
-            add_stats(res->stats, st);
-            break;
-        }
-    }
-    tcw_walk_end(w);
-    return TCW_OK;
-}
-
-// Steps per function version: max(factor * N, 2 walks / theta), but no more than the table holds
-// at half load (slots / 2 distinguished points, i.e. slots / (2 theta) steps).
 // Ranges of the search parameters, checked before any of them enters a shift or a launch.  In a
 // batch, walks and log2_table <= 0 take the autotuner's choice.
 int check_params(tcw_ctx* c, const tcw_walk_params* p, int n, bool batch) {
@@ -984,14 +1050,29 @@ int check_params(tcw_ctx* c, const tcw_walk_params* p, int n, bool batch) {
         return fail(c, TCW_EINVAL, "log2_table must be in 4..32");
     if (p->trail_cap_factor < 1 || p->budget_beta < 1 || p->version_factor < 1)
         return fail(c, TCW_EINVAL, "trail_cap_factor, budget_beta and version_factor must be positive");
+    if (p->delta >= 0 && ((uint64_t)p->trail_cap_factor << p->delta) > TCW_MAX_TRAIL_CAP)
+        return fail(c, TCW_EINVAL, "trail_cap_factor * 2^delta exceeds TCW_MAX_TRAIL_CAP");
     if (p->enum_max < 0) return fail(c, TCW_EINVAL, "enum_max must be non-negative");
     const int32_t xi = (int32_t)xi_of(n);
     if (p->chunk_first < 0 || p->chunk_first > xi || p->chunk_last < 0 || p->chunk_last > xi)
         return fail(c, TCW_EINVAL, "chunk_first and chunk_last must lie in 1..xi (0: default)");
     if (!(p->max_seconds >= 0)) return fail(c, TCW_EINVAL, "max_seconds must be non-negative");
+    if (p->launch_limit < 0) return fail(c, TCW_EINVAL, "launch_limit must be non-negative");
     return TCW_OK;
 }
 
+// Trail cap of a walk space: trail_cap_factor * 2^delta, at most TCW_MAX_TRAIL_CAP (a table value
+// keeps 30 bits of trail length).
+int trail_cap_of(tcw_ctx* c, const tcw_walk_params* p, int delta, uint32_t* cap) {
+    const uint64_t v = (uint64_t)p->trail_cap_factor << delta;
+    if (delta > 32 || v > TCW_MAX_TRAIL_CAP)
+        return fail(c, TCW_EINVAL, "trail_cap_factor * 2^delta exceeds TCW_MAX_TRAIL_CAP for this space");
+    *cap = (uint32_t)v;
+    return TCW_OK;
+}
+
+// Steps per function version: max(factor * N, 2 walks / theta), but no more than the table holds
+// at half load (slots / 2 distinguished points, i.e. slots / (2 theta) steps).
 uint64_t version_steps(const tcw_walk_params* p, uint64_t npts, int delta, int64_t walks, int log2_table) {
     uint64_t per_version = (uint64_t)p->version_factor * npts;
     const uint64_t floor_v = 2ull * (uint64_t)walks << delta;
@@ -1003,16 +1084,308 @@ uint64_t version_steps(const tcw_walk_params* p, uint64_t npts, int delta, int64
 // the tables of one group of concurrently searched chunks stay within 2^35 bytes (32 GiB)
 constexpr int CHUNK_TABLE_POOL_LOG2 = 35;
 
+// What may end a batched run early: a stop request on the context, or a launch limit.
+struct StopCtl {
+    std::atomic<int>* flag = nullptr;
+    int64_t* launches = nullptr;  // launches so far in the calling search
+    int64_t limit = 0;            // 0: none
+    bool stopped = false;
+    bool due() const {
+        return (flag && flag->load(std::memory_order_relaxed) != 0) || (limit > 0 && launches && *launches >= limit);
+    }
+};
+
 struct BatchTarget;
 int search_chunks_concurrent(tcw_ctx* c, const tcw_target* t, const tcw_walk_params* p, int k, int c_first,
-                             int c_last, int delta, tcw_result* res, int* found, double t0);
+                             int c_last, int delta, tcw_result* res, int* found, bool* cut, StopCtl* stop, double t0);
+
+}  // namespace
+
+// One tcw_search as a state machine that advances by one launch (or one set-up step) at a time, so
+// that a stop request or a launch limit can end the call at a launch boundary and a stopped search
+// can be serialised and resumed.
+struct SearchRun {
+    const tcw_target* t = nullptr;
+    tcw_walk_params p{};
+    tcw_result res{};
+    std::vector<int32_t> order;   // depths in search order (a given order, then the plain fallback)
+    int32_t oi = 0;               // next entry of order
+    std::vector<int32_t> refine;  // TCW_ORDER_GIVEN after a hit: the depths below it not yet searched
+    int32_t ri = 0;
+    int32_t refining = 0;
+    int32_t finished = 0;
+    uint64_t searched = 0;        // bit k: depth k was started
+    // current depth
+    int32_t in_depth = 0, k = -1, cf = 0, cl = 0, chunk = 0, delta = 0, enumerate = 0, iters = 0;
+    int32_t depth_cut = 0;        // the depth was cut short by the wall-clock cap
+    uint64_t npts = 0;
+    // current space: a walk session
+    tcw_walk* w = nullptr;
+    uint64_t budget = 0, per_version = 0, used = 0, used_v = 0;
+    uint32_t version = 0;
+    int64_t seen = 0;
+    double elapsed = 0;           // seconds spent in earlier calls (before a stop)
+    bool checkpointable = true;   // false after a stop inside a group of concurrent chunks
+    ~SearchRun() {
+        if (w) tcw_walk_end(w);
+    }
+};
+
+void free_search_run(SearchRun* r) { delete r; }
+
+namespace {
+
+bool over_time(const SearchRun& s, double t0) {
+    return s.p.max_seconds > 0 && s.elapsed + (now_s() - t0) > s.p.max_seconds;
+}
+
+void close_space(SearchRun& s) {
+    if (s.w) {
+        tcw_walk_end(s.w);
+        s.w = nullptr;
+    }
+}
+
+// A verified decomposition at depth s.k (already in s.res).  With TCW_ORDER_GIVEN the depths below it
+// that have not been searched are searched next, in increasing order; the first of them to yield a
+// decomposition is the lowest, and ends the search.
+void on_hit(SearchRun& s) {
+    close_space(s);
+    s.in_depth = 0;
+    if (s.p.depth_order_kind == TCW_ORDER_GIVEN && !s.refining) {
+        s.refining = 1;
+        s.refine.clear();
+        for (int d = 0; d < s.res.t; ++d)
+            if (!(s.searched >> d & 1)) s.refine.push_back(d);
+        s.ri = 0;
+        if (!s.refine.empty()) return;
+    }
+    s.finished = 1;
+}
+
+// Open the walk session of chunk s.chunk of the current depth.
+int open_space(tcw_ctx* c, SearchRun& s) {
+    const tcw_target* t = s.t;
+    const tcw_walk_params* p = &s.p;
+    tcw_space sp{s.k, s.chunk, p->seed, p->version, s.enumerate ? 0 : s.delta};
+    s.res.spaces++;
+    s.res.versions++;
+    s.version = p->version;
+    s.used = s.used_v = 0;
+    s.seen = 0;
+    int rc = TCW_OK;
+    if (s.enumerate) {
+        int64_t walks = (int64_t)s.npts < p->walks ? (int64_t)s.npts : p->walks;
+        if (walks < 64) walks = (int64_t)s.npts < 64 ? (int64_t)s.npts : 64;
+        int lg = 4;
+        while ((1ull << lg) < 4 * s.npts && lg < 30) ++lg;
+        s.budget = s.npts;
+        s.per_version = ~0ull;
+        rc = tcw_walk_begin(c, t, &sp, walks, lg, 2, 1, &s.w);
+    } else {
+        uint32_t cap = 0;
+        if ((rc = trail_cap_of(c, p, s.delta, &cap))) return rc;
+        s.budget = (uint64_t)p->budget_beta * s.npts << s.delta;
+        s.per_version = version_steps(p, s.npts, s.delta, p->walks, p->log2_table);
+        // a launch must not overrun a function version
+        const uint64_t fit = s.per_version / (uint64_t)p->walks;
+        if ((uint64_t)s.iters > fit) s.iters = fit > 0 ? (int)fit : 1;
+        rc = tcw_walk_begin(c, t, &sp, p->walks, p->log2_table, cap, 0, &s.w);
+    }
+    return rc;
+}
+
+// Start the next depth of the order (or of the refinement list); sets s.finished when none is left.
+int next_depth(tcw_ctx* c, SearchRun& s, StopCtl* stop, double t0) {
+    const tcw_target* t = s.t;
+    const tcw_walk_params* p = &s.p;
+    const int n = t->n;
+    int k = -1;
+    for (;;) {
+        if (s.refining) {
+            if (s.ri >= (int32_t)s.refine.size()) break;
+            k = s.refine[s.ri++];
+        } else {
+            if (s.oi >= (int32_t)s.order.size()) break;
+            k = s.order[s.oi++];
+        }
+        if (!(s.searched >> k & 1)) break;
+        k = -1;
+    }
+    if (k < 0) {
+        s.finished = 1;
+        return TCW_OK;
+    }
+    s.searched |= 1ull << k;
+    s.k = k;
+    s.depth_cut = 0;
+    int found = 0, rc = TCW_OK;
+    if (k == 0) {
+        if ((rc = search_k0(c, t, &s.res, &found))) return rc;
+        if (found) on_hit(s);
+        else s.res.failed_depths |= 1ull;
+        return TCW_OK;
+    }
+    const uint64_t nh = n_half_of(n, k / 2);
+    if (nh == 0) return TCW_OK;  // space beyond 32-bit points: not searchable here (not a failed depth)
+    s.npts = 2 * nh;
+    s.cf = s.cl = 0;
+    if (k % 2) {
+        s.cf = p->chunk_first > 0 ? p->chunk_first : 1;
+        s.cl = p->chunk_last > 0 ? std::min<int>(p->chunk_last, (int)xi_of(n)) : (int)xi_of(n);
+    }
+    s.enumerate = (int64_t)s.npts <= p->enum_max;
+    s.delta = p->delta >= 0 ? p->delta : auto_delta(s.npts, p->log2_table);
+    s.iters = p->iters_per_launch > 0 ? p->iters_per_launch : default_iters(n);
+    // odd depths with chunk_parallel != 1 run their chunks as concurrent batch members; enumerated
+    // chunks only while their tables (4 npts slots of 16 B each) fit the chunk pool
+    const uint64_t n_chunks = (uint64_t)(s.cl - s.cf + 1);
+    const bool concurrent = k % 2 && p->chunk_parallel != 1 &&
+                            (!s.enumerate || n_chunks * 64 * s.npts <= (1ull << CHUNK_TABLE_POOL_LOG2));
+    if (concurrent) {
+        if (!s.enumerate) {
+            uint32_t cap = 0;
+            if ((rc = trail_cap_of(c, p, s.delta, &cap))) return rc;
+        }
+        const int G = p->chunk_parallel <= 0 ? s.cl - s.cf + 1 : p->chunk_parallel;
+        bool cut = false;
+        for (int first = s.cf; first <= s.cl && !found; first += G) {
+            if (over_time(s, t0)) {
+                cut = true;
+                break;
+            }
+            // each member resolves an open delta against its own (smaller) table
+            rc = search_chunks_concurrent(c, t, p, k, first, std::min(s.cl, first + G - 1), p->delta, &s.res, &found,
+                                          &cut, stop, t0 - s.elapsed);
+            if (rc) return rc;
+            if (stop && stop->stopped) {
+                // stopped inside a group: the members are not serialised, so this search cannot be
+                // checkpointed; a later call would repeat the depth
+                s.checkpointable = false;
+                return TCW_OK;
+            }
+        }
+        if (found) on_hit(s);
+        else if (!cut) s.res.failed_depths |= 1ull << k;
+        return TCW_OK;
+    }
+    s.in_depth = 1;
+    s.chunk = s.cf;
+    return open_space(c, s);
+}
+
+// One launch of the current space, then the exact check of its new claw candidates and the
+// bookkeeping of budgets, function versions and chunks.
+int space_launch(tcw_ctx* c, SearchRun& s, int64_t* launches, double t0) {
+    tcw_walk* w = s.w;
+    int rc = tcw_walk_run(w, s.iters);
+    s.res.launches++;
+    (*launches)++;
+    tcw_walk_stats st{};
+    if (!rc) rc = tcw_walk_stats_get(w, &st);
+    int found = 0;
+    if (!rc && (!s.enumerate || st.active_walks == 0)) rc = check_claws(c, w, s.seen, &s.res, &found);
+    if (rc) return rc;
+    s.used = s.used - s.used_v + (uint64_t)st.steps;
+    s.used_v = (uint64_t)st.steps;
+    const bool space_done = s.enumerate ? st.active_walks == 0 : s.used >= s.budget;
+    if (found || space_done) {
+        add_stats(s.res.stats, st);
+        close_space(s);
+        if (found) {
+            on_hit(s);
+            return TCW_OK;
+        }
+        if (s.k % 2 && s.chunk < s.cl) {
+            s.chunk++;
+            return open_space(c, s);
+        }
+        s.in_depth = 0;
+        if (!s.depth_cut) s.res.failed_depths |= 1ull << s.k;
+        return TCW_OK;
+    }
+    if (over_time(s, t0)) {
+        add_stats(s.res.stats, st);
+        close_space(s);
+        s.in_depth = 0;
+        s.depth_cut = 1;
+        s.finished = 1;
+        return TCW_OK;
+    }
+    if (!s.enumerate && s.used_v >= s.per_version) {
+        add_stats(s.res.stats, st);
+        s.used_v = 0;
+        s.seen = 0;
+        ++s.version;
+        s.res.versions++;
+        return tcw_walk_reset(w, s.version);
+    }
+    return TCW_OK;
+}
+
+void finish_result(SearchRun& s, double t0) {
+    tcw_result& r = s.res;
+    r.seconds = s.elapsed + (now_s() - t0);
+    if (r.status != TCW_STATUS_FOUND) {
+        r.status = TCW_STATUS_NOT_FOUND;
+        r.minimal = 0;
+        return;
+    }
+    const uint64_t below = r.t >= 64 ? ~0ull : ((1ull << r.t) - 1);
+    r.minimal = (r.failed_depths & below) == below ? 1 : 0;
+}
+
+// Runs s until it finishes, fails, or a stop request or the launch limit ends the call.  A stopped
+// search moves into the context (c->stopped) with status TCW_STATUS_STOPPED in *res.
+int run_search(tcw_ctx* c, SearchRun* s, tcw_result* res) {
+    const double t0 = now_s();
+    int64_t launches = 0;
+    StopCtl stop;
+    stop.flag = &c->stop_req;
+    stop.launches = &launches;
+    stop.limit = s->p.launch_limit;
+    int rc = TCW_OK;
+    while (!s->finished) {
+        if (stop.due()) {
+            c->stop_req.store(0);
+            stop.stopped = true;
+        }
+        if (stop.stopped) break;
+        if (s->in_depth) rc = space_launch(c, *s, &launches, t0);
+        else if (over_time(*s, t0)) s->finished = 1;
+        else rc = next_depth(c, *s, &stop, t0);
+        if (rc) break;
+    }
+    if (rc) {
+        delete s;
+        return rc;
+    }
+    if (stop.stopped && !s->finished) {
+        s->elapsed += now_s() - t0;
+        *res = s->res;
+        res->status = TCW_STATUS_STOPPED;
+        res->minimal = 0;
+        res->seconds = s->elapsed;
+        if (s->res.status == TCW_STATUS_FOUND) res->t = s->res.t;  // a hit awaiting the depths below it
+        if (c->stopped) free_search_run(c->stopped);
+        c->stopped = s;
+        return TCW_OK;
+    }
+    finish_result(*s, t0);
+    *res = s->res;
+    delete s;
+    return TCW_OK;
+}
 
 }  // namespace
 
 extern "C" int tcw_search(tcw_ctx* c, const tcw_target* t, const tcw_walk_params* p, tcw_result* res) {
     if (!c || !t || !p || !res) return TCW_EINVAL;
     std::memset(res, 0, sizeof(*res));
-    const double t0 = now_s();
+    if (c->stopped) {
+        free_search_run(c->stopped);
+        c->stopped = nullptr;
+    }
     const int n = t->n;
     res->n = n;
     int rc = check_params(c, p, n, false);
@@ -1020,109 +1393,265 @@ extern "C" int tcw_search(tcw_ctx* c, const tcw_target* t, const tcw_walk_params
     std::vector<int> order;
     rc = depth_order_of(c, p, order);
     if (rc) return rc;
-    const uint32_t xi = xi_of(n);
-    const int iters = p->iters_per_launch > 0 ? p->iters_per_launch : default_iters(n);
-    for (int k : order) {
-        if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) break;
-        int found = 0;
-        if (k == 0) {
-            if ((rc = search_k0(c, t, res, &found))) return rc;
-            if (found) {
-                res->seconds = now_s() - t0;
-                return TCW_OK;
-            }
-            continue;
-        }
-        const int h = k / 2;
-        const uint64_t nh = n_half_of(n, h);
-        if (nh == 0) continue;  // space beyond 32-bit points: not searchable here
-        const uint64_t npts = 2 * nh;
-        int cf = 0, cl = 0;
-        if (k % 2) {
-            cf = p->chunk_first > 0 ? p->chunk_first : 1;
-            cl = p->chunk_last > 0 ? p->chunk_last : (int)xi;
-            if (cl > (int)xi) cl = (int)xi;
-        }
-        const bool enumerate = (int64_t)npts <= p->enum_max;
-        const int delta = p->delta >= 0 ? p->delta : auto_delta(npts, p->log2_table);
-        // odd depths with chunk_parallel != 1 run their chunks as concurrent batch members; for
-        // enumerated chunks only while their tables (4 npts slots of 16 B each) fit the chunk pool
-        const uint64_t n_chunks = (uint64_t)(cl - cf + 1);
-        const bool concurrent =
-            k % 2 && p->chunk_parallel != 1 &&
-            (!enumerate || n_chunks * 64 * npts <= (1ull << CHUNK_TABLE_POOL_LOG2));
-        if (concurrent) {
-            // chunks in groups of G searched concurrently, one batch member each
-            const int G = p->chunk_parallel <= 0 ? cl - cf + 1 : p->chunk_parallel;
-            for (int first = cf; first <= cl && !found; first += G) {
-                if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) break;
-                // each member resolves an open delta against its own (smaller) table
-                rc = search_chunks_concurrent(c, t, p, k, first, std::min(cl, first + G - 1), p->delta, res, &found,
-                                              t0);
-                if (rc) return rc;
-            }
-        }
-        for (int chunk = cf; chunk <= cl && !found && !concurrent; ++chunk) {
-            if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) break;
-            if (enumerate) {
-                if ((rc = search_enum(c, t, p, k, chunk, iters, res, &found, t0))) return rc;
-                continue;
-            }
-            tcw_space sp{k, chunk, p->seed, p->version, delta};
-            res->spaces++;
-            const uint64_t budget = (uint64_t)p->budget_beta * npts << delta;
-            const uint64_t per_version = version_steps(p, npts, delta, p->walks, p->log2_table);
-            const uint32_t cap = (uint32_t)p->trail_cap_factor << delta;
-            // a launch must not overrun a function version
-            int iters_v = iters;
-            const uint64_t fit = per_version / (uint64_t)p->walks;
-            if ((uint64_t)iters_v > fit) iters_v = fit > 0 ? (int)fit : 1;
-            tcw_walk* w = nullptr;
-            rc = tcw_walk_begin(c, t, &sp, p->walks, p->log2_table, cap, 0, &w);
-            if (rc) return rc;
-            uint64_t used = 0, used_v = 0;
-            uint32_t version = p->version;
-            int64_t seen = 0;
-            res->versions++;
-            tcw_walk_stats st{};
-            while (used < budget) {
-                rc = tcw_walk_run(w, iters_v);
-                res->launches++;
-                if (!rc) rc = tcw_walk_stats_get(w, &st);
-                if (!rc) rc = check_claws(c, w, seen, res, &found);
-                if (rc) {
-                    tcw_walk_end(w);
-                    return rc;
-                }
-                used = used - used_v + (uint64_t)st.steps;
-                used_v = (uint64_t)st.steps;
-                if (found) break;
-                if (p->max_seconds > 0 && now_s() - t0 > p->max_seconds) break;
-                if (used_v >= per_version && used < budget) {
-                    add_stats(res->stats, st);
-                    std::memset(&st, 0, sizeof(st));
-                    used_v = 0;
-                    seen = 0;
-                    ++version;
-                    res->versions++;
-                    rc = tcw_walk_reset(w, version);
-                    if (rc) {
-                        tcw_walk_end(w);
-                        return rc;
-                    }
-                }
-            }
-            add_stats(res->stats, st);
-            tcw_walk_end(w);
-        }
-        if (found) {
-            res->seconds = now_s() - t0;
-            return TCW_OK;
-        }
-    }
-    res->status = 0;
-    res->seconds = now_s() - t0;
+    SearchRun* s = new (std::nothrow) SearchRun();
+    if (!s) return TCW_ENOMEM;
+    s->t = t;
+    s->p = *p;
+    s->res.n = n;
+    s->order.assign(order.begin(), order.end());
+    return run_search(c, s, res);
+}
+
+extern "C" int tcw_search_stop(tcw_ctx* c) {
+    if (!c) return TCW_EINVAL;
+    c->stop_req.store(1);
     return TCW_OK;
+}
+
+// ---- checkpoints of a stopped search ----
+namespace {
+
+constexpr uint64_t CKPT_MAGIC = 0x3154504B43574354ull;  // "TCWCKPT1"
+
+struct Writer {
+    std::vector<uint8_t> buf;
+    template <typename T>
+    void put(const T& v) {
+        const uint8_t* q = reinterpret_cast<const uint8_t*>(&v);
+        buf.insert(buf.end(), q, q + sizeof(T));
+    }
+    void bytes(const void* q, size_t len) {
+        const uint8_t* b = static_cast<const uint8_t*>(q);
+        buf.insert(buf.end(), b, b + len);
+    }
+    template <typename T>
+    void vec(const std::vector<T>& v) {
+        put<uint64_t>(v.size());
+        if (!v.empty()) bytes(v.data(), v.size() * sizeof(T));
+    }
+};
+
+struct Reader {
+    const uint8_t* p;
+    size_t len, at = 0;
+    bool ok = true;
+    template <typename T>
+    T get() {
+        T v{};
+        if (at + sizeof(T) > len) {
+            ok = false;
+            return v;
+        }
+        std::memcpy(&v, p + at, sizeof(T));
+        at += sizeof(T);
+        return v;
+    }
+    const uint8_t* take(size_t n) {
+        if (!ok || at + n > len || at + n < at) {
+            ok = false;
+            return nullptr;
+        }
+        const uint8_t* q = p + at;
+        at += n;
+        return q;
+    }
+    template <typename T>
+    void vec(std::vector<T>& v, size_t max_count) {
+        const uint64_t cnt = get<uint64_t>();
+        if (!ok || cnt > max_count) {
+            ok = false;
+            return;
+        }
+        const uint8_t* q = take(cnt * sizeof(T));
+        if (!q) return;
+        v.resize(cnt);
+        if (cnt) std::memcpy(v.data(), q, cnt * sizeof(T));
+    }
+};
+
+// A fingerprint of the target's exact channel rep (reduced form), to refuse a resume on another target.
+int target_fingerprint(tcw_ctx* c, const tcw_target* t, uint64_t* fp) {
+    const size_t rr = (size_t)1 << (4 * t->n);
+    std::vector<int32_t> a(rr), b(rr);
+    int32_t e = 0;
+    int rc = tcw_target_channel(c, t, a.data(), b.data(), &e);
+    if (rc) return rc;
+    uint64_t h = tcw::mix64(0x5450524e54ull ^ (uint64_t)t->n);
+    h = tcw::mix64(h ^ (uint64_t)(uint32_t)e);
+    for (size_t i = 0; i < rr; ++i) h = tcw::mix64(h ^ (((uint64_t)(uint32_t)a[i] << 32) | (uint32_t)b[i]));
+    *fp = h;
+    return TCW_OK;
+}
+
+int serialise(tcw_ctx* c, const SearchRun& s, std::vector<uint8_t>& out) {
+    Writer w;
+    uint64_t fp = 0;
+    int rc = target_fingerprint(c, s.t, &fp);
+    if (rc) return rc;
+    w.put(CKPT_MAGIC);
+    w.put<uint32_t>(sizeof(tcw_walk_params));
+    w.put<uint32_t>(sizeof(tcw_result));
+    w.put<int32_t>(s.t->n);
+    w.put(fp);
+    w.put(s.p);
+    w.put(s.res);
+    w.vec(s.order);
+    w.put(s.oi);
+    w.vec(s.refine);
+    w.put(s.ri);
+    w.put(s.refining);
+    w.put(s.searched);
+    w.put(s.in_depth);
+    w.put(s.k);
+    w.put(s.cf);
+    w.put(s.cl);
+    w.put(s.chunk);
+    w.put(s.delta);
+    w.put(s.enumerate);
+    w.put(s.iters);
+    w.put(s.depth_cut);
+    w.put(s.npts);
+    w.put(s.elapsed);
+    const int32_t has_space = s.w ? 1 : 0;
+    w.put(has_space);
+    if (has_space) {
+        const tcw::WalkDev& wd = s.w->wd;
+        w.put(s.budget);
+        w.put(s.per_version);
+        w.put(s.used);
+        w.put(s.used_v);
+        w.put(s.version);
+        w.put(s.seen);
+        w.put<int64_t>(wd.walks);
+        w.put<int32_t>(wd.log2_table);
+        w.put<uint32_t>(wd.cap);
+        w.put<int32_t>(wd.enumerate);
+        w.put<int64_t>(s.w->launches);
+        unsigned long long st[tcw::ST_COUNT];
+        unsigned long long cc = 0;
+        HIP_TRY(c, hipMemcpyAsync(st, wd.stats, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(&cc, wd.claw_count, sizeof(cc), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        w.bytes(st, sizeof(st));
+        w.put<uint64_t>(cc);
+        const size_t sbytes = (size_t)wd.walks * sizeof(tcw::WalkState);
+        const size_t tbytes = ((size_t)1 << wd.log2_table) * 16;
+        const size_t at = w.buf.size();
+        w.buf.resize(at + sbytes + tbytes);
+        HIP_TRY(c, hipMemcpyAsync(w.buf.data() + at, wd.states, sbytes, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(w.buf.data() + at + sbytes, wd.table, tbytes, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    out.swap(w.buf);
+    return TCW_OK;
+}
+
+}  // namespace
+
+extern "C" int tcw_checkpoint(tcw_ctx* c, void* host_buf, size_t* len) {
+    if (!c || !len) return TCW_EINVAL;
+    if (!c->stopped) return fail(c, TCW_ESTATE, "no stopped search in this context");
+    if (!c->stopped->checkpointable)
+        return fail(c, TCW_ESTATE, "the search stopped inside a group of concurrent chunks (chunk_parallel != 1)");
+    std::vector<uint8_t> buf;
+    int rc = serialise(c, *c->stopped, buf);
+    if (rc) return rc;
+    const size_t have = *len;
+    *len = buf.size();
+    if (!host_buf) return TCW_OK;
+    if (have < buf.size()) return fail(c, TCW_EINVAL, "checkpoint buffer too small");
+    std::memcpy(host_buf, buf.data(), buf.size());
+    return TCW_OK;
+}
+
+extern "C" int tcw_resume(tcw_ctx* c, const tcw_target* t, const void* host_buf, size_t len, int64_t launch_limit,
+                          tcw_result* res) {
+    if (!c || !t || !host_buf || !res || launch_limit < 0) return TCW_EINVAL;
+    std::memset(res, 0, sizeof(*res));
+    if (c->stopped) {
+        free_search_run(c->stopped);
+        c->stopped = nullptr;
+    }
+    Reader r{static_cast<const uint8_t*>(host_buf), len};
+    auto bad = [&](const char* what) { return fail(c, TCW_EINVAL, std::string("checkpoint: ") + what); };
+    if (r.get<uint64_t>() != CKPT_MAGIC) return bad("not a search checkpoint");
+    if (r.get<uint32_t>() != sizeof(tcw_walk_params) || r.get<uint32_t>() != sizeof(tcw_result))
+        return bad("written by another version of the library");
+    const int32_t n = r.get<int32_t>();
+    const uint64_t fp = r.get<uint64_t>();
+    if (!r.ok || n != t->n) return bad("target has another qubit count");
+    uint64_t fp_t = 0;
+    int rc = target_fingerprint(c, t, &fp_t);
+    if (rc) return rc;
+    if (fp != fp_t) return bad("taken on another target");
+    std::unique_ptr<SearchRun> s(new (std::nothrow) SearchRun());
+    if (!s) return TCW_ENOMEM;
+    s->t = t;
+    s->p = r.get<tcw_walk_params>();
+    s->res = r.get<tcw_result>();
+    r.vec(s->order, 65);
+    s->oi = r.get<int32_t>();
+    r.vec(s->refine, 65);
+    s->ri = r.get<int32_t>();
+    s->refining = r.get<int32_t>();
+    s->searched = r.get<uint64_t>();
+    s->in_depth = r.get<int32_t>();
+    s->k = r.get<int32_t>();
+    s->cf = r.get<int32_t>();
+    s->cl = r.get<int32_t>();
+    s->chunk = r.get<int32_t>();
+    s->delta = r.get<int32_t>();
+    s->enumerate = r.get<int32_t>();
+    s->iters = r.get<int32_t>();
+    s->depth_cut = r.get<int32_t>();
+    s->npts = r.get<uint64_t>();
+    s->elapsed = r.get<double>();
+    const int32_t has_space = r.get<int32_t>();
+    if (!r.ok) return bad("truncated");
+    s->p.launch_limit = launch_limit;
+    if ((rc = check_params(c, &s->p, n, false))) return rc;
+    if (s->oi < 0 || s->oi > (int32_t)s->order.size() || s->ri < 0 || s->ri > (int32_t)s->refine.size())
+        return bad("depth-loop position out of range");
+    for (int32_t k : s->order)
+        if (k < 0 || k > TCW_MAX_T) return bad("depth out of range");
+    for (int32_t k : s->refine)
+        if (k < 0 || k > TCW_MAX_T) return bad("depth out of range");
+    if (s->in_depth != (has_space ? 1 : 0)) return bad("inconsistent space state");
+    if (has_space) {
+        s->budget = r.get<uint64_t>();
+        s->per_version = r.get<uint64_t>();
+        s->used = r.get<uint64_t>();
+        s->used_v = r.get<uint64_t>();
+        s->version = r.get<uint32_t>();
+        s->seen = r.get<int64_t>();
+        const int64_t walks = r.get<int64_t>();
+        const int32_t lg = r.get<int32_t>();
+        const uint32_t cap = r.get<uint32_t>();
+        const int32_t en = r.get<int32_t>();
+        const int64_t wl = r.get<int64_t>();
+        unsigned long long st[tcw::ST_COUNT];
+        const uint8_t* stq = r.take(sizeof(st));
+        const uint64_t cc = r.get<uint64_t>();
+        if (!r.ok || walks < 1 || walks > (1ll << 31) || lg < 4 || lg > 32 || en != s->enumerate)
+            return bad("malformed walk session");
+        const size_t sbytes = (size_t)walks * sizeof(tcw::WalkState);
+        const size_t tbytes = ((size_t)1 << lg) * 16;
+        const uint8_t* sq = r.take(sbytes);
+        const uint8_t* tq = r.take(tbytes);
+        if (!r.ok || !sq || !tq) return bad("truncated walk session");
+        std::memcpy(st, stq, sizeof(st));
+        tcw_space sp{s->k, s->chunk, s->p.seed, s->version, s->enumerate ? 0 : s->delta};
+        if ((rc = tcw_walk_begin(c, t, &sp, walks, lg, cap, en, &s->w))) return rc;
+        tcw::WalkDev& wd = s->w->wd;
+        s->w->launches = wl;
+        HIP_TRY(c, hipMemcpyAsync(wd.states, sq, sbytes, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(wd.table, tq, tbytes, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(wd.stats, st, sizeof(st), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(wd.claw_count, &cc, sizeof(cc), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    if (r.at != len) return bad("trailing bytes");
+    return run_search(c, s.release(), res);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1154,7 +1683,8 @@ int autotune(tcw_ctx* c, const tcw_target* t, int k, int chunk, int delta, uint6
     std::vector<double> rates;
     for (int64_t w : cands) {
         tcw_walk* ws = nullptr;
-        int rc = tcw_walk_begin(c, t, &sp, w, 16, (uint32_t)20 << delta, 0, &ws);
+        const uint64_t acap = std::min<uint64_t>((uint64_t)20 << delta, TCW_MAX_TRAIL_CAP);
+        int rc = tcw_walk_begin(c, t, &sp, w, 16, (uint32_t)acap, 0, &ws);
         if (rc) return rc;
         const int iters = (int)std::max<int64_t>(1, std::min<int64_t>(64, (1 << 21) / w));
         float ms = 0, tot = 0;
@@ -1200,8 +1730,12 @@ struct BatchTarget {
     tcw_result* res = nullptr;
     std::vector<int> order;
     size_t oi = 0;
+    std::vector<int> refine;  // TCW_ORDER_GIVEN after a hit: unsearched depths below it, ascending
+    size_t ri = 0;
+    bool refining = false;
+    uint64_t searched = 0;    // bit k: depth k was started
     int k = -1, chunk = 0, cl = 0;
-    bool walking = false, done = false;
+    bool walking = false, done = false, cut = false;
     std::unique_ptr<Space> space;
     tcw::WalkDev wd{};
     int64_t walks = 0;
@@ -1242,32 +1776,65 @@ void free_walk_buffers(BatchTarget& b) {
 
 // (Re)start the walks of a target's current space on stream s: table cleared, counters zeroed.
 int batch_restart(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStream_t s) {
-    HIP_TRY(c, tcw::launch_table_clear(b.wd.table, b.wd.log2_table, s));
+    HIP_TRY(c, tcw::launch_table_clear(b.wd.table, b.wd.log2_table, b.wd.enumerate ? tcw::ENUM_TABLE_INIT : 0, s));
     HIP_TRY(c, hipMemsetAsync(bb.stats + (size_t)slot * tcw::ST_COUNT, 0, tcw::ST_COUNT * 8, s));
     HIP_TRY(c, hipMemsetAsync(bb.claw_count + slot, 0, 8, s));
     HIP_TRY(c, tcw::launch_walk_init(b.space->dev, b.wd, s));
     return TCW_OK;
 }
 
+// A verified decomposition of member b (in b.res).  TCW_ORDER_GIVEN then searches the depths below it
+// not yet searched, in increasing order (the first further hit is the lowest); otherwise b is done.
+void batch_on_hit(BatchTarget& b) {
+    if (b.p.depth_order_kind == TCW_ORDER_GIVEN && !b.refining) {
+        b.refining = true;
+        b.refine.clear();
+        for (int d = 0; d < b.res->t; ++d)
+            if (!(b.searched >> d & 1)) b.refine.push_back(d);
+        b.ri = 0;
+        b.chunk = b.cl = 0;  // the next space starts a new depth
+        if (!b.refine.empty()) return;
+    }
+    b.done = true;
+}
+
 // Move a target to its next space: depth 0 is checked on the spot; the next space of a positive
-// depth, enumerated when small and walked otherwise, leaves the target `walking`.
-int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStream_t s, double t0) {
+// depth, enumerated when small and walked otherwise, leaves the target `walking`.  prev_done: the
+// current space ran to its budget without a verified decomposition (so its depth is failed once its
+// last chunk is done).
+int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStream_t s, double t0, bool prev_done) {
     const int n = b.t->n;
     const uint32_t xi = xi_of(n);
     while (!b.done) {
         if (b.p.max_seconds > 0 && now_s() - t0 > b.p.max_seconds) {
             b.done = true;
+            b.cut = true;
             break;
         }
         // next (k, chunk)
-        if (b.k >= 0 && b.k % 2 == 1 && b.chunk < b.cl) {
+        if (prev_done && b.k >= 0 && b.k % 2 == 1 && b.chunk < b.cl) {
             b.chunk++;
         } else {
-            if (b.oi >= b.order.size()) {
+            if (prev_done && b.k >= 1) b.res->failed_depths |= 1ull << b.k;
+            prev_done = false;
+            int k = -1;
+            for (;;) {
+                if (b.refining) {
+                    if (b.ri >= b.refine.size()) break;
+                    k = b.refine[b.ri++];
+                } else {
+                    if (b.oi >= b.order.size()) break;
+                    k = b.order[b.oi++];
+                }
+                if (!(b.searched >> k & 1)) break;
+                k = -1;
+            }
+            if (k < 0) {
                 b.done = true;
                 break;
             }
-            b.k = b.order[b.oi++];
+            b.searched |= 1ull << k;
+            b.k = k;
             b.chunk = 0;
             b.cl = 0;
             if (b.k % 2) {
@@ -1278,7 +1845,11 @@ int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStr
         int found = 0, rc = 0;
         if (b.k == 0) {
             if ((rc = search_k0(c, b.t, b.res, &found))) return rc;
-            if (found) b.done = true;
+            if (found) {
+                batch_on_hit(b);
+            } else {
+                b.res->failed_depths |= 1ull;
+            }
             continue;
         }
         const uint64_t nh = n_half_of(n, b.k / 2);
@@ -1292,6 +1863,7 @@ int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStr
         // spaces are walked.
         const bool enumerate = (int64_t)npts <= b.p.enum_max;
         int delta = 0;
+        uint32_t cap = 2;
         if (enumerate) {
             const int64_t wmax = std::max<int64_t>(64, b.p.walks);
             b.walks = (int64_t)npts < wmax ? (int64_t)npts : wmax;
@@ -1302,6 +1874,7 @@ int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStr
         } else {
             delta = b.p.delta >= 0 ? b.p.delta
                                    : auto_delta(npts, b.p.log2_table > 0 ? b.p.log2_table : default_log2_table(n));
+            if ((rc = trail_cap_of(c, &b.p, delta, &cap))) return rc;
             TunedCfg cfg;
             if (b.p.walks <= 0 || b.p.log2_table <= 0 || b.p.iters_per_launch <= 0) {
                 if ((rc = autotune(c, b.t, b.k, b.chunk, delta, b.p.seed, &cfg))) return rc;
@@ -1331,17 +1904,21 @@ int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStr
         const size_t sbytes = (size_t)b.walks * sizeof(tcw::WalkState);
         if (b.states_cap < sbytes) {
             if (b.wd.states) (void)hipFree(b.wd.states);
+            b.wd.states = nullptr;
+            b.states_cap = 0;
             HIP_TRY(c, hipMalloc(&b.wd.states, sbytes));
             b.states_cap = sbytes;
         }
         if (b.table_cap < b.log2) {
             if (b.wd.table) (void)hipFree(b.wd.table);
+            b.wd.table = nullptr;
+            b.table_cap = 0;
             HIP_TRY(c, hipMalloc(&b.wd.table, ((size_t)1 << b.log2) * 16));
             b.table_cap = b.log2;
         }
         b.wd.walks = b.walks;
         b.wd.log2_table = b.log2;
-        b.wd.cap = enumerate ? 2u : (uint32_t)b.p.trail_cap_factor << delta;
+        b.wd.cap = cap;
         b.wd.enumerate = enumerate ? 1 : 0;
         b.wd.n_points = npts;
         b.wd.stats = bb.stats + (size_t)slot * tcw::ST_COUNT;
@@ -1365,6 +1942,7 @@ extern "C" int tcw_autotune(tcw_ctx* c, const tcw_target* t, int k, int chunk, i
     tcw_space sp{k, chunk, seed, 0, delta};
     int rc = check_space(c, t->n, &sp);
     if (rc) return rc;
+    if (((uint64_t)20 << delta) > TCW_MAX_TRAIL_CAP) return fail(c, TCW_EINVAL, "delta too large for a trail cap");
     TunedCfg cfg;
     rc = autotune(c, t, k, chunk, delta, seed, &cfg);
     if (rc) return rc;
@@ -1377,7 +1955,7 @@ extern "C" int tcw_autotune(tcw_ctx* c, const tcw_target* t, int k, int chunk, i
 
 namespace {
 
-tcw_walk_stats stats_of(const unsigned long long* st) {
+tcw_walk_stats stats_of(const unsigned long long* st, unsigned long long claw_count, uint32_t claw_cap) {
     tcw_walk_stats ws{};
     ws.steps = (int64_t)st[tcw::ST_STEPS];
     ws.dps = (int64_t)st[tcw::ST_DPS];
@@ -1389,13 +1967,24 @@ tcw_walk_stats stats_of(const unsigned long long* st) {
     ws.claws = (int64_t)st[tcw::ST_CLAWS];
     ws.table_full = (int64_t)st[tcw::ST_FULL];
     ws.spin_timeouts = (int64_t)st[tcw::ST_SPIN];
+    ws.claws_dropped = claw_count > claw_cap ? (int64_t)(claw_count - claw_cap) : 0;
     return ws;
+}
+
+void set_minimal(tcw_result* r) {
+    if (r->status != TCW_STATUS_FOUND) {
+        r->minimal = 0;
+        return;
+    }
+    const uint64_t below = r->t >= 64 ? ~0ull : ((1ull << r->t) - 1);
+    r->minimal = (r->failed_depths & below) == below ? 1 : 0;
 }
 
 // Runs every member search of bt (each with its own depth order, chunk range, walks and table)
 // in graph-captured rounds until all are done, or, with stop_on_first, until one member holds a
-// verified decomposition.  *agg: walk steps per second of walk-kernel time.
-int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, double t0, double* agg) {
+// verified decomposition, or until `stop` is due (members still running then end with
+// TCW_STATUS_STOPPED).  *agg: walk steps per second of walk-kernel time.
+int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, double t0, double* agg, StopCtl* stop) {
     const int count = (int)bt.size();
     BatchBuffers bb;
     HIP_TRY(c, hipMalloc(&bb.stats, (size_t)count * tcw::ST_COUNT * 8));
@@ -1409,33 +1998,20 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
     HIP_TRY(c, hipMemsetAsync(bb.claw_count, 0, (size_t)count * 8, c->stream));
     int rc = TCW_OK;
     for (int i = 0; i < count && !rc; ++i) {
-        rc = batch_advance(c, bt[i], i, bb, c->stream, t0);
+        rc = batch_advance(c, bt[i], i, bb, c->stream, t0, false);
         if (bt[i].done) bt[i].res->seconds = now_s() - t0;
     }
-    if (rc) return rc;
+    if (rc) {
+        for (auto& b : bt) free_walk_buffers(b);
+        return rc;
+    }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
 
     // streams for the graph: one branch per qubit count (default priority)
     hipStream_t gs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hipEvent_t fork = nullptr, join[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    HIP_TRY(c, hipStreamCreateWithFlags(&gs[0], hipStreamNonBlocking));
-    for (int n = 1; n <= 4; ++n) {
-        HIP_TRY(c, hipStreamCreateWithFlags(&gs[n], hipStreamNonBlocking));
-        HIP_TRY(c, hipEventCreateWithFlags(&join[n], hipEventDisableTiming));
-    }
-    HIP_TRY(c, hipEventCreateWithFlags(&fork, hipEventDisableTiming));
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
-    bool dirty = true;
-    int cus = 256;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
-    int64_t total_steps = 0;
-    double walk_seconds = 0;
-    std::vector<unsigned long long> stats((size_t)count * tcw::ST_COUNT), ccount(count);
-    std::vector<tcw::SpaceDev> h_sps(count);
-    std::vector<tcw::WalkDev> h_wds(count);
-    std::vector<int32_t> h_first(count, 0), h_blocks(count, 0);
-    int iters_n[5] = {0, 0, 0, 0, 0}, blocks_n[5] = {0, 0, 0, 0, 0};
     auto cleanup = [&]() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -1454,11 +2030,37 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
             return hip_fail(c, _e, #expr);   \
         }                                    \
     } while (0)
-    bool stop = false;
+#define BATCH_RC(expr)     \
+    do {                   \
+        rc = (expr);       \
+        if (rc) {          \
+            cleanup();     \
+            return rc;     \
+        }                  \
+    } while (0)
+    BATCH_TRY(hipStreamCreateWithFlags(&gs[0], hipStreamNonBlocking));
+    for (int n = 1; n <= 4; ++n) {
+        BATCH_TRY(hipStreamCreateWithFlags(&gs[n], hipStreamNonBlocking));
+        BATCH_TRY(hipEventCreateWithFlags(&join[n], hipEventDisableTiming));
+    }
+    BATCH_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    bool dirty = true;
+    int64_t total_steps = 0;
+    double walk_seconds = 0;
+    std::vector<unsigned long long> stats((size_t)count * tcw::ST_COUNT), ccount(count);
+    std::vector<tcw::SpaceDev> h_sps(count);
+    std::vector<tcw::WalkDev> h_wds(count);
+    std::vector<int32_t> h_first(count, 0), h_blocks(count, 0);
+    int iters_n[5] = {0, 0, 0, 0, 0}, blocks_n[5] = {0, 0, 0, 0, 0};
+    bool stop_first = false;
     for (;;) {
         bool any = false;
         for (auto& b : bt) any |= b.walking;
         if (!any) break;
+        if (stop && stop->due()) {
+            stop->stopped = true;
+            break;
+        }
         if (dirty) {
             // block ranges per target, per qubit count
             std::vector<int32_t> blk[5];
@@ -1483,6 +2085,7 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
                 }
                 blocks_n[n] = (int)blk[n].size();
                 if (bb.blk_target[n]) (void)hipFree(bb.blk_target[n]);
+                bb.blk_target[n] = nullptr;
                 BATCH_TRY(hipMalloc(&bb.blk_target[n], blk[n].size() * 4));
                 BATCH_TRY(hipMemcpy(bb.blk_target[n], blk[n].data(), blk[n].size() * 4, hipMemcpyHostToDevice));
             }
@@ -1518,9 +2121,22 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
         const double tl = now_s();
         BATCH_TRY(hipGraphLaunch(exec, gs[0]));
         BATCH_TRY(hipMemcpyAsync(stats.data(), bb.stats, stats.size() * 8, hipMemcpyDeviceToHost, gs[0]));
-        BATCH_TRY(hipMemcpyAsync(ccount.data(), bb.claw_count, count * 8, hipMemcpyDeviceToHost, gs[0]));
         BATCH_TRY(hipStreamSynchronize(gs[0]));
         walk_seconds += now_s() - tl;
+        if (stop && stop->launches) (*stop->launches)++;
+        // enumerated members whose last point is done: read out their candidates
+        bool formed = false;
+        for (int i = 0; i < count; ++i) {
+            BatchTarget& b = bt[i];
+            if (!b.walking || !b.wd.enumerate) continue;
+            if (stats[(size_t)i * tcw::ST_COUNT + tcw::ST_STEPS] >= b.budget) {
+                BATCH_TRY(tcw::launch_enum_pairs(b.wd, gs[0]));
+                formed = true;
+            }
+        }
+        if (formed) BATCH_TRY(hipMemcpyAsync(stats.data(), bb.stats, stats.size() * 8, hipMemcpyDeviceToHost, gs[0]));
+        BATCH_TRY(hipMemcpyAsync(ccount.data(), bb.claw_count, count * 8, hipMemcpyDeviceToHost, gs[0]));
+        BATCH_TRY(hipStreamSynchronize(gs[0]));
         for (int i = 0; i < count; ++i) {
             BatchTarget& b = bt[i];
             if (!b.walking) continue;
@@ -1541,29 +2157,26 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
                     u0[j] = pairs[2 * j];
                     u1[j] = pairs[2 * j + 1];
                 }
-                rc = check_pairs(c, *b.space, u0.data(), u1.data(), m, b.res, &found);
-                if (rc) {
-                    cleanup();
-                    return rc;
-                }
+                if (b.wd.enumerate) sort_pairs(u0.data(), u1.data(), m);
+                BATCH_RC(check_pairs(c, *b.space, u0.data(), u1.data(), m, b.res, &found));
                 b.seen = avail;
             }
-            const tcw_walk_stats ws = stats_of(st);
+            const tcw_walk_stats ws = stats_of(st, ccount[i], b.wd.claw_cap);
             const bool over_time = b.p.max_seconds > 0 && now_s() - t0 > b.p.max_seconds;
             if (found || over_time || b.used >= b.budget) {
                 add_stats(b.res->stats, ws);
                 b.walking = false;
                 dirty = true;
-                if (found || over_time) {
+                if (found) batch_on_hit(b);
+                if (over_time) {
                     b.done = true;
+                    b.cut = true;
+                }
+                if (b.done) {
                     b.res->seconds = now_s() - t0;
                     free_walk_buffers(b);
                 } else {
-                    rc = batch_advance(c, b, i, bb, gs[0], t0);
-                    if (rc) {
-                        cleanup();
-                        return rc;
-                    }
+                    BATCH_RC(batch_advance(c, b, i, bb, gs[0], t0, !found));
                     if (b.done) b.res->seconds = now_s() - t0;
                 }
             } else if (b.used_v >= b.per_version) {
@@ -1573,32 +2186,32 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
                 b.space->set_version(b.version);
                 b.used_v = 0;
                 b.seen = 0;
-                rc = batch_restart(c, b, i, bb, gs[0]);
-                if (rc) {
-                    cleanup();
-                    return rc;
-                }
+                BATCH_RC(batch_restart(c, b, i, bb, gs[0]));
             }
-            if (stop_on_first && b.res->status == 1) stop = true;
+            if (stop_on_first && b.res->status == TCW_STATUS_FOUND && b.done) stop_first = true;
         }
         BATCH_TRY(hipStreamSynchronize(gs[0]));
-        if (stop) {
-            // one member found a verified decomposition: end the others with their counts so far
-            for (int i = 0; i < count; ++i) {
-                BatchTarget& b = bt[i];
-                if (!b.walking) continue;
-                add_stats(b.res->stats, stats_of(&stats[(size_t)i * tcw::ST_COUNT]));
-                b.walking = false;
-                b.done = true;
-                b.res->seconds = now_s() - t0;
-            }
-            break;
+        if (stop_first) break;
+    }
+    if (stop_first || (stop && stop->stopped)) {
+        // end the members still running with their counts so far
+        for (int i = 0; i < count; ++i) {
+            BatchTarget& b = bt[i];
+            if (!b.walking) continue;
+            add_stats(b.res->stats, stats_of(&stats[(size_t)i * tcw::ST_COUNT], ccount[i], b.wd.claw_cap));
+            b.walking = false;
+            b.done = true;
+            b.res->seconds = now_s() - t0;
+            if (stop && stop->stopped) b.res->status = TCW_STATUS_STOPPED;
         }
     }
 #undef BATCH_TRY
+#undef BATCH_RC
     cleanup();
-    for (auto& b : bt)
+    for (auto& b : bt) {
         if (b.res->seconds == 0) b.res->seconds = now_s() - t0;
+        set_minimal(b.res);
+    }
     if (agg) *agg = walk_seconds > 0 ? (double)total_steps / walk_seconds : 0.0;
     return TCW_OK;
 }
@@ -1608,7 +2221,7 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
 namespace {
 
 int search_chunks_concurrent(tcw_ctx* c, const tcw_target* t, const tcw_walk_params* p, int k, int c_first,
-                             int c_last, int delta, tcw_result* res, int* found, double t0) {
+                             int c_last, int delta, tcw_result* res, int* found, bool* cut, StopCtl* stop, double t0) {
     const int n = t->n;
     const int G = c_last - c_first + 1;
     int lg_g = 0;
@@ -1626,13 +2239,14 @@ int search_chunks_concurrent(tcw_ctx* c, const tcw_target* t, const tcw_walk_par
         b.p.log2_table = log2_c;
         b.p.iters_per_launch = iters;
         b.p.delta = delta;
+        b.p.depth_order_kind = TCW_ORDER_PLAIN;
         b.p.chunk_first = b.p.chunk_last = c_first + i;
         b.order.assign(1, k);
         std::memset(&rs[i], 0, sizeof(tcw_result));
         rs[i].n = n;
         b.res = &rs[i];
     }
-    const int rc = batch_run(c, bt, true, t0, nullptr);
+    const int rc = batch_run(c, bt, true, t0, nullptr, stop);
     if (rc) return rc;
     int64_t launches = 0;
     for (int i = 0; i < G; ++i) {
@@ -1642,9 +2256,10 @@ int search_chunks_concurrent(tcw_ctx* c, const tcw_target* t, const tcw_walk_par
         res->versions += r.versions;
         res->false_claws += r.false_claws;
         launches = std::max(launches, r.launches);
-        if (r.status == 1 && !*found) {
+        *cut = *cut || bt[i].cut;
+        if (r.status == TCW_STATUS_FOUND && !*found) {
             *found = 1;
-            res->status = 1;
+            res->status = TCW_STATUS_FOUND;
             res->t = r.t;
             res->chunk = r.chunk;
             std::memcpy(res->paulis, r.paulis, sizeof(res->paulis));
@@ -1677,7 +2292,11 @@ extern "C" int tcw_search_batch(tcw_ctx* c, const tcw_target* const* targets, in
         if (!rc) rc = depth_order_of(c, &b.p, b.order);
     }
     if (rc) return rc;
-    return batch_run(c, bt, false, t0, aggregate_steps_per_s);
+    StopCtl stop;
+    stop.flag = &c->stop_req;
+    rc = batch_run(c, bt, false, t0, aggregate_steps_per_s, &stop);
+    if (stop.stopped) c->stop_req.store(0);
+    return rc;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -2001,7 +2620,7 @@ int build_level_table(tcw_ctx* c, int n, int h_max, uint64_t seed, LevelTable& l
     lt.lg = 10;
     while ((1ull << lt.lg) < 4 * entries && lt.lg < 30) ++lt.lg;
     HIP_TRY(c, hipMalloc(&lt.table, ((size_t)1 << lt.lg) * 16));
-    HIP_TRY(c, tcw::launch_table_clear(lt.table, lt.lg, c->stream));
+    HIP_TRY(c, tcw::launch_table_clear(lt.table, lt.lg, 0, c->stream));
     lt.sp.delta = 0;
     lt.sp.salt_h = tcw::sm64(tcw::sm64(seed, 2), 0x4C4142454Cull);
     lt.sp.keys = lt.keys;

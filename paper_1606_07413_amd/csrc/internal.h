@@ -27,6 +27,11 @@ struct SpaceDev {
 
 enum : uint32_t { MODE_WALK = 0, MODE_ALIGN = 1, MODE_LOCK = 2, MODE_DONE = 3 };
 
+// Enumeration tables keep, per key, the least x of side 0 and of side 1 in the low and high halves of
+// the value; ENUM_NONE marks a side that has not reached the key (x < xi^h < 2^32 - 1).
+constexpr uint32_t ENUM_NONE = 0xffffffffu;
+constexpr uint64_t ENUM_TABLE_INIT = ~0ull;
+
 // 64-byte walk state, kept in HBM between launches.
 struct WalkState {
     uint64_t start;  // start point of the current trail
@@ -130,7 +135,11 @@ hipError_t launch_walk_init(const SpaceDev& sp, const WalkDev& wd, hipStream_t s
 hipError_t launch_walk_batch(int n, const SpaceDev* sps, const WalkDev* wds, const int32_t* blk_target,
                              const int32_t* tgt_first, const int32_t* tgt_blocks, int blocks, int iters, hipStream_t s);
 int walks_per_block(int n);
-hipError_t launch_table_clear(uint64_t* table, int log2_table, hipStream_t s);
+// value: what every slot's value word starts at (0 for walk tables: "not ready"; ENUM_TABLE_INIT for
+// enumeration tables: no x on either side)
+hipError_t launch_table_clear(uint64_t* table, int log2_table, uint64_t value, hipStream_t s);
+// enumeration mode, after the last point: one claw candidate per key reached from both sides
+hipError_t launch_enum_pairs(const WalkDev& wd, hipStream_t s);
 int walk_grid_blocks(int n, int device);
 hipError_t pack_phi_i32(int n, const int32_t* a, const int32_t* b, int64_t count, uint32_t* phi_out,
                         int* flag_dev, hipStream_t s);

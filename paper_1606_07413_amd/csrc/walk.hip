@@ -883,42 +883,22 @@ __device__ void walk_block(const SpaceDev& sp, const WalkDev& wd, int iters, Lds
             c_steps++;
             bool restart = false;
             if (mode == MODE_WALK && wd.enumerate) {
-                // exhaustive mode: every point once, the table keyed by its full matrix hash, so two
-                // points meet exactly when their cosets (or 64-bit hashes) coincide
+                // exhaustive mode: every point once, the table keyed by its full matrix hash and holding,
+                // in the two 32-bit halves of the value, the least x of each side that reached the key (a
+                // 32-bit atomic minimum, so no ordering between writers is needed).  The pairs are read
+                // out after the last point (k_enum_pairs): which pairs are reported does not depend on
+                // the order in which walks arrive.
                 c_dps++;
                 const uint64_t key = H == EMPTY_KEY ? (H ^ 1) : H;
-                int kind = 0;
-                uint64_t slot = 0, other = 0;
-                if (leader) kind = table_claim(wd, key, slot);
-                if (leader && kind == 1)
-                    __hip_atomic_store(&wd.table[2 * slot + 1], pack_value(st.start, 1), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                if (leader && kind == 2) {
-                    int spin = 0;
-                    do {
-                        other = __hip_atomic_load(&wd.table[2 * slot + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    } while (other == 0 && ++spin < (1 << 20));
-                    if (other == 0) kind = 4;
-                }
                 if (leader) {
-                    if (kind == 1) {
-                        c_ins++;
-                    } else if (kind == 3) {
+                    uint64_t slot = 0;
+                    const int kind = table_claim(wd, key, slot);
+                    if (kind == 3) {
                         c_full++;
-                    } else if (kind == 4) {
-                        c_spin++;
                     } else {
-                        const uint64_t ostart = other & 0x1ffffffffull;
-                        if (((ostart >> 32) & 1) == ((st.start >> 32) & 1)) {
-                            c_same++;
-                        } else {
-                            c_claw++;
-                            const unsigned long long idx = atomicAdd(wd.claw_count, 1ull);
-                            if (idx < wd.claw_cap) {
-                                wd.claws[2 * idx] = ostart;
-                                wd.claws[2 * idx + 1] = st.start;
-                            }
-                        }
+                        if (kind == 1) c_ins++;
+                        uint32_t* half = reinterpret_cast<uint32_t*>(&wd.table[2 * slot + 1]) + ((arg >> 32) & 1);
+                        atomicMin(half, (uint32_t)arg);
                     }
                 }
                 restart = true;
@@ -1110,12 +1090,33 @@ __global__ void k_walk_init(SpaceDev sp, WalkDev wd) {
     }
 }
 
-__global__ void k_table_clear(uint64_t* table, uint64_t slots) {
+__global__ void k_table_clear(uint64_t* table, uint64_t slots, uint64_t value) {
     for (uint64_t i = threadIdx.x + (uint64_t)blockIdx.x * blockDim.x; i < slots;
          i += (uint64_t)blockDim.x * gridDim.x) {
         table[2 * i] = EMPTY_KEY;
-        table[2 * i + 1] = 0;
+        table[2 * i + 1] = value;
     }
+}
+
+// After an exhaustive pass (enumeration mode): every key reached from both sides gives one
+// candidate, the least x of side 0 against the least x of side 1.
+__global__ void k_enum_pairs(WalkDev wd) {
+    const uint64_t slots = 1ull << wd.log2_table;
+    unsigned long long found = 0;
+    for (uint64_t i = threadIdx.x + (uint64_t)blockIdx.x * blockDim.x; i < slots;
+         i += (uint64_t)blockDim.x * gridDim.x) {
+        if (wd.table[2 * i] == EMPTY_KEY) continue;
+        const uint64_t v = wd.table[2 * i + 1];
+        const uint32_t x0 = (uint32_t)v, x1 = (uint32_t)(v >> 32);
+        if (x0 == ENUM_NONE || x1 == ENUM_NONE) continue;
+        ++found;
+        const unsigned long long idx = atomicAdd(wd.claw_count, 1ull);
+        if (idx < wd.claw_cap) {
+            wd.claws[2 * idx] = (uint64_t)x0;
+            wd.claws[2 * idx + 1] = (uint64_t)x1 | (1ull << 32);
+        }
+    }
+    if (found) atomicAdd(&wd.stats[ST_CLAWS], found);
 }
 
 // ---- meet-in-the-middle labels for the depth-order network ----
@@ -1347,11 +1348,19 @@ hipError_t launch_walk_init(const SpaceDev& sp, const WalkDev& wd, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_table_clear(uint64_t* table, int log2_table, hipStream_t s) {
+hipError_t launch_table_clear(uint64_t* table, int log2_table, uint64_t value, hipStream_t s) {
     const uint64_t slots = 1ull << log2_table;
     uint64_t blocks = (slots + 255) / 256;
     if (blocks > 65535) blocks = 65535;
-    hipLaunchKernelGGL(k_table_clear, dim3((unsigned)blocks), dim3(256), 0, s, table, slots);
+    hipLaunchKernelGGL(k_table_clear, dim3((unsigned)blocks), dim3(256), 0, s, table, slots, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_enum_pairs(const WalkDev& wd, hipStream_t s) {
+    const uint64_t slots = 1ull << wd.log2_table;
+    uint64_t blocks = (slots + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_enum_pairs, dim3((unsigned)blocks), dim3(256), 0, s, wd);
     return hipGetLastError();
 }
 

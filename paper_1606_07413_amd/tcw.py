@@ -23,6 +23,11 @@ MAX_T = 64
 MAX_R = 256
 ORDER_PLAIN = 0
 ORDER_GIVEN = 1
+ORDER_GIVEN_FIRST = 2
+STATUS_NOT_FOUND = 0
+STATUS_FOUND = 1
+STATUS_STOPPED = 2
+MAX_TRAIL_CAP = (1 << 30) - 1
 
 
 class TcwError(RuntimeError):
@@ -38,7 +43,8 @@ class Space(C.Structure):
 
 class WalkStats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("steps", "dps", "inserts", "abandoned", "robin_hood", "same_side",
-                                          "reduction", "claws", "table_full", "spin_timeouts", "active_walks")]
+                                          "reduction", "claws", "table_full", "spin_timeouts", "active_walks",
+                                          "claws_dropped")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -51,7 +57,7 @@ class WalkParams(C.Structure):
         ("budget_beta", C.c_int32), ("version_factor", C.c_int32), ("enum_max", C.c_int64),
         ("iters_per_launch", C.c_int32), ("depth_order_kind", C.c_int32), ("depth_order_len", C.c_int32),
         ("depth_order", C.c_int32 * 16), ("chunk_first", C.c_int32), ("chunk_last", C.c_int32),
-        ("max_seconds", C.c_double), ("chunk_parallel", C.c_int32),
+        ("max_seconds", C.c_double), ("chunk_parallel", C.c_int32), ("launch_limit", C.c_int64),
     ]
 
 
@@ -67,7 +73,8 @@ class Result(C.Structure):
         ("status", C.c_int32), ("t", C.c_int32), ("n", C.c_int32), ("chunk", C.c_int32),
         ("paulis", C.c_uint16 * MAX_T), ("clifford_perm", C.c_int32 * MAX_R), ("clifford_sign", C.c_int8 * MAX_R),
         ("stats", WalkStats), ("spaces", C.c_int64), ("versions", C.c_int64), ("launches", C.c_int64),
-        ("false_claws", C.c_int64), ("seconds", C.c_double),
+        ("false_claws", C.c_int64), ("seconds", C.c_double), ("failed_depths", C.c_uint64),
+        ("minimal", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -82,6 +89,8 @@ _SIGS = {
     "tcw_target_from_channel": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
                                           C.POINTER(_P)]),
     "tcw_target_from_unitary": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int64), C.c_int32, C.POINTER(_P)]),
+    "tcw_target_random": (C.c_int, [_P, C.c_int, C.c_int, C.c_uint64, C.POINTER(_P), C.POINTER(C.c_uint16),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_int8)]),
     "tcw_target_free": (C.c_int, [_P]),
     "tcw_target_channel": (C.c_int, [_P, _P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "tcw_target_n": (C.c_int, [_P]),
@@ -105,6 +114,9 @@ _SIGS = {
     "tcw_walk_end": (C.c_int, [_P]),
     "tcw_default_params": (None, [C.POINTER(WalkParams), C.c_int]),
     "tcw_search": (C.c_int, [_P, _P, C.POINTER(WalkParams), C.POINTER(Result)]),
+    "tcw_search_stop": (C.c_int, [_P]),
+    "tcw_checkpoint": (C.c_int, [_P, _P, C.POINTER(C.c_size_t)]),
+    "tcw_resume": (C.c_int, [_P, _P, _P, C.c_size_t, C.c_int64, C.POINTER(Result)]),
     "tcw_search_batch": (C.c_int, [_P, C.POINTER(_P), C.c_int, C.POINTER(WalkParams), C.POINTER(Result),
                                    C.POINTER(C.c_double)]),
     "tcw_autotune": (C.c_int, [_P, _P, C.c_int, C.c_int, C.c_int, C.c_uint64, C.POINTER(C.c_int64),
@@ -242,6 +254,16 @@ class Context:
                                                      C.byref(out)))
         return Target(self, out, n)
 
+    def target_random(self, n: int, k: int, seed: int):
+        """Seeded synthetic target; returns (Target, [P_1..P_k], perm, sign) with D P_q D^dag = sign[q] P_perm[q]."""
+        r = 4 ** n
+        out = _P()
+        ps = (C.c_uint16 * max(1, k))()
+        perm = (C.c_int32 * r)()
+        sign = (C.c_int8 * r)()
+        self._check(self.lib.tcw_target_random(self.h, n, k, seed, C.byref(out), ps, perm, sign))
+        return Target(self, out, n), list(ps[:k]), list(perm), list(sign)
+
     def min_tcount(self, target, h_max: int, seed: int = 1) -> int:
         """Minimal T-count by meet in the middle when it is at most 2 h_max, else -1."""
         out = C.c_int32(0)
@@ -297,6 +319,23 @@ class Context:
     def search(self, target, params: WalkParams) -> Result:
         res = Result()
         self._check(self.lib.tcw_search(self.h, target.h, C.byref(params), C.byref(res)))
+        return res
+
+    def search_stop(self):
+        self._check(self.lib.tcw_search_stop(self.h))
+
+    def checkpoint(self) -> bytes:
+        """The stopped search of this context, serialised (host bytes)."""
+        n = C.c_size_t(0)
+        self._check(self.lib.tcw_checkpoint(self.h, None, C.byref(n)))
+        buf = (C.c_uint8 * max(1, n.value))()
+        self._check(self.lib.tcw_checkpoint(self.h, buf, C.byref(n)))
+        return bytes(buf[:n.value])
+
+    def resume(self, target, blob: bytes, launch_limit: int = 0) -> Result:
+        res = Result()
+        buf = (C.c_uint8 * max(1, len(blob))).from_buffer_copy(blob if blob else b"\0")
+        self._check(self.lib.tcw_resume(self.h, target.h, buf, len(blob), launch_limit, C.byref(res)))
         return res
 
 

@@ -24,19 +24,25 @@ def test_peaks_are_the_published_ones():
     assert bench.HBM_PEAK_BYTES == 8.0e12
 
 
-def test_traffic_summary_matches_the_sources(tmp_path, monkeypatch):
-    # the committed summary: fetch x scale + write, per launch of 2^20 walks x 8 steps
-    got = bench.measured_traffic(1 << 20, 8)
-    assert got is not None and 1.6e10 < got < 1.8e10
-    # another launch shape is not covered by it
-    assert bench.measured_traffic(1 << 19, 8) is None
-    # a changed kernel source no longer matches the recorded digest
-    for p in bench.WALK_KERNEL_SOURCES + (bench.TRAFFIC_SUMMARY, "paper_1606_07413_amd/build.py",
-                                            "paper_1606_07413_amd/__init__.py"):
+def test_traffic_summary_reading(tmp_path, monkeypatch):
+    """bench.measured_traffic reads a summary written for the current kernel sources and launch shape
+    (fetch x scale + write, per launch) and gives None for another shape or for changed sources."""
+    for p in bench.WALK_KERNEL_SOURCES + ("paper_1606_07413_amd/build.py", "paper_1606_07413_amd/__init__.py"):
         dst = tmp_path / p
         dst.parent.mkdir(parents=True, exist_ok=True)
         shutil.copy(os.path.join(bench.ROOT, p), dst)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    summary = tmp_path / bench.TRAFFIC_SUMMARY
+    summary.parent.mkdir(parents=True, exist_ok=True)
+    summary.write_text("# traffic\n\n"
+                       f"- source_sha256: {bench.kernel_source_digest()}\n"
+                       "- walks: 1048576\n- iters_per_launch: 8\n"
+                       "- fetch_kib_per_launch: 1000.0\n- fetch_scale: 2.0\n"
+                       "- write_kib_per_launch: 24.0\n- write_scale: 1.0\n")
+    assert bench.measured_traffic(1 << 20, 8) == pytest.approx(2024.0 * 1024)
+    # another launch shape is not covered by it
+    assert bench.measured_traffic(1 << 19, 8) is None
+    # a changed kernel source no longer matches the recorded digest
     with open(tmp_path / bench.WALK_KERNEL_SOURCES[0], "a") as f:
         f.write("\n// changed\n")
-    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.measured_traffic(1 << 20, 8) is None
