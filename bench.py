@@ -327,6 +327,7 @@ def tts_n4_leg(ctx, cap: float, slice_s: float = 60.0, seeds=(1, 2, 3, 4)):
     of at most slice_s seconds, each starting a fresh range of function versions (a version starts
     from an empty table anyway), until a verified decomposition or the cap."""
     import seeded_inputs
+    from paper_1606_07413_amd import tcw
     runs = []
     for ts in seeds:
         twn = seeded_inputs.target_words(4, 7, ts)
@@ -342,7 +343,7 @@ def tts_n4_leg(ctx, cap: float, slice_s: float = 60.0, seeds=(1, 2, 3, 4)):
             p4.chunk_parallel = 0
             p4.max_seconds = seconds
             if only is not None:
-                p4.depth_order_kind = 1
+                p4.depth_order_kind = tcw.ORDER_GIVEN_FIRST
                 p4.depth_order_len = 1
                 p4.depth_order[0] = only
             return p4
@@ -372,6 +373,7 @@ def tts_n4_planted_leg(ctx, cap: float, slice_s: float = 120.0, seeds=(2, 3, 4))
     accepts a decomposition, in calls of at most slice_s seconds (each a fresh range of function
     versions) with a line of progress after each, until the cap."""
     import seeded_inputs
+    from paper_1606_07413_amd import tcw
     runs = []
     for ts in seeds:
         twn = seeded_inputs.target_words(4, 7, ts)
@@ -388,7 +390,7 @@ def tts_n4_planted_leg(ctx, cap: float, slice_s: float = 120.0, seeds=(2, 3, 4))
             p4.seed = 3200 + ts
             p4.version = slices << 20
             p4.chunk_first = p4.chunk_last = chunk
-            p4.depth_order_kind = 1
+            p4.depth_order_kind = tcw.ORDER_GIVEN_FIRST
             p4.depth_order_len = 1
             p4.depth_order[0] = 7
             p4.max_seconds = max(1e-3, min(slice_s, cap - (time.perf_counter() - t0)))

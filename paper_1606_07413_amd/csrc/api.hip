@@ -19,14 +19,6 @@
 #include "common.h"
 #include "internal.h"
 
-namespace tcw {
-// Depth-order network, weight gradient (mlp.hip): dW = H^T G (H: K x M, G: K x N, both bf16
-// row-major; dW: M x N fp32) with the batch K split over workgroups when that fills the GPU better;
-// `part` (mlp_dw_part_floats(M, N, K) floats, or null) holds the partial tiles, added in a fixed order.
-size_t mlp_dw_part_floats(int M, int N, int K);
-hipError_t mlp_gemm_dw(const void* H, const void* G, int M, int N, int K, float* dW, float* part, size_t part_floats,
-                       hipStream_t s);
-}  // namespace tcw
 
 struct TunedCfg {
     int64_t walks = 0;
@@ -148,6 +140,14 @@ int read_flag(tcw_ctx* c, int* out) {
     return TCW_OK;
 }
 
+// Salts of the matrix hash, the distinguished-point test and the trail starts of a space.
+void space_salts(tcw::SpaceDev& dev, uint64_t seed, uint32_t version, int k, int chunk) {
+    const uint64_t ctxi = ((uint64_t)version << 16) | ((uint64_t)k << 8) | (uint64_t)chunk;
+    dev.salt_h = tcw::sm64(tcw::sm64(seed, 2), ctxi);
+    dev.salt_d = tcw::sm64(tcw::sm64(seed, 3), ctxi);
+    dev.salt_s = tcw::sm64(tcw::sm64(seed, 4), ctxi);
+}
+
 // A prepared search space: S_c on the device (exact and int8-packed), keys, salts.
 struct Space {
     tcw_ctx* ctx = nullptr;
@@ -169,10 +169,7 @@ struct Space {
 
     void set_version(uint32_t v) {
         version = v;
-        const uint64_t ctxi = ((uint64_t)v << 16) | ((uint64_t)k << 8) | (uint64_t)chunk;
-        dev.salt_h = tcw::sm64(tcw::sm64(seed, 2), ctxi);
-        dev.salt_d = tcw::sm64(tcw::sm64(seed, 3), ctxi);
-        dev.salt_s = tcw::sm64(tcw::sm64(seed, 4), ctxi);
+        space_salts(dev, seed, v, k, chunk);
     }
 };
 
@@ -1363,6 +1360,15 @@ int run_search(tcw_ctx* c, SearchRun* s, tcw_result* res) {
     if (stop.stopped && !s->finished) {
         s->elapsed += now_s() - t0;
         *res = s->res;
+        if (s->w) {
+            // the open space's counters so far (kept out of s->res, which adds them when the space ends)
+            tcw_walk_stats st{};
+            if ((rc = tcw_walk_stats_get(s->w, &st))) {
+                delete s;
+                return rc;
+            }
+            add_stats(res->stats, st);
+        }
         res->status = TCW_STATUS_STOPPED;
         res->minimal = 0;
         res->seconds = s->elapsed;
@@ -2308,119 +2314,143 @@ struct tcw_mlp {
     std::vector<int64_t> w_off, b_off;
     int64_t count = 0;
     float *P = nullptr, *G = nullptr, *M = nullptr, *V = nullptr;
-    std::vector<void*> Wb;
+    std::vector<void*> Wb, Wt;  // bf16 weights: W_l (in x out) and W_l^T (out x in)
     int step = 0;
     int cap_b = 0;
-    void* Xb = nullptr;
+    void *Xb = nullptr, *Xt = nullptr;
     std::vector<float*> Z, Gf;
-    std::vector<void*> Hb, Gb;
+    std::vector<void*> Hb, Ht, Gb, Gt;
     float *logits = nullptr, *probs = nullptr, *loss = nullptr, *xdev = nullptr;
-    float* dw_part = nullptr;  // partial weight-gradient tiles of the batch split
-    size_t dw_part_floats = 0;
+    float* part = nullptr;  // partial products of the GEMMs whose K is split over workgroups
+    size_t part_floats = 0;
 
     void free_batch() {
-        for (void* q : {Xb, (void*)logits, (void*)probs, (void*)dw_part})
+        for (void* q : {Xb, Xt, (void*)logits, (void*)probs, (void*)part})
             if (q) (void)hipFree(q);
-        dw_part = nullptr;
-        dw_part_floats = 0;
-        for (auto* q : Z)
-            if (q) (void)hipFree(q);
-        for (auto* q : Gf)
-            if (q) (void)hipFree(q);
-        for (auto* q : Hb)
-            if (q) (void)hipFree(q);
-        for (auto* q : Gb)
-            if (q) (void)hipFree(q);
-        Xb = nullptr;
+        Xb = Xt = nullptr;
+        part = nullptr;
+        part_floats = 0;
+        for (auto* v : {&Hb, &Ht, &Gb, &Gt}) {
+            for (void* q : *v)
+                if (q) (void)hipFree(q);
+            v->clear();
+        }
+        for (auto* v : {&Z, &Gf}) {
+            for (float* q : *v)
+                if (q) (void)hipFree(q);
+            v->clear();
+        }
         logits = probs = nullptr;
-        Z.clear();
-        Gf.clear();
-        Hb.clear();
-        Gb.clear();
         cap_b = 0;
     }
     ~tcw_mlp() {
         free_batch();
         for (void* q : {(void*)P, (void*)G, (void*)M, (void*)V, (void*)loss, (void*)xdev})
             if (q) (void)hipFree(q);
-        for (auto* q : Wb)
-            if (q) (void)hipFree(q);
+        for (auto* v : {&Wb, &Wt})
+            for (void* q : *v)
+                if (q) (void)hipFree(q);
     }
 };
 
 namespace {
 
+// leading dimension of a bf16 buffer: a multiple of 8 elements, so every row starts 16-byte aligned
+int ld8(int cols) { return (cols + 7) / 8 * 8; }
+
 int mlp_ensure_batch(tcw_mlp* m, int b) {
     tcw_ctx* c = m->ctx;
     if (b <= m->cap_b) return TCW_OK;
     m->free_batch();
-    HIP_TRY(c, hipMalloc(&m->Xb, (size_t)b * m->inp * 2));
+    const size_t b8 = (size_t)ld8(b);
+    HIP_TRY(c, hipMalloc(&m->Xb, (size_t)b * ld8(m->inp) * 2));
+    HIP_TRY(c, hipMalloc(&m->Xt, (size_t)m->inp * b8 * 2));
     m->Z.assign(m->depth, nullptr);
     m->Hb.assign(m->depth, nullptr);
+    m->Ht.assign(m->depth, nullptr);
     m->Gf.assign(m->L, nullptr);
     m->Gb.assign(m->L, nullptr);
+    m->Gt.assign(m->L, nullptr);
     for (int l = 0; l < m->depth; ++l) {
         HIP_TRY(c, hipMalloc(&m->Z[l], (size_t)b * m->hidden * 4));
-        HIP_TRY(c, hipMalloc(&m->Hb[l], (size_t)b * m->hidden * 2));
+        HIP_TRY(c, hipMalloc(&m->Hb[l], (size_t)b * ld8(m->hidden) * 2));
+        HIP_TRY(c, hipMalloc(&m->Ht[l], (size_t)m->hidden * b8 * 2));
     }
     for (int l = 0; l < m->L; ++l) {
-        HIP_TRY(c, hipMalloc(&m->Gf[l], (size_t)b * m->sz[l + 1] * 4));
-        HIP_TRY(c, hipMalloc(&m->Gb[l], (size_t)b * m->sz[l + 1] * 2));
+        const int out = m->sz[l + 1];
+        HIP_TRY(c, hipMalloc(&m->Gf[l], (size_t)b * out * 4));
+        HIP_TRY(c, hipMalloc(&m->Gb[l], (size_t)b * ld8(out) * 2));
+        HIP_TRY(c, hipMalloc(&m->Gt[l], (size_t)out * b8 * 2));
     }
     HIP_TRY(c, hipMalloc(&m->logits, (size_t)b * m->classes * 4));
     HIP_TRY(c, hipMalloc(&m->probs, (size_t)b * m->classes * 4));
+    // workspace of the split products: forward (b x out, K = in), dX (b x in, K = out), dW (in x out, K = b)
     size_t part = 0;
-    for (int l = 0; l < m->L; ++l) part = std::max(part, tcw::mlp_dw_part_floats(m->sz[l], m->sz[l + 1], b));
+    for (int l = 0; l < m->L; ++l) {
+        const int in = m->sz[l], out = m->sz[l + 1];
+        part = std::max({part, tcw::mlp_gemm_part_floats(b, out, in), tcw::mlp_gemm_part_floats(b, in, out),
+                         tcw::mlp_gemm_part_floats(in, out, b)});
+    }
     if (part > 0) {
-        HIP_TRY(c, hipMalloc(&m->dw_part, part * 4));
-        m->dw_part_floats = part;
+        HIP_TRY(c, hipMalloc(&m->part, part * 4));
+        m->part_floats = part;
     }
     m->cap_b = b;
     return TCW_OK;
 }
 
+// bf16 copies of the weights in both orientations, from the FP32 masters
 int mlp_sync_bf16(tcw_mlp* m) {
     for (int l = 0; l < m->L; ++l)
-        HIP_TRY(m->ctx, tcw::mlp_to_bf16(m->P + m->w_off[l], m->Wb[l], (int64_t)m->sz[l] * m->sz[l + 1], m->ctx->stream));
+        HIP_TRY(m->ctx, tcw::mlp_weights_bf16(m->P + m->w_off[l], m->sz[l], m->sz[l + 1], m->Wb[l], ld8(m->sz[l + 1]),
+                                              m->Wt[l], ld8(m->sz[l]), m->ctx->stream));
     return TCW_OK;
 }
 
-// forward over a batch; with labels also the loss sum and the output-layer gradient
+// forward over a batch; with labels (training) also the transposed activations, the loss sum and the
+// output-layer gradient
 int mlp_forward(tcw_mlp* m, const float* x, int b, const int32_t* labels) {
     tcw_ctx* c = m->ctx;
     int rc = mlp_ensure_batch(m, b);
     if (rc) return rc;
-    HIP_TRY(c, tcw::mlp_to_bf16(x, m->Xb, (int64_t)b * m->inp, c->stream));
+    const bool train = labels != nullptr;
+    const int b8 = ld8(b);
+    HIP_TRY(c, tcw::mlp_input_bf16(x, b, m->inp, m->Xb, ld8(m->inp), train ? m->Xt : nullptr, b8, c->stream));
     for (int l = 0; l < m->L; ++l) {
         const void* A = l == 0 ? m->Xb : m->Hb[l - 1];
         const int K = m->sz[l], N = m->sz[l + 1];
         if (l < m->L - 1) {
-            HIP_TRY(c, tcw::mlp_gemm(1, A, m->Wb[l], b, N, K, K, N, m->Z[l], N, m->P + m->b_off[l], nullptr, m->Hb[l],
-                                     c->stream));
+            HIP_TRY(c, tcw::mlp_gemm_nt(2, A, ld8(K), m->Wt[l], ld8(K), b, N, K, m->Z[l], N, m->P + m->b_off[l], nullptr,
+                                        0, m->Hb[l], ld8(N), train ? m->Ht[l] : nullptr, b8, m->part, m->part_floats,
+                                        c->stream));
         } else {
-            HIP_TRY(c, tcw::mlp_gemm(2, A, m->Wb[l], b, N, K, K, N, m->logits, N, m->P + m->b_off[l], nullptr, nullptr,
-                                     c->stream));
+            HIP_TRY(c, tcw::mlp_gemm_nt(1, A, ld8(K), m->Wt[l], ld8(K), b, N, K, m->logits, N, m->P + m->b_off[l],
+                                        nullptr, 0, nullptr, 0, nullptr, 0, m->part, m->part_floats, c->stream));
         }
     }
-    if (labels) HIP_TRY(c, hipMemsetAsync(m->loss, 0, 4, c->stream));
-    HIP_TRY(c, tcw::mlp_softmax_ce(m->logits, labels, b, m->classes, m->probs, labels ? m->Gf[m->L - 1] : nullptr,
-                                   labels ? m->Gb[m->L - 1] : nullptr, labels ? m->loss : nullptr, c->stream));
+    if (train) HIP_TRY(c, hipMemsetAsync(m->loss, 0, 4, c->stream));
+    const int lo = m->L - 1;
+    HIP_TRY(c, tcw::mlp_softmax_ce(m->logits, labels, b, m->classes, m->probs, train ? m->Gf[lo] : nullptr,
+                                   train ? m->Gb[lo] : nullptr, ld8(m->classes), train ? m->Gt[lo] : nullptr, b8,
+                                   train ? m->loss : nullptr, c->stream));
     return TCW_OK;
 }
 
 int mlp_backward(tcw_mlp* m, int b) {
     tcw_ctx* c = m->ctx;
+    const int b8 = ld8(b);
     for (int l = m->L - 1; l >= 0; --l) {
-        const void* Hin = l == 0 ? m->Xb : m->Hb[l - 1];
+        const void* Hin_t = l == 0 ? m->Xt : m->Ht[l - 1];
         const int in = m->sz[l], out = m->sz[l + 1];
-        // dW_l = H_in^T G_l
-        HIP_TRY(c, tcw::mlp_gemm_dw(Hin, m->Gb[l], in, out, b, m->G + m->w_off[l], m->dw_part, m->dw_part_floats,
-                                    c->stream));
+        // dW_l = H_in^T G_l: rows of H_in^T and of G_l^T run over the batch
+        HIP_TRY(c, tcw::mlp_gemm_nt(0, Hin_t, b8, m->Gt[l], b8, in, out, b, m->G + m->w_off[l], out, nullptr, nullptr,
+                                    0, nullptr, 0, nullptr, 0, m->part, m->part_floats, c->stream));
         HIP_TRY(c, tcw::mlp_colsum(m->Gf[l], b, out, m->G + m->b_off[l], c->stream));
         if (l > 0) {
-            // G_{l-1} = (G_l W_l^T) * gelu'(Z_{l-1})
-            HIP_TRY(c, tcw::mlp_gemm(4, m->Gb[l], m->Wb[l], b, in, out, out, out, m->Gf[l - 1], in, nullptr, m->Z[l - 1],
-                                     m->Gb[l - 1], c->stream));
+            // G_{l-1} = (G_l W_l^T) * gelu'(Z_{l-1}): B = W_l (in x out), rows over out
+            HIP_TRY(c, tcw::mlp_gemm_nt(3, m->Gb[l], ld8(out), m->Wb[l], ld8(out), b, in, out, m->Gf[l - 1], in,
+                                        nullptr, m->Z[l - 1], in, m->Gb[l - 1], ld8(in), m->Gt[l - 1], b8, m->part,
+                                        m->part_floats, c->stream));
         }
     }
     return TCW_OK;
@@ -2462,7 +2492,11 @@ extern "C" int tcw_mlp_create(tcw_ctx* c, int inp, int hidden, int depth, int cl
     if (e == hipSuccess) e = hipMalloc(&m->loss, 4);
     if (e != hipSuccess) return bail(e);
     m->Wb.assign(m->L, nullptr);
-    for (int l = 0; l < m->L && e == hipSuccess; ++l) e = hipMalloc(&m->Wb[l], (size_t)m->sz[l] * m->sz[l + 1] * 2);
+    m->Wt.assign(m->L, nullptr);
+    for (int l = 0; l < m->L && e == hipSuccess; ++l) {
+        e = hipMalloc(&m->Wb[l], (size_t)m->sz[l] * ld8(m->sz[l + 1]) * 2);
+        if (e == hipSuccess) e = hipMalloc(&m->Wt[l], (size_t)m->sz[l + 1] * ld8(m->sz[l]) * 2);
+    }
     if (e == hipSuccess) e = hipMemsetAsync(m->M, 0, off * 4, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(m->V, 0, off * 4, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(m->P, 0, off * 4, c->stream);

@@ -638,6 +638,16 @@ void scratch_free(ScratchPair& sp) {
 }
 }  // namespace
 
+hipError_t exact_apply_ws(ExactDev& dst, const ExactDev& src, const uint16_t* seq, const uint8_t* tr, int nseq,
+                          void* ta, void* tb, int* flag, hipStream_t s) {
+    auto f = [&]<int NQ, typename T>() -> hipError_t {
+        hipLaunchKernelGGL((k_apply<NQ, T>), dim3(1), dim3(1024), 0, s, (T*)dst.a, (T*)dst.b, (T*)ta, (T*)tb, dst.e,
+                           (const T*)src.a, (const T*)src.b, src.e, seq, tr, nseq, flag);
+        return hipGetLastError();
+    };
+    return dispatch_exact(dst.n, f);
+}
+
 hipError_t exact_apply(ExactDev& dst, const ExactDev& src, const uint16_t* seq, const uint8_t* tr, int nseq,
                        int* flag, hipStream_t s) {
     ScratchPair sp;
@@ -646,16 +656,12 @@ hipError_t exact_apply(ExactDev& dst, const ExactDev& src, const uint16_t* seq, 
         scratch_free(sp);
         return err;
     }
-    auto f = [&]<int NQ, typename T>() -> hipError_t {
-        hipLaunchKernelGGL((k_apply<NQ, T>), dim3(1), dim3(1024), 0, s, (T*)dst.a, (T*)dst.b, (T*)sp.ta, (T*)sp.tb,
-                           dst.e, (const T*)src.a, (const T*)src.b, src.e, seq, tr, nseq, flag);
-        return hipGetLastError();
-    };
-    err = dispatch_exact(dst.n, f);
+    err = exact_apply_ws(dst, src, seq, tr, nseq, sp.ta, sp.tb, flag, s);
     if (err == hipSuccess) err = hipStreamSynchronize(s);
     scratch_free(sp);
     return err;
 }
+
 
 hipError_t exact_build(ExactDev& m, const uint16_t* seq, const uint8_t* tr, int nseq, int* flag, hipStream_t s) {
     auto f = [&]<int NQ, typename T>() -> hipError_t {

@@ -85,6 +85,10 @@ hipError_t exact_build(ExactDev& m, const uint16_t* seq_dev, const uint8_t* tran
 // dst = src * R(seq[0])^(T?) * ... , reduced; dst and src may alias.
 hipError_t exact_apply(ExactDev& dst, const ExactDev& src, const uint16_t* seq_dev, const uint8_t* transpose_dev,
                        int nseq, int* flag_dev, hipStream_t s);
+// as exact_apply, with the two R x R work matrices given (ta, tb) instead of allocated, and no
+// synchronisation
+hipError_t exact_apply_ws(ExactDev& dst, const ExactDev& src, const uint16_t* seq, const uint8_t* tr, int nseq,
+                          void* ta, void* tb, int* flag, hipStream_t s);
 // load int32 host-provided values already on the device
 hipError_t exact_from_i32(ExactDev& m, const int32_t* a_dev, const int32_t* b_dev, int32_t e, int* flag_dev,
                           hipStream_t s);
@@ -145,14 +149,25 @@ hipError_t pack_phi_i32(int n, const int32_t* a, const int32_t* b, int64_t count
                         int* flag_dev, hipStream_t s);
 
 // ---- depth-order network (mlp.hip) ----
-// mode: 0 plain, 1 bias+gelu (C = Z, H = gelu bf16), 2 bias, 3 A transposed, 4 B transposed with
-// gelu'(Z) (C fp32 and H bf16), 5 B transposed, 6 both transposed
-hipError_t mlp_gemm(int mode, const void* A, const void* B, int M, int N, int K, int lda, int ldb, float* C, int ldc,
-                    const float* bias, const float* Z, void* H, hipStream_t s);
+// C = A B^T: A (M x K) and B (N x K) bf16 with K-contiguous rows (leading dimensions multiples of 8),
+// FP32 accumulation.  epi 0: C = acc; 1: C = acc + bias; 2: C = Z = acc + bias, H = gelu(Z) (bf16, ld
+// ldh) and, if T != null, T = H^T (bf16, ld ldt); 3: C = acc * gelu'(Z) (Z fp32, ld ldz), H = C (bf16),
+// T = H^T if T != null.  C is fp32 with leading dimension ldc.  When the output has few tiles, K is
+// split over workgroups and part (mlp_gemm_part_floats(M, N, K) floats) holds the partial products,
+// summed in a fixed order; with a smaller workspace one workgroup takes each tile.  Products on one
+// stream may share the workspace.
+size_t mlp_gemm_part_floats(int M, int N, int K);
+hipError_t mlp_gemm_nt(int epi, const void* A, int lda, const void* B, int ldb, int M, int N, int K, float* C, int ldc,
+                       const float* bias, const float* Z, int ldz, void* H, int ldh, void* T, int ldt, float* part,
+                       size_t part_floats, hipStream_t s);
+// probabilities, loss sum and G = (p - onehot) / batch (fp32; bf16 with ld ldgb; transposed bf16 if gt)
 hipError_t mlp_softmax_ce(const float* logits, const int32_t* labels, int batch, int classes, float* probs, float* g,
-                          void* gb, float* loss_sum, hipStream_t s);
+                          void* gb, int ldgb, void* gt, int ldgt, float* loss_sum, hipStream_t s);
 hipError_t mlp_colsum(const float* g, int rows, int cols, float* out, hipStream_t s);
-hipError_t mlp_to_bf16(const float* x, void* y, int64_t count, hipStream_t s);
+// x (rows x cols fp32) -> bf16 (ld ldy) and, if t != null, its transpose (ld ldt)
+hipError_t mlp_input_bf16(const float* x, int rows, int cols, void* y, int ldy, void* t, int ldt, hipStream_t s);
+// W (rows x cols fp32) -> bf16 W (ld ldb) and bf16 W^T (ld ldt)
+hipError_t mlp_weights_bf16(const float* w, int rows, int cols, void* wb, int ldb, void* wt, int ldt, hipStream_t s);
 hipError_t mlp_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1, float b2,
                     float eps, int step, hipStream_t s);
 hipError_t mlp_init(float* w, int64_t count, int64_t index0, int fan_in, uint64_t seed, hipStream_t s);

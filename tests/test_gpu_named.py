@@ -239,7 +239,7 @@ def test_n4k7_all_chunks_concurrent(ctx):
     tgt = ctx.target_from_words(4, tw.paulis, tw.clifford)
     p = ctx.default_params(4)
     p.k_max = 7
-    p.depth_order_kind = 1
+    p.depth_order_kind = tcw.ORDER_GIVEN_FIRST
     p.depth_order_len = 1
     p.depth_order[0] = 7
     p.delta = 1

@@ -190,46 +190,48 @@ def parse_checkpoint(blob):
 
 
 def test_checkpoint_resume_continues_trails(ctx):
-    """n = 3, depth 6 by walks: a search stopped after 3 launches and resumed in a fresh context for 2
-    more launches holds, for every walk still on the same trail and walking, the same start, current
-    point and length as a search stopped after 5 launches (a trail is its start, end and length)."""
+    """n = 3, depth 6 by walks: a search stopped after 3 launches is resumed twice from its checkpoint
+    for 2 more launches, in its own context and in a fresh one.  Every walk that reached no
+    distinguished point after the checkpoint holds, in both, the same start, current point and length,
+    and the current point is the oracle's f^len(start) (a trail is its start, end and length)."""
     from paper_1606_07413_amd import tcw
     say("checkpoint walk mode")
     tw, u = oracle_target(3, 6, 3)
     tgt = ctx.target_from_words(3, tw.paulis, tw.clifford)
-
-    def params(limit):
-        p = ctx.default_params(3)
-        p.k_max = 6
-        p.seed = 77
-        p.delta = 8
-        p.walks = 4096
-        p.log2_table = 16
-        p.iters_per_launch = 16
-        p.launch_limit = limit
-        _given(p, [6], tcw.ORDER_GIVEN_FIRST)
-        return p
-
-    r5 = ctx.search(tgt, params(5))
-    assert r5.status == tcw.STATUS_STOPPED
-    a = parse_checkpoint(ctx.checkpoint())
-    r3 = ctx.search(tgt, params(3))
+    p = ctx.default_params(3)
+    p.k_max = 6
+    p.seed = 77
+    p.delta = 8
+    p.walks = 4096
+    p.log2_table = 16
+    p.iters_per_launch = 16
+    p.launch_limit = 3
+    _given(p, [6], tcw.ORDER_GIVEN_FIRST)
+    r3 = ctx.search(tgt, p)
     assert r3.status == tcw.STATUS_STOPPED and r3.launches == 3
     blob = ctx.checkpoint()
+    c = parse_checkpoint(blob)
+    assert c["k"] == 6 and c["steps"] == 3 * 16 * 4096
+    ra = ctx.resume(tgt, blob, launch_limit=2)
+    assert r3.stats.steps == 3 * 16 * 4096
+    assert ra.status == tcw.STATUS_STOPPED and ra.launches == 5 and ra.stats.steps == 5 * 16 * 4096
+    a = parse_checkpoint(ctx.checkpoint())
     ctx2 = tcw.Context(0)
     tgt2 = ctx2.target_from_words(3, tw.paulis, tw.clifford)
-    rr = ctx2.resume(tgt2, blob, launch_limit=2)
-    assert rr.status == tcw.STATUS_STOPPED and rr.launches == 5
+    rb = ctx2.resume(tgt2, blob, launch_limit=2)
+    assert rb.status == tcw.STATUS_STOPPED and rb.launches == 5
     b = parse_checkpoint(ctx2.checkpoint())
-    assert a["k"] == b["k"] == 6 and a["steps"] == b["steps"] == 5 * 16 * 4096
-    sa, sb = a["states"], b["states"]
-    same = (sa["trail"] == sb["trail"]) & (sa["mode"] == 0) & (sb["mode"] == 0)
+    assert a["steps"] == b["steps"] == 5 * 16 * 4096
+    sa, sb, sc = a["states"], b["states"], c["states"]
+    same = ((sa["trail"] == sc["trail"]) & (sb["trail"] == sc["trail"]) & (sa["mode"] == 0) & (sb["mode"] == 0)
+            & (sc["mode"] == 0))
     assert same.sum() > 2000
     for f in ("start", "cur", "len"):
         assert np.array_equal(sa[f][same], sb[f][same])
-    # spot-check resumed walks against the oracle: cur = f^len(start(w, trail))
+    assert np.array_equal(sa["len"][same], sc["len"][same] + 32)     # 2 launches of 16 steps each
+    # resumed walks against the oracle: cur = f^len(start(w, trail))
     spec = owalk.make_spec(u, 3, 6, 0, 77, delta=8)
-    for w in np.flatnonzero(same)[:3]:
+    for w in np.flatnonzero(same)[:2]:
         s = sb[w]
         pt = owalk.start_point(spec, int(w), int(s["trail"]))
         assert int(s["start"]) == pt
