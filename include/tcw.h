@@ -113,6 +113,21 @@ typedef struct tcw_space {
 int tcw_step(tcw_ctx* ctx, const tcw_target* t, const tcw_space* sp, const uint64_t* pts_in_dev,
              uint64_t* pts_out_dev, uint64_t* hash_out_dev, int64_t count);
 
+/* tcw_step_noalloc: for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  The same outputs as tcw_step, bit for bit, from
+ * the same arguments, with every per-call buffer (the chunk matrix S_c and the two work matrices of
+ * its construction, its int8 packing, the keys) in one fixed device array of
+ * TCW_STEP_NOALLOC_SCRATCH bytes that the library holds on each device it runs on until the process
+ * ends; it calls no allocating routine.  At n = 4 its steps apply every rotation themselves instead
+ * of reading the context's rotated-key tables.  Calls that overlap on one device share that array and
+ * race: serialise them (one call at a time per device, across contexts and threads).  Blocking (it
+ * reads S_c's exponent and the range flag back).  Errors as for tcw_step; TCW_EINVAL for a space
+ * whose buffers exceed the array (none with n <= 4 does); TCW_EDEVICE if the array's device address
+ * could not be obtained when the context was created. */
+#define TCW_STEP_NOALLOC_SCRATCH 1182464
+int tcw_step_noalloc(tcw_ctx* ctx, const tcw_target* t, const tcw_space* sp, const uint64_t* pts_in_dev,
+                     uint64_t* pts_out_dev, uint64_t* hash_out_dev, int64_t count);
+
 /* tcw_trails (parity): from each start, apply f until the next point is distinguished (Sec. 3).
  * dp_out_dev[i] = that point, len_out_dev[i] = steps taken (>= 1); len 0 = no distinguished point
  * within `cap` steps (trail abandoned; dp_out undefined). */

@@ -11,6 +11,7 @@
 #include <atomic>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -62,6 +63,8 @@ struct tcw_ctx {
     void* claw_scratch = nullptr;
     size_t claw_scratch_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    void* noalloc = nullptr;        // this device's copy of the tcw_step_noalloc scratch array
+    hipError_t noalloc_err = hipSuccess;
     std::atomic<int> stop_req{0};   // tcw_search_stop: end the running search at its next launch boundary
     SearchRun* stopped = nullptr;   // the last search that ended on a stop, for tcw_checkpoint
 };
@@ -314,6 +317,52 @@ int walk_restart(tcw_walk* w) {
 
 }  // namespace
 
+// ---- device memory of tcw_step_noalloc ----
+// One fixed array per device holds every per-call buffer of the step: the chunk matrix S_c (A and B,
+// R x R of int32 at n >= 3, of int64 at n <= 2: at most 256 KiB each), the two work matrices of its
+// construction, its exponent, the one-rotation word that forms it, its int8 packing and the keys.
+namespace {
+constexpr size_t NA_MAT = (size_t)256 * 256 * 4;
+constexpr size_t NA_OFF_SA = 0, NA_OFF_SB = NA_MAT, NA_OFF_TA = 2 * NA_MAT, NA_OFF_TB = 3 * NA_MAT;
+constexpr size_t NA_OFF_E = 4 * NA_MAT;          // S_c's exponent (int32)
+constexpr size_t NA_OFF_SEQ = NA_OFF_E + 256;     // the rotation code (uint16) at +0, its transpose flag at +16
+constexpr size_t NA_OFF_PHI = NA_OFF_SEQ + 256;   // int8 packing of S_c
+constexpr size_t NA_PHI = (size_t)256 * 256 / 2 * 4 + 256;
+constexpr size_t NA_OFF_KEYS = NA_OFF_PHI + NA_PHI;  // R keys (uint64)
+constexpr size_t NA_BYTES = NA_OFF_KEYS + 256 * 8;
+static_assert(NA_BYTES == TCW_STEP_NOALLOC_SCRATCH, "scratch size stated in tcw.h");
+static_assert(NA_OFF_PHI % 256 == 0 && NA_OFF_KEYS % 256 == 0, "aligned parts");
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex na_mutex;
+void* na_ptr[NA_MAX_DEVICES] = {};
+
+// With the context's device current: this device's address of `scratch` (taken once per device).  The
+// array's name in host code is a host-side stand-in, never a device address.
+void noalloc_setup(tcw_ctx* c) {
+    std::lock_guard<std::mutex> lock(na_mutex);
+    if (c->device < 0 || c->device >= NA_MAX_DEVICES) {
+        c->noalloc_err = hipErrorInvalidDevice;
+        return;
+    }
+    if (!na_ptr[c->device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            c->noalloc_err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            (void)hipGetLastError();
+            return;
+        }
+        na_ptr[c->device] = p;
+    }
+    c->noalloc = na_ptr[c->device];
+}
+}  // namespace
+
 extern "C" {
 
 int tcw_create(tcw_ctx** out, int device, void* stream) {
@@ -333,6 +382,7 @@ int tcw_create(tcw_ctx** out, int device, void* stream) {
         delete c;
         return TCW_EDEVICE;
     }
+    noalloc_setup(c);
     *out = c;
     return TCW_OK;
 }
@@ -581,6 +631,64 @@ int tcw_step(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, const uint64_
     int rc = prepare_space(c, t, sp, s);
     if (rc) return rc;
     HIP_TRY(c, tcw::launch_step(t->n, s.dev, in, out, hash, count, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TCW_OK;
+}
+
+int tcw_step_noalloc(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, const uint64_t* in, uint64_t* out,
+                     uint64_t* hash, int64_t count) {
+    if (!c || !t || count < 0 || (count > 0 && (!in || !out))) return TCW_EINVAL;
+    int rc = check_space(c, t->n, sp);
+    if (rc || count == 0) return rc;
+    const int n = t->n;
+    const int R = 1 << (2 * n);
+    const size_t elem = n <= 2 ? 8 : 4;
+    if ((size_t)R * R * elem > NA_MAT || (size_t)R * R / 2 * 4 + 16 > NA_PHI || (size_t)R * 8 > NA_BYTES - NA_OFF_KEYS)
+        return fail(c, TCW_EINVAL, "space larger than the no-allocation scratch (TCW_STEP_NOALLOC_SCRATCH bytes)");
+    if (!c->noalloc)
+        return fail(c, TCW_EDEVICE, std::string("no-allocation scratch unavailable on this device: ") +
+                                        hipGetErrorString(c->noalloc_err));
+    uint8_t* base = static_cast<uint8_t*>(c->noalloc);
+    ExactDev S;
+    S.n = n;
+    S.r = R;
+    S.elem = elem;
+    S.a = base + NA_OFF_SA;
+    S.b = base + NA_OFF_SB;
+    S.e = reinterpret_cast<int32_t*>(base + NA_OFF_E);
+    uint16_t* seq = reinterpret_cast<uint16_t*>(base + NA_OFF_SEQ);
+    uint8_t* tr = base + NA_OFF_SEQ + 16;
+    uint32_t* phi = reinterpret_cast<uint32_t*>(base + NA_OFF_PHI);
+    uint64_t* keys = reinterpret_cast<uint64_t*>(base + NA_OFF_KEYS);
+    // S_c = U R(c)^T for odd k, U for even k, built in the scratch array; range flags cleared by a kernel
+    HIP_TRY(c, tcw::fill_i32(c->flag, 0, 1, c->stream));
+    int nseq = 0;
+    if (sp->k % 2 == 1) {
+        HIP_TRY(c, tcw::exact_seq_one(seq, tr, (uint16_t)sp->chunk, 1, c->stream));
+        nseq = 1;
+    }
+    HIP_TRY(c, tcw::exact_apply_ws(S, t->U, seq, tr, nseq, base + NA_OFF_TA, base + NA_OFF_TB, c->flag, c->stream));
+    HIP_TRY(c, tcw::exact_pack_phi(S, phi, c->flag, c->stream));
+    HIP_TRY(c, tcw::keys_fill(n, sp->seed, keys, c->stream));
+    int32_t e_s = 0;
+    int flag = 0;
+    HIP_TRY(c, hipMemcpyAsync(&e_s, S.e, sizeof(e_s), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&flag, c->flag, sizeof(flag), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (flag & 4) return fail(c, TCW_EOVERFLOW, "exact value out of range while forming S_c");
+    if (flag & 2) return fail(c, TCW_EOVERFLOW, "S_c entry outside int8 range (exponent too large)");
+    tcw::SpaceDev dev{};
+    const int h = sp->k / 2;
+    dev.n_half = (uint32_t)n_half_of(n, h);
+    dev.h = h;
+    dev.delta = sp->delta;
+    dev.rot_e = (int32_t)((30ll * e_s) % 61);
+    dev.phi = phi;
+    dev.keys = keys;
+    dev.rkeys = nullptr;   // every rotation of the step is applied (no rotated-key tables)
+    dev.rkeys2 = nullptr;
+    space_salts(dev, sp->seed, sp->version, sp->k, sp->chunk);
+    HIP_TRY(c, tcw::launch_step(n, dev, in, out, hash, count, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return TCW_OK;
 }

@@ -662,6 +662,27 @@ hipError_t exact_apply(ExactDev& dst, const ExactDev& src, const uint16_t* seq, 
     return err;
 }
 
+namespace {
+__global__ void k_seq_one(uint16_t* seq, uint8_t* tr, uint16_t p, uint8_t t) {
+    if (threadIdx.x == 0) {
+        seq[0] = p;
+        tr[0] = t;
+    }
+}
+__global__ void k_fill_i32(int* dst, int v, int count) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = v;
+}
+}  // namespace
+
+hipError_t exact_seq_one(uint16_t* seq, uint8_t* tr, uint16_t p, uint8_t transpose, hipStream_t s) {
+    hipLaunchKernelGGL(k_seq_one, dim3(1), dim3(64), 0, s, seq, tr, p, transpose);
+    return hipGetLastError();
+}
+
+hipError_t fill_i32(int* dst, int v, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, dst, v, count);
+    return hipGetLastError();
+}
 
 hipError_t exact_build(ExactDev& m, const uint16_t* seq, const uint8_t* tr, int nseq, int* flag, hipStream_t s) {
     auto f = [&]<int NQ, typename T>() -> hipError_t {

@@ -89,6 +89,10 @@ hipError_t exact_apply(ExactDev& dst, const ExactDev& src, const uint16_t* seq_d
 // synchronisation
 hipError_t exact_apply_ws(ExactDev& dst, const ExactDev& src, const uint16_t* seq, const uint8_t* tr, int nseq,
                           void* ta, void* tb, int* flag, hipStream_t s);
+// seq[0] = p, tr[0] = transpose (a one-rotation word on the device, written by a kernel)
+hipError_t exact_seq_one(uint16_t* seq, uint8_t* tr, uint16_t p, uint8_t transpose, hipStream_t s);
+// dst[0..count) = v by a kernel (no memset node, so it may sit in captured work)
+hipError_t fill_i32(int* dst, int v, int count, hipStream_t s);
 // load int32 host-provided values already on the device
 hipError_t exact_from_i32(ExactDev& m, const int32_t* a_dev, const int32_t* b_dev, int32_t e, int* flag_dev,
                           hipStream_t s);

@@ -95,6 +95,7 @@ _SIGS = {
     "tcw_target_channel": (C.c_int, [_P, _P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "tcw_target_n": (C.c_int, [_P]),
     "tcw_step": (C.c_int, [_P, _P, C.POINTER(Space), _P, _P, _P, C.c_int64]),
+    "tcw_step_noalloc": (C.c_int, [_P, _P, C.POINTER(Space), _P, _P, _P, C.c_int64]),
     "tcw_trails": (C.c_int, [_P, _P, C.POINTER(Space), _P, C.c_int64, C.c_uint32, _P, _P]),
     "tcw_start_points": (C.c_int, [_P, _P, C.POINTER(Space), C.c_int64, C.c_uint32, C.c_int64, _P]),
     "tcw_canon_hash": (C.c_int, [_P, C.c_int, C.POINTER(Space), _P, _P, _P, C.c_int64, _P]),
@@ -277,6 +278,14 @@ class Context:
         self._check(self.lib.tcw_step(self.h, target.h, C.byref(sp), _dev(pts_in, 8, count, "pts_in", d),
                                       _dev(pts_out, 8, count, "pts_out", d), _dev(hash_out, 8, count, "hash_out", d),
                                       count))
+
+    def step_noalloc(self, target, k, chunk, seed, delta, pts_in, pts_out, hash_out=None, version=0):
+        """tcw_step computed with the library's fixed scratch array (no device allocation)."""
+        sp = Space(k, chunk, seed, version, delta)
+        count, d = pts_in.numel(), self.device
+        self._check(self.lib.tcw_step_noalloc(self.h, target.h, C.byref(sp), _dev(pts_in, 8, count, "pts_in", d),
+                                              _dev(pts_out, 8, count, "pts_out", d),
+                                              _dev(hash_out, 8, count, "hash_out", d), count))
 
     def trails(self, target, k, chunk, seed, delta, starts, cap, dp_out, len_out, version=0):
         sp = Space(k, chunk, seed, version, delta)
