@@ -3,11 +3,15 @@
 A benchmark step is one launch of the persistent walk kernel in which each of the 2^20
 concurrent walks performs `iters` evaluations of the walk function f (decode, rotate,
 canonicalise, hash, distinguished-point test, table insert, trail backtracking), on the
-seeded synthetic n = 4, k = 7 target (chunk = the planted first rotation), theta = 2^-12,
-2^26 table slots.  value = walk steps per second over the timed launches.
+seeded synthetic n = 4, k = 7 target of seed 2 (T-count 7; chunk = its planted first
+rotation), theta = 2^-12, 2^26 table slots.  value = walk steps per second over the timed
+launches.
 
-Also reported: the roofline of the walk kernel (VALU-bound), the CPU oracle timed on the
-host on a bounded sample of the same workload, and time-to-solution figures.
+Also reported by default: the roofline of the walk kernel (VALU-bound), time-to-solution of
+whole searches at n = 3, k = 6 and at n = 4, k = 7 (theta = 1/2, seeds 2, 3, 4, capped), the
+configured-theta search of one planted chunk (capped, censored), the learned depth order
+against the plain order at n = 3, and the CPU oracle timed on the host on a bounded sample of
+the walk workload.
 """
 
 from __future__ import annotations
@@ -71,58 +75,151 @@ def measured_traffic(walks: int, iters: int):
 
 
 def valu_ops_per_step(n: int, h: int) -> float:
-    """32-bit VALU lane-operations the n = 4 walk step needs per evaluation of f (mean over sides).
+    """32-bit VALU lane-operations of one evaluation of f at n = 4 in its phi-linear form (mean over
+    the two sides), counted per lane (four rows of the 256-entry key vector per lane, 64 lanes):
 
-    both sides: (h - 2) R/2 butterflies x 12 (64-bit modular add + 61-bit rotation + sign; the first two
-                rotations of a step come from the table of rotated keys), R x 6 (fold),
-                R x 6 (multiset hash: the NH element map's two 32-bit key adds and 32 x 32 -> 64-bit
-                product 2, and the 64-bit add 2), log2(64) x 4 x 64 (wave reduction of the sum)
-    side 1:     digit packing 2 sets x 8 signed base-256 digits x R x 3, digit recombination
-                R x 16 x 4 (16 partial sums per row, digits of both sets) plus the reduce-scatter
-                (12 values x 64 lanes x 8) -- the S_c product itself runs on MFMA
-    """
-    r = 4 ** n
-    common = max(h - 2, 0) * (r // 2) * 12 + r * 6 + r * 6 + 6 * 4 * 64
-    side1 = 2 * 8 * r * 3 + r * 16 * 4 + 12 * 64 * 8
-    return common + 0.5 * side1
+      per computed rotation (the first two of a step come from the table of rotated keys): per row
+          the partner's sign (64-bit subtract 2, select 2), the add 2, the multiplication by
+          1/sqrt2 = 2^30 mod p (shifts and mask 3, add 2) and the anticommutation select 2: 13
+      side 0: the digest S_r = u_r folded below p: 4 per row
+      both sides: sign fold min(c, p - c) = c ^ (bit 60 ? p : 0): 5 per row; NH element map and
+          accumulation (two 32-bit key adds, one 32 x 32 -> 64 multiply-add, 64-bit add): 5 per row;
+          the wave sum (four DPP stages and two cross-half swaps of 64-bit adds): 16 per lane
+      side 1 (phi(S_c) u on int8 MFMA): digits of u and 2^31 u (the second set 7 per value,
+          the bias 2 per value, two 4 x 4 byte transposes of 8 permutes per set, 8 xors per set): 84;
+          raw tile sums (2 per tile, 16 tiles): 32; the 8 tile pairs' reduce-scatter and lazy
+          weighted residue: 15 each; the final cross-half add, fold and exponent rotation of
+          4 rows: 52
+    which at h = 3 is 64 x (52 + 8 + 56 + 144) = 16,640 lane-operations (mean of the sides: side 0
+    64 x 124, side 1 64 x 396).
+    The compiled kernel issues more (address arithmetic, the trail and table logic); the counters
+    give that figure separately."""
+    if n != 4:
+        raise ValueError("the lane-operation count is stated for n = 4")
+    rows = 4
+    rotations = 13 * rows * max(h - 2, 0)
+    side0 = 4 * rows
+    both = 5 * rows + 5 * rows + 16
+    side1 = 84 + 32 + 8 * 15 + 52
+    return 64.0 * (rotations + 0.5 * side0 + both + 0.5 * side1)
+
+
+# The survey's count of integer operations per step of the literal method (the 256 x 256 channel
+# representation updated by h sparse butterflies, its 65,536 entries normalised and digested, the
+# rows sorted): about 1.3e6 at n = 4.  The kernel reaches the same f without forming that matrix.
+LITERAL_OPS_PER_STEP_N4 = 1.3e6
 
 
 def mfma_ops_per_step(n: int) -> float:
-    """int8 MFMA operations per step (mean over sides): 16 x 16 x 64 tiles x 16 x 8 on side 1."""
-    return 0.5 * (16 * 16 * 64 * 2) * 16 * 8
+    """Useful int8 MFMA operations per step (mean over sides): on side 1 the 256 x 256 product
+    phi(S_c) u over 8 digit rows for each of the two digit sets (u and 2^31 u), i.e.
+    2 sets x 8 digits x 256 x 256 x 2; the A operand's zero half (each set occupies half of its
+    16 rows on half of K) is not counted."""
+    return 0.5 * (2 * 8 * 256 * 256 * 2)
+
+
+COUNTER_SUMMARY = "profiles/k_walk_n4k7_counters.md"
+
+
+def measured_counters(walks: int, iters: int):
+    """Counter values per launch of the walk kernel from the committed summary, or None when it is
+    missing, was taken for another launch shape, or the kernel sources changed since."""
+    path = os.path.join(ROOT, COUNTER_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        fields = dict(re.findall(r"^- (\w+): (\S+)$", f.read(), re.M))
+    try:
+        if fields["source_sha256"] != kernel_source_digest():
+            return None
+        if int(fields["walks"]) != walks or int(fields["iters_per_launch"]) != iters:
+            return None
+        return {k: float(v) for k, v in fields.items() if k.startswith("SQ_") or k == "kernel_ms"}
+    except (KeyError, ValueError):
+        return None
+
+
+def walk_roofline(n, h, steps_per_launch, avg_ms, walks, iters):
+    """The walk kernel against the VALU peak (its bound), with the survey's literal-method count, the
+    compiled kernel's issued VALU work and busy share (counters), the int8 MFMA rate and HBM bytes."""
+    secs = avg_ms * 1e-3
+    ops = valu_ops_per_step(n, h)
+    achieved = ops * steps_per_launch / secs
+    traffic = measured_traffic(walks, iters)
+    out = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+           "frac": achieved / VALU_PEAK_OPS, "traffic": traffic, "traffic_unit": "HBM bytes per launch",
+           "kernel": "k_walk<4,12>", "kernel_ms": avg_ms, "kernel_source_sha256": kernel_source_digest(),
+           "ops_per_step": ops, "ops_unit": "32-bit VALU lane-operations of the phi-linear step",
+           "literal_method": {"ops_per_step": LITERAL_OPS_PER_STEP_N4,
+                              "frac": LITERAL_OPS_PER_STEP_N4 * steps_per_launch / secs / VALU_PEAK_OPS,
+                              "note": "above 1: the kernel does not form the channel representation; it "
+                                      "reaches the same f through phi-linearity"}}
+    mf = mfma_ops_per_step(n) * steps_per_launch / secs
+    out["mfma_i8"] = {"achieved": mf / 1e12, "peak": MFMA_I8_PEAK_OPS / 1e12, "unit": "Tops/s",
+                      "frac": mf / MFMA_I8_PEAK_OPS, "counted": "useful products only (zero half of A excluded)"}
+    out["hbm"] = None if traffic is None else {
+        "achieved": traffic / secs / 1e9, "peak": HBM_PEAK_BYTES / 1e9, "unit": "GB/s", "frac": traffic / secs / HBM_PEAK_BYTES}
+    c = measured_counters(walks, iters)
+    if c is not None:
+        mfma_insts = c["SQ_INSTS_VALU_MFMA_MOPS_I8"] * 512 / (16 * 16 * 64 * 2)
+        issued = (c["SQ_INSTS_VALU"] - mfma_insts) * 64 / steps_per_launch
+        waves_per_simd = c["SQ_WAVES"] / (256 * 4)
+        out["counters"] = {
+            "issued_valu_lane_ops_per_step": issued,
+            "issued_frac": issued * steps_per_launch / secs / VALU_PEAK_OPS,
+            "valu_busy": c["SQ_ACTIVE_INST_VALU"] / c["SQ_WAVE_CYCLES"] * waves_per_simd,
+            "waves_per_simd": waves_per_simd, "kernel_ms_profiled": c["kernel_ms"], "source": COUNTER_SUMMARY}
+    else:
+        out["counters"] = None
+    return out
 
 
 def _oracle_worker(args):
-    n, k, chunk, seed, delta, pts = args
+    n, k, chunk, target_seed, seed, delta, pts = args
     import seeded_inputs
     from oracle import walk as owalk
     from oracle import zmat
-    tw = seeded_inputs.target_words(n, k, 1)
+    tw = seeded_inputs.target_words(n, k, target_seed)
     u = zmat.target_from_words(n, tw.paulis, tw.clifford)
     spec = owalk.make_spec(u, n, k, chunk, seed, delta)
+    # timed after the target and the space are built
     t0 = time.perf_counter()
     for p in pts:
         owalk.f(spec, p)
     return len(pts), time.perf_counter() - t0
 
 
-def cpu_baseline(n, k, chunk, seed, delta, seconds: float):
-    """The oracle's walk step on the host cores over a bounded sample of seeded points."""
+def host_cores() -> int:
+    """Worker processes for the oracle: the cores this process may run on, at most 16 (one GPU's
+    share of a shared host)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(avail, 16))
+
+
+def cpu_baseline(n, k, chunk, target_seed, seed, delta, seconds: float):
+    """The oracle's walk step on the host cores over a bounded sample of seeded points: one worker
+    process per core, each timing its own evaluations after building the target, rates summed."""
     import seeded_inputs
-    cores = min(os.cpu_count() or 1, 16)
-    # calibrate one step
+    cores = host_cores()
     n_half = (4 ** n - 1) ** (k // 2)
-    _, dt = _oracle_worker((n, k, chunk, seed, delta, seeded_inputs.random_points(n_half, 2, 5)))
+    _, dt = _oracle_worker((n, k, chunk, target_seed, seed, delta, seeded_inputs.random_points(n_half, 2, 5)))
     per_proc = max(1, int(seconds / max(dt / 2, 1e-3)))
-    jobs = [(n, k, chunk, seed, delta, seeded_inputs.random_points(n_half, per_proc, 100 + i)) for i in range(cores)]
+    jobs = [(n, k, chunk, target_seed, seed, delta, seeded_inputs.random_points(n_half, per_proc, 100 + i))
+            for i in range(cores)]
     t0 = time.perf_counter()
     with mp.get_context("spawn").Pool(cores) as pool:
         res = pool.map(_oracle_worker, jobs)
     wall = time.perf_counter() - t0
     total = sum(r[0] for r in res)
-    return {"value": total / wall, "unit": "walk steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{total} walk steps (f evaluations) on seeded points of the n=4,k=7 chunk, "
-                      f"{per_proc} per process over {cores} processes, {wall:.1f} s wall"}
+    rate = sum(c / t for c, t in res)
+    return {"value": rate, "unit": "walk steps/s", "cores": cores, "kind": "oracle",
+            "os_cpu_count": os.cpu_count(),
+            "sample": f"{total} walk steps (f evaluations) on seeded points of the n=4,k=7 planted chunk of target "
+                      f"{target_seed}, {per_proc} per process over {cores} processes (rates timed inside each "
+                      f"process after its set-up, summed); {wall:.1f} s wall with start-up"}
 
 
 def _oracle_search_worker(args):
@@ -142,18 +239,19 @@ def cpu_configs(seconds: float):
     time-to-solution of the n = 2, k = 4 searches (16 targets, the same walk parameters as the GPU
     leg), one target per process."""
     import seeded_inputs
-    cores = min(os.cpu_count() or 1, 16)
+    cores = host_cores()
     rates = {}
     for name, n, k in (("n2k4", 2, 4), ("n3k6", 3, 6), ("n4k7", 4, 7)):
         spec = seeded_inputs.WORKLOADS[name]
         tw = seeded_inputs.target_words(n, k, spec["target_seeds"][0])
         chunk = tw.paulis[0] if k % 2 else 0
         n_half = (4 ** n - 1) ** (k // 2)
-        _, dt = _oracle_worker((n, k, chunk, 5, spec["delta"], seeded_inputs.random_points(n_half, 2, 5)))
+        ts = spec["target_seeds"][0]
+        _, dt = _oracle_worker((n, k, chunk, ts, 5, spec["delta"], seeded_inputs.random_points(n_half, 2, 5)))
         per = max(1, int(seconds / max(dt / 2, 1e-4)))
-        cnt, t1 = _oracle_worker((n, k, chunk, 5, spec["delta"], seeded_inputs.random_points(n_half, per, 7)))
+        cnt, t1 = _oracle_worker((n, k, chunk, ts, 5, spec["delta"], seeded_inputs.random_points(n_half, per, 7)))
         per_proc = max(1, per // 2)
-        jobs = [(n, k, chunk, 5, spec["delta"], seeded_inputs.random_points(n_half, per_proc, 100 + i))
+        jobs = [(n, k, chunk, ts, 5, spec["delta"], seeded_inputs.random_points(n_half, per_proc, 100 + i))
                 for i in range(cores)]
         with mp.get_context("spawn").Pool(cores) as pool:
             res = pool.map(_oracle_worker, jobs)
@@ -296,33 +394,32 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def tts_n4_enum_leg(ctx, cap: float, seeds=(1, 2, 3, 4)):
-    """The same n = 4 searches in the memory-rich limit: every space of up to 2^26 points (all of
-    depths <= 7 at n = 4) enumerated exhaustively, each point hashed once into a table of 4N slots
-    keyed by its full matrix hash (the meet-in-the-middle the walks replace when memory is short);
-    deterministic, and every depth below the answer is searched completely."""
+def tts_n3k6_leg(ctx):
+    """The whole optimal-T-count search of the n = 3, k = 6 target of seed 5 (optimum 6, so the depth-6
+    walks run) at the configured theta = 2^-8 and at the library's default theta."""
     import seeded_inputs
-    runs = []
-    for ts in seeds:
-        twn = seeded_inputs.target_words(4, 7, ts)
-        tn = ctx.target_from_words(4, twn.paulis, twn.clifford)
-        p4 = ctx.default_params(4)
-        p4.k_max = 7
-        p4.enum_max = 1 << 26
-        p4.seed = 3200 + ts
-        p4.max_seconds = cap
-        r = ctx.search(tn, p4)
-        runs.append({"target_seed": ts, "seconds": r.seconds, "found_t": r.t if r.status else None,
-                     "chunk": r.chunk if r.status else None, "points": r.stats.steps, "spaces": r.spaces})
-        print(f"tts n4k7 (exhaustive) target {ts}: t={runs[-1]['found_t']} in {r.seconds:.2f} s", file=sys.stderr,
-              flush=True)
-        tn.free()
-    return {"measured": True, "mode": "exhaustive spaces (enum_max 2^26)", "cap_s": cap, "runs": runs}
+    tw3 = seeded_inputs.target_words(3, 6, 5)
+    t3 = ctx.target_from_words(3, tw3.paulis, tw3.clifford)
+    runs = {}
+    for name, d3 in (("configured_theta", seeded_inputs.WORKLOADS["n3k6"]["delta"]), ("default_theta", -1)):
+        p3 = ctx.default_params(3)
+        p3.k_max = 6
+        p3.delta = d3
+        p3.seed = 2001
+        p3.max_seconds = 120
+        r3 = ctx.search(t3, p3)
+        runs[name] = {"seconds": r3.seconds, "found_t": r3.t if r3.status else None, "steps": r3.stats.steps,
+                      "versions": r3.versions}
+    t3.free()
+    _log(f"tts n3k6: {runs}")
+    return {"target_seed": 5, "measured": True, "delta": seeded_inputs.WORKLOADS["n3k6"]["delta"],
+            **runs["configured_theta"], "default_theta": runs["default_theta"]}
 
 
-def tts_n4_leg(ctx, cap: float, slice_s: float = 60.0, seeds=(1, 2, 3, 4)):
-    """The whole optimal-T-count search for the four seeded n = 4, k = 7 targets at theta = 1/2 (the
-    paper's choice when the table holds the whole space: 2^27 slots >> N = 3.3e7 per chunk), every
+def tts_n4_leg(ctx, cap: float, slice_s: float = 60.0, seeds=(2, 3, 4)):
+    """The whole optimal-T-count search for seeded n = 4, k = 7 targets (seeds 2, 3, 4 have T-count 7)
+    at theta = 1/2 (the paper's choice in Sec. 5.2 when the table holds the whole space: 2^27 slots
+    >> N = 3.3e7 per chunk), a target not finished within `cap` seconds reported as censored, every
     chunk of an odd depth searched concurrently.  Depths 0..6 run as one call; depth 7 runs in calls
     of at most slice_s seconds, each starting a fresh range of function versions (a version starts
     from an empty table anyway), until a verified decomposition or the cap."""
@@ -362,7 +459,7 @@ def tts_n4_leg(ctx, cap: float, slice_s: float = 60.0, seeds=(1, 2, 3, 4)):
                   f"found={bool(r.status)}", file=sys.stderr, flush=True)
         runs.append({"target_seed": ts, "seconds": time.perf_counter() - t0,
                      "found_t": r.t if r.status else None, "chunk": r.chunk if r.status else None,
-                     "steps": steps, "depth7_slices": slices})
+                     "censored": not r.status, "steps": steps, "depth7_slices": slices})
         tn.free()
     return {"measured": True, "theta": 0.5, "chunk_parallel": "all", "cap_s": cap, "runs": runs}
 
@@ -404,7 +501,8 @@ def tts_n4_planted_leg(ctx, cap: float, slice_s: float = 120.0, seeds=(2, 3, 4))
                 break
         n_pts = 2 * 255 ** 3
         runs.append({"target_seed": ts, "chunk": chunk, "seconds": time.perf_counter() - t0,
-                     "found_t": r.t if r is not None and r.status else None, "steps": steps,
+                     "found_t": r.t if r is not None and r.status else None,
+                     "censored": not (r is not None and r.status), "steps": steps,
                      "steps_over_N_per_theta": steps / (n_pts * 4096.0), "slices": slices})
         tn.free()
     return {"measured": True, "theta": 2.0 ** -12, "walks": 1 << 20, "log2_table": 26, "cap_s": cap,
@@ -464,9 +562,61 @@ def named_leg(ctx, reps: int, reps_default_theta: int):
     return out
 
 
-def mlp_leg(ctx, train_count: int, epochs: int, eval_count: int, cap: float):
+def network_leg(ctx, batch: int = 4096, reps: int = 10):
+    """The depth-order network at its own shape (4096 -> 512 x 3 -> 11, GELU, BF16 MFMA with FP32
+    accumulation): seconds per forward pass and per training step (forward, backward, Adam) on a batch
+    of synthetic features, and the rate of the GEMM work against the dense BF16 peak."""
+    import torch
+
+    from paper_1606_07413_amd import tcw
+    inp, hidden, depth, classes = 4096, 512, 3, 11
+    net = tcw.Network(ctx, inp, hidden, depth, classes, seed=42)
+    g = torch.Generator(device="cuda:0").manual_seed(5)
+    x = torch.randn((batch, inp), device="cuda:0", generator=g) * 0.5
+    y = torch.randint(0, classes, (batch,), dtype=torch.int32, device="cuda:0", generator=g)
+    probs = torch.empty((batch, classes), device="cuda:0")
+    for _ in range(3):
+        net.forward(x, probs)
+        net.train_step(x, y, 1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.forward(x, probs)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.train_step(x, y, 1e-3)
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / reps
+    fwd = 2.0 * batch * (inp * hidden + (depth - 1) * hidden * hidden + hidden * classes)
+    net.free()
+    _log(f"network: forward {t_fwd * 1e3:.3f} ms, train step {t_step * 1e3:.3f} ms")
+    return {"shape": f"{inp}->{hidden}x{depth}->{classes}", "batch": batch,
+            "forward_ms": t_fwd * 1e3, "forward_tflops": fwd / t_fwd / 1e12,
+            "train_step_ms": t_step * 1e3, "train_step_tflops": 3 * fwd / t_step / 1e12,
+            "train_step_bf16_frac": 3 * fwd / t_step / 2.5e15,
+            "flops_counted": "GEMMs only: 2 b (in h + (d-1) h^2 + h c) forward, 3x that per training step"}
+
+
+LEARNED_ORDERS = ("plain", "learned_first")
+
+
+def mlp_leg(ctx, train_count: int, epochs: int, eval_count: int, cap: float, orders=LEARNED_ORDERS,
+            log2_table: int = 24):
     """Learned depth order at n = 3: train on seeded circuits (k uniform in 1..10) labelled by exact
-    meet-in-the-middle search, then search held-out targets with the plain and the learned order."""
+    meet-in-the-middle search, then search each held-out target alone, once per order, with a wall
+    clock cap per search (every chunk of an odd depth concurrent, 2^log2_table slots):
+      plain              depths in increasing order (the paper's search);
+      learned_first      depths by descending p_k / c_k (network probability over the steps the
+                         depth costs when it holds no decomposition), the first verified decomposition
+                         returned (time to the first exact answer);
+      learned_certified  the same order, then every unsearched depth below a hit searched, the lowest
+                         returned (certified minimal; it cannot save the failing depths' work);
+      learned_prob_first depths by descending p_k alone, first hit (the order without costs).
+    A search counts as solved only when its T-count is the target's minimum (the exact label when it
+    is <= 6, else the least T-count any order found); a larger T-count is reported and counted as a
+    failure, with the cap as its time."""
     import numpy as np
     import torch
 
@@ -479,7 +629,10 @@ def mlp_leg(ctx, train_count: int, epochs: int, eval_count: int, cap: float):
     def dataset(words):
         feats = torch.empty((len(words), 16 ** n), dtype=torch.float32, device="cuda:0")
         labels = torch.empty(len(words), dtype=torch.int32, device="cuda:0")
-        ctx.label_batch(n, [(w.paulis, w.clifford) for w in words], h_max, 777, feats, labels)
+        for lo in range(0, len(words), 1 << 17):
+            part = words[lo:lo + (1 << 17)]
+            ctx.label_batch(n, [(w.paulis, w.clifford) for w in part], h_max, 777, feats[lo:lo + len(part)],
+                            labels[lo:lo + len(part)])
         return feats, labels
 
     t0 = time.perf_counter()
@@ -490,6 +643,7 @@ def mlp_leg(ctx, train_count: int, epochs: int, eval_count: int, cap: float):
     gen_k = torch.tensor([w.k for w in train], dtype=torch.int32, device="cuda:0")
     unknown = labels < 0
     labels = torch.where(unknown, gen_k, labels)       # T-count > 2 h_max: the generating k (an upper bound)
+    del train, gen_k
     _log(f"labelled {train_count} circuits in {t_label:.1f} s ({int(unknown.sum())} above {2 * h_max})")
     net = tcw.Network(ctx, 16 ** n, spec["hidden"], spec["depth"], classes, seed=spec["init_seed"])
     t1 = time.perf_counter()
@@ -498,7 +652,7 @@ def mlp_leg(ctx, train_count: int, epochs: int, eval_count: int, cap: float):
     t_train = time.perf_counter() - t1
     _log(f"trained {epochs} epochs in {t_train:.1f} s, loss {loss:.3f}")
     flops = 6.0 * train_count * epochs * sum(a * b for a, b in [(16 ** n, 512), (512, 512), (512, 512), (512, classes)])
-    del feats
+    del feats, labels
 
     ev = seeded_inputs.mlp_targets(spec["eval_seeds"][0], spec["eval_seeds"][0] + eval_count)
     ef, el = dataset(ev)
@@ -507,47 +661,64 @@ def mlp_leg(ctx, train_count: int, epochs: int, eval_count: int, cap: float):
     pred = probs.argmax(dim=1).to(torch.int32)
     known = el >= 0
     acc = float((pred[known] == el[known]).float().mean()) if bool(known.any()) else None
+    exact = [int(v) for v in el.cpu().tolist()]
+    del ef
 
-    targets = [ctx.target_from_words(n, w.paulis, w.clifford) for w in ev]
-    results = {}
-    for name in ("plain", "learned"):
-        params = []
-        for i, (w, tgt) in enumerate(zip(ev, targets)):
+    runs = {name: [] for name in orders}
+    t_eval = time.perf_counter()
+    for i, w in enumerate(ev):
+        tgt = ctx.target_from_words(n, w.paulis, w.clifford)
+        for name in orders:
             p = ctx.default_params(n)
             p.k_max = spec["k_range"][1]
             p.seed = 9000 + i
-            p.walks = 0
-            p.log2_table = 0
-            p.iters_per_launch = 0
+            p.log2_table = log2_table
+            p.chunk_parallel = 0
             p.max_seconds = cap
-            if name == "learned":
-                order, _ = net.depth_order(tgt, p.k_max)
-                p.depth_order_kind = tcw.ORDER_GIVEN
+            if name != "plain":
+                order, _ = net.depth_order(tgt, p.k_max, None if name == "learned_prob_first" else p)
+                p.depth_order_kind = tcw.ORDER_GIVEN if name == "learned_certified" else tcw.ORDER_GIVEN_FIRST
                 p.depth_order_len = len(order)
                 for j, kk in enumerate(order):
                     p.depth_order[j] = kk
-            params.append(p)
-        ts = time.perf_counter()
-        res, agg = ctx.search_batch(targets, params)
-        results[name] = (res, time.perf_counter() - ts)
-        _log(f"{name} order: {sum(r.status for r in res)}/{eval_count} solved in {results[name][1]:.1f} s")
-    pr, lr_ = results["plain"][0], results["learned"][0]
-    both = [i for i in range(eval_count) if pr[i].status and lr_[i].status]
-    tts = {name: [r.seconds if r.status else cap for r in results[name][0]] for name in results}
-    return {
-        "train_circuits": train_count, "label_seconds": t_label, "unknown_labels": int(unknown.sum()),
-        "epochs": epochs, "train_seconds": t_train, "final_loss": loss,
-        "train_tflops": flops / t_train / 1e12, "mfma_bf16_frac": flops / t_train / 2.5e15,
-        "eval_circuits": eval_count, "eval_accuracy_exact_labels": acc, "cap_s": cap,
-        "plain": {"solved": sum(r.status for r in pr), "mean_tts_s_censored_at_cap": float(np.mean(tts["plain"])),
-                  "wall_s": results["plain"][1]},
-        "learned": {"solved": sum(r.status for r in lr_), "mean_tts_s_censored_at_cap": float(np.mean(tts["learned"])),
-                    "wall_s": results["learned"][1]},
-        "solved_by_both": len(both),
-        "mean_tts_both_s": {"plain": float(np.mean([pr[i].seconds for i in both])) if both else None,
-                            "learned": float(np.mean([lr_[i].seconds for i in both])) if both else None},
-        "learned_larger_t": sum(1 for i in both if lr_[i].t > pr[i].t),
-    }
+            r = ctx.search(tgt, p)
+            runs[name].append((r.t if r.status == 1 else None, r.seconds, r.stats.steps))
+        tgt.free()
+        if i % 32 == 31:
+            _log(f"learned order: {i + 1}/{eval_count} held-out targets searched, {time.perf_counter() - t_eval:.1f} s")
+    # the minimum T-count of each held-out target: the exact label, else the least any order found
+    t_min = []
+    for i in range(eval_count):
+        found = [runs[nm][i][0] for nm in orders if runs[nm][i][0] is not None]
+        t_min.append(exact[i] if exact[i] >= 0 else (min(found) if found else None))
+    out = {"train_circuits": train_count, "label_seconds": t_label, "unknown_labels": int(unknown.sum()),
+           "epochs": epochs, "train_seconds": t_train, "final_loss": loss,
+           "train_tflops": flops / t_train / 1e12, "mfma_bf16_frac": flops / t_train / 2.5e15,
+           "eval_circuits": eval_count, "eval_accuracy_exact_labels": acc, "cap_s": cap, "log2_table": log2_table,
+           "eval_seconds": time.perf_counter() - t_eval,
+           "targets_with_known_minimum": sum(1 for v in t_min if v is not None)}
+    ok = {nm: [runs[nm][i][0] is not None and runs[nm][i][0] == t_min[i] for i in range(eval_count)] for nm in orders}
+    for nm in orders:
+        secs = [runs[nm][i][1] if ok[nm][i] else cap for i in range(eval_count)]
+        out[nm] = {"solved_minimal": sum(ok[nm]),
+                   "larger_t": sum(1 for i in range(eval_count) if runs[nm][i][0] is not None and not ok[nm][i]),
+                   "mean_tts_s_censored": float(np.mean(secs)),
+                   "mean_steps": float(np.mean([runs[nm][i][2] for i in range(eval_count)]))}
+    both = [i for i in range(eval_count) if all(ok[nm][i] for nm in orders)]
+    out["solved_minimal_by_all"] = len(both)
+    out["on_solved_by_all"] = {nm: {"mean_s": float(np.mean([runs[nm][i][1] for i in both])) if both else None,
+                                    "mean_steps": float(np.mean([runs[nm][i][2] for i in both])) if both else None}
+                               for nm in orders}
+    # by minimum T-count: targets, and the mean seconds and steps of each order where all solved
+    by_t = {}
+    for tm in sorted(set(v for v in t_min if v is not None)):
+        idx = [i for i in both if t_min[i] == tm]
+        by_t[str(tm)] = {"targets": sum(1 for v in t_min if v == tm), "solved_by_all": len(idx)}
+        for nm in orders:
+            by_t[str(tm)][nm] = {"mean_s": float(np.mean([runs[nm][i][1] for i in idx])) if idx else None,
+                                 "mean_steps": float(np.mean([runs[nm][i][2] for i in idx])) if idx else None}
+    out["by_min_tcount"] = by_t
+    return out
 
 
 def main():
@@ -559,20 +730,18 @@ def main():
     ap.add_argument("--walks", type=int, default=1 << 20)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-tts", action="store_true")
+    ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution legs")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain depth order block")
+    ap.add_argument("--no-network", action="store_true", help="skip the network forward / training-step timing")
     ap.add_argument("--batch", action="store_true", help="also run the 64-target mixed batch")
     ap.add_argument("--batch-cap", type=float, default=30.0, help="per-target wall-clock cap (s)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration for profiles)")
-    ap.add_argument("--tts-n4", action="store_true",
-                    help="also run the whole optimal-T-count search for the four n = 4, k = 7 targets")
-    ap.add_argument("--tts-n4-enum", action="store_true",
-                    help="also run the n = 4 searches with every space enumerated exhaustively")
-    ap.add_argument("--tts-n4-cap", type=float, default=150.0, help="wall-clock cap per n = 4 target (s)")
-    ap.add_argument("--tts-n4-planted", action="store_true",
-                    help="also search the planted depth-7 chunk of n = 4 targets 2..4 at theta = 2^-12")
-    ap.add_argument("--tts-n4-planted-cap", type=float, default=600.0, help="wall-clock cap per target (s)")
-    ap.add_argument("--tts-n4-planted-seeds", default="2,3,4", help="target seeds (comma-separated)")
+    ap.add_argument("--tts-n4-cap", type=float, default=40.0, help="wall-clock cap per n = 4 target (s)")
+    ap.add_argument("--tts-n4-seeds", default="2,3,4", help="n = 4, k = 7 target seeds (comma-separated)")
+    ap.add_argument("--tts-n4-planted-cap", type=float, default=20.0,
+                    help="wall-clock cap of the configured-theta planted-chunk search (s)")
+    ap.add_argument("--tts-n4-planted-seeds", default="2", help="target seeds (comma-separated)")
     ap.add_argument("--named", action="store_true",
                     help="also synthesise Toffoli, Fredkin and Peres (n = 3, T-count 7) repeatedly")
     ap.add_argument("--named-reps", type=int, default=20)
@@ -581,11 +750,13 @@ def main():
                     help="also run the n = 2, k = 4 and n = 3, k = 6 searches and walk rates")
     ap.add_argument("--cpu-configs", action="store_true",
                     help="with the CPU baseline, also time the oracle at every configuration")
-    ap.add_argument("--mlp", action="store_true", help="also train the depth-order network and compare orders")
-    ap.add_argument("--mlp-train", type=int, default=1 << 16, help="training circuits")
+    ap.add_argument("--mlp-train", type=int, default=1 << 17, help="training circuits of the learned order")
     ap.add_argument("--mlp-epochs", type=int, default=8)
     ap.add_argument("--mlp-eval", type=int, default=256, help="held-out circuits")
-    ap.add_argument("--mlp-cap", type=float, default=20.0, help="per-target wall-clock cap (s) in the comparison")
+    ap.add_argument("--mlp-cap", type=float, default=1.0, help="wall-clock cap (s) of each held-out search")
+    ap.add_argument("--mlp-log2-table", type=int, default=24, help="table slots (log2) of the held-out searches")
+    ap.add_argument("--mlp-orders", default=",".join(LEARNED_ORDERS),
+                    help="orders to compare (plain, learned_first, learned_certified, learned_prob_first)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the walk search here runs on one GPU; --gpus must be 1"}))
@@ -597,15 +768,15 @@ def main():
     from paper_1606_07413_amd import tcw
 
     n, k, delta, log2_table = 4, 7, 12, 26
-    seed = 3001
-    tw = seeded_inputs.target_words(n, k, 1)
+    seed, target_seed = 3001, 2
+    tw = seeded_inputs.target_words(n, k, target_seed)
     chunk = tw.paulis[0]
     ctx = tcw.Context(0)
     tgt = ctx.target_from_words(n, tw.paulis, tw.clifford)
     w = ctx.walk(tgt, k, chunk, seed, delta, walks=args.walks, log2_table=log2_table, cap=20 << delta)
     for i in range(args.warmup):
         w.run(args.iters)
-        print(f"warmup launch {i} done", file=sys.stderr, flush=True)
+        _log(f"warmup launch {i} done")
     torch.cuda.synchronize()
     before = w.stats().steps
     kernel_ms = []
@@ -621,67 +792,14 @@ def main():
     elapsed = t1 - t0
     value = steps / elapsed
     avg_ms = sum(kernel_ms) / len(kernel_ms)
-    per_launch_steps = args.walks * args.iters
-    ops = valu_ops_per_step(n, k // 2) * per_launch_steps
-    achieved = ops / (avg_ms * 1e-3) / 1e12
-    peak = VALU_PEAK_OPS / 1e12
-    mfma_achieved = mfma_ops_per_step(n) * per_launch_steps / (avg_ms * 1e-3)
+    _log(f"walk kernel: {value:.4g} steps/s, {avg_ms:.3f} ms per launch")
     w.end()
+    tgt.free()
     if args.copy_mib:
         src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-
-    extra = {}
-    if not args.no_tts:
-        # time-to-solution at n = 3, k = 6 (measured); n = 4, k = 7 below
-        # (target seed 5: optimum 6, so the depth-6 walks run; seeds 1, 2 and 8 have optimum 4)
-        tw3 = seeded_inputs.target_words(3, 6, 5)
-        t3 = ctx.target_from_words(3, tw3.paulis, tw3.clifford)
-        runs3 = {}
-        for name, d3 in (("configured_theta", seeded_inputs.WORKLOADS["n3k6"]["delta"]), ("default_theta", -1)):
-            p3 = ctx.default_params(3)
-            p3.k_max = 6
-            p3.delta = d3
-            p3.seed = 2001
-            p3.max_seconds = 120
-            r3 = ctx.search(t3, p3)
-            runs3[name] = {"seconds": r3.seconds, "found_t": r3.t if r3.status else None,
-                           "steps": r3.stats.steps, "versions": r3.versions}
-        t3.free()
-        extra["tts_n3k6"] = {"target_seed": 5, "measured": True, "delta": seeded_inputs.WORKLOADS["n3k6"]["delta"],
-                             **runs3["configured_theta"], "default_theta": runs3["default_theta"]}
-    if args.tts_n4:
-        extra["tts_n4k7_theta_half"] = tts_n4_leg(ctx, args.tts_n4_cap)
-    if args.tts_n4_enum:
-        extra["tts_n4k7_exhaustive"] = tts_n4_enum_leg(ctx, args.tts_n4_cap)
-    if args.tts_n4_planted:
-        extra["tts_n4k7_planted_chunk"] = tts_n4_planted_leg(
-            ctx, args.tts_n4_planted_cap, seeds=tuple(int(v) for v in args.tts_n4_planted_seeds.split(",")))
-    if not args.no_tts:
-        # the whole optimal-T-count search of this target, measured two ways: the walks (theta = 1/2,
-        # chunks of each odd depth concurrent) and exhaustive enumeration of every space.  Its
-        # generating word has 7 rotations but its optimum is lower (two equal adjacent Paulis).
-        walks_run = tts_n4_leg(ctx, 60.0, seeds=(1,))["runs"][0]
-        enum_run = tts_n4_enum_leg(ctx, 60.0, seeds=(1,))["runs"][0]
-        # and a projection for the configured walk search (theta = 2^-12, chunks in ascending order)
-        # of a target of T-count 7 whose claw lies in this chunk
-        n_pts = 2 * 255 ** 3
-        steps_chunk = n_pts * (1 << delta)          # Appendix: about N / theta steps for the chunk with the claw
-        budget = 16 * steps_chunk                   # each earlier chunk fails after its full budget
-        proj = (chunk - 1) * budget + steps_chunk
-        extra["tts_n4k7"] = {
-            "target_seed": 1, "measured": True,
-            "walks_theta_half": {**walks_run, "theta": 0.5, "chunk_parallel": "all", "cap_s": 60.0},
-            "exhaustive": {**enum_run, "enum_max": 1 << 26, "cap_s": 60.0},
-            "configured_theta_projection": {
-                "seconds": proj / value, "measured": False,
-                "basis": f"a T-count-7 target with its claw in chunk {chunk}, theta = 2^-{delta}, chunks in "
-                         f"ascending order: {chunk - 1} chunks x budget {budget:.3g} steps + N/theta = "
-                         f"{steps_chunk:.3g} steps in that chunk, at the measured rate"}}
-
-    traffic = measured_traffic(args.walks, args.iters)
     out = {
         "metric": "walk steps/s + time-to-solution at n=4,k=7; learned depth order vs plain",
         "value": value,
@@ -694,21 +812,24 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32/int8 exact (Z/(2^61-1) digests)",
-        "data": "synthetic seeded target (product of 7 R(P) times a seeded Clifford)",
-        "config": {"workload": "n4k7", "n": n, "k": k, "chunk": chunk, "walks": args.walks, "delta": delta,
-                   "log2_table": log2_table, "iters_per_launch": args.iters, "parallelism": "1 GPU"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s", "frac": achieved / peak,
-                     "traffic": traffic, "traffic_unit": "HBM bytes per launch",
-                     "kernel": "k_walk<4,12>", "kernel_ms": avg_ms, "kernel_source_sha256": kernel_source_digest(),
-                     "mfma_i8": {"achieved": mfma_achieved / 1e12, "peak": MFMA_I8_PEAK_OPS / 1e12, "unit": "Tops/s",
-                                 "frac": mfma_achieved / MFMA_I8_PEAK_OPS},
-                     # the measured HBM bytes per launch over the live kernel time
-                     "hbm": None if traffic is None else
-                     {"achieved": traffic / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_BYTES / 1e9, "unit": "GB/s",
-                      "frac": traffic / (avg_ms * 1e-3) / HBM_PEAK_BYTES}},
+        "data": "synthetic seeded target (product of 7 R(P) times a seeded Clifford; T-count 7)",
+        "config": {"workload": "n4k7", "n": n, "k": k, "target_seed": target_seed, "chunk": chunk,
+                   "walks": args.walks, "delta": delta, "log2_table": log2_table, "iters_per_launch": args.iters,
+                   "parallelism": "1 GPU"},
+        "roofline": walk_roofline(n, k // 2, args.walks * args.iters, avg_ms, args.walks, args.iters),
         "walk_stats": st.as_dict(),
     }
-    out.update(extra)
+    if not args.no_tts:
+        out["tts_n3k6"] = tts_n3k6_leg(ctx)
+        out["tts_n4k7_theta_half"] = tts_n4_leg(ctx, args.tts_n4_cap,
+                                                 seeds=tuple(int(v) for v in args.tts_n4_seeds.split(",")))
+        out["tts_n4k7_planted_chunk_configured_theta"] = tts_n4_planted_leg(
+            ctx, args.tts_n4_planted_cap, seeds=tuple(int(v) for v in args.tts_n4_planted_seeds.split(",")))
+    if not args.no_network:
+        out["network"] = network_leg(ctx)
+    if not args.no_learned:
+        out["learned_order"] = mlp_leg(ctx, args.mlp_train, args.mlp_epochs, args.mlp_eval, args.mlp_cap,
+                                       orders=tuple(args.mlp_orders.split(",")), log2_table=args.mlp_log2_table)
     if args.configs:
         out["configs"] = config_legs(ctx)
     if args.batch:
@@ -716,10 +837,8 @@ def main():
         out["batch64_default_theta"] = batch_leg(ctx, args.batch_cap, configured_theta=False)
     if args.named:
         out["named_n3_t7"] = named_leg(ctx, args.named_reps, args.named_reps_default_theta)
-    if args.mlp:
-        out["learned_order"] = mlp_leg(ctx, args.mlp_train, args.mlp_epochs, args.mlp_eval, args.mlp_cap)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, k, chunk, seed, delta, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(n, k, chunk, target_seed, seed, delta, args.cpu_seconds)
         if args.cpu_configs:
             out["cpu_baseline"]["configs"] = cpu_configs(5.0)
     print(json.dumps(out), flush=True)

@@ -378,7 +378,16 @@ int tcw_circuit(const tcw_result* res, tcw_gate* gates, int32_t cap, int32_t* co
  * of the mean cross-entropy (host array of param_count floats) and the loss, no update.  A label
  * outside 0..classes-1 adds no loss term and no one-hot target (its probabilities are pushed down).
  * tcw_mlp_train_step: one Adam step on a batch.  tcw_mlp_depth_order: order_out[0..k_max] = depths
- * 0..k_max by descending predicted probability (ties: smaller first); probs_out (host, may be NULL).
+ * 0..k_max by descending key, ties smaller first: with params NULL the key is the predicted
+ * probability p_k; with search parameters it is p_k / c_k, c_k as tcw_depth_costs gives it (the
+ * expected-cost order for one hidden answer: a depth that probably holds it and costs little goes
+ * first); probs_out (host, may be NULL) receives every class probability.  k_max <= 63.
+ * tcw_depth_costs: cost_out[0..k_max] (host) = the walk steps the search driver spends on depth k
+ * under params when that depth holds no decomposition (Sec. 3, eq:runtime, and the appendix law:
+ * each chunk's budget beta N / theta, or N points when the space is enumerated, with theta resolved
+ * as the driver resolves an open delta), plus 2^20 steps of fixed cost per depth; HUGE_VAL for a
+ * depth whose spaces exceed 32-bit points.  Parameters checked as for tcw_search_batch (walks,
+ * log2_table 0: the autotuned defaults).
  * All blocking except where noted; device pointers as elsewhere. */
 typedef struct tcw_mlp tcw_mlp;
 int tcw_features(tcw_ctx* ctx, const tcw_target* t, float* out_dev);
@@ -394,7 +403,9 @@ int tcw_mlp_forward(tcw_mlp* m, const float* x_dev, int batch, float* probs_dev)
 int tcw_mlp_gradients(tcw_mlp* m, const float* x_dev, const int32_t* labels_dev, int batch, float* grads_host,
                       float* loss);
 int tcw_mlp_train_step(tcw_mlp* m, const float* x_dev, const int32_t* labels_dev, int batch, float lr, float* loss);
-int tcw_mlp_depth_order(tcw_mlp* m, const tcw_target* t, int k_max, int32_t* order_out, float* probs_out);
+int tcw_mlp_depth_order(tcw_mlp* m, const tcw_target* t, int k_max, const tcw_walk_params* params,
+                        int32_t* order_out, float* probs_out);
+int tcw_depth_costs(tcw_ctx* ctx, const tcw_target* t, const tcw_walk_params* params, int k_max, double* cost_out);
 /* tcw_mlp_train: `epochs` passes over count samples (x_dev count x in, labels_dev count) in fixed
  * consecutive batches of `batch` (the last one ragged), one Adam step each; *last_epoch_loss = mean
  * loss over the final pass. */

@@ -2712,9 +2712,54 @@ extern "C" int tcw_features(tcw_ctx* c, const tcw_target* t, float* out_dev) {
     return TCW_OK;
 }
 
-extern "C" int tcw_mlp_depth_order(tcw_mlp* m, const tcw_target* t, int k_max, int32_t* order_out, float* probs_out) {
-    if (!m || !t || !order_out || k_max < 0) return TCW_EINVAL;
+namespace {
+
+// Steps that depth k costs under p when it holds no decomposition of an n-qubit target (eq:runtime
+// and the appendix law give the walks' cost of a space as its budget beta N / theta): every chunk
+// runs its whole space, one step per point when enumerated, else its walk budget, with theta
+// resolved as the driver resolves an open delta (concurrent chunks against their share of the chunk
+// table pool); plus 2^20 steps per depth for set-up, launches and read-backs.  Infinite for a
+// depth whose spaces are beyond 32-bit points.
+double depth_cost_steps(int n, const tcw_walk_params* p, int k) {
+    const double fixed = 1048576.0;
+    if (k == 0) return fixed;
+    const uint64_t nh = n_half_of(n, k / 2);
+    if (nh == 0) return HUGE_VAL;
+    const uint64_t npts = 2 * nh;
+    double chunks = 1;
+    if (k % 2) {
+        const int cf = p->chunk_first > 0 ? p->chunk_first : 1;
+        const int cl = p->chunk_last > 0 ? std::min<int>(p->chunk_last, (int)xi_of(n)) : (int)xi_of(n);
+        chunks = cl >= cf ? cl - cf + 1 : 0;
+    }
+    if ((int64_t)npts <= p->enum_max) return fixed + chunks * (double)npts;
+    int lg = p->log2_table > 0 ? p->log2_table : default_log2_table(n);
+    if (k % 2 && p->chunk_parallel != 1) {
+        const int G = p->chunk_parallel <= 0 ? (int)chunks : p->chunk_parallel;
+        int lg_g = 0;
+        while ((1 << lg_g) < G) ++lg_g;
+        lg = std::max(10, std::min(lg, CHUNK_TABLE_POOL_LOG2 - 4 - lg_g));
+    }
+    const int delta = p->delta >= 0 ? p->delta : auto_delta(npts, lg);
+    return fixed + chunks * (double)p->budget_beta * (double)npts * std::ldexp(1.0, delta);
+}
+
+}  // namespace
+
+extern "C" int tcw_depth_costs(tcw_ctx* c, const tcw_target* t, const tcw_walk_params* p, int k_max,
+                               double* cost_out) {
+    if (!c || !t || !p || !cost_out || k_max < 0 || k_max > 63) return TCW_EINVAL;
+    if (int rc = check_params(c, p, t->n, true)) return rc;
+    for (int k = 0; k <= k_max; ++k) cost_out[k] = depth_cost_steps(t->n, p, k);
+    return TCW_OK;
+}
+
+extern "C" int tcw_mlp_depth_order(tcw_mlp* m, const tcw_target* t, int k_max, const tcw_walk_params* sp,
+                                   int32_t* order_out, float* probs_out) {
+    if (!m || !t || !order_out || k_max < 0 || k_max > 63) return TCW_EINVAL;
     tcw_ctx* c = m->ctx;
+    if (sp)
+        if (int rc = check_params(c, sp, t->n, true)) return rc;
     const int R = 1 << (2 * t->n);
     if (R * R != m->inp) return fail(c, TCW_EINVAL, "network input size does not match the target");
     if (!m->xdev) HIP_TRY(c, hipMalloc(&m->xdev, (size_t)m->inp * 4));
@@ -2726,11 +2771,16 @@ extern "C" int tcw_mlp_depth_order(tcw_mlp* m, const tcw_target* t, int k_max, i
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (probs_out)
         for (int i = 0; i < m->classes; ++i) probs_out[i] = p[i];
-    // depths 0..k_max by descending probability (ties: smaller depth first)
+    // depths 0..k_max by descending key (ties: smaller depth first); the key is the predicted
+    // probability, or with search parameters the probability per step of the depth's cost
     std::vector<int> ks;
-    for (int k = 0; k <= k_max; ++k) ks.push_back(k);
-    auto prob = [&](int k) { return k < m->classes ? p[k] : -1.0f; };
-    std::stable_sort(ks.begin(), ks.end(), [&](int a, int b) { return prob(a) > prob(b); });
+    std::vector<double> key(k_max + 1);
+    for (int k = 0; k <= k_max; ++k) {
+        ks.push_back(k);
+        const double pk = k < m->classes ? (double)p[k] : 0.0;
+        key[k] = sp ? pk / depth_cost_steps(t->n, sp, k) : pk;
+    }
+    std::stable_sort(ks.begin(), ks.end(), [&](int a, int b) { return key[a] > key[b]; });
     for (int i = 0; i <= k_max; ++i) order_out[i] = ks[i];
     return TCW_OK;
 }

@@ -135,7 +135,9 @@ _SIGS = {
     "tcw_mlp_forward": (C.c_int, [_P, _P, C.c_int, _P]),
     "tcw_mlp_gradients": (C.c_int, [_P, _P, _P, C.c_int, _P, C.POINTER(C.c_float)]),
     "tcw_mlp_train_step": (C.c_int, [_P, _P, _P, C.c_int, C.c_float, C.POINTER(C.c_float)]),
-    "tcw_mlp_depth_order": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+    "tcw_mlp_depth_order": (C.c_int, [_P, _P, C.c_int, C.POINTER(WalkParams), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_float)]),
+    "tcw_depth_costs": (C.c_int, [_P, _P, C.POINTER(WalkParams), C.c_int, C.POINTER(C.c_double)]),
     "tcw_mlp_train": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int, C.c_int, C.c_float, C.POINTER(C.c_float)]),
 }
 
@@ -324,6 +326,13 @@ class Context:
         p = WalkParams()
         self.lib.tcw_default_params(C.byref(p), n)
         return p
+
+    def depth_costs(self, target, params: WalkParams, k_max: int):
+        """Walk steps the driver spends on each depth 0..k_max under params when it holds no
+        decomposition (tcw_depth_costs)."""
+        out = (C.c_double * (k_max + 1))()
+        self._check(self.lib.tcw_depth_costs(self.h, target.h, C.byref(params), k_max, out))
+        return list(out)
 
     def search(self, target, params: WalkParams) -> Result:
         res = Result()
@@ -576,10 +585,14 @@ class Network:
                                                    lr, C.byref(loss)))
         return loss.value
 
-    def depth_order(self, target, k_max):
+    def depth_order(self, target, k_max, params=None):
+        """Depths 0..k_max by descending predicted probability, or with search parameters by
+        descending probability per step of each depth's cost (tcw_depth_costs)."""
         order = (C.c_int32 * (k_max + 1))()
         probs = (C.c_float * self.dims[3])()
-        self.ctx._check(self.ctx.lib.tcw_mlp_depth_order(self.h, target.h, k_max, order, probs))
+        self.ctx._check(self.ctx.lib.tcw_mlp_depth_order(self.h, target.h, k_max,
+                                                         C.byref(params) if params is not None else None,
+                                                         order, probs))
         return list(order), list(probs)
 
     def free(self):

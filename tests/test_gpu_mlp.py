@@ -331,52 +331,129 @@ def test_training_reduces_loss_and_orders_depths(ctx):
     assert probs[order[0]] == max(probs[:7])
 
 
+def test_depth_costs_and_cost_aware_order(ctx):
+    """tcw_depth_costs: a depth's cost is the steps the driver spends on it when it holds no
+    decomposition (every chunk's budget beta N / theta, or its N points when enumerated, plus a fixed
+    2^20); the cost-aware order sorts depths by p_k / c_k."""
+    from paper_1606_07413_amd import tcw
+    print("depth costs", flush=True)
+    tw = seeded_inputs.target_words(3, 6, 5)
+    tgt = ctx.target_from_words(3, tw.paulis, tw.clifford)
+    p = ctx.default_params(3)
+    p.k_max = 10
+    p.log2_table = 24
+    p.delta = -1
+    costs = ctx.depth_costs(tgt, p, 10)
+    fixed = float(1 << 20)
+    assert costs[0] == fixed
+    # depths 1..5: enumerated (N = 2 * 63^(k // 2) <= 2^16), 63 chunks at odd k
+    assert costs[1] == fixed + 63 * 2
+    assert costs[2] == fixed + 2 * 63
+    assert costs[5] == fixed + 63 * 2 * 63 ** 2
+    # depth 6: walks, N = 2 * 63^3, theta from the table: 8 N <= 2^(24 + delta) -> delta = 1
+    n6 = 2 * 63 ** 3
+    assert costs[6] == fixed + 16 * n6 * 2
+    # depth 8: N = 2 * 63^4 -> delta = 4
+    n8 = 2 * 63 ** 4
+    assert costs[8] == fixed + 16 * n8 * 16
+    assert all(costs[k] < costs[k + 2] for k in range(9))
+    # a given delta and budget are used as given
+    p.delta = 3
+    p.budget_beta = 4
+    assert ctx.depth_costs(tgt, p, 6)[6] == fixed + 4 * n6 * 8
+    # order: depths by p_k / c_k (a network of untrained weights gives some p)
+    net = tcw.Network(ctx, 4096, 64, 3, 11, seed=3)
+    p.delta = -1
+    p.budget_beta = 16
+    order, probs = net.depth_order(tgt, 10, p)
+    key = [probs[k] / costs[k] for k in range(11)]
+    assert order == sorted(range(11), key=lambda k: (-key[k], k))
+    order_p, _ = net.depth_order(tgt, 10)
+    assert order_p == sorted(range(11), key=lambda k: (-probs[k], k))
+    bad = ctx.default_params(3)
+    bad.budget_beta = 0
+    with pytest.raises(tcw.TcwError):
+        ctx.depth_costs(tgt, bad, 6)
+    with pytest.raises(tcw.TcwError):
+        net.depth_order(tgt, 10, bad)
+
+
 def test_learned_order_gains_over_plain(ctx):
-    """A network trained on n = 3 circuits with k in 1..6 (exact labels) orders depths; searched with
-    TCW_ORDER_GIVEN_FIRST (the first verified decomposition) the search visits fewer spaces than the
-    plain increasing order.  Answers stay exact; their T-count is at least the plain order's, and a
-    larger one is reported as not minimal."""
+    """A network trained on n = 3 circuits (k in 1..8; exact labels up to 6, the generating k above)
+    orders depths by p_k / c_k.  On 64 held-out targets (k in 4..7), each searched alone, the first
+    verified decomposition under that order (TCW_ORDER_GIVEN_FIRST) takes less wall time in total than
+    the plain increasing order, which must fail every depth below the answer first (compared over the
+    targets both orders solve with the minimal T-count).  Every learned answer is exact; one with a
+    larger T-count than the plain order's is flagged not minimal.  The walk search is randomised, so
+    either order can miss a decomposition within its budget: a few such misses are allowed and
+    counted.  With the same order certified (TCW_ORDER_GIVEN) the answer is the minimum: for T-count
+    <= 6 it equals the meet-in-the-middle certificate's."""
     import torch
     from oracle import search as osearch
     from paper_1606_07413_amd import tcw
     print("learned gain", flush=True)
-    train = seeded_inputs.mlp_targets(20_000, 20_000 + 4096, k_lo=1, k_hi=6)
+    train = seeded_inputs.mlp_targets(20_000, 20_000 + 8192, k_lo=1, k_hi=8)
     feats, labels = _label(ctx, 3, [(w.paulis, w.clifford) for w in train], 3)
-    lab = torch.tensor(labels, dtype=torch.int32, device="cuda:0")
-    assert (lab >= 0).all()
+    lab = torch.tensor([v if v >= 0 else w.k for v, w in zip(labels, train)], dtype=torch.int32, device="cuda:0")
     net = tcw.Network(ctx, 4096, 256, 3, 11, seed=42)
     net.train(feats, lab, 512, 6, 1e-3)
-    held = seeded_inputs.mlp_targets(30_000, 30_012, k_lo=5, k_hi=6)
-    spaces = {"plain": 0, "learned": 0}
+    held = seeded_inputs.mlp_targets(30_000, 30_064, k_lo=4, k_hi=7)
+    _, exact = _label(ctx, 3, [(w.paulis, w.clifford) for w in held], 3)
+    secs = {"plain": 0.0, "learned": 0.0}
+    misses = {"plain": 0, "learned": 0}
+    larger = compared = 0
     for i, w in enumerate(held):
         tgt = ctx.target_from_words(3, w.paulis, w.clifford)
         found = {}
-        for name in ("plain", "learned"):
+        for name in ("plain", "learned", "certified"):
+            if name == "certified" and i % 4:
+                continue
             p = ctx.default_params(3)
-            p.k_max = 6
+            p.k_max = 8
             p.seed = 40 + i
-            p.walks = 1 << 14       # walk spaces at depth 6: generous budget so both orders finish
-            p.budget_beta = 64
-            p.max_seconds = 60
-            if name == "learned":
-                order, _ = net.depth_order(tgt, 6)
-                p.depth_order_kind = tcw.ORDER_GIVEN_FIRST
+            p.log2_table = 22
+            p.chunk_parallel = 0
+            p.max_seconds = 5.0
+            if name != "plain":
+                order, _ = net.depth_order(tgt, 8, p)
+                p.depth_order_kind = tcw.ORDER_GIVEN_FIRST if name == "learned" else tcw.ORDER_GIVEN
                 p.depth_order_len = len(order)
                 for j, kk in enumerate(order):
                     p.depth_order[j] = kk
-            r = ctx.search(tgt, p)
-            assert r.status == 1
-            spaces[name] += r.spaces
-            found[name] = r
+            found[name] = ctx.search(tgt, p)
         u = zmat.target_from_words(3, w.paulis, w.clifford)
-        d = tcw.decomposition_of(found["learned"])
-        assert osearch.reconstruct(3, osearch.Decomposition(t=d.t, paulis_desc=d.paulis_desc, perm=d.perm,
-                                                            sign=d.sign)).equals(u)
-        assert found["learned"].t >= found["plain"].t and found["plain"].minimal == 1
-        if found["learned"].t > found["plain"].t:
-            assert found["learned"].minimal == 0
-    print("spaces searched", spaces, flush=True)
-    assert spaces["learned"] < spaces["plain"]
+        for name, r in found.items():
+            if r.status == 1:
+                d = tcw.decomposition_of(r)
+                assert osearch.reconstruct(3, osearch.Decomposition(t=d.t, paulis_desc=d.paulis_desc, perm=d.perm,
+                                                                    sign=d.sign)).equals(u), (i, name)
+                if exact[i] >= 0:
+                    assert r.t >= exact[i]
+                    assert r.minimal == 0 or r.t == exact[i], (i, name)
+            elif name in misses:
+                misses[name] += 1
+        pl, le = found["plain"], found["learned"]
+        if pl.status == 1 and exact[i] >= 0:
+            assert pl.t == exact[i] and pl.minimal == 1
+        if pl.status == 1 and le.status == 1:
+            if le.t > pl.t:
+                assert le.minimal == 0
+                larger += 1
+            else:
+                assert le.t == pl.t
+                secs["plain"] += pl.seconds
+                secs["learned"] += le.seconds
+                compared += 1
+        if "certified" in found and found["certified"].status == 1:
+            ce = found["certified"]
+            assert ce.minimal == 1
+            if exact[i] >= 0:
+                assert ce.t == exact[i] == ctx.min_tcount(tgt, 3)
+        tgt.free()
+    print("total seconds", secs, "over", compared, "targets; misses", misses, "larger T-count", larger, flush=True)
+    assert misses["plain"] <= 2 and misses["learned"] <= 2 and larger <= 2
+    assert compared >= 58
+    assert secs["learned"] < secs["plain"]
 
 
 def test_label_batch_validates_words(ctx):
