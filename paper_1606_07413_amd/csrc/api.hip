@@ -996,23 +996,44 @@ void add_stats(tcw_walk_stats& a, const tcw_walk_stats& b) {
 
 // Exact check of claw candidate pairs (host arrays) of a space: the first that passes, in the order
 // given, fills res.
-int check_pairs(tcw_ctx* c, const Space& sp, const uint64_t* u0, const uint64_t* u1, int64_t m, tcw_result* res,
-                int* found) {
-    *found = 0;
-    if (m <= 0) return TCW_OK;
-    const int n = sp.n;
-    const int R = 1 << (2 * n);
+// Device buffers of the exact claw check for up to `cap` candidate pairs of targets with up to r rows.
+struct ClawWs {
     uint64_t *d0 = nullptr, *d1 = nullptr;
-    int32_t *dok = nullptr, *dperm = nullptr;
-    int8_t* dsign = nullptr;
-    DevScope scope;
-    HIP_TRY(c, scope.alloc(&d0, m * 8));
-    HIP_TRY(c, scope.alloc(&d1, m * 8));
-    HIP_TRY(c, scope.alloc(&dok, m * 4));
-    HIP_TRY(c, scope.alloc(&dperm, m * R * 4));
-    HIP_TRY(c, scope.alloc(&dsign, m * R));
-    HIP_TRY(c, hipMemcpyAsync(d0, u0, m * 8, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(d1, u1, m * 8, hipMemcpyHostToDevice, c->stream));
+    int32_t *ok = nullptr, *perm = nullptr;
+    int8_t* sign = nullptr;
+    int64_t cap = 0;
+    int r = 0;
+    ClawWs() = default;
+    ClawWs(const ClawWs&) = delete;
+    ClawWs& operator=(const ClawWs&) = delete;
+    ~ClawWs() { release(); }
+    void release() {
+        for (void* q : {(void*)d0, (void*)d1, (void*)ok, (void*)perm, (void*)sign})
+            if (q) (void)hipFree(q);
+        d0 = d1 = nullptr;
+        ok = perm = nullptr;
+        sign = nullptr;
+        cap = 0;
+        r = 0;
+    }
+    hipError_t reserve(int64_t m, int rows) {
+        if (m <= cap && rows <= r) return hipSuccess;
+        release();
+        hipError_t e;
+        if ((e = hipMalloc(&d0, m * 8)) != hipSuccess || (e = hipMalloc(&d1, m * 8)) != hipSuccess ||
+            (e = hipMalloc(&ok, m * 4)) != hipSuccess || (e = hipMalloc(&perm, m * rows * 4)) != hipSuccess ||
+            (e = hipMalloc(&sign, m * rows)) != hipSuccess) {
+            release();
+            return e;
+        }
+        cap = m;
+        r = rows;
+        return hipSuccess;
+    }
+};
+
+// The context's scratch for exact claw checks of n-qubit spaces, grown when too small.
+int ensure_claw_scratch(tcw_ctx* c, int n) {
     const size_t need = tcw::exact_claw_scratch_bytes(n);
     if (c->claw_scratch_bytes < need) {
         if (c->claw_scratch) (void)hipFree(c->claw_scratch);
@@ -1021,13 +1042,29 @@ int check_pairs(tcw_ctx* c, const Space& sp, const uint64_t* u0, const uint64_t*
         HIP_TRY(c, hipMalloc(&c->claw_scratch, need));
         c->claw_scratch_bytes = need;
     }
-    HIP_TRY(c, tcw::exact_claw_check(sp.S, sp.k, d0, d1, m, c->claw_scratch, c->claw_scratch_bytes, dok, dperm, dsign,
-                                     c->stream));
+    return TCW_OK;
+}
+
+// Exact check of candidate pairs (u0[i], u1[i]) on the context's stream, in the given order; the first
+// verified one fills res.  With ws and the claw scratch already large enough, it allocates nothing (so
+// it can run beside other device work).
+int check_pairs_ws(tcw_ctx* c, const Space& sp, const uint64_t* u0, const uint64_t* u1, int64_t m, tcw_result* res,
+                   int* found, ClawWs& ws) {
+    *found = 0;
+    if (m <= 0) return TCW_OK;
+    const int n = sp.n;
+    const int R = 1 << (2 * n);
+    HIP_TRY(c, ws.reserve(m, R));
+    HIP_TRY(c, hipMemcpyAsync(ws.d0, u0, m * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(ws.d1, u1, m * 8, hipMemcpyHostToDevice, c->stream));
+    if (int rc = ensure_claw_scratch(c, n)) return rc;
+    HIP_TRY(c, tcw::exact_claw_check(sp.S, sp.k, ws.d0, ws.d1, m, c->claw_scratch, c->claw_scratch_bytes, ws.ok,
+                                     ws.perm, ws.sign, c->stream));
     std::vector<int32_t> ok(m), perm(m * R);
     std::vector<int8_t> sign(m * R);
-    HIP_TRY(c, hipMemcpyAsync(ok.data(), dok, m * 4, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(perm.data(), dperm, m * R * 4, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(sign.data(), dsign, m * R, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(ok.data(), ws.ok, m * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(perm.data(), ws.perm, m * R * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(sign.data(), ws.sign, m * R, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     for (int64_t i = 0; i < m; ++i) {
         if (!ok[i]) {
@@ -1056,6 +1093,12 @@ int check_pairs(tcw_ctx* c, const Space& sp, const uint64_t* u0, const uint64_t*
         break;
     }
     return TCW_OK;
+}
+
+int check_pairs(tcw_ctx* c, const Space& sp, const uint64_t* u0, const uint64_t* u1, int64_t m, tcw_result* res,
+                int* found) {
+    ClawWs ws;
+    return check_pairs_ws(c, sp, u0, u1, m, res, found, ws);
 }
 
 // Candidates of an enumerated space are checked in increasing (u0, u1) order, so the decomposition
@@ -1850,10 +1893,14 @@ struct BatchTarget {
     uint64_t searched = 0;    // bit k: depth k was started
     int k = -1, chunk = 0, cl = 0;
     bool walking = false, done = false, cut = false;
+    // held: the space is at its budget or version end but claw candidates of its last round are still
+    // being checked; the member sits out the rounds until they are
+    bool held = false;
+    std::vector<uint64_t> pu0, pu1;  // candidates read after the last round, checked during the next
     std::unique_ptr<Space> space;
     tcw::WalkDev wd{};
     int64_t walks = 0;
-    int iters = 0, log2 = 0, blocks = 0;
+    int iters = 0, log2 = 0;
     uint64_t budget = 0, per_version = 0, used = 0, used_v = 0;
     uint32_t version = 0;
     int64_t seen = 0;
@@ -1867,14 +1914,15 @@ struct BatchBuffers {
     uint64_t* claws = nullptr;             // count x BATCH_CLAW_CAP x 2
     tcw::SpaceDev* sps = nullptr;          // count
     tcw::WalkDev* wds = nullptr;           // count
-    int32_t* blk_target[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    int32_t* tgt_first = nullptr;          // count
-    int32_t* tgt_blocks = nullptr;         // count
+    tcw::WorkItem* items[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // work queue per qubit count
+    int64_t items_cap[5] = {0, 0, 0, 0, 0};
+    int32_t* counts = nullptr;             // 5: items queued per qubit count
+    int32_t* heads = nullptr;              // 5: queue positions (zeroed by a kernel at the start of a round)
     ~BatchBuffers() {
-        for (void* q : {(void*)stats, (void*)claw_count, (void*)claws, (void*)sps, (void*)wds, (void*)tgt_first,
-                        (void*)tgt_blocks})
+        for (void* q : {(void*)stats, (void*)claw_count, (void*)claws, (void*)sps, (void*)wds, (void*)counts,
+                        (void*)heads})
             if (q) (void)hipFree(q);
-        for (auto* q : blk_target)
+        for (auto* q : items)
             if (q) (void)hipFree(q);
     }
 };
@@ -2094,10 +2142,13 @@ void set_minimal(tcw_result* r) {
     r->minimal = (r->failed_depths & below) == below ? 1 : 0;
 }
 
-// Runs every member search of bt (each with its own depth order, chunk range, walks and table)
-// in graph-captured rounds until all are done, or, with stop_on_first, until one member holds a
-// verified decomposition, or until `stop` is due (members still running then end with
-// TCW_STATUS_STOPPED).  *agg: walk steps per second of walk-kernel time.
+// Runs every member search of bt (each with its own depth order, chunk range, walks and table) in
+// rounds until all are done, or, with stop_on_first, until one member holds a verified decomposition,
+// or until `stop` is due (members still running then end with TCW_STATUS_STOPPED).  A round is one
+// replay of a graph captured once: a kernel zeroes the queue positions, then one persistent queue
+// kernel per qubit count takes (member, slice of walks) items until its queue is empty.  Between
+// rounds the host refreshes the queues and the members' descriptors; claw candidates read after a
+// round are checked exactly while the next round runs.  *agg: walk steps per second of round time.
 int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, double t0, double* agg, StopCtl* stop) {
     const int count = (int)bt.size();
     BatchBuffers bb;
@@ -2106,10 +2157,21 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
     HIP_TRY(c, hipMalloc(&bb.claws, (size_t)count * BATCH_CLAW_CAP * 16));
     HIP_TRY(c, hipMalloc(&bb.sps, (size_t)count * sizeof(tcw::SpaceDev)));
     HIP_TRY(c, hipMalloc(&bb.wds, (size_t)count * sizeof(tcw::WalkDev)));
-    HIP_TRY(c, hipMalloc(&bb.tgt_first, (size_t)count * 4));
-    HIP_TRY(c, hipMalloc(&bb.tgt_blocks, (size_t)count * 4));
+    HIP_TRY(c, hipMalloc(&bb.counts, 5 * 4));
+    HIP_TRY(c, hipMalloc(&bb.heads, 5 * 4));
     HIP_TRY(c, hipMemsetAsync(bb.stats, 0, (size_t)count * tcw::ST_COUNT * 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(bb.claw_count, 0, (size_t)count * 8, c->stream));
+    HIP_TRY(c, hipMemsetAsync(bb.counts, 0, 5 * 4, c->stream));
+    // claw-check buffers sized once, so the checks that run beside a round allocate nothing
+    int nmax = 1;
+    bool has_n[5] = {false, false, false, false, false};
+    for (auto& b : bt) {
+        nmax = std::max(nmax, b.t->n);
+        has_n[b.t->n] = true;
+    }
+    ClawWs cws;
+    HIP_TRY(c, cws.reserve(BATCH_CLAW_CAP, 1 << (2 * nmax)));
+    if (int e = ensure_claw_scratch(c, nmax)) return e;
     int rc = TCW_OK;
     for (int i = 0; i < count && !rc; ++i) {
         rc = batch_advance(c, bt[i], i, bb, c->stream, t0, false);
@@ -2158,149 +2220,218 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
         BATCH_TRY(hipEventCreateWithFlags(&join[n], hipEventDisableTiming));
     }
     BATCH_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-    bool dirty = true;
+    int grid[5] = {0, 0, 0, 0, 0};
+    for (int n = 1; n <= 4; ++n) grid[n] = has_n[n] ? tcw::walk_grid_blocks(n, c->device) : 0;
+    bool dirty = true, recapture = true;
     int64_t total_steps = 0;
     double walk_seconds = 0;
     std::vector<unsigned long long> stats((size_t)count * tcw::ST_COUNT), ccount(count);
     std::vector<tcw::SpaceDev> h_sps(count);
     std::vector<tcw::WalkDev> h_wds(count);
-    std::vector<int32_t> h_first(count, 0), h_blocks(count, 0);
-    int iters_n[5] = {0, 0, 0, 0, 0}, blocks_n[5] = {0, 0, 0, 0, 0};
+    std::vector<tcw::WorkItem> h_items[5];
+    int32_t h_counts[5] = {0, 0, 0, 0, 0};
+    std::vector<char> queued(count, 0), hit(count, 0);
     bool stop_first = false;
+
+    // the member's space ended (budget, version, time) or a check found a decomposition: act on it
+    auto settle = [&](int i, bool found) -> int {
+        BatchTarget& b = bt[i];
+        const tcw_walk_stats ws = stats_of(&stats[(size_t)i * tcw::ST_COUNT], ccount[i], b.wd.claw_cap);
+        const bool over_time = b.p.max_seconds > 0 && now_s() - t0 > b.p.max_seconds;
+        if (found || over_time || b.used >= b.budget) {
+            add_stats(b.res->stats, ws);
+            b.walking = false;
+            b.held = false;
+            dirty = true;
+            if (found) batch_on_hit(b);
+            if (over_time && !b.done) {
+                b.done = true;
+                b.cut = true;
+            }
+            if (b.done) {
+                b.res->seconds = now_s() - t0;
+                free_walk_buffers(b);
+            } else {
+                int e = batch_advance(c, b, i, bb, gs[0], t0, !found);
+                if (e) return e;
+                if (b.done) b.res->seconds = now_s() - t0;
+            }
+        } else if (b.used_v >= b.per_version) {
+            add_stats(b.res->stats, ws);
+            b.version++;
+            b.res->versions++;
+            b.space->set_version(b.version);
+            b.used_v = 0;
+            b.seen = 0;
+            b.held = false;
+            dirty = true;
+            int e = batch_restart(c, b, i, bb, gs[0]);
+            if (e) return e;
+        }
+        return TCW_OK;
+    };
+
     for (;;) {
         bool any = false;
-        for (auto& b : bt) any |= b.walking;
+        for (auto& b : bt) any |= b.walking || !b.pu0.empty();
         if (!any) break;
         if (stop && stop->due()) {
             stop->stopped = true;
             break;
         }
         if (dirty) {
-            // block ranges per target, per qubit count
-            std::vector<int32_t> blk[5];
-            for (int n = 1; n <= 4; ++n) {
-                int active = 0;
-                for (auto& b : bt) active += (b.walking && b.t->n == n);
-                if (!active) {
-                    blocks_n[n] = 0;
-                    continue;
-                }
-                const int cap_blocks = std::max(1, tcw::walk_grid_blocks(n, c->device) / active);
-                iters_n[n] = 1 << 30;
-                for (int i = 0; i < count; ++i) {
-                    BatchTarget& b = bt[i];
-                    if (!b.walking || b.t->n != n) continue;
-                    const int wpb = tcw::walks_per_block(n);
-                    b.blocks = (int)std::min<int64_t>((b.walks + wpb - 1) / wpb, cap_blocks);
-                    h_first[i] = (int32_t)blk[n].size();
-                    h_blocks[i] = b.blocks;
-                    for (int j = 0; j < b.blocks; ++j) blk[n].push_back(i);
-                    iters_n[n] = std::min(iters_n[n], b.iters);
-                }
-                blocks_n[n] = (int)blk[n].size();
-                if (bb.blk_target[n]) (void)hipFree(bb.blk_target[n]);
-                bb.blk_target[n] = nullptr;
-                BATCH_TRY(hipMalloc(&bb.blk_target[n], blk[n].size() * 4));
-                BATCH_TRY(hipMemcpy(bb.blk_target[n], blk[n].data(), blk[n].size() * 4, hipMemcpyHostToDevice));
+            // the queues: every walking member that is not held, in slices of its walks (one block's
+            // walks each, or more when that would give over four slices per block of the grid)
+            for (int n = 1; n <= 4; ++n) h_items[n].clear();
+            for (int i = 0; i < count; ++i) {
+                BatchTarget& b = bt[i];
+                queued[i] = b.walking && !b.held;
+                if (!queued[i]) continue;
+                const int n = b.t->n;
+                const int wpb = tcw::walks_per_block(n);
+                const int32_t units = (int32_t)std::min<int64_t>((b.walks + wpb - 1) / wpb, 4 * (int64_t)grid[n]);
+                for (int32_t u = 0; u < units; ++u) h_items[n].push_back(tcw::WorkItem{i, u, units, b.iters});
             }
-            BATCH_TRY(hipMemcpy(bb.tgt_first, h_first.data(), count * 4, hipMemcpyHostToDevice));
-            BATCH_TRY(hipMemcpy(bb.tgt_blocks, h_blocks.data(), count * 4, hipMemcpyHostToDevice));
+            for (int n = 1; n <= 4; ++n) {
+                const int64_t m = (int64_t)h_items[n].size();
+                h_counts[n] = (int32_t)m;
+                if (m > bb.items_cap[n]) {
+                    // a larger queue buffer: its address is a kernel argument, so the graph is captured again
+                    const int64_t cap = std::max<int64_t>(m, 2 * bb.items_cap[n]);
+                    if (bb.items[n]) (void)hipFree(bb.items[n]);
+                    bb.items[n] = nullptr;
+                    bb.items_cap[n] = 0;
+                    BATCH_TRY(hipMalloc(&bb.items[n], (size_t)cap * sizeof(tcw::WorkItem)));
+                    bb.items_cap[n] = cap;
+                    recapture = true;
+                }
+                if (m > 0)
+                    BATCH_TRY(hipMemcpy(bb.items[n], h_items[n].data(), (size_t)m * sizeof(tcw::WorkItem),
+                                        hipMemcpyHostToDevice));
+            }
+            BATCH_TRY(hipMemcpy(bb.counts, h_counts, 5 * 4, hipMemcpyHostToDevice));
+            dirty = false;
+        }
+        if (recapture) {
             if (exec) (void)hipGraphExecDestroy(exec);
             if (graph) (void)hipGraphDestroy(graph);
             exec = nullptr;
             graph = nullptr;
-            // capture: fork one branch per qubit count, join
+            // capture: zero the queue positions (a kernel, not a memset node), fork one branch per qubit
+            // count present in the batch, join
             BATCH_TRY(hipStreamBeginCapture(gs[0], hipStreamCaptureModeThreadLocal));
+            BATCH_TRY(tcw::fill_i32(bb.heads, 0, 5, gs[0]));
             BATCH_TRY(hipEventRecord(fork, gs[0]));
             for (int n = 1; n <= 4; ++n) {
-                if (!blocks_n[n]) continue;
+                if (!grid[n] || !bb.items[n]) continue;
                 BATCH_TRY(hipStreamWaitEvent(gs[n], fork, 0));
-                BATCH_TRY(tcw::launch_walk_batch(n, bb.sps, bb.wds, bb.blk_target[n], bb.tgt_first, bb.tgt_blocks,
-                                                 blocks_n[n], iters_n[n], gs[n]));
+                BATCH_TRY(tcw::launch_walk_queue(n, bb.sps, bb.wds, bb.items[n], bb.counts + n,
+                                                 reinterpret_cast<uint32_t*>(bb.heads + n), grid[n], gs[n]));
                 BATCH_TRY(hipEventRecord(join[n], gs[n]));
                 BATCH_TRY(hipStreamWaitEvent(gs[0], join[n], 0));
             }
             BATCH_TRY(hipStreamEndCapture(gs[0], &graph));
             BATCH_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-            dirty = false;
+            recapture = false;
         }
-        // descriptors for the next graph replay (salts change with versions)
+        bool round = false;
         for (int i = 0; i < count; ++i) {
-            if (!bt[i].walking) continue;
+            if (!queued[i]) continue;
+            round = true;
             h_sps[i] = bt[i].space->dev;
             h_wds[i] = bt[i].wd;
         }
-        BATCH_TRY(hipMemcpyAsync(bb.sps, h_sps.data(), count * sizeof(tcw::SpaceDev), hipMemcpyHostToDevice, gs[0]));
-        BATCH_TRY(hipMemcpyAsync(bb.wds, h_wds.data(), count * sizeof(tcw::WalkDev), hipMemcpyHostToDevice, gs[0]));
         const double tl = now_s();
-        BATCH_TRY(hipGraphLaunch(exec, gs[0]));
-        BATCH_TRY(hipMemcpyAsync(stats.data(), bb.stats, stats.size() * 8, hipMemcpyDeviceToHost, gs[0]));
-        BATCH_TRY(hipStreamSynchronize(gs[0]));
-        walk_seconds += now_s() - tl;
-        if (stop && stop->launches) (*stop->launches)++;
-        // enumerated members whose last point is done: read out their candidates
-        bool formed = false;
+        if (round) {
+            // descriptors for this replay (salts change with versions), then the round itself
+            BATCH_TRY(hipMemcpyAsync(bb.sps, h_sps.data(), count * sizeof(tcw::SpaceDev), hipMemcpyHostToDevice,
+                                     gs[0]));
+            BATCH_TRY(hipMemcpyAsync(bb.wds, h_wds.data(), count * sizeof(tcw::WalkDev), hipMemcpyHostToDevice,
+                                     gs[0]));
+            BATCH_TRY(hipGraphLaunch(exec, gs[0]));
+        }
+        // the last round's claw candidates, checked exactly while this round runs
         for (int i = 0; i < count; ++i) {
             BatchTarget& b = bt[i];
-            if (!b.walking || !b.wd.enumerate) continue;
-            if (stats[(size_t)i * tcw::ST_COUNT + tcw::ST_STEPS] >= b.budget) {
-                BATCH_TRY(tcw::launch_enum_pairs(b.wd, gs[0]));
-                formed = true;
-            }
+            hit[i] = 0;
+            if (b.pu0.empty()) continue;
+            int found = 0;
+            BATCH_RC(check_pairs_ws(c, *b.space, b.pu0.data(), b.pu1.data(), (int64_t)b.pu0.size(), b.res, &found,
+                                    cws));
+            b.pu0.clear();
+            b.pu1.clear();
+            hit[i] = (char)found;
         }
-        if (formed) BATCH_TRY(hipMemcpyAsync(stats.data(), bb.stats, stats.size() * 8, hipMemcpyDeviceToHost, gs[0]));
-        BATCH_TRY(hipMemcpyAsync(ccount.data(), bb.claw_count, count * 8, hipMemcpyDeviceToHost, gs[0]));
-        BATCH_TRY(hipStreamSynchronize(gs[0]));
+        if (round) {
+            BATCH_TRY(hipMemcpyAsync(stats.data(), bb.stats, stats.size() * 8, hipMemcpyDeviceToHost, gs[0]));
+            BATCH_TRY(hipStreamSynchronize(gs[0]));
+            walk_seconds += now_s() - tl;
+            if (stop && stop->launches) (*stop->launches)++;
+            // enumerated members whose last point is done: read out their candidates
+            bool formed = false;
+            for (int i = 0; i < count; ++i) {
+                BatchTarget& b = bt[i];
+                if (!queued[i] || !b.wd.enumerate) continue;
+                if (stats[(size_t)i * tcw::ST_COUNT + tcw::ST_STEPS] >= b.budget) {
+                    BATCH_TRY(tcw::launch_enum_pairs(b.wd, gs[0]));
+                    formed = true;
+                }
+            }
+            if (formed)
+                BATCH_TRY(hipMemcpyAsync(stats.data(), bb.stats, stats.size() * 8, hipMemcpyDeviceToHost, gs[0]));
+            BATCH_TRY(hipMemcpyAsync(ccount.data(), bb.claw_count, count * 8, hipMemcpyDeviceToHost, gs[0]));
+            BATCH_TRY(hipStreamSynchronize(gs[0]));
+        }
         for (int i = 0; i < count; ++i) {
             BatchTarget& b = bt[i];
             if (!b.walking) continue;
-            b.res->launches++;
-            const unsigned long long* st = &stats[(size_t)i * tcw::ST_COUNT];
-            const uint64_t steps_now = st[tcw::ST_STEPS];
-            total_steps += (int64_t)(steps_now - b.used_v);
-            b.used += steps_now - b.used_v;
-            b.used_v = steps_now;
-            int found = 0;
-            const int64_t avail = (int64_t)std::min<unsigned long long>(ccount[i], BATCH_CLAW_CAP);
-            if (avail > b.seen) {
-                const int64_t m = avail - b.seen;
-                std::vector<uint64_t> pairs(2 * m);
-                BATCH_TRY(hipMemcpy(pairs.data(), b.wd.claws + 2 * b.seen, 16 * m, hipMemcpyDeviceToHost));
-                std::vector<uint64_t> u0(m), u1(m);
-                for (int64_t j = 0; j < m; ++j) {
-                    u0[j] = pairs[2 * j];
-                    u1[j] = pairs[2 * j + 1];
-                }
-                if (b.wd.enumerate) sort_pairs(u0.data(), u1.data(), m);
-                BATCH_RC(check_pairs(c, *b.space, u0.data(), u1.data(), m, b.res, &found));
-                b.seen = avail;
+            if (queued[i]) {
+                b.res->launches++;
+                const uint64_t steps_now = stats[(size_t)i * tcw::ST_COUNT + tcw::ST_STEPS];
+                total_steps += (int64_t)(steps_now - b.used_v);
+                b.used += steps_now - b.used_v;
+                b.used_v = steps_now;
             }
-            const tcw_walk_stats ws = stats_of(st, ccount[i], b.wd.claw_cap);
-            const bool over_time = b.p.max_seconds > 0 && now_s() - t0 > b.p.max_seconds;
-            if (found || over_time || b.used >= b.budget) {
-                add_stats(b.res->stats, ws);
-                b.walking = false;
-                dirty = true;
-                if (found) batch_on_hit(b);
-                if (over_time) {
-                    b.done = true;
-                    b.cut = true;
+            if (hit[i]) {
+                BATCH_RC(settle(i, true));
+            } else {
+                if (queued[i]) {
+                    // new candidates of this round: checked during the next round
+                    const int64_t avail = (int64_t)std::min<unsigned long long>(ccount[i], BATCH_CLAW_CAP);
+                    if (avail > b.seen) {
+                        const int64_t m = avail - b.seen;
+                        std::vector<uint64_t> pairs(2 * m);
+                        BATCH_TRY(hipMemcpy(pairs.data(), b.wd.claws + 2 * b.seen, 16 * m, hipMemcpyDeviceToHost));
+                        b.pu0.resize(m);
+                        b.pu1.resize(m);
+                        for (int64_t j = 0; j < m; ++j) {
+                            b.pu0[j] = pairs[2 * j];
+                            b.pu1[j] = pairs[2 * j + 1];
+                        }
+                        if (b.wd.enumerate) sort_pairs(b.pu0.data(), b.pu1.data(), m);
+                        b.seen = avail;
+                    }
                 }
-                if (b.done) {
-                    b.res->seconds = now_s() - t0;
-                    free_walk_buffers(b);
-                } else {
-                    BATCH_RC(batch_advance(c, b, i, bb, gs[0], t0, !found));
-                    if (b.done) b.res->seconds = now_s() - t0;
+                const bool over_time = b.p.max_seconds > 0 && now_s() - t0 > b.p.max_seconds;
+                const bool ends = over_time || b.used >= b.budget || b.used_v >= b.per_version;
+                if (ends && !b.pu0.empty() && !over_time) {
+                    // the space ends, but its last candidates are not checked yet: sit out until they are
+                    if (!b.held) {
+                        b.held = true;
+                        dirty = true;
+                    }
+                } else if (ends) {
+                    if (!b.pu0.empty()) {
+                        // out of time: check what is pending now rather than lose it
+                        int found = 0;
+                        BATCH_RC(check_pairs_ws(c, *b.space, b.pu0.data(), b.pu1.data(), (int64_t)b.pu0.size(), b.res,
+                                                &found, cws));
+                        b.pu0.clear();
+                        b.pu1.clear();
+                        hit[i] = (char)found;
+                    }
+                    BATCH_RC(settle(i, hit[i] != 0));
                 }
-            } else if (b.used_v >= b.per_version) {
-                add_stats(b.res->stats, ws);
-                b.version++;
-                b.res->versions++;
-                b.space->set_version(b.version);
-                b.used_v = 0;
-                b.seen = 0;
-                BATCH_RC(batch_restart(c, b, i, bb, gs[0]));
             }
             if (stop_on_first && b.res->status == TCW_STATUS_FOUND && b.done) stop_first = true;
         }
@@ -2314,6 +2445,9 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
             if (!b.walking) continue;
             add_stats(b.res->stats, stats_of(&stats[(size_t)i * tcw::ST_COUNT], ccount[i], b.wd.claw_cap));
             b.walking = false;
+            b.held = false;
+            b.pu0.clear();
+            b.pu1.clear();
             b.done = true;
             b.res->seconds = now_s() - t0;
             if (stop && stop->stopped) b.res->status = TCW_STATUS_STOPPED;

@@ -140,8 +140,14 @@ hipError_t launch_canon_hash(int n, const SpaceDev& sp, const uint32_t* phi_all,
                              uint64_t* out, hipStream_t s);
 hipError_t launch_walk(int n, const SpaceDev& sp, const WalkDev& wd, int iters, int grid_blocks, hipStream_t s);
 hipError_t launch_walk_init(const SpaceDev& sp, const WalkDev& wd, hipStream_t s);
-hipError_t launch_walk_batch(int n, const SpaceDev* sps, const WalkDev* wds, const int32_t* blk_target,
-                             const int32_t* tgt_first, const int32_t* tgt_blocks, int blocks, int iters, hipStream_t s);
+// One item of the batch work queue: `iters` evaluations of f for slice `unit` of `units` of the walks
+// of member `slot` (the slice of walk_block(..., unit, units)).
+struct WorkItem {
+    int32_t slot, unit, units, iters;
+};
+// persistent queue kernel of qubit count n over `blocks` blocks (see k_walk_queue)
+hipError_t launch_walk_queue(int n, const SpaceDev* sps, const WalkDev* wds, const WorkItem* items,
+                             const int32_t* count, uint32_t* head, int blocks, hipStream_t s);
 int walks_per_block(int n);
 // value: what every slot's value word starts at (0 for walk tables: "not ready"; ENUM_TABLE_INIT for
 // enumeration tables: no x on either side)

@@ -846,9 +846,34 @@ __device__ inline uint64_t pack_value(uint64_t start, uint32_t len) {
 }
 
 // The walks of one block: walk slots first_block * WAVES * WPW + ... strided by nblocks blocks.
+// A walk group's event counts, added to the member's statistics by its leader lane (flush_counts).
+struct WalkCounts {
+    uint64_t steps = 0, dps = 0, ins = 0, ab = 0, rh = 0, same = 0, red = 0, claw = 0, full = 0, spin = 0,
+             active = 0;
+};
+
+__device__ inline void flush_counts(const WalkDev& wd, WalkCounts& c, bool leader) {
+    if (leader) {
+        atomicAdd(&wd.stats[ST_STEPS], (unsigned long long)c.steps);
+        atomicAdd(&wd.stats[ST_DPS], (unsigned long long)c.dps);
+        atomicAdd(&wd.stats[ST_INSERTS], (unsigned long long)c.ins);
+        atomicAdd(&wd.stats[ST_ABANDONED], (unsigned long long)c.ab);
+        atomicAdd(&wd.stats[ST_ROBIN], (unsigned long long)c.rh);
+        atomicAdd(&wd.stats[ST_SAME], (unsigned long long)c.same);
+        atomicAdd(&wd.stats[ST_REDUCTION], (unsigned long long)c.red);
+        atomicAdd(&wd.stats[ST_CLAWS], (unsigned long long)c.claw);
+        atomicAdd(&wd.stats[ST_FULL], (unsigned long long)c.full);
+        atomicAdd(&wd.stats[ST_SPIN], (unsigned long long)c.spin);
+        atomicAdd(&wd.stats[ST_ACTIVE], (unsigned long long)c.active);
+    }
+    c = WalkCounts{};
+}
+
+// `iters` evaluations of f for every walk of slice `block` of `nblocks` (walks (block * WAVES + wave)
+// * WPW + group, then every nblocks * WAVES * WPW further); events are added to cnt.
 template <int NQ, int WAVES>
 __device__ void walk_block(const SpaceDev& sp, const WalkDev& wd, int iters, Lds<NQ, WAVES>& L, int64_t block,
-                           int64_t nblocks) {
+                           int64_t nblocks, WalkCounts& cnt) {
     using Gm = Geo<NQ>;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int gi = lane / Gm::G, gl = lane % Gm::G, gbase = gi * Gm::G;
@@ -1025,19 +1050,17 @@ __device__ void walk_block(const SpaceDev& sp, const WalkDev& wd, int iters, Lds
         if ((st.mode & 0xff) != MODE_DONE) c_active++;
         if (leader) wd.states[w] = st;
     }
-    if (leader) {
-        atomicAdd(&wd.stats[ST_STEPS], (unsigned long long)c_steps);
-        atomicAdd(&wd.stats[ST_DPS], (unsigned long long)c_dps);
-        atomicAdd(&wd.stats[ST_INSERTS], (unsigned long long)c_ins);
-        atomicAdd(&wd.stats[ST_ABANDONED], (unsigned long long)c_ab);
-        atomicAdd(&wd.stats[ST_ROBIN], (unsigned long long)c_rh);
-        atomicAdd(&wd.stats[ST_SAME], (unsigned long long)c_same);
-        atomicAdd(&wd.stats[ST_REDUCTION], (unsigned long long)c_red);
-        atomicAdd(&wd.stats[ST_CLAWS], (unsigned long long)c_claw);
-        atomicAdd(&wd.stats[ST_FULL], (unsigned long long)c_full);
-        atomicAdd(&wd.stats[ST_SPIN], (unsigned long long)c_spin);
-        atomicAdd(&wd.stats[ST_ACTIVE], (unsigned long long)c_active);
-    }
+    cnt.steps += c_steps;
+    cnt.dps += c_dps;
+    cnt.ins += c_ins;
+    cnt.ab += c_ab;
+    cnt.rh += c_rh;
+    cnt.same += c_same;
+    cnt.red += c_red;
+    cnt.claw += c_claw;
+    cnt.full += c_full;
+    cnt.spin += c_spin;
+    cnt.active += c_active;
 }
 
 template <int NQ, int WAVES>
@@ -1045,24 +1068,43 @@ __global__ __launch_bounds__(WAVES * 64) void k_walk(SpaceDev sp, WalkDev wd, in
     __shared__ Lds<NQ, WAVES> L;
     load_lds(L, sp);
     __syncthreads();
-    walk_block<NQ, WAVES>(sp, wd, iters, L, blockIdx.x, gridDim.x);
+    WalkCounts cnt;
+    walk_block<NQ, WAVES>(sp, wd, iters, L, blockIdx.x, gridDim.x, cnt);
+    flush_counts(wd, cnt, (threadIdx.x & 63) % Geo<NQ>::G == 0);
 }
 
-// Many targets in one launch: block b serves target blk_target[b] (< 0: idle) as its
-// (b - tgt_first[t])-th of tgt_blocks[t] blocks; every target brings its own S_c, keys, salts,
-// walk states, table and counters.
+// Many members in one persistent launch per qubit count, fed from a device queue: each block takes
+// the next item (a slice of one member's walks for that member's number of evaluations) until the
+// queue is empty, and reloads the member's S_c and keys into LDS only when the member changes.
+// head[0] is the queue position (zeroed by a kernel before the launch); count[0] items are queued.
+// Every block leaves once the position passes the count, so the grid always drains.
 template <int NQ, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void k_walk_batch(const SpaceDev* sps, const WalkDev* wds,
-                                                            const int32_t* blk_target, const int32_t* tgt_first,
-                                                            const int32_t* tgt_blocks, int iters) {
+__global__ __launch_bounds__(WAVES * 64) void k_walk_queue(const SpaceDev* sps, const WalkDev* wds,
+                                                           const WorkItem* items, const int32_t* count,
+                                                           uint32_t* head) {
     __shared__ Lds<NQ, WAVES> L;
-    const int t = blk_target[blockIdx.x];
-    if (t < 0) return;
-    const SpaceDev sp = sps[t];
-    const WalkDev wd = wds[t];
-    load_lds(L, sp);
-    __syncthreads();
-    walk_block<NQ, WAVES>(sp, wd, iters, L, (int64_t)blockIdx.x - tgt_first[t], tgt_blocks[t]);
+    __shared__ int32_t s_next;
+    const int32_t n_items = *count;
+    const bool leader = (threadIdx.x & 63) % Geo<NQ>::G == 0;
+    int32_t loaded = -1;
+    WalkCounts cnt;  // the loaded member's events, added to its statistics when the member changes
+    for (;;) {
+        if (threadIdx.x == 0) s_next = (int32_t)atomicAdd(head, 1u);
+        __syncthreads();
+        const int32_t i = s_next;
+        if (i >= n_items) break;  // the same value in every thread of the block
+        const WorkItem it = items[i];
+        const SpaceDev sp = sps[it.slot];
+        if (it.slot != loaded) {
+            if (loaded >= 0) flush_counts(wds[loaded], cnt, leader);
+            load_lds(L, sp);
+            loaded = it.slot;
+        }
+        __syncthreads();
+        walk_block<NQ, WAVES>(sp, wds[it.slot], it.iters, L, it.unit, it.units, cnt);
+        __syncthreads();  // s_next and, for the next member, the LDS are rewritten after this
+    }
+    if (loaded >= 0) flush_counts(wds[loaded], cnt, leader);
 }
 
 __global__ void k_walk_init(SpaceDev sp, WalkDev wd) {
@@ -1320,13 +1362,13 @@ hipError_t launch_walk(int n, const SpaceDev& sp, const WalkDev& wd, int iters, 
     return dispatch_n(n, f);
 }
 
-hipError_t launch_walk_batch(int n, const SpaceDev* sps, const WalkDev* wds, const int32_t* blk_target,
-                             const int32_t* tgt_first, const int32_t* tgt_blocks, int blocks, int iters, hipStream_t s) {
+hipError_t launch_walk_queue(int n, const SpaceDev* sps, const WalkDev* wds, const WorkItem* items,
+                             const int32_t* count, uint32_t* head, int blocks, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
     auto f = [&]<int NQ>() -> hipError_t {
         constexpr int W = WalkWaves<NQ>::value;
-        hipLaunchKernelGGL((k_walk_batch<NQ, W>), dim3((unsigned)blocks), dim3(W * 64), 0, s, sps, wds, blk_target,
-                           tgt_first, tgt_blocks, iters);
+        hipLaunchKernelGGL((k_walk_queue<NQ, W>), dim3((unsigned)blocks), dim3(W * 64), 0, s, sps, wds, items, count,
+                           head);
         return hipGetLastError();
     };
     return dispatch_n(n, f);

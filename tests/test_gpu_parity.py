@@ -487,14 +487,16 @@ def test_autotune_choices(ctx):
 
 
 def test_search_batch_mixed(ctx):
-    """Mixed n and k in one batched search: every decomposition found reconstructs its target
-    exactly, with T-count at most the generating k; n <= 2 minima match brute force."""
+    """Mixed n and k in one batched search (the queue kernels of n = 1..4 in one round): every
+    decomposition found reconstructs its target exactly, with T-count at most the generating k;
+    n <= 2 minima match brute force; the n = 4 members (depths below 4 enumerated) are certified
+    minimal."""
     from paper_1606_07413_amd import tcw
     say("batch")
     _, seen1, _ = bfs.cosets_by_tcount(1, 7)
     _, seen2, _ = bfs.cosets_by_tcount(2, 3)
     specs = [(1, 5, 1), (1, 7, 2), (2, 3, 3), (2, 4, 4), (2, 5, 5), (3, 3, 6), (3, 4, 7), (3, 6, 8), (2, 4, 9),
-             (1, 6, 10)]
+             (1, 6, 10), (4, 3, 11), (4, 4, 12)]
     targets, params, oracle_u = [], [], []
     for n, k, seed in specs:
         tw, u = oracle_target(n, k, 200 + seed)
@@ -523,3 +525,5 @@ def test_search_batch_mixed(ctx):
         if n == 2:
             tmin = bfs.min_tcount(u, seen2)
             assert dec.t == (tmin if tmin is not None else dec.t)
+        if n == 4:
+            assert r.minimal == 1 and r.failed_depths & ((1 << dec.t) - 1) == (1 << dec.t) - 1
