@@ -509,6 +509,47 @@ def tts_n4_planted_leg(ctx, cap: float, slice_s: float = 120.0, seeds=(2, 3, 4))
             "runs": runs}
 
 
+def sweep_leg(ctx, reps: int):
+    """The scaling laws of Sec. 5.1 on one GPU, on the Toffoli gate (T-count 7, the whole search:
+    depths 0..7, chunks of odd depths in ascending order, 2^20 slots), `reps` walk seeds per point:
+      walks m = 2^10 .. 2^20 at theta = 1/2: the paper's runtime falls as 1/(processors); here m
+      walks share one GPU, so steps-to-solution should stay about flat in m (until m / theta nears
+      N) while the step rate rises until the GPU is full, and wall time = steps / rate;
+      theta = 1/2 .. 1/32 at m = 2^16: steps and time rise about as 1/theta while the table holds
+      every distinguished point (the appendix)."""
+    import statistics
+
+    import seeded_inputs
+    v = seeded_inputs.permutation_unitary(seeded_inputs.NAMED_GATES["toffoli"])
+    tgt = ctx.target_from_unitary(3, v, 0)
+
+    def point(walks, delta):
+        secs, steps, ts = [], [], []
+        for r in range(reps):
+            p = ctx.default_params(3)
+            p.k_max = 7
+            p.delta = delta
+            p.walks = walks
+            p.log2_table = 20
+            p.seed = 7000 + 31 * r
+            p.chunk_parallel = 1
+            p.max_seconds = 60
+            res = ctx.search(tgt, p)
+            secs.append(res.seconds)
+            steps.append(res.stats.steps)
+            ts.append(res.t if res.status == 1 else None)
+        out = {"walks": walks, "theta": 2.0 ** -delta, "reps": reps, "found_t": sorted(set(t for t in ts if t)),
+               "not_found": sum(1 for t in ts if t is None), "mean_s": statistics.mean(secs),
+               "mean_steps": statistics.mean(steps), "steps_per_s": sum(steps) / sum(secs)}
+        _log(f"sweep toffoli walks {walks} theta 2^-{delta}: {out['mean_s']:.3f} s, {out['mean_steps']:.3g} steps")
+        return out
+
+    res = {"walks_theta_half": [point(1 << lg, 1) for lg in range(10, 21, 2)],
+           "theta_walks_2^16": [point(1 << 16, d) for d in range(1, 6)]}
+    tgt.free()
+    return res
+
+
 # Sec. 5.2, Table 1: mean synthesis time of the T-count-7 three-qubit gates over 100 trials on
 # 4096 Blue Gene/Q cores with half of the points distinguished (another machine: context only).
 PAPER_TABLE1_SECONDS = {"toffoli": 25.9870, "fredkin": 25.0031, "peres": 25.4931}
@@ -745,6 +786,8 @@ def main():
     ap.add_argument("--named", action="store_true",
                     help="also synthesise Toffoli, Fredkin and Peres (n = 3, T-count 7) repeatedly")
     ap.add_argument("--named-reps", type=int, default=20)
+    ap.add_argument("--sweeps", action="store_true", help="also run the walk-count and theta sweeps on Toffoli")
+    ap.add_argument("--sweep-reps", type=int, default=8)
     ap.add_argument("--named-reps-default-theta", type=int, default=3)
     ap.add_argument("--configs", action="store_true",
                     help="also run the n = 2, k = 4 and n = 3, k = 6 searches and walk rates")
@@ -837,6 +880,8 @@ def main():
         out["batch64_default_theta"] = batch_leg(ctx, args.batch_cap, configured_theta=False)
     if args.named:
         out["named_n3_t7"] = named_leg(ctx, args.named_reps, args.named_reps_default_theta)
+    if args.sweeps:
+        out["sweeps_toffoli"] = sweep_leg(ctx, args.sweep_reps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, k, chunk, target_seed, seed, delta, args.cpu_seconds)
         if args.cpu_configs:

@@ -140,8 +140,10 @@ int tcw_start_points(tcw_ctx* ctx, const tcw_target* t, const tcw_space* sp, int
                      int64_t count, uint64_t* pts_out_dev);
 
 /* tcw_canon_hash (parity): matrix hash H of `count` exact matrices (the nu + h part of the walk
- * step): a_dev, b_dev are count x R x R int32, e_dev count int32; keys from (n, sp).  Values must
- * fit int8 (|a|, |b| <= 127) else TCW_EOVERFLOW; count above 2^31: TCW_EINVAL. */
+ * step): a_dev, b_dev are count x R x R int32 (any values), e_dev count int32 (any sign); keys from
+ * (n, sp).  When every entry fits int8 (|a|, |b| <= 127) the digests come from the walk's own
+ * side-1 product (int8 MFMA at n >= 3), otherwise from 64-bit modular products; the hash is the same
+ * function either way.  count above 2^31: TCW_EINVAL. */
 int tcw_canon_hash(tcw_ctx* ctx, int n, const tcw_space* sp, const int32_t* a_dev, const int32_t* b_dev,
                    const int32_t* e_dev, int64_t count, uint64_t* h_out_dev);
 

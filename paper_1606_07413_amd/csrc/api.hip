@@ -281,6 +281,14 @@ int auto_delta(uint64_t npts, int log2_table) {
 }
 int default_iters(int n) { return n <= 2 ? 64 : (n == 3 ? 32 : 8); }
 
+// Walks of a walked space: at most a quarter of its points.  With more walks than that, a function
+// version (at most the table's half load of steps) ends before the walks' trails and their
+// backtracking do, and the search stops reporting claws (measured on Toffoli: 2^20 walks in depth-7
+// chunks of 5e5 points never finish, 2^18 do).
+int64_t walks_for(int64_t walks, uint64_t npts) {
+    return std::min<int64_t>(walks, std::max<int64_t>(64, (int64_t)(npts / 4)));
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------
@@ -746,8 +754,10 @@ int tcw_canon_hash(tcw_ctx* c, int n, const tcw_space* sp, const int32_t* a, con
     if (!rc && err == hipSuccess) err = tcw::keys_fill(n, sp->seed, keys, c->stream);
     int flag = 0;
     if (!rc && err == hipSuccess) rc = read_flag(c, &flag);
-    if (!rc && err == hipSuccess && flag) rc = fail(c, TCW_EOVERFLOW, "matrix entry outside int8 range");
-    if (!rc && err == hipSuccess) err = tcw::launch_canon_hash(n, s.dev, phi, e, count, h_out, c->stream);
+    // entries that fit int8 go through the walk's own side-1 product; others through 64-bit products
+    if (!rc && err == hipSuccess)
+        err = flag ? tcw::launch_canon_wide(n, s.dev, a, b, e, count, h_out, c->stream)
+                   : tcw::launch_canon_hash(n, s.dev, phi, e, count, h_out, c->stream);
     if (!rc && err == hipSuccess) err = hipStreamSynchronize(c->stream);
     if (!rc && err != hipSuccess) rc = hip_fail(c, err, "canon hash");
     return rc;
@@ -1333,12 +1343,13 @@ int open_space(tcw_ctx* c, SearchRun& s) {
     } else {
         uint32_t cap = 0;
         if ((rc = trail_cap_of(c, p, s.delta, &cap))) return rc;
+        const int64_t walks = walks_for(p->walks, s.npts);
         s.budget = (uint64_t)p->budget_beta * s.npts << s.delta;
-        s.per_version = version_steps(p, s.npts, s.delta, p->walks, p->log2_table);
+        s.per_version = version_steps(p, s.npts, s.delta, walks, p->log2_table);
         // a launch must not overrun a function version
-        const uint64_t fit = s.per_version / (uint64_t)p->walks;
+        const uint64_t fit = s.per_version / (uint64_t)walks;
         if ((uint64_t)s.iters > fit) s.iters = fit > 0 ? (int)fit : 1;
-        rc = tcw_walk_begin(c, t, &sp, p->walks, p->log2_table, cap, 0, &s.w);
+        rc = tcw_walk_begin(c, t, &sp, walks, p->log2_table, cap, 0, &s.w);
     }
     return rc;
 }
@@ -2041,7 +2052,7 @@ int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStr
             if (b.p.walks <= 0 || b.p.log2_table <= 0 || b.p.iters_per_launch <= 0) {
                 if ((rc = autotune(c, b.t, b.k, b.chunk, delta, b.p.seed, &cfg))) return rc;
             }
-            b.walks = b.p.walks > 0 ? b.p.walks : cfg.walks;
+            b.walks = walks_for(b.p.walks > 0 ? b.p.walks : cfg.walks, npts);
             b.log2 = b.p.log2_table > 0 ? b.p.log2_table : cfg.log2_table;
             b.iters = b.p.iters_per_launch > 0 ? b.p.iters_per_launch : cfg.iters;
         }

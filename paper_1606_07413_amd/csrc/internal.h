@@ -138,6 +138,9 @@ hipError_t launch_trails(int n, const SpaceDev& sp, const uint64_t* starts, int6
 hipError_t launch_starts(const SpaceDev& sp, int64_t w0, uint32_t j, int64_t count, uint64_t* out, hipStream_t s);
 hipError_t launch_canon_hash(int n, const SpaceDev& sp, const uint32_t* phi_all, const int32_t* e, int64_t count,
                              uint64_t* out, hipStream_t s);
+// canonical hash of matrices with entries of any int32 value (64-bit modular row digests)
+hipError_t launch_canon_wide(int n, const SpaceDev& sp, const int32_t* a, const int32_t* b, const int32_t* e,
+                             int64_t count, uint64_t* out, hipStream_t s);
 hipError_t launch_walk(int n, const SpaceDev& sp, const WalkDev& wd, int iters, int grid_blocks, hipStream_t s);
 hipError_t launch_walk_init(const SpaceDev& sp, const WalkDev& wd, hipStream_t s);
 // One item of the batch work queue: `iters` evaluations of f for slice `unit` of `units` of the walks

@@ -706,7 +706,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_canon(SpaceDev sp, const uint32_
         SpaceDev s2 = sp;
         s2.phi = phi_all + (size_t)m * 2 * NPHI;
         s2.h = 0;
-        s2.rot_e = (int32_t)((30ll * e[m]) % 61);
+        s2.rot_e = (int32_t)(((30ll * e[m]) % 61 + 61) % 61);
         s2.n_half = 1;
         __syncthreads();
         load_lds(L, s2);
@@ -716,6 +716,43 @@ __global__ __launch_bounds__(WAVES * 64) void k_canon(SpaceDev sp, const uint32_
             walk_step<NQ, WAVES>(s2, L, limbs, 1ull << 32, gl, gbase, o, hh);
             if (gl == 0) out[m] = hh;
         }
+    }
+}
+
+// x y mod p for x, y < 2^61: x y = hi 2^64 + lo = 8 hi + lo (mod p), lo split at bit 61.
+__device__ inline uint64_t m61_mul(uint64_t x, uint64_t y) {
+    const uint64_t lo = x * y, hi = __umul64hi(x, y);
+    return m61_fold((lo & P61) + (lo >> 61) + (hi << 3));
+}
+
+// Canonical hash of explicit matrices whose entries do not fit int8: the row digests
+// S_r = sum_q phi(M_rq) K[q] by 64-bit modular products (one matrix per 64-lane block, rows over
+// lanes), then the same sign fold, element map and sum as walk_step.  Exact for any int32 entries.
+template <int NQ>
+__global__ __launch_bounds__(64) void k_canon_wide(SpaceDev sp, const int32_t* a, const int32_t* b,
+                                                   const int32_t* e, int64_t count, uint64_t* out) {
+    constexpr int R = Geo<NQ>::R;
+    const int lane = threadIdx.x;
+    const uint32_t ka = (uint32_t)sp.salt_h, kb = (uint32_t)(sp.salt_h >> 32);
+    for (int64_t m = blockIdx.x; m < count; m += gridDim.x) {
+        // (a + b sqrt2) / sqrt2^e: phi(1/sqrt2) = 2^30, so the scale is a rotation by 30 e mod 61
+        const int rot = (int)(((30ll * e[m]) % 61 + 61) % 61);
+        uint64_t acc = 0;
+        for (int r = lane; r < R; r += 64) {
+            const int32_t* ar = a + ((size_t)m * R + r) * R;
+            const int32_t* br = b + ((size_t)m * R + r) * R;
+            uint64_t sum = 0;
+            for (int q = 0; q < R; ++q) {
+                const uint64_t v = m61_add(m61_from_i32(ar[q]), m61_rot(m61_from_i32(br[q]), 31));
+                sum = m61_add(sum, m61_mul(v, sp.keys[q]));
+            }
+            const uint64_t c = m61_rot(sum, rot);
+            const uint64_t d = c ^ (P61 & (0ull - ((c >> 60) & 1)));
+            acc += (uint64_t)((uint32_t)d + ka) * (uint64_t)((uint32_t)(d >> 32) + kb);
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) acc += shfl64(acc, lane ^ off);
+        if (lane == 0) out[m] = mix64(acc);
     }
 }
 
@@ -1345,6 +1382,17 @@ hipError_t launch_canon_hash(int n, const SpaceDev& sp, const uint32_t* phi_all,
         const int64_t blocks = count < 1024 ? count : 1024;
         hipLaunchKernelGGL((k_canon<NQ, W>), dim3((unsigned)blocks), dim3(W * 64), 0, s, sp, phi_all, e, count,
                            out);
+        return hipGetLastError();
+    };
+    return dispatch_n(n, f);
+}
+
+hipError_t launch_canon_wide(int n, const SpaceDev& sp, const int32_t* a, const int32_t* b, const int32_t* e,
+                             int64_t count, uint64_t* out, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    auto f = [&]<int NQ>() -> hipError_t {
+        const int64_t blocks = count < 4096 ? count : 4096;
+        hipLaunchKernelGGL((k_canon_wide<NQ>), dim3((unsigned)blocks), dim3(64), 0, s, sp, a, b, e, count, out);
         return hipGetLastError();
     };
     return dispatch_n(n, f);

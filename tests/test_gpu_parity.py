@@ -236,6 +236,41 @@ def test_canon_hash_parity(ctx, n):
     assert got[-1] == got[-3] == got[-2]   # representation and left-Clifford invariance
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_canon_hash_wide_entries(ctx, n):
+    """tcw_canon_hash with entries beyond int8 (the 64-bit modular path): random int32 matrices with
+    exponents of either sign against the oracle, and a target raised by sqrt2^16 (entries x 256) hashes
+    to what the int8 path gives for the target itself."""
+    import torch
+    say("canon hash wide", n)
+    r = 4 ** n
+    rng = np.random.default_rng(40 + n)
+    mats = []
+    for i in range(3 if n < 4 else 2):
+        A = rng.integers(-(1 << 31), (1 << 31) - 1, size=(r, r), dtype=np.int64)
+        B = rng.integers(-(1 << 31), (1 << 31) - 1, size=(r, r), dtype=np.int64)
+        if i == 0:
+            A[0, 0], B[0, 0] = -(1 << 31), (1 << 31) - 1
+        mats.append(zmat.ZMat(A.astype(object), B.astype(object), int(rng.integers(-7, 40))))
+    tw, u = oracle_target(n, 5, 2)
+    big = u.raise_to(u.e + 16)
+    assert max(abs(int(v)) for v in np.concatenate([big.A.ravel(), big.B.ravel()])) > 127
+    mats.append(big)
+
+    def run(ms):
+        a = torch.tensor(np.stack([np.array(m.A, dtype=np.int64) for m in ms]).astype(np.int32), device="cuda:0")
+        b = torch.tensor(np.stack([np.array(m.B, dtype=np.int64) for m in ms]).astype(np.int32), device="cuda:0")
+        e = torch.tensor([m.e for m in ms], dtype=torch.int32, device="cuda:0")
+        out = torch.empty(len(ms), dtype=torch.int64, device="cuda:0")
+        ctx.canon_hash(n, 5, 3, 31, a, b, e, out, version=1)
+        return host_u64(out)
+
+    keys = owalk.make_keys(n, 5, 3, 31, version=1)
+    got = run(mats)
+    assert got == [owalk.matrix_hash(m, keys) for m in mats]
+    assert run([u]) == [got[-1]]     # the int8 path on the target itself
+
+
 @pytest.mark.parametrize("n,k,seed", [(1, 5, 2), (2, 4, 1), (2, 5, 3), (3, 6, 1), (3, 5, 4), (4, 7, 1)])
 def test_claw_check_parity(ctx, n, k, seed):
     import torch

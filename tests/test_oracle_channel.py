@@ -153,3 +153,55 @@ def test_canonical_form_left_clifford_invariance():
             assert zmat.canonical_form(d @ u) == base
         # a rotation on the left changes the coset
         assert zmat.canonical_form(zmat.rot_hat(1, n) @ u) != base
+
+
+def _sign_decimal(a, b):
+    """Sign of a + b sqrt2 by 120-digit decimal arithmetic (independent of zmat's exact rule)."""
+    import decimal
+    with decimal.localcontext() as ctx:
+        ctx.prec = 120
+        v = decimal.Decimal(a) + decimal.Decimal(b) * decimal.Decimal(2).sqrt()
+    return (v > 0) - (v < 0)
+
+
+def test_real_sign_against_decimal_and_pell_boundary():
+    """zmat.real_sign, which decides every row sign of the canonical form, against 120-digit
+    decimal arithmetic: random pairs of every sign pattern and size, and the hardest cases, the Pell
+    pairs p^2 - 2 q^2 = +-1 whose p - q sqrt2 = +-1 / (p + q sqrt2) is within 1e-40 of zero."""
+    rng = np.random.default_rng(17)
+    cases = [(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1), (3, -2), (-3, 2), (1, -1), (-1, 1), (2, -1), (-2, 1)]
+    for bits in (3, 10, 31, 62, 120):
+        for _ in range(200):
+            a = int(rng.integers(-(1 << 62), 1 << 62)) >> max(0, 62 - bits)
+            b = int(rng.integers(-(1 << 62), 1 << 62)) >> max(0, 62 - bits)
+            cases.append((a << max(0, bits - 62), b << max(0, bits - 62)))
+    p, q = 1, 1                      # 1 + sqrt2 and its powers give every Pell pair
+    for _ in range(60):
+        cases += [(p, -q), (-p, q)]
+        p, q = p + 2 * q, p + q
+    assert max(abs(a) for a, _ in cases) > 10 ** 30
+    for a, b in cases:
+        assert zmat.real_sign(a, b) == _sign_decimal(a, b), (a, b)
+
+
+def test_canonical_form_row_sign_rule():
+    """A row whose first nonzero entry is -3 + 2 sqrt2 (about -0.17, negative although b > 0) is
+    negated in the canonical form; one whose first nonzero entry is 3 - 2 sqrt2 is kept; zero entries
+    before it do not count; rows then sort as integer tuples."""
+    A = np.zeros((16, 16), dtype=object)
+    B = np.zeros((16, 16), dtype=object)
+    A[0, 0], B[0, 0], A[0, 5] = -3, 2, 7      # row 0: (-3 + 2 sqrt2, ..., 7 at column 5)
+    A[1, 1], B[1, 1], A[1, 2] = 3, -2, -1     # row 1: first nonzero at column 1, positive
+    A[2, 3], B[2, 4] = 0, -1                  # row 2: first nonzero is -sqrt2 at column 4
+    for r in range(3, 16):
+        A[r, r] = 1
+    e, rows = zmat.canonical_form(zmat.ZMat(A, B, 0))
+    row0 = [0] * 32
+    row0[0], row0[1], row0[10] = 3, -2, -7
+    row1 = [0] * 32
+    row1[2], row1[3], row1[4] = 3, -2, -1
+    row2 = [0] * 32
+    row2[9] = 1
+    assert e == 0
+    assert tuple(row0) in rows and tuple(row1) in rows and tuple(row2) in rows
+    assert list(rows) == sorted(rows)
