@@ -2637,12 +2637,13 @@ int mlp_ensure_batch(tcw_mlp* m, int b) {
     }
     HIP_TRY(c, hipMalloc(&m->logits, (size_t)b * m->classes * 4));
     HIP_TRY(c, hipMalloc(&m->probs, (size_t)b * m->classes * 4));
-    // workspace of the split products: forward (b x out, K = in), dX (b x in, K = out), dW (in x out, K = b)
+    // workspace of the split products (forward b x out, K = in; dX b x in, K = out; dW in x out, K = b) and
+    // of the bias gradients' column sums
     size_t part = 0;
     for (int l = 0; l < m->L; ++l) {
         const int in = m->sz[l], out = m->sz[l + 1];
         part = std::max({part, tcw::mlp_gemm_part_floats(b, out, in), tcw::mlp_gemm_part_floats(b, in, out),
-                         tcw::mlp_gemm_part_floats(in, out, b)});
+                         tcw::mlp_gemm_part_floats(in, out, b), tcw::mlp_colsum_part_floats(b, out)});
     }
     if (part > 0) {
         HIP_TRY(c, hipMalloc(&m->part, part * 4));
@@ -2698,7 +2699,7 @@ int mlp_backward(tcw_mlp* m, int b) {
         // dW_l = H_in^T G_l: rows of H_in^T and of G_l^T run over the batch
         HIP_TRY(c, tcw::mlp_gemm_nt(0, Hin_t, b8, m->Gt[l], b8, in, out, b, m->G + m->w_off[l], out, nullptr, nullptr,
                                     0, nullptr, 0, nullptr, 0, m->part, m->part_floats, c->stream));
-        HIP_TRY(c, tcw::mlp_colsum(m->Gf[l], b, out, m->G + m->b_off[l], c->stream));
+        HIP_TRY(c, tcw::mlp_colsum(m->Gf[l], b, out, m->G + m->b_off[l], m->part, m->part_floats, c->stream));
         if (l > 0) {
             // G_{l-1} = (G_l W_l^T) * gelu'(Z_{l-1}): B = W_l (in x out), rows over out
             HIP_TRY(c, tcw::mlp_gemm_nt(3, m->Gb[l], ld8(out), m->Wb[l], ld8(out), b, in, out, m->Gf[l - 1], in,

@@ -170,13 +170,17 @@ hipError_t pack_phi_i32(int n, const int32_t* a, const int32_t* b, int64_t count
 // summed in a fixed order; with a smaller workspace one workgroup takes each tile.  Products on one
 // stream may share the workspace.
 size_t mlp_gemm_part_floats(int M, int N, int K);
+// workspace floats of mlp_colsum over a rows x cols matrix
+size_t mlp_colsum_part_floats(int rows, int cols);
 hipError_t mlp_gemm_nt(int epi, const void* A, int lda, const void* B, int ldb, int M, int N, int K, float* C, int ldc,
                        const float* bias, const float* Z, int ldz, void* H, int ldh, void* T, int ldt, float* part,
                        size_t part_floats, hipStream_t s);
 // probabilities, loss sum and G = (p - onehot) / batch (fp32; bf16 with ld ldgb; transposed bf16 if gt)
 hipError_t mlp_softmax_ce(const float* logits, const int32_t* labels, int batch, int classes, float* probs, float* g,
                           void* gb, int ldgb, void* gt, int ldgt, float* loss_sum, hipStream_t s);
-hipError_t mlp_colsum(const float* g, int rows, int cols, float* out, hipStream_t s);
+// out[c] = sum over rows of g[r][c], in a fixed order; part: mlp_colsum_part_floats(rows, cols) floats
+hipError_t mlp_colsum(const float* g, int rows, int cols, float* out, float* part, size_t part_floats,
+                      hipStream_t s);
 // x (rows x cols fp32) -> bf16 (ld ldy) and, if t != null, its transpose (ld ldt)
 hipError_t mlp_input_bf16(const float* x, int rows, int cols, void* y, int ldy, void* t, int ldt, hipStream_t s);
 // W (rows x cols fp32) -> bf16 W (ld ldb) and bf16 W^T (ld ldt)

@@ -74,8 +74,9 @@ __device__ inline void epilogue(float v, int gm, int gn, float* __restrict__ C, 
 // tile of 32 x 32 MFMA tiles (v_mfma_f32_32x32x16_bf16); K in steps of BK = 64 staged through
 // double-buffered LDS, the next step's 16-byte global loads held in registers while the current step
 // computes.
-// K split: blockIdx.z = z takes k in [z kchunk, (z + 1) kchunk) and, with gridDim.z > 1, writes its FP32
-// partial tile to part[z]; k_splitk_epilogue then adds the partials and applies the epilogue.
+// K split: blockIdx.z = z takes k in [z kchunk, (z + 1) kchunk).  With a workspace `part` every block
+// writes its FP32 partial tile to part[z] and k_splitk_epilogue adds the partials and applies the
+// epilogue; without one (only when gridDim.z = 1) the block applies the epilogue itself.
 template <int BM, int BN_, int WM, int WN, int EPI>
 __global__ __launch_bounds__((BM / WM) * (BN_ / WN) * 64) void k_gemm_nt(
     const __bf16* __restrict__ A, int lda, const __bf16* __restrict__ B, int ldb, int M, int N, int K,
@@ -100,7 +101,6 @@ __global__ __launch_bounds__((BM / WM) * (BN_ / WN) * 64) void k_gemm_nt(
     }
     const int m0 = by * BM, n0 = bx * BN_;
     const int wm = (wave / WAVES_N) * WM, wn = (wave % WAVES_N) * WN;
-    const int splits = gridDim.z;
     const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
     const int kv = (t & 7) * 8, r0 = t >> 3;  // this thread's vectors: rows r0 + RSTEP i, k offset kv
     const bool inner_rows = m0 + BM <= M && n0 + BN_ <= N;  // uniform over the block
@@ -166,7 +166,8 @@ __global__ __launch_bounds__((BM / WM) * (BN_ / WN) * 64) void k_gemm_nt(
     }
     // D layout of a 32 x 32 tile: lane l holds column l % 32 and, in value r, row
     // 8 (r / 4) + 4 (l / 32) + r % 4
-    if (splits == 1) {
+    if (part == nullptr) {
+        // no workspace: the epilogue here (the host passes one whenever K is split)
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -234,8 +235,18 @@ __global__ __launch_bounds__(256) void k_splitk_epilogue(const float* __restrict
         __bf16 tv = (__bf16)0.0f;
         if (gm < M && gn < N) {
             const float* p = part + (size_t)gm * N + gn;
+            // left to right over z, four partials loaded ahead of their adds
             float v = 0.f;
-            for (int z = 0; z < splits; ++z) v += p[(size_t)z * mn];
+            int z = 0;
+            for (; z + 4 <= splits; z += 4) {
+                const float a0 = p[(size_t)z * mn], a1 = p[(size_t)(z + 1) * mn], a2 = p[(size_t)(z + 2) * mn],
+                            a3 = p[(size_t)(z + 3) * mn];
+                v += a0;
+                v += a1;
+                v += a2;
+                v += a3;
+            }
+            for (; z < splits; ++z) v += p[(size_t)z * mn];
             epilogue<EPI>(v, gm, gn, C, ldc, bias, Zin, ldz, Hout, ldh, tv);
         }
         tile[rr][tx] = tv;
@@ -276,41 +287,99 @@ __global__ void k_softmax_ce(const float* logits, const int32_t* labels, int bat
 }
 
 // column sums: db[n] = sum_i G[i][n]
-__global__ void k_colsum(const float* g, int rows, int cols, float* out) {
-    const int n = blockIdx.x;
-    float s = 0.f;
-    for (int i = threadIdx.x; i < rows; i += blockDim.x) s += g[(size_t)i * cols + n];
-    __shared__ float red[256];
-    red[threadIdx.x] = s;
+// Column sums of g (rows x cols, row-major) in a fixed order.  k_colsum_part: a block covers 64
+// columns x a slab of COLSUM_SLAB = 64 rows; its four groups of 64 threads each load 16 consecutive
+// rows of one column at once (coalesced across the columns), sum them in row order, and the four
+// group sums are added in group order.  k_colsum_fin adds the slab sums the same way (four groups
+// of consecutive slabs, then the groups in order).
+constexpr int COLSUM_SLAB = 64;
+
+__global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ g, int rows, int cols,
+                                                     float* __restrict__ part) {
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int col = blockIdx.x * 64 + lane, r0 = blockIdx.y * COLSUM_SLAB + grp * 16;
+    float a[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a[i] = (col < cols && r0 + i < rows) ? g[(size_t)(r0 + i) * cols + col] : 0.f;
+    float sum = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) sum += a[i];
+    red[grp][lane] = sum;
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
+    if (grp == 0 && col < cols)
+        part[(size_t)blockIdx.y * cols + col] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+__global__ __launch_bounds__(256) void k_colsum_fin(const float* __restrict__ part, int slabs, int cols,
+                                                    float* __restrict__ out) {
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int col = blockIdx.x * 64 + lane;
+    const int per = (slabs + 3) / 4, z0 = grp * per, z1 = min(slabs, z0 + per);
+    float sum = 0.f;
+    if (col < cols) {
+        int z = z0;
+        for (; z + 8 <= z1; z += 8) {
+            float a[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) a[i] = part[(size_t)(z + i) * cols + col];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) sum += a[i];
+        }
+        for (; z < z1; ++z) sum += part[(size_t)z * cols + col];
     }
-    if (threadIdx.x == 0) out[n] = red[0];
+    red[grp][lane] = sum;
+    __syncthreads();
+    if (grp == 0 && col < cols) out[col] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 // x (rows x cols fp32, ld cols) -> y (bf16, ld ldy) and, if t != null, its transpose (cols x rows, ld
-// ldt); 32 x 32 tiles through LDS so both stores are coalesced.
+// ldt).  64 x 64 tiles through LDS, each thread 4 consecutive values per row: 16-byte loads, 8-byte
+// stores in both directions (a row of 64 halves padded to 66 spreads a column read over the banks).
 __global__ __launch_bounds__(256) void k_to_bf16_t(const float* __restrict__ x, int rows, int cols,
                                                    __bf16* __restrict__ y, int ldy, __bf16* __restrict__ t, int ldt) {
-    __shared__ __bf16 tile[32][33];
-    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-    for (int rr = ty; rr < 32; rr += 8) {
-        const int r = r0 + rr, c = c0 + tx;
-        __bf16 v = (__bf16)0.0f;
-        if (r < rows && c < cols) {
-            v = (__bf16)x[(size_t)r * cols + c];
-            y[(size_t)r * ldy + c] = v;
+    __shared__ __bf16 tile[64][66];
+    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+    const int q = (threadIdx.x & 15) * 4, tr = threadIdx.x >> 4;  // 16 groups of 4 columns x 16 rows
+    const bool vec = (cols & 3) == 0 && (ldy & 3) == 0;
+    for (int rr = tr; rr < 64; rr += 16) {
+        const int r = r0 + rr, c = c0 + q;
+        bf16x4 v;
+        if (r < rows && vec && c + 4 <= cols) {
+            const float4 f = *reinterpret_cast<const float4*>(x + (size_t)r * cols + c);
+            v[0] = (__bf16)f.x;
+            v[1] = (__bf16)f.y;
+            v[2] = (__bf16)f.z;
+            v[3] = (__bf16)f.w;
+            *reinterpret_cast<bf16x4*>(y + (size_t)r * ldy + c) = v;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                v[e] = (__bf16)0.0f;
+                if (r < rows && c + e < cols) {
+                    v[e] = (__bf16)x[(size_t)r * cols + c + e];
+                    y[(size_t)r * ldy + c + e] = v[e];
+                }
+            }
         }
-        tile[rr][tx] = v;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) tile[rr][q + e] = v[e];
     }
     if (!t) return;
     __syncthreads();
-    for (int cc = ty; cc < 32; cc += 8) {
-        const int c = c0 + cc, r = r0 + tx;
-        if (c < cols && r < rows) t[(size_t)c * ldt + r] = tile[tx][cc];
+    const bool tvec = (ldt & 3) == 0;
+    for (int cc = tr; cc < 64; cc += 16) {
+        const int c = c0 + cc, r = r0 + q;
+        if (c >= cols) continue;
+        bf16x4 w;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[e] = tile[q + e][cc];
+        if (tvec && r + 4 <= rows) {
+            *reinterpret_cast<bf16x4*>(t + (size_t)c * ldt + r) = w;
+        } else {
+            for (int e = 0; e < 4 && r + e < rows; ++e) t[(size_t)c * ldt + r + e] = w[e];
+        }
     }
 }
 
@@ -397,19 +466,25 @@ hipError_t gemm_nt_t(const __bf16* A, int lda, const __bf16* B, int ldb, int M, 
                      size_t part_floats, hipStream_t s) {
     if (M <= 0 || N <= 0) return hipSuccess;
     int splits = splits_of(M, N, K);
-    if (splits > 1 && (part == nullptr || part_floats < (size_t)splits * M * N))
-        splits = 1;  // no workspace for the split: one workgroup per tile
+    // an epilogue with a transposed BF16 copy always goes through the partial-sum kernel, which
+    // transposes through LDS (stored from the MFMA layout, each lane would write its own row of T)
+    const bool transposed = (EPI == EPI_BIAS_GELU || EPI == EPI_GELU_GRAD) && T != nullptr;
+    bool via_part = splits > 1 || transposed;
+    if (via_part && (part == nullptr || part_floats < (size_t)splits * M * N)) {
+        splits = 1;  // no workspace: one workgroup per tile, epilogue in the GEMM
+        via_part = false;
+    }
     const int kchunk = ((K + splits - 1) / splits + BK - 1) / BK * BK;
     if (big_tiles(M, N)) {
         dim3 grid((N + BN - 1) / BN, (M + 127) / 128, splits);
         hipLaunchKernelGGL((k_gemm_nt<128, BN, 64, 64, EPI>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, C, ldc,
-                           bias, Z, ldz, H, ldh, T, ldt, kchunk, part);
+                           bias, Z, ldz, H, ldh, T, ldt, kchunk, via_part ? part : nullptr);
     } else {
         dim3 grid((N + BN - 1) / BN, (M + 63) / 64, splits);
         hipLaunchKernelGGL((k_gemm_nt<64, BN, 32, 64, EPI>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, C, ldc,
-                           bias, Z, ldz, H, ldh, T, ldt, kchunk, part);
+                           bias, Z, ldz, H, ldh, T, ldt, kchunk, via_part ? part : nullptr);
     }
-    if (splits > 1) {
+    if (via_part) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         dim3 grid((N + 31) / 32, (M + 31) / 32);
@@ -422,8 +497,12 @@ hipError_t gemm_nt_t(const __bf16* A, int lda, const __bf16* B, int ldb, int M, 
 }  // namespace
 
 size_t mlp_gemm_part_floats(int M, int N, int K) {
-    const int splits = splits_of(M, N, K);
-    return splits > 1 ? (size_t)splits * M * N : 0;
+    // splits x M x N partials; M x N when unsplit (epilogues with a transposed copy)
+    return (size_t)splits_of(M, N, K) * M * N;
+}
+
+size_t mlp_colsum_part_floats(int rows, int cols) {
+    return (size_t)((rows + COLSUM_SLAB - 1) / COLSUM_SLAB) * cols;
 }
 
 hipError_t mlp_gemm_nt(int epi, const void* A, int lda, const void* B, int ldb, int M, int N, int K, float* C, int ldc,
@@ -457,14 +536,20 @@ hipError_t mlp_softmax_ce(const float* logits, const int32_t* labels, int batch,
     return hipGetLastError();
 }
 
-hipError_t mlp_colsum(const float* g, int rows, int cols, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_colsum, dim3(cols), dim3(256), 0, s, g, rows, cols, out);
+hipError_t mlp_colsum(const float* g, int rows, int cols, float* out, float* part, size_t part_floats,
+                      hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    const int slabs = (rows + COLSUM_SLAB - 1) / COLSUM_SLAB;
+    if (part == nullptr || part_floats < (size_t)slabs * cols) return hipErrorInvalidValue;
+    const unsigned strips = (unsigned)((cols + 63) / 64);
+    hipLaunchKernelGGL(k_colsum_part, dim3(strips, (unsigned)slabs), dim3(256), 0, s, g, rows, cols, part);
+    hipLaunchKernelGGL(k_colsum_fin, dim3(strips), dim3(256), 0, s, part, slabs, cols, out);
     return hipGetLastError();
 }
 
 hipError_t mlp_input_bf16(const float* x, int rows, int cols, void* y, int ldy, void* t, int ldt, hipStream_t s) {
     if (rows <= 0 || cols <= 0) return hipSuccess;
-    dim3 grid((cols + 31) / 32, (rows + 31) / 32);
+    dim3 grid((cols + 63) / 64, (rows + 63) / 64);
     hipLaunchKernelGGL(k_to_bf16_t, grid, dim3(256), 0, s, x, rows, cols, (__bf16*)y, ldy, (__bf16*)t, ldt);
     return hipGetLastError();
 }
