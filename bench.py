@@ -10,8 +10,8 @@ launches.
 Also reported by default: the roofline of the walk kernel (VALU-bound), time-to-solution of
 whole searches at n = 3, k = 6 and at n = 4, k = 7 (theta = 1/2, seeds 2, 3, 4, capped), the
 configured-theta search of one planted chunk (capped, censored), the learned depth order
-against the plain order at n = 3, and the CPU oracle timed on the host on a bounded sample of
-the walk workload.
+against the plain order at n = 3, the 64-target mixed batch (solved count and aggregate rate),
+and the CPU oracle timed on the host on a bounded sample of the walk workload.
 """
 
 from __future__ import annotations
@@ -774,8 +774,10 @@ def main():
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution legs")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain depth order block")
     ap.add_argument("--no-network", action="store_true", help="skip the network forward / training-step timing")
-    ap.add_argument("--batch", action="store_true", help="also run the 64-target mixed batch")
-    ap.add_argument("--batch-cap", type=float, default=30.0, help="per-target wall-clock cap (s)")
+    ap.add_argument("--batch", action="store_true",
+                    help="run the 64-target mixed batch at the configured thetas too (the default theta runs anyway)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-target mixed batch")
+    ap.add_argument("--batch-cap", type=float, default=20.0, help="per-target wall-clock cap (s)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration for profiles)")
     ap.add_argument("--tts-n4-cap", type=float, default=40.0, help="wall-clock cap per n = 4 target (s)")
@@ -875,9 +877,10 @@ def main():
                                        orders=tuple(args.mlp_orders.split(",")), log2_table=args.mlp_log2_table)
     if args.configs:
         out["configs"] = config_legs(ctx)
-    if args.batch:
-        out["batch64"] = batch_leg(ctx, args.batch_cap)
+    if not args.no_batch:
         out["batch64_default_theta"] = batch_leg(ctx, args.batch_cap, configured_theta=False)
+        if args.batch:
+            out["batch64"] = batch_leg(ctx, args.batch_cap)
     if args.named:
         out["named_n3_t7"] = named_leg(ctx, args.named_reps, args.named_reps_default_theta)
     if args.sweeps:

@@ -2291,16 +2291,25 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
             break;
         }
         if (dirty) {
-            // the queues: every walking member that is not held, in slices of its walks (one block's
-            // walks each, or more when that would give over four slices per block of the grid)
+            // the queues: every walking member that is not held, in slices of its walks.  A qubit count's
+            // queue holds about four items per block of its grid, shared out by walks, so an item spans
+            // many walks per wavefront: the block's wavefronts meet at a barrier and reload the member's
+            // LDS state only between items (one walk per wavefront per item ran four times slower)
             for (int n = 1; n <= 4; ++n) h_items[n].clear();
+            int64_t walks_n[5] = {0, 0, 0, 0, 0};
             for (int i = 0; i < count; ++i) {
                 BatchTarget& b = bt[i];
                 queued[i] = b.walking && !b.held;
+                if (queued[i]) walks_n[b.t->n] += b.walks;
+            }
+            for (int i = 0; i < count; ++i) {
+                BatchTarget& b = bt[i];
                 if (!queued[i]) continue;
                 const int n = b.t->n;
                 const int wpb = tcw::walks_per_block(n);
-                const int32_t units = (int32_t)std::min<int64_t>((b.walks + wpb - 1) / wpb, 4 * (int64_t)grid[n]);
+                const double share = 4.0 * grid[n] * (double)b.walks / (double)walks_n[n];
+                const int64_t most = (b.walks + wpb - 1) / wpb;
+                const int32_t units = (int32_t)std::max<int64_t>(1, std::min<int64_t>(most, std::llround(share)));
                 for (int32_t u = 0; u < units; ++u) h_items[n].push_back(tcw::WorkItem{i, u, units, b.iters});
             }
             for (int n = 1; n <= 4; ++n) {

@@ -1121,27 +1121,48 @@ __global__ __launch_bounds__(WAVES * 64) void k_walk_queue(const SpaceDev* sps, 
                                                            uint32_t* head) {
     __shared__ Lds<NQ, WAVES> L;
     __shared__ int32_t s_next;
+    // the loaded member's event counts so far, one slot per walk group, owned by the group's leader
+    // (kept in LDS: across items they would hold 22 more VGPRs through the step and spill)
+    __shared__ __attribute__((aligned(8))) unsigned char s_cnt[WAVES * Geo<NQ>::WPW * sizeof(WalkCounts)];
     const int32_t n_items = *count;
-    const bool leader = (threadIdx.x & 63) % Geo<NQ>::G == 0;
+    const int lane = threadIdx.x & 63;
+    const bool leader = lane % Geo<NQ>::G == 0;
+    WalkCounts& mine = reinterpret_cast<WalkCounts*>(s_cnt)[(threadIdx.x >> 6) * Geo<NQ>::WPW + lane / Geo<NQ>::G];
+    if (leader) mine = WalkCounts{};
     int32_t loaded = -1;
-    WalkCounts cnt;  // the loaded member's events, added to its statistics when the member changes
     for (;;) {
         if (threadIdx.x == 0) s_next = (int32_t)atomicAdd(head, 1u);
         __syncthreads();
-        const int32_t i = s_next;
-        if (i >= n_items) break;  // the same value in every thread of the block
+        // the same value in every thread of the block; read from the first lane so that the item and
+        // the member's descriptors are scalar loads
+        const int32_t i = __builtin_amdgcn_readfirstlane(s_next);
+        if (i >= n_items) break;
         const WorkItem it = items[i];
         const SpaceDev sp = sps[it.slot];
         if (it.slot != loaded) {
-            if (loaded >= 0) flush_counts(wds[loaded], cnt, leader);
+            if (loaded >= 0) flush_counts(wds[loaded], mine, leader);
             load_lds(L, sp);
             loaded = it.slot;
         }
         __syncthreads();
-        walk_block<NQ, WAVES>(sp, wds[it.slot], it.iters, L, it.unit, it.units, cnt);
+        WalkCounts c;
+        walk_block<NQ, WAVES>(sp, wds[it.slot], it.iters, L, it.unit, it.units, c);
+        if (leader) {
+            mine.steps += c.steps;
+            mine.dps += c.dps;
+            mine.ins += c.ins;
+            mine.ab += c.ab;
+            mine.rh += c.rh;
+            mine.same += c.same;
+            mine.red += c.red;
+            mine.claw += c.claw;
+            mine.full += c.full;
+            mine.spin += c.spin;
+            mine.active += c.active;
+        }
         __syncthreads();  // s_next and, for the next member, the LDS are rewritten after this
     }
-    if (loaded >= 0) flush_counts(wds[loaded], cnt, leader);
+    if (loaded >= 0) flush_counts(wds[loaded], mine, leader);
 }
 
 __global__ void k_walk_init(SpaceDev sp, WalkDev wd) {
