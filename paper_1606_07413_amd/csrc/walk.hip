@@ -285,7 +285,7 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
     // s = 61 - 32 (g & 1),
     //   2^(61 - s) x = (x >> s) 2^61 + (x mod 2^s) 2^(61 - s) = (x >> s) + (x mod 2^s) 2^(61 - s)  (mod p)
     // and y = p + (x >> s) + (x mod 2^s) 2^(61 - s).  Four such values sum below 2^64.
-    constexpr int NG = 4;
+    constexpr int NG = 2;
     const uint32_t s_g = 61 - 32 * (uint32_t)(g & 1);
     const uint64_t m_g = (1ull << s_g) - 1;
     // Fragments of tiles 8..15 lie beyond the 64 KiB reach of a DS immediate offset: they are read
@@ -300,24 +300,31 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
     // tile groups in the order 0..3, 8..11, 4..7, 12..15: after the second and the fourth group the
     // tile pairs (i, 8 + i) are complete and reduce at once, which keeps few halves live
 #pragma unroll
-    for (int gi = 0; gi < 4; ++gi) {
+    for (int gi = 0; gi < N4_NT / NG; ++gi) {
         const int n0 = (gi & 1) * 8 + (gi >> 1) * NG;
         v4i acc[NG];
 #pragma unroll
         for (int i = 0; i < NG; ++i) acc[i] = v4i{0, 0, 0, 0};
+        // B fragments double-buffered: the next K step's NG fragments are read while this step's MFMAs
+        // run, so each read has a whole step of MFMAs to cover its LDS latency
+        auto frag = [&](int t, int kk) -> v4i {
+            return t < 8 ? L.frag[(t * N4_KK + kk) * 64 + lane] : frag_hi[((t - 8) * N4_KK + kk) * 64 + lane];
+        };
+        v4i bf[2][NG];
+#pragma unroll
+        for (int i = 0; i < NG; ++i) bf[0][i] = frag(n0 + i, 0);
 #pragma unroll
         for (int kk = 0; kk < N4_KK; ++kk) {
-            v4i bf[NG];
+            if (kk + 1 < N4_KK) {
 #pragma unroll
-            for (int i = 0; i < NG; ++i) {
-                const int t = n0 + i;
-                bf[i] = t < 8 ? L.frag[(t * N4_KK + kk) * 64 + lane] : frag_hi[((t - 8) * N4_KK + kk) * 64 + lane];
+                for (int i = 0; i < NG; ++i) bf[(kk + 1) & 1][i] = frag(n0 + i, kk + 1);
             }
+            // the reads above are issued before this step's MFMAs (nothing moves across)
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int i = 0; i < NG; ++i)
-                acc[i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(afr[kk], bf[i], acc[i], 0, 0, 0);
-            __builtin_amdgcn_sched_group_barrier(0x100, NG, 0);  // DS reads
-            __builtin_amdgcn_sched_group_barrier(0x008, NG, 0);  // MFMA
+                acc[i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(afr[kk], bf[kk & 1][i], acc[i], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int i = 0; i < NG; ++i) {

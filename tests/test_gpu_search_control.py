@@ -448,3 +448,40 @@ def test_trail_n4k7_to_a_distinguished_point(ctx):
         want_dp, want_len = owalk.trail(spec, s, 80)
         assert got_len[i] == want_len and want_len >= 1
         assert got_dp[i] == want_dp
+
+
+def test_batch_exhaustive_matches_single_searches(ctx):
+    """Exhaustive mode does not depend on walk count or arrival order (the table keeps each side's
+    least point per key, candidates are read after the last point and checked in sorted order), so a
+    batch of enumerated members of every qubit count -- the queue kernels of n = 1..4 sharing rounds,
+    one target entered twice -- returns, member by member, the decomposition that searching the
+    target alone returns, bit for bit."""
+    from paper_1606_07413_amd import tcw
+    say("batch exhaustive vs single")
+    specs = [(1, 3, 21), (1, 7, 22), (2, 4, 23), (2, 5, 24), (3, 4, 25), (3, 5, 26), (4, 3, 27), (4, 4, 28),
+             (2, 4, 23)]
+
+    def params(n, k, walks):
+        p = ctx.default_params(n)
+        p.k_max = k
+        p.seed = 610
+        p.walks = walks
+        p.enum_max = 1 << 18      # every space of these targets is enumerated
+        p.max_seconds = 60
+        return p
+
+    targets, us = [], []
+    for n, k, seed in specs:
+        tw, u = oracle_target(n, k, seed)
+        targets.append(ctx.target_from_words(n, tw.paulis, tw.clifford))
+        us.append(u)
+    batch, _ = ctx.search_batch(targets, [params(n, k, 256) for n, k, _ in specs])
+    for (n, k, seed), tgt, u, rb in zip(specs, targets, us, batch):
+        rs = ctx.search(tgt, params(n, k, 1024))
+        assert rs.status == rb.status == tcw.STATUS_FOUND, (n, k, seed)
+        assert rs.t == rb.t <= k and rs.minimal == rb.minimal == 1
+        t, r = rs.t, 4 ** n
+        assert list(rb.paulis[:t]) == list(rs.paulis[:t]) and rb.chunk == rs.chunk, (n, k, seed)
+        assert list(rb.clifford_perm[:r]) == list(rs.clifford_perm[:r])
+        assert list(rb.clifford_sign[:r]) == list(rs.clifford_sign[:r])
+        assert reconstructs(n, rb, u)
