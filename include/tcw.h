@@ -302,16 +302,20 @@ int tcw_checkpoint(tcw_ctx* ctx, void* host_buf, size_t* len);
 int tcw_resume(tcw_ctx* ctx, const tcw_target* t, const void* host_buf, size_t len, int64_t launch_limit,
                tcw_result* res);
 
-/* ---- batching: many targets of mixed n and k in one graph-captured launch per round ----------
+/* ---- batching: many targets of mixed n and k, one graph replay per round ------------------------
  * tcw_search_batch: targets[i] is searched with params[i] (its own k_max, seed, budgets, wall-clock
  * cap max_seconds); walks <= 0, log2_table <= 0 or iters_per_launch <= 0 take the autotuner's
- * choice for that (n, k).  Depth 0 and small spaces are searched on the spot; every target that is
- * in a walk space advances together: each round replays one hipGraph whose parallel branches run one
- * persistent batch kernel per qubit count, each block serving one target (its own S_c, keys, walk
- * states and table).  Between rounds the host checks claw candidates exactly, switches function
- * versions, chunks and depths per target.  results[i] as for tcw_search (status 0: not found within
- * budget or cap).  *aggregate_steps_per_s (may be NULL): walk steps of all targets per second of
- * graph execution.  Blocking.
+ * choice for that (n, k).  Depth 0 is checked on the spot; every other space (walked, or enumerated
+ * when small) is a batch member, and all members advance together in rounds: each round replays one
+ * hipGraph, captured once per call, whose parallel branches run one persistent queue kernel per qubit
+ * count; its blocks take (member, slice of walks) items from a device queue until it is empty (each
+ * member with its own S_c, keys, walk states and table; about four items per block, shared out by
+ * walks).  Between rounds the host rewrites the queues and the member descriptors, switches function
+ * versions, chunks and depths; claw candidates read after a round are checked exactly while the
+ * next round runs, and a member whose space ends with unchecked candidates waits for them.
+ * results[i] as for tcw_search (status 0: not found within budget or cap).
+ * *aggregate_steps_per_s (may be NULL): walk steps of all targets per second of round time (graph
+ * execution and the checks beside it).  Blocking.
  * tcw_autotune: times short walk launches of (n, k) over walk counts 64, 256, ... up to min(N/4, 2^20)
  * and returns the smallest count within 85% of the best rate, launch iterations for ~4 ms launches
  * and a table size holding a version's distinguished points with 4x headroom.  Results are cached
