@@ -277,7 +277,8 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
         wave_sync();
     }
     // N tiles in groups of NG: NG independent accumulation chains over the 8 K steps, then each
-    // finished tile is combined at once, so only NG accumulators and NG fragments are live.
+    // finished tile is combined at once, so only NG accumulators and 2 NG fragments (the current
+    // and the next K step's) are live.
     // Accumulator row m = 4g + j of this lane is digit m % 8 of set g >> 1 (u, or 2^31 u), weight
     // 2^(8 (m % 8)) = 2^(32 (g & 1)) 2^(8j).  Each row sums 256 products, |acc| <= 256 * 128 * 127
     // < 2^22, so x = acc_0 + 2^8 acc_1 + 2^16 acc_2 + 2^24 acc_3 lies in (-2^45, 2^45) and the sum of
@@ -297,8 +298,8 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
     // |lo|, |hi| <= 257 * 256 * 128 * 127 < 2^30.
     int32_t lo[N4_NT], hi[N4_NT];
     uint64_t Q[8];
-    // tile groups in the order 0..3, 8..11, 4..7, 12..15: after the second and the fourth group the
-    // tile pairs (i, 8 + i) are complete and reduce at once, which keeps few halves live
+    // tile groups in the order 0..1, 8..9, 2..3, 10..11, ...: after every second group the tile
+    // pairs (i, 8 + i) are complete and reduce at once, which keeps few halves live
 #pragma unroll
     for (int gi = 0; gi < N4_NT / NG; ++gi) {
         const int n0 = (gi & 1) * 8 + (gi >> 1) * NG;
