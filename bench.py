@@ -667,25 +667,26 @@ def mlp_leg(ctx, train_count: int, epochs: int, eval_count: int, cap: float, ord
     n, classes = spec["n"], spec["classes"]
     h_max = 3
 
-    def dataset(words):
-        feats = torch.empty((len(words), 16 ** n), dtype=torch.float32, device="cuda:0")
-        labels = torch.empty(len(words), dtype=torch.int32, device="cuda:0")
-        for lo in range(0, len(words), 1 << 17):
-            part = words[lo:lo + (1 << 17)]
-            ctx.label_batch(n, [(w.paulis, w.clifford) for w in part], h_max, 777, feats[lo:lo + len(part)],
-                            labels[lo:lo + len(part)])
-        return feats, labels
+    def dataset(seed_lo, count):
+        words, offsets, ks = seeded_inputs.mlp_target_arrays(seed_lo, seed_lo + count, n)
+        feats = torch.empty((count, 16 ** n), dtype=torch.float32, device="cuda:0")
+        labels = torch.empty(count, dtype=torch.int32, device="cuda:0")
+        part = 1 << 18
+        for lo in range(0, count, part):
+            hi = min(count, lo + part)
+            ctx.label_words(n, words[offsets[lo]:offsets[hi]], offsets[lo:hi + 1] - offsets[lo], ks[lo:hi], h_max,
+                            777, feats[lo:hi], labels[lo:hi])
+        return feats, labels, ks
 
     t0 = time.perf_counter()
-    train = seeded_inputs.mlp_targets(spec["train_seeds"][0], spec["train_seeds"][0] + train_count)
-    feats, labels = dataset(train)
+    feats, labels, ks = dataset(spec["train_seeds"][0], train_count)
     torch.cuda.synchronize()
     t_label = time.perf_counter() - t0
-    gen_k = torch.tensor([w.k for w in train], dtype=torch.int32, device="cuda:0")
+    gen_k = torch.from_numpy(ks).to("cuda:0")
     unknown = labels < 0
     labels = torch.where(unknown, gen_k, labels)       # T-count > 2 h_max: the generating k (an upper bound)
-    del train, gen_k
-    _log(f"labelled {train_count} circuits in {t_label:.1f} s ({int(unknown.sum())} above {2 * h_max})")
+    del gen_k, ks
+    _log(f"generated and labelled {train_count} circuits in {t_label:.1f} s ({int(unknown.sum())} above {2 * h_max})")
     net = tcw.Network(ctx, 16 ** n, spec["hidden"], spec["depth"], classes, seed=spec["init_seed"])
     t1 = time.perf_counter()
     loss = net.train(feats, labels, spec["batch"], epochs, 1e-3)
@@ -696,7 +697,7 @@ def mlp_leg(ctx, train_count: int, epochs: int, eval_count: int, cap: float, ord
     del feats, labels
 
     ev = seeded_inputs.mlp_targets(spec["eval_seeds"][0], spec["eval_seeds"][0] + eval_count)
-    ef, el = dataset(ev)
+    ef, el, _ = dataset(spec["eval_seeds"][0], eval_count)
     probs = torch.empty((eval_count, classes), dtype=torch.float32, device="cuda:0")
     net.forward(ef, probs)
     pred = probs.argmax(dim=1).to(torch.int32)
@@ -795,7 +796,7 @@ def main():
                     help="also run the n = 2, k = 4 and n = 3, k = 6 searches and walk rates")
     ap.add_argument("--cpu-configs", action="store_true",
                     help="with the CPU baseline, also time the oracle at every configuration")
-    ap.add_argument("--mlp-train", type=int, default=1 << 17, help="training circuits of the learned order")
+    ap.add_argument("--mlp-train", type=int, default=1_000_000, help="training circuits of the learned order")
     ap.add_argument("--mlp-epochs", type=int, default=8)
     ap.add_argument("--mlp-eval", type=int, default=256, help="held-out circuits")
     ap.add_argument("--mlp-cap", type=float, default=1.0, help="wall-clock cap (s) of each held-out search")

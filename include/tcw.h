@@ -326,10 +326,13 @@ int tcw_autotune(tcw_ctx* ctx, const tcw_target* t, int k, int chunk, int delta,
                  int* iters, int* log2_table, double* steps_per_s);
 
 /* tcw_min_tcount: minimal T-count of a target (n <= 3) by meet in the middle (Sec. 3, the split
- * of the synthesis equation into two halves): every left-Clifford coset of T-count <= h_max
- * reached from the identity is tabled by its matrix hash (keyed by seed), then every product U R(P_1)^T ... R(P_j)^T, j <= h_max, is looked up.  *t_out
- * is the least i + j over matches, which is the T-count whenever that is at most 2 h_max, else -1
- * (no decomposition with T-count <= 2 h_max exists).  A 64-bit hash collision could only lower the
+ * of the synthesis equation into two halves): every left-Clifford coset of T-count <= h_id
+ * reached from the identity is tabled by its matrix hash (keyed by seed), then every product
+ * U R(P_1)^T ... R(P_j)^T, j <= 2 h_max - h_id, is looked up.  The split h_id is chosen on the host to
+ * minimise table plus probe steps (h_max itself for one target; the table holds at most 2^25 entries
+ * unless the balanced split needs more); every split covers the same T-counts.  *t_out is the least
+ * i + j over matches, which is the T-count whenever that is at most 2 h_max, else -1 (no
+ * decomposition with T-count <= 2 h_max exists).  A 64-bit hash collision could only lower the
  * answer, never hide a match.  TCW_EOVERFLOW if U's entries do not fit int8 at its exponent.
  * Blocking. */
 int tcw_min_tcount(tcw_ctx* ctx, const tcw_target* t, int h_max, uint64_t seed, int32_t* t_out);
@@ -372,9 +375,10 @@ int tcw_circuit(const tcw_result* res, tcw_gate* gates, int32_t cap, int32_t* co
  * tcw_features: features of one target into out_dev (4^n * 4^n floats, device).
  * tcw_label_batch: `count` targets given as words (words[offsets[i] .. offsets[i+1]) = P_1..P_k then
  * C_1..C_m, k = kof[i]) are built exactly on the GPU; features_dev[i] gets their features and
- * labels_dev[i] their minimal T-count when it is at most 2 h_max (meet in the middle: every coset
- * of T-count <= h_max from the identity side against every product of <= h_max rotations on the
- * target side, by matrix hash), else -1.  Host arrays: offsets[0] = 0 and non-decreasing,
+ * labels_dev[i] their minimal T-count when it is at most 2 h_max (meet in the middle as in
+ * tcw_min_tcount, with the split chosen for `count` targets: the table is built once per call, so a
+ * large batch tables deeper identity-side levels and probes fewer rotations per target), else -1.
+ * Host arrays: offsets[0] = 0 and non-decreasing,
  * 0 <= kof[i] <= word length, 2 m + k <= 256 rotations per word, codes in 1..4^n - 1, else
  * TCW_EINVAL before any device work.
  * tcw_mlp_create: parameters are W_0, b_0, W_1, b_1, ... (W_l row-major in x out); init (host,

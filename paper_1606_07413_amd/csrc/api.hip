@@ -2942,7 +2942,7 @@ extern "C" int tcw_mlp_depth_order(tcw_mlp* m, const tcw_target* t, int k_max, c
 
 namespace {
 
-// Hash table of every left-Clifford coset reached by <= h_max rotations from the identity, keyed by
+// Hash table of every left-Clifford coset reached by <= h rotations from the identity, keyed by
 // matrix hash, value 255 - (least number of rotations); shared by the labelling and certificate calls.
 struct LevelTable {
     uint64_t* table = nullptr;
@@ -2956,14 +2956,14 @@ struct LevelTable {
     }
 };
 
-int build_level_table(tcw_ctx* c, int n, int h_max, uint64_t seed, LevelTable& lt) {
+int build_level_table(tcw_ctx* c, int n, int h_levels, uint64_t seed, LevelTable& lt) {
     const int R = 1 << (2 * n);
     HIP_TRY(c, hipMalloc(&lt.zero_phi, (size_t)R * R / 2 * 4));
     HIP_TRY(c, hipMemsetAsync(lt.zero_phi, 0, (size_t)R * R / 2 * 4, c->stream));
     HIP_TRY(c, hipMalloc(&lt.keys, (size_t)R * 8));
     HIP_TRY(c, tcw::keys_fill(n, seed, lt.keys, c->stream));
     uint64_t entries = 0;
-    for (int h = 0; h <= h_max; ++h) entries += n_half_of(n, h);
+    for (int h = 0; h <= h_levels; ++h) entries += n_half_of(n, h);
     lt.lg = 10;
     while ((1ull << lt.lg) < 4 * entries && lt.lg < 30) ++lt.lg;
     HIP_TRY(c, hipMalloc(&lt.table, ((size_t)1 << lt.lg) * 16));
@@ -2972,12 +2972,37 @@ int build_level_table(tcw_ctx* c, int n, int h_max, uint64_t seed, LevelTable& l
     lt.sp.salt_h = tcw::sm64(tcw::sm64(seed, 2), 0x4C4142454Cull);
     lt.sp.keys = lt.keys;
     lt.sp.phi = lt.zero_phi;
-    for (int h = 0; h <= h_max; ++h) {
+    for (int h = 0; h <= h_levels; ++h) {
         lt.sp.h = h;
         lt.sp.n_half = (uint32_t)n_half_of(n, h);
         HIP_TRY(c, tcw::mitm_levels(n, lt.sp, h, lt.table, lt.lg, c->stream));
     }
     return TCW_OK;
+}
+
+uint64_t level_entries(int n, int h) {
+    uint64_t e = 0;
+    for (int i = 0; i <= h; ++i) e += n_half_of(n, i);
+    return e;
+}
+
+// Identity-side depth h_id of the meet-in-the-middle split for `count` targets.  The table holds every
+// coset reached by <= h_id rotations and each target probes its products with <= 2 h_max - h_id
+// rotations, so any split finds every T-count up to 2 h_max.  The one chosen minimises the table's
+// steps plus the targets' worst-case probe steps, with the table at most 2^25 entries (or the
+// balanced split's size, if larger): one target keeps the balanced split, a large batch moves
+// work into the table it builds once.
+int mitm_split(int n, int h_max, int64_t count) {
+    const uint64_t cap = std::max<uint64_t>(1ull << 25, level_entries(n, h_max));
+    auto cost = [&](int h) {
+        return (double)level_entries(n, h) + (double)count * (double)level_entries(n, 2 * h_max - h);
+    };
+    int best = h_max;
+    for (int h = 0; h <= 2 * h_max; ++h) {
+        if (n_half_of(n, h) == 0 || n_half_of(n, 2 * h_max - h) == 0 || level_entries(n, h) > cap) continue;
+        if (cost(h) < cost(best)) best = h;
+    }
+    return best;
 }
 
 int check_mitm_args(tcw_ctx* c, int n, int h_max) {
@@ -3034,8 +3059,9 @@ extern "C" int tcw_label_batch(tcw_ctx* c, int n, int count, const uint16_t* wor
     LB_TRY(hipMalloc(&rot, chunk * 4));
     LB_TRY(hipMalloc(&phi, (size_t)chunk * R * R / 2 * 4));
     LB_TRY(hipMalloc(&scratch, tcw::build_batch_scratch_bytes(n, blocks)));
+    const int h_id = mitm_split(n, h_max, count);
     LevelTable lt;
-    if ((rc = build_level_table(c, n, h_max, seed, lt)) || (rc = clear_flag(c))) {
+    if ((rc = build_level_table(c, n, h_id, seed, lt)) || (rc = clear_flag(c))) {
         cleanup();
         return rc;
     }
@@ -3043,7 +3069,8 @@ extern "C" int tcw_label_batch(tcw_ctx* c, int n, int count, const uint16_t* wor
         const int cnt = std::min(chunk, count - first);
         LB_TRY(tcw::build_batch(n, dwords, doff + first, dk + first, cnt, scratch, blocks, phi, rot,
                                 features_dev + (size_t)first * R * R, c->flag, c->stream));
-        LB_TRY(tcw::mitm_probe(n, lt.sp, phi, rot, cnt, h_max, lt.table, lt.lg, labels_dev + first, c->stream));
+        LB_TRY(tcw::mitm_probe(n, lt.sp, phi, rot, cnt, 2 * h_max - h_id, lt.table, lt.lg, labels_dev + first,
+                               c->stream));
     }
     int flag = 0;
     rc = read_flag(c, &flag);
@@ -3092,11 +3119,12 @@ extern "C" int tcw_min_tcount(tcw_ctx* c, const tcw_target* t, int h_max, uint64
         cleanup();
         return hip_fail(c, err, "rot_e upload");
     }
-    if ((rc = build_level_table(c, n, h_max, seed, lt))) {
+    const int h_id = mitm_split(n, h_max, 1);
+    if ((rc = build_level_table(c, n, h_id, seed, lt))) {
         cleanup();
         return rc;
     }
-    err = tcw::mitm_probe(n, lt.sp, phi, dev_i32, 1, h_max, lt.table, lt.lg, dev_i32 + 1, c->stream);
+    err = tcw::mitm_probe(n, lt.sp, phi, dev_i32, 1, 2 * h_max - h_id, lt.table, lt.lg, dev_i32 + 1, c->stream);
     if (err == hipSuccess) err = hipMemcpyAsync(t_out, dev_i32 + 1, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
     if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
     cleanup();

@@ -501,23 +501,39 @@ def _features(self, target, out):
 
 def _label_batch(self, n, words_list, h_max, seed, features_out, labels_out):
     """words_list: [(paulis, clifford), ...]; fills device tensors features_out, labels_out."""
+    import numpy as np
     flat, offs, ks = [], [0], []
     for paulis, clifford in words_list:
         flat.extend(paulis)
         flat.extend(clifford)
         offs.append(len(flat))
         ks.append(len(paulis))
-    w = (C.c_uint16 * max(1, len(flat)))(*flat)
-    o = (C.c_int32 * len(offs))(*offs)
-    k = (C.c_int32 * len(ks))(*ks)
+    self.label_words(n, np.asarray(flat, dtype=np.uint16), np.asarray(offs, dtype=np.int32),
+                     np.asarray(ks, dtype=np.int32), h_max, seed, features_out, labels_out)
+
+
+def _label_words(self, n, words, offsets, kof, h_max, seed, features_out, labels_out):
+    """tcw_label_batch on flat host arrays: words (uint16), offsets (int32, count + 1), kof (int32)."""
+    import numpy as np
+    words = np.ascontiguousarray(words, dtype=np.uint16)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int32)
+    kof = np.ascontiguousarray(kof, dtype=np.int32)
+    count = len(kof)
+    if len(offsets) != count + 1 or count < 1 or int(offsets[-1]) > len(words):
+        raise ValueError("offsets must hold count + 1 entries within words")
+    if len(words) == 0:
+        words = np.zeros(1, dtype=np.uint16)
     d = self.device
-    self._check(self.lib.tcw_label_batch(self.h, n, len(ks), w, o, k, h_max, seed,
-                                         _dev(features_out, 4, len(ks) * 16 ** n, "features_out", d),
-                                         _dev(labels_out, 4, len(ks), "labels_out", d)))
+    self._check(self.lib.tcw_label_batch(self.h, n, count, words.ctypes.data_as(C.POINTER(C.c_uint16)),
+                                         offsets.ctypes.data_as(C.POINTER(C.c_int32)),
+                                         kof.ctypes.data_as(C.POINTER(C.c_int32)), h_max, seed,
+                                         _dev(features_out, 4, count * 16 ** n, "features_out", d),
+                                         _dev(labels_out, 4, count, "labels_out", d)))
 
 
 Context.features = _features
 Context.label_batch = _label_batch
+Context.label_words = _label_words
 
 
 class Network:

@@ -22,6 +22,8 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 from typing import List
 
+import numpy as np
+
 MASK64 = (1 << 64) - 1
 GAMMA = 0x9E3779B97F4A7C15
 
@@ -141,6 +143,43 @@ def mlp_targets(seed_lo: int, seed_hi: int, n: int = 3, k_lo: int = 1, k_hi: int
         k = k_lo + uniform_below(s ^ 0x6B, 0, k_hi - k_lo + 1)
         out.append(target_words(n, k, s))
     return out
+
+
+def _mix_np(z):
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def uniform_below_np(seeds, i, bound: int):
+    """uniform_below over arrays: seeds and i broadcast (uint64 arithmetic wraps mod 2^64 as the scalar
+    form's masks do); the 64 x 32-bit multiply-high is taken from the two 32-bit halves of r."""
+    if not 1 <= bound < (1 << 32):
+        raise ValueError("bound must be in 1 .. 2^32 - 1")
+    seeds = np.asarray(seeds, dtype=np.uint64)
+    i = np.asarray(i, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        r = _mix_np(seeds + (i + np.uint64(1)) * np.uint64(GAMMA))
+    b = np.uint64(bound)
+    hi, lo = r >> np.uint64(32), r & np.uint64(0xFFFFFFFF)
+    return ((hi * b + ((lo * b) >> np.uint64(32))) >> np.uint64(32)).astype(np.int64)
+
+
+def mlp_target_arrays(seed_lo: int, seed_hi: int, n: int = 3, k_lo: int = 1, k_hi: int = 10):
+    """The targets of mlp_targets(seed_lo, seed_hi, n, k_lo, k_hi) as flat arrays: words (uint16,
+    every target's k rotation Paulis then its 16 n Clifford Paulis), offsets (int32, count + 1) and
+    ks (int32)."""
+    seeds = np.arange(seed_lo, seed_hi, dtype=np.uint64)
+    ks = (k_lo + uniform_below_np(seeds ^ np.uint64(0x6B), 0, k_hi - k_lo + 1)).astype(np.int32)
+    m = 16 * n
+    lens = ks.astype(np.int64) + m
+    offsets = np.zeros(len(seeds) + 1, dtype=np.int64)
+    np.cumsum(lens, out=offsets[1:])
+    total = int(offsets[-1])
+    owner = np.repeat(np.arange(len(seeds)), lens)
+    pos = np.arange(total, dtype=np.int64) - offsets[:-1][owner]
+    words = (uniform_below_np(seeds[owner], pos.astype(np.uint64), 4 ** n - 1) + 1).astype(np.uint16)
+    return words, offsets.astype(np.int32), ks
 
 
 # Named 3-qubit reversible gates (Sec. 5.2, benchmarking known circuits), from their textbook

@@ -120,6 +120,36 @@ def test_labels_n3_consistent(ctx):
             assert res.status == 1 and res.t == a
 
 
+def test_labels_n3_batch_split(ctx):
+    """n = 3, a batch of 256: large enough that the labeller tables identity-side cosets up to T-count 4
+    and probes at most 2 rotations per target.  Its labels equal the one-target certificate's, which
+    keeps the balanced 3 + 3 split, and the exhaustive search's for small generating k."""
+    print("labels n3 batch split", flush=True)
+    words, tws = [], []
+    for seed in range(256):
+        k = 1 + seed % 10
+        tw = seeded_inputs.target_words(3, k, 7000 + seed)
+        words.append((tw.paulis, tw.clifford))
+        tws.append((k, tw))
+    _, labels = _label(ctx, 3, words, 3)
+    seen = set()
+    for i in range(0, 200, 3):      # every generating k in 1..10
+        k, tw = tws[i]
+        tgt = ctx.target_from_words(3, tw.paulis, tw.clifford)
+        want = ctx.min_tcount(tgt, 3)
+        assert labels[i] == want, (i, k)
+        assert labels[i] <= k
+        if 2 <= k <= 4:
+            p = ctx.default_params(3)
+            p.k_max = 4
+            res = ctx.search(tgt, p)
+            assert res.status == 1 and res.t == labels[i]
+        tgt.free()
+        seen.add(labels[i])
+    # T-counts that need 0, 1 and 2 target-side rotations, and some beyond 6, are all covered
+    assert {3, 4, 5, 6, -1} <= seen
+
+
 def test_init_bit_exact(ctx):
     from paper_1606_07413_amd import tcw
     net = tcw.Network(ctx, 256, 64, 3, 11, seed=42)

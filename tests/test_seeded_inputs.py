@@ -44,3 +44,20 @@ def test_random_points_cover_both_sides_uniformly():
     for x in xs:
         bins[x * 16 // n_half] += 1
     assert abs(_chi2(bins, 1250) - 15) < 6 * (30 ** 0.5)
+
+
+def test_array_generator_equals_scalar_one():
+    """The vectorised generator draws exactly what the scalar SplitMix64 form draws, including
+    bounds near 2^32 (the 64 x 32-bit multiply-high taken from two halves) and seeds near 2^64."""
+    import numpy as np
+    seeds = [0, 1, 7, (1 << 64) - 1, (1 << 63) + 12345, 0x6B]
+    for bound in (1, 3, 63, 255, 1000003, (1 << 32) - 1):
+        got = seeded_inputs.uniform_below_np(np.array(seeds, dtype=np.uint64), np.arange(len(seeds)), bound)
+        want = [seeded_inputs.uniform_below(s, i, bound) for i, s in enumerate(seeds)]
+        assert got.tolist() == want
+    words, offsets, ks = seeded_inputs.mlp_target_arrays(123, 423)
+    ref = seeded_inputs.mlp_targets(123, 423)
+    assert ks.tolist() == [t.k for t in ref]
+    for i, t in enumerate(ref):
+        assert words[offsets[i]:offsets[i + 1]].tolist() == t.paulis + t.clifford
+    assert offsets[0] == 0 and offsets[-1] == len(words)
