@@ -351,6 +351,95 @@ __device__ inline void side1_mfma(const Lds<4, WAVES>& L, uint32_t* limbs, const
     for (int i = 0; i < 4; ++i) S[i] = m61_rot(m61_fold(half_add16(Q[i], Q[4 + i])), rot_e);
 }
 
+// n = 4, two walks of one wavefront on side 1 together: walk w's digit rows become A-operand rows
+// 8w .. 8w + 7, each over the whole K = [u | 2^31 u] (digit m of u on the A half, digit m of 2^31 u
+// on the B half), so no A row is zero and one pass of the 128 MFMAs serves both walks.  Walk w's
+// u goes through the wavefront's 8-row digit buffer one digit set at a time; only the lanes that
+// hold rows of walk w (n16 / 8 == w) take fragments from it.
+__device__ inline void digits_pair(uint32_t* limbs, const uint64_t* u, int lane, int w, v4i* afr) {
+    const int g = lane >> 4, n16 = lane & 15;
+    const bool mine = (n16 >> 3) == w;
+    const uint32_t* arow = limbs + (n16 & 7) * N4_ROW;
+#pragma unroll
+    for (int set = 0; set < 2; ++set) {
+        // signed base-256 digits of u (set 0) or of 2^31 u (set 1), as in side1_mfma
+        uint32_t lo[4], hi[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t v = set ? (u[j] >> 30) + ((u[j] & 0x3fffffffull) << 31) : u[j];
+            const uint64_t b = v + 0x8080808080808080ull;
+            lo[j] = (uint32_t)b;
+            hi[j] = (uint32_t)(b >> 32);
+        }
+        uint32_t dg[N4_DIG];
+        transpose_bytes4(lo, dg);
+        transpose_bytes4(hi, dg + 4);
+#pragma unroll
+        for (int m = 0; m < N4_DIG; ++m) limbs[m * N4_ROW + lane] = dg[m] ^ 0x80808080u;
+        wave_sync();
+        if (mine) {
+#pragma unroll
+            for (int kq = 0; kq < 4; ++kq) afr[set * 4 + kq] = *reinterpret_cast<const v4i*>(&arow[kq * 16 + g * 4]);
+        }
+        wave_sync();
+    }
+}
+
+// The product of both walks on the shared A operand.  Accumulator row m = 4g + j of lane l is
+// digit 4 (g & 1) + j of walk g >> 1 summed over both digit sets: 512 products of at most
+// 128 x 127, |acc| < 2^23, so lo = acc_0 + 2^8 acc_1 and hi = acc_2 + 2^8 acc_3 stay within
+// 257 x 512 x 128 x 127 < 2^31.  Each tile's raw sum x = lo + 2^16 hi becomes its lazy weighted
+// residue (weight 2^(32 (g & 1)), as in side1_mfma); the two digit halves of a row sit in lanes l
+// and l ^ 16 and are added by one cross-row swap per tile pair (i, 8 + i).  R[i] is then, in lanes
+// of even g, row 16 i + n16 and, in lanes of odd g, row 16 (8 + i) + n16 of walk g >> 1.
+template <int WAVES>
+__device__ inline void side1_mfma_pair(const Lds<4, WAVES>& L, const v4i* afr, int lane, int rot_e, uint64_t* R) {
+    const int g = lane >> 4;
+    constexpr int NG = 2;
+    const uint32_t s_g = 61 - 32 * (uint32_t)(g & 1);
+    const uint64_t m_g = (1ull << s_g) - 1;
+    uint32_t hi_base = 8 * N4_KK * 64;
+    asm("" : "+v"(hi_base));
+    const v4i* frag_hi = L.frag + hi_base;
+    uint64_t Q[8];
+#pragma unroll
+    for (int gi = 0; gi < N4_NT / NG; ++gi) {
+        const int n0 = (gi & 1) * 8 + (gi >> 1) * NG;
+        v4i acc[NG];
+#pragma unroll
+        for (int i = 0; i < NG; ++i) acc[i] = v4i{0, 0, 0, 0};
+        auto frag = [&](int t, int kk) -> v4i {
+            return t < 8 ? L.frag[(t * N4_KK + kk) * 64 + lane] : frag_hi[((t - 8) * N4_KK + kk) * 64 + lane];
+        };
+        v4i bf[2][NG];
+#pragma unroll
+        for (int i = 0; i < NG; ++i) bf[0][i] = frag(n0 + i, 0);
+#pragma unroll
+        for (int kk = 0; kk < N4_KK; ++kk) {
+            if (kk + 1 < N4_KK) {
+#pragma unroll
+                for (int i = 0; i < NG; ++i) bf[(kk + 1) & 1][i] = frag(n0 + i, kk + 1);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < NG; ++i)
+                acc[i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(afr[kk], bf[kk & 1][i], acc[i], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int i = 0; i < NG; ++i) {
+            const int64_t x = (int64_t)(acc[i][0] + acc[i][1] * 256) + (int64_t)(acc[i][2] + acc[i][3] * 256) * 65536;
+            const uint64_t q = P61 + (uint64_t)(x >> s_g) + (((uint64_t)x & m_g) << (61 - s_g));
+            if (gi & 1)
+                R[n0 - 8 + i] = half_add16(Q[n0 - 8 + i], q);
+            else
+                Q[n0 + i] = q;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) R[i] = m61_rot(m61_fold(R[i]), rot_e);
+}
+
 // n = 3: phi(S_c) u on MFMA, the n = 4 scheme at R = 64 with one row per lane: A-operand rows 0..7
 // are the signed base-256 digits of u on the A half of K = 128, rows 8..15 those of 2^31 u on the
 // B half; 4 N tiles x 2 K steps.  Lane l holds accumulator rows 4g..4g+3 (g = l/16) of column l%16
@@ -523,6 +612,31 @@ __device__ inline void rotate4(uint64_t* u, const uint32_t* dig, int h, int side
     }
 }
 
+// n = 4: the key vector with the first rotations already applied -- R(p_{h-2}) R(p_{h-1}) K or the
+// transposes' from the two-rotation table, one rotation from the one-rotation table, or K itself --
+// into u (lane gl's four rows); returns how many rotations are left to apply.
+template <int WAVES>
+__device__ inline int key_row4(const SpaceDev& sp, const Lds<4, WAVES>& L, const uint32_t* dig, int side, int gl,
+                               uint64_t* u) {
+    const int h = sp.h;
+    if (sp.rkeys2 != nullptr && h >= 2) {
+        const uint64_t* tp =
+            sp.rkeys2 + ((((uint32_t)side * 256u + dig[h - 1]) * 256u + dig[h - 2]) * 256u + 4u * (uint32_t)gl);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) u[j] = tp[j];
+        return h - 2;
+    }
+    if (sp.rkeys != nullptr && h >= 1) {
+        const uint64_t* tp = sp.rkeys + ((uint32_t)side * 256u + dig[h - 1]) * 256u + 4u * (uint32_t)gl;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) u[j] = tp[j];
+        return h - 1;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) u[j] = L.K[gl * 4 + j];
+    return h;
+}
+
 // One evaluation of f on `pt` by the walk group; every lane of the group returns the same values.
 template <int NQ, int WAVES>
 __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t* limbs, uint64_t pt, int gl,
@@ -551,22 +665,7 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
         // the first two rotations, R(p_{h-2}) R(p_{h-1}) K or the transposes', come precomputed for
         // every pair of Paulis (a 256 MiB table in HBM, 2 KiB per step in 32 contiguous bytes per
         // lane); with one rotation only, from a 1 MiB table; the others are applied here
-        int h_left = h;
-        if (sp.rkeys2 != nullptr && h >= 2) {
-            const uint64_t* tp =
-                sp.rkeys2 + ((((uint32_t)side * 256u + dig[h - 1]) * 256u + dig[h - 2]) * 256u + 4u * (uint32_t)gl);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) u[j] = tp[j];
-            h_left = h - 2;
-        } else if (sp.rkeys != nullptr && h >= 1) {
-            const uint64_t* tp = sp.rkeys + ((uint32_t)side * 256u + dig[h - 1]) * 256u + 4u * (uint32_t)gl;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) u[j] = tp[j];
-            h_left = h - 1;
-        } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) u[j] = L.K[gl * 4 + j];
-        }
+        const int h_left = key_row4(sp, L, dig, side, gl, u);
         rotate4(u, dig, h_left, side, gl, gbase);
     } else {
         u[0] = L.K[gl];
@@ -622,6 +721,57 @@ __device__ void walk_step(const SpaceDev& sp, const Lds<NQ, WAVES>& L, uint32_t*
     const uint64_t H = mix64(acc);
     out_h = H;
     out_pt = mulhi64(H, sp.n_half) | ((H & 1) << 32);
+}
+
+// n = 4: one evaluation of f for each of the wavefront's two walks, both points on side 1 (pa, pb
+// uniform).  Each walk's key row, rotations and digits in turn, then the shared MFMA product, and each 32-lane half of the wavefront hashes its walk's
+// 256 rows (eight per lane).  The values equal those of two walk_step calls.
+template <int WAVES>
+__device__ void walk_step_pair4(const SpaceDev& sp, const Lds<4, WAVES>& L, uint32_t* limbs, uint64_t pa,
+                                uint64_t pb, int lane, uint64_t& out_a, uint64_t& h_a, uint64_t& out_b,
+                                uint64_t& h_b) {
+    constexpr int HMAX = Geo<4>::HMAX;
+    v4i afr[N4_KK];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+        uint32_t dig[HMAX];
+        uint32_t xx = (uint32_t)(w ? pb : pa);
+#pragma unroll
+        for (int t = 0; t < HMAX; ++t) {
+            dig[t] = xx % Geo<4>::XI + 1;
+            xx /= Geo<4>::XI;
+        }
+        uint64_t u[4];
+        const int h_left = key_row4(sp, L, dig, 1, lane, u);
+        rotate4(u, dig, h_left, 1, lane, 0);
+        digits_pair(limbs, u, lane, w, afr);
+    }
+    uint64_t R[8];
+    side1_mfma_pair<WAVES>(L, afr, lane, sp.rot_e, R);
+    uint64_t acc = 0;
+    const uint32_t ka = (uint32_t)sp.salt_h, kb = (uint32_t)(sp.salt_h >> 32);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const uint64_t c = R[i];
+        const uint64_t d = c ^ (P61 & (0ull - ((c >> 60) & 1)));
+        acc += (uint64_t)((uint32_t)d + ka) * (uint64_t)((uint32_t)(d >> 32) + kb);
+    }
+    acc += dpp64<0xB1>(acc);   // quad_perm [1,0,3,2]
+    acc += dpp64<0x4E>(acc);   // quad_perm [2,3,0,1]
+    acc += dpp64<0x124>(acc);  // row_ror:4
+    acc += dpp64<0x128>(acc);  // row_ror:8
+    acc = half_add16(acc, acc);
+    // lanes 0..31 now hold walk a's sum, lanes 32..63 walk b's
+    auto lane64 = [&](int l) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)acc, l);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(acc >> 32), l);
+        return ((uint64_t)hi << 32) | lo;
+    };
+    const uint64_t sa = lane64(0), sb = lane64(32);
+    h_a = mix64(sa);
+    h_b = mix64(sb);
+    out_a = mulhi64(h_a, sp.n_half) | ((h_a & 1) << 32);
+    out_b = mulhi64(h_b, sp.n_half) | ((h_b & 1) << 32);
 }
 
 __device__ inline bool is_dist(const SpaceDev& sp, uint64_t pt) {
@@ -914,198 +1064,312 @@ __device__ inline void flush_counts(const WalkDev& wd, WalkCounts& c, bool leade
     c = WalkCounts{};
 }
 
+__device__ inline void add_counts(WalkCounts& to, const WalkCounts& c) {
+    to.steps += c.steps;
+    to.dps += c.dps;
+    to.ins += c.ins;
+    to.ab += c.ab;
+    to.rh += c.rh;
+    to.same += c.same;
+    to.red += c.red;
+    to.claw += c.claw;
+    to.full += c.full;
+    to.spin += c.spin;
+    to.active += c.active;
+}
+
+__device__ inline WalkState load_state(const WalkDev& wd, int64_t w, bool uniform) {
+    WalkState st = wd.states[w];
+    if (uniform) {
+        st.start = uniform64(st.start);
+        st.cur = uniform64(st.cur);
+        st.pa = uniform64(st.pa);
+        st.pb = uniform64(st.pb);
+        st.na = uniform64(st.na);
+        st.ha = uniform64(st.ha);
+        st.len = uniform32(st.len);
+        st.trail = uniform32(st.trail);
+        st.mode = uniform32(st.mode);
+        st.rem = uniform32(st.rem);
+    }
+    return st;
+}
+
+// The point a walk evaluates f on next: its current point while walking, else the backtracking
+// point that ALIGN / LOCK advances.
+__device__ inline uint64_t step_arg(const WalkState& st) {
+    // as masks rather than a choice of field, so the states stay in registers
+    const uint64_t walk = 0ull - (uint64_t)((st.mode & 0xff) == MODE_WALK);
+    const uint64_t second = 0ull - (uint64_t)((st.mode >> 8) & 1);
+    return (st.cur & walk) | (((st.pb & second) | (st.pa & ~second)) & ~walk);
+}
+
+// Walk w's state after one evaluation f(arg) = (nxt, H): distinguished points into the table,
+// backtracking of two trails that met (Sec. 3, Fig. 2), claws recorded, trails restarted.  WHOLE:
+// the walk occupies the whole wavefront (its leader is lane 0).
+template <bool WHOLE>
+__device__ inline void advance_walk(const SpaceDev& sp, const WalkDev& wd, WalkState& st, int64_t w, uint64_t arg,
+                                    uint64_t nxt, uint64_t H, bool leader, int gbase, WalkCounts& c) {
+    const uint32_t mode = st.mode & 0xff;
+    const uint32_t which = (st.mode >> 8) & 1;
+    bool restart = false;
+    if (mode == MODE_WALK && wd.enumerate) {
+        // exhaustive mode: every point once, the table keyed by its full matrix hash and holding,
+        // in the two 32-bit halves of the value, the least x of each side that reached the key (a
+        // 32-bit atomic minimum, so no ordering between writers is needed).  The pairs are read
+        // out after the last point (k_enum_pairs): which pairs are reported does not depend on
+        // the order in which walks arrive.
+        c.dps++;
+        const uint64_t key = H == EMPTY_KEY ? (H ^ 1) : H;
+        int kind = 0;
+        if (leader) {
+            uint64_t slot = 0;
+            kind = table_claim(wd, key, slot);
+            if (kind != 3) {
+                uint32_t* half = reinterpret_cast<uint32_t*>(&wd.table[2 * slot + 1]) + ((arg >> 32) & 1);
+                atomicMin(half, (uint32_t)arg);
+            }
+        }
+        if constexpr (WHOLE)
+            kind = (int)uniform32((uint32_t)kind);
+        else
+            kind = (int)shfl32((uint32_t)kind, gbase);
+        if (kind == 3)
+            c.full++;
+        else if (kind == 1)
+            c.ins++;
+        restart = true;
+    } else if (mode == MODE_WALK) {
+        st.len++;
+        if (is_dist(sp, nxt)) {
+            c.dps++;
+            int kind = 0;
+            uint64_t slot = 0, other = 0;
+            if (leader) kind = table_claim(wd, nxt, slot);
+            // The slot's writer publishes its value right after its claim.  The value word is
+            // all a reader uses (start, length and a ready bit), so relaxed device-scope atomics
+            // suffice; release and acquire would write back and invalidate the L2 of the
+            // wavefront's XCD at every distinguished point.
+            if (leader && kind == 1)
+                __hip_atomic_store(&wd.table[2 * slot + 1], pack_value(st.start, st.len), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            if (leader && kind == 2) {
+                int spin = 0;
+                do {
+                    other = __hip_atomic_load(&wd.table[2 * slot + 1], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                } while (other == 0 && ++spin < (1 << 20));
+                if (other == 0) kind = 4;
+            }
+            if constexpr (WHOLE) {
+                // the walk is the whole wavefront and its leader is lane 0: the answer stays scalar
+                kind = (int)uniform32((uint32_t)kind);
+                other = uniform64(other);
+            } else {
+                kind = (int)shfl32((uint32_t)kind, gbase);
+                other = shfl64(other, gbase);
+            }
+            restart = true;
+            if (kind == 1) {
+                c.ins++;
+            } else if (kind == 3) {
+                c.full++;
+            } else if (kind == 4) {
+                c.spin++;
+            } else if (kind == 2) {
+                const uint64_t ostart = other & 0x1ffffffffull;
+                const uint32_t olen = (uint32_t)((other >> 33) & 0x3fffffffu);
+                if (ostart != st.start) {
+                    // backtrack the two trails (Sec. 3, Fig. 2)
+                    restart = false;
+                    st.pa = st.start;
+                    st.pb = ostart;
+                    const uint32_t la = st.len, lb = olen;
+                    if (la > lb) {
+                        st.mode = MODE_ALIGN;
+                        st.rem = la - lb;
+                        st.len = lb;
+                    } else if (lb > la) {
+                        st.mode = MODE_ALIGN | (1u << 8);
+                        st.rem = lb - la;
+                        st.len = la;
+                    } else {
+                        st.mode = MODE_LOCK;
+                        st.rem = la;
+                    }
+                }
+            }
+        } else if (st.len >= wd.cap) {
+            c.ab++;
+            restart = true;
+        } else {
+            st.cur = nxt;
+        }
+    } else if (mode == MODE_ALIGN) {
+        if (which) st.pb = nxt; else st.pa = nxt;
+        if (--st.rem == 0) {
+            if (st.pa == st.pb) {
+                c.rh++;  // one trail started on the other
+                restart = true;
+            } else {
+                st.mode = MODE_LOCK;
+                st.rem = st.len;
+            }
+        }
+    } else {  // MODE_LOCK
+        if (!which) {
+            st.na = nxt;
+            st.ha = H;
+            st.mode = MODE_LOCK | (1u << 8);
+        } else {
+            if (st.na == nxt) {
+                // f(pa) = f(pb) with pa != pb: the merge
+                const uint64_t sa = (st.pa >> 32) & 1, sb = (st.pb >> 32) & 1;
+                if (sa == sb) {
+                    c.same++;
+                } else if (st.ha != H) {
+                    c.red++;
+                } else {
+                    c.claw++;
+                    if (leader) {
+                        const unsigned long long idx = atomicAdd(wd.claw_count, 1ull);
+                        if (idx < wd.claw_cap) {
+                            wd.claws[2 * idx] = st.pa;
+                            wd.claws[2 * idx + 1] = st.pb;
+                        }
+                    }
+                }
+                restart = true;
+            } else {
+                st.pa = st.na;
+                st.pb = nxt;
+                st.mode = MODE_LOCK;
+                if (--st.rem == 0) restart = true;  // cannot happen for two trails with one end
+            }
+        }
+    }
+    if (restart) {
+        st.trail++;
+        st.len = 0;
+        st.mode = MODE_WALK;
+        if (wd.enumerate) {
+            const uint64_t idx = (uint64_t)w + (uint64_t)wd.walks * st.trail;
+            if (idx >= wd.n_points) {
+                st.mode = MODE_DONE;
+            } else {
+                st.start = (idx % sp.n_half) | ((idx / sp.n_half) << 32);
+            }
+        } else {
+            st.start = start_point(sp, (uint64_t)w, st.trail);
+        }
+        st.cur = st.start;
+    }
+}
+
 // `iters` evaluations of f for every walk of slice `block` of `nblocks` (walks (block * WAVES + wave)
 // * WPW + group, then every nblocks * WAVES * WPW further); events are added to cnt.
 template <int NQ, int WAVES>
-__device__ void walk_block(const SpaceDev& sp, const WalkDev& wd, int iters, Lds<NQ, WAVES>& L, int64_t block,
-                           int64_t nblocks, WalkCounts& cnt) {
+__device__ void walk_block_single(const SpaceDev& sp, const WalkDev& wd, int iters, Lds<NQ, WAVES>& L, int64_t block,
+                                  int64_t nblocks, WalkCounts& cnt) {
     using Gm = Geo<NQ>;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int gi = lane / Gm::G, gl = lane % Gm::G, gbase = gi * Gm::G;
     const bool leader = gl == 0;
     uint32_t* limbs = L.limbs[wave * Gm::WPW + gi];
-    uint64_t c_steps = 0, c_dps = 0, c_ins = 0, c_ab = 0, c_rh = 0, c_same = 0, c_red = 0, c_claw = 0, c_full = 0,
-             c_spin = 0, c_active = 0;
+    WalkCounts c;
     const int64_t stride = nblocks * WAVES * Gm::WPW;
     for (int64_t base = (block * WAVES + wave) * Gm::WPW; base < wd.walks; base += stride) {
         const int64_t w = base + gi;
         if (w >= wd.walks) continue;
-        WalkState st = wd.states[w];
-        if constexpr (Gm::G == 64) {
-            st.start = uniform64(st.start);
-            st.cur = uniform64(st.cur);
-            st.pa = uniform64(st.pa);
-            st.pb = uniform64(st.pb);
-            st.na = uniform64(st.na);
-            st.ha = uniform64(st.ha);
-            st.len = uniform32(st.len);
-            st.trail = uniform32(st.trail);
-            st.mode = uniform32(st.mode);
-            st.rem = uniform32(st.rem);
-        }
+        WalkState st = load_state(wd, w, Gm::G == 64);
         for (int it = 0; it < iters; ++it) {
-            const uint32_t mode = st.mode & 0xff;
-            if (mode == MODE_DONE) break;
-            const uint32_t which = (st.mode >> 8) & 1;
-            const uint64_t arg = mode == MODE_WALK ? st.cur : (which ? st.pb : st.pa);
+            if ((st.mode & 0xff) == MODE_DONE) break;
+            const uint64_t arg = step_arg(st);
             uint64_t nxt, H;
             walk_step<NQ, WAVES>(sp, L, limbs, arg, gl, gbase, nxt, H);
-            c_steps++;
-            bool restart = false;
-            if (mode == MODE_WALK && wd.enumerate) {
-                // exhaustive mode: every point once, the table keyed by its full matrix hash and holding,
-                // in the two 32-bit halves of the value, the least x of each side that reached the key (a
-                // 32-bit atomic minimum, so no ordering between writers is needed).  The pairs are read
-                // out after the last point (k_enum_pairs): which pairs are reported does not depend on
-                // the order in which walks arrive.
-                c_dps++;
-                const uint64_t key = H == EMPTY_KEY ? (H ^ 1) : H;
-                if (leader) {
-                    uint64_t slot = 0;
-                    const int kind = table_claim(wd, key, slot);
-                    if (kind == 3) {
-                        c_full++;
-                    } else {
-                        if (kind == 1) c_ins++;
-                        uint32_t* half = reinterpret_cast<uint32_t*>(&wd.table[2 * slot + 1]) + ((arg >> 32) & 1);
-                        atomicMin(half, (uint32_t)arg);
-                    }
-                }
-                restart = true;
-            } else if (mode == MODE_WALK) {
-                st.len++;
-                if (is_dist(sp, nxt)) {
-                    c_dps++;
-                    int kind = 0;
-                    uint64_t slot = 0, other = 0;
-                    if (leader) kind = table_claim(wd, nxt, slot);
-                    // The slot's writer publishes its value right after its claim.  The value word is
-                    // all a reader uses (start, length and a ready bit), so relaxed device-scope atomics
-                    // suffice; release and acquire would write back and invalidate the L2 of the
-                    // wavefront's XCD at every distinguished point.
-                    if (leader && kind == 1)
-                        __hip_atomic_store(&wd.table[2 * slot + 1], pack_value(st.start, st.len), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    if (leader && kind == 2) {
-                        int spin = 0;
-                        do {
-                            other = __hip_atomic_load(&wd.table[2 * slot + 1], __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                        } while (other == 0 && ++spin < (1 << 20));
-                        if (other == 0) kind = 4;
-                    }
-                    kind = (int)shfl32((uint32_t)kind, gbase);
-                    other = shfl64(other, gbase);
-                    restart = true;
-                    if (kind == 1) {
-                        c_ins++;
-                    } else if (kind == 3) {
-                        c_full++;
-                    } else if (kind == 4) {
-                        c_spin++;
-                    } else if (kind == 2) {
-                        const uint64_t ostart = other & 0x1ffffffffull;
-                        const uint32_t olen = (uint32_t)((other >> 33) & 0x3fffffffu);
-                        if (ostart != st.start) {
-                            // backtrack the two trails (Sec. 3, Fig. 2)
-                            restart = false;
-                            st.pa = st.start;
-                            st.pb = ostart;
-                            const uint32_t la = st.len, lb = olen;
-                            if (la > lb) {
-                                st.mode = MODE_ALIGN;
-                                st.rem = la - lb;
-                                st.len = lb;
-                            } else if (lb > la) {
-                                st.mode = MODE_ALIGN | (1u << 8);
-                                st.rem = lb - la;
-                                st.len = la;
-                            } else {
-                                st.mode = MODE_LOCK;
-                                st.rem = la;
-                            }
-                        }
-                    }
-                } else if (st.len >= wd.cap) {
-                    c_ab++;
-                    restart = true;
-                } else {
-                    st.cur = nxt;
-                }
-            } else if (mode == MODE_ALIGN) {
-                if (which) st.pb = nxt; else st.pa = nxt;
-                if (--st.rem == 0) {
-                    if (st.pa == st.pb) {
-                        c_rh++;  // one trail started on the other
-                        restart = true;
-                    } else {
-                        st.mode = MODE_LOCK;
-                        st.rem = st.len;
-                    }
-                }
-            } else {  // MODE_LOCK
-                if (!which) {
-                    st.na = nxt;
-                    st.ha = H;
-                    st.mode = MODE_LOCK | (1u << 8);
-                } else {
-                    if (st.na == nxt) {
-                        // f(pa) = f(pb) with pa != pb: the merge
-                        const uint64_t sa = (st.pa >> 32) & 1, sb = (st.pb >> 32) & 1;
-                        if (sa == sb) {
-                            c_same++;
-                        } else if (st.ha != H) {
-                            c_red++;
-                        } else {
-                            c_claw++;
-                            if (leader) {
-                                const unsigned long long idx = atomicAdd(wd.claw_count, 1ull);
-                                if (idx < wd.claw_cap) {
-                                    wd.claws[2 * idx] = st.pa;
-                                    wd.claws[2 * idx + 1] = st.pb;
-                                }
-                            }
-                        }
-                        restart = true;
-                    } else {
-                        st.pa = st.na;
-                        st.pb = nxt;
-                        st.mode = MODE_LOCK;
-                        if (--st.rem == 0) restart = true;  // cannot happen for two trails with one end
-                    }
-                }
-            }
-            if (restart) {
-                st.trail++;
-                st.len = 0;
-                st.mode = MODE_WALK;
-                if (wd.enumerate) {
-                    const uint64_t idx = (uint64_t)w + (uint64_t)wd.walks * st.trail;
-                    if (idx >= wd.n_points) {
-                        st.mode = MODE_DONE;
-                    } else {
-                        st.start = (idx % sp.n_half) | ((idx / sp.n_half) << 32);
-                    }
-                } else {
-                    st.start = start_point(sp, (uint64_t)w, st.trail);
-                }
-                st.cur = st.start;
-            }
+            c.steps++;
+            advance_walk<Gm::G == 64>(sp, wd, st, w, arg, nxt, H, leader, gbase, c);
         }
-        if ((st.mode & 0xff) != MODE_DONE) c_active++;
+        if ((st.mode & 0xff) != MODE_DONE) c.active++;
         if (leader) wd.states[w] = st;
     }
-    cnt.steps += c_steps;
-    cnt.dps += c_dps;
-    cnt.ins += c_ins;
-    cnt.ab += c_ab;
-    cnt.rh += c_rh;
-    cnt.same += c_same;
-    cnt.red += c_red;
-    cnt.claw += c_claw;
-    cnt.full += c_full;
-    cnt.spin += c_spin;
-    cnt.active += c_active;
+    add_counts(cnt, c);
+}
+
+// n = 4: each wavefront runs two walks, 2q and 2q + 1 for q = block * WAVES + wave, then every
+// nblocks * WAVES further, and gives the pair 2 iters evaluations of f (a walk without a partner
+// gets iters).  A walk whose next point is on side 0 steps alone; when both next points are on side
+// 1 the two steps share one MFMA product (walk_step_pair4).  So the pair's steps add up to 2 iters
+// while each walk's share varies with its sides: a launch's total is walks x iters as before.
+template <int WAVES>
+__device__ void walk_block_pairs(const SpaceDev& sp, const WalkDev& wd, int iters, Lds<4, WAVES>& L, int64_t block,
+                                 int64_t nblocks, WalkCounts& cnt) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool leader = lane == 0;
+    uint32_t* limbs = L.limbs[wave];
+    WalkCounts c;
+    const int64_t pairs = (wd.walks + 1) / 2;
+    for (int64_t q = block * WAVES + wave; q < pairs; q += nblocks * WAVES) {
+        const int64_t w0 = 2 * q, w1 = 2 * q + 1;
+        const bool has_b = w1 < wd.walks;
+        WalkState sa = load_state(wd, w0, true);
+        WalkState sb = has_b ? load_state(wd, w1, true) : sa;
+        const int total = has_b ? 2 * iters : iters;
+        int left = total;
+        while (left > 0) {
+            const bool act_a = (sa.mode & 0xff) != MODE_DONE;
+            const bool act_b = has_b && (sb.mode & 0xff) != MODE_DONE;
+            if (!act_a && !act_b) break;
+            const uint64_t arg_a = step_arg(sa), arg_b = step_arg(sb);
+            const bool s1a = (arg_a >> 32) & 1, s1b = (arg_b >> 32) & 1;
+            uint64_t na = 0, ha = 0, nb = 0, hb = 0;
+            bool do_a, do_b;
+            if (act_a && act_b && s1a && s1b && left >= 2) {
+                walk_step_pair4<WAVES>(sp, L, limbs, arg_a, arg_b, lane, na, ha, nb, hb);
+                do_a = do_b = true;
+                left -= 2;
+            } else {
+                // a side-0 step first; otherwise the one walk still stepping (or walk a, on the last step)
+                const bool pick_b = !act_a || (act_b && s1a && !s1b);
+                uint64_t nx, hh;
+                walk_step<4, WAVES>(sp, L, limbs, pick_b ? arg_b : arg_a, lane, 0, nx, hh);
+                na = nb = nx;
+                ha = hb = hh;
+                do_a = !pick_b;
+                do_b = pick_b;
+                left -= 1;
+            }
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (!(k ? do_b : do_a)) continue;
+                WalkState st = k ? sb : sa;
+                advance_walk<true>(sp, wd, st, k ? w1 : w0, k ? arg_b : arg_a, k ? nb : na, k ? hb : ha, leader, 0,
+                                   c);
+                if (k)
+                    sb = st;
+                else
+                    sa = st;
+            }
+        }
+        c.steps += (uint64_t)(total - left);
+        if ((sa.mode & 0xff) != MODE_DONE) c.active++;
+        if (has_b && (sb.mode & 0xff) != MODE_DONE) c.active++;
+        if (leader) {
+            wd.states[w0] = sa;
+            if (has_b) wd.states[w1] = sb;
+        }
+    }
+    add_counts(cnt, c);
+}
+
+// The walks of one slice: paired on side 1 at n = 4, one walk group at a time otherwise.
+template <int NQ, int WAVES>
+__device__ void walk_block(const SpaceDev& sp, const WalkDev& wd, int iters, Lds<NQ, WAVES>& L, int64_t block,
+                           int64_t nblocks, WalkCounts& cnt) {
+    if constexpr (NQ == 4)
+        walk_block_pairs<WAVES>(sp, wd, iters, L, block, nblocks, cnt);
+    else
+        walk_block_single<NQ, WAVES>(sp, wd, iters, L, block, nblocks, cnt);
 }
 
 template <int NQ, int WAVES>
