@@ -113,8 +113,10 @@ LITERAL_OPS_PER_STEP_N4 = 1.3e6
 def mfma_ops_per_step(n: int) -> float:
     """Useful int8 MFMA operations per step (mean over sides): on side 1 the 256 x 256 product
     phi(S_c) u over 8 digit rows for each of the two digit sets (u and 2^31 u), i.e.
-    2 sets x 8 digits x 256 x 256 x 2; the A operand's zero half (each set occupies half of its
-    16 rows on half of K) is not counted."""
+    2 sets x 8 digits x 256 x 256 x 2.  Two walks of a wavefront whose next points are both on side 1
+    share one pass of the 16 x 8 MFMAs (one walk's digits in A rows 0..7, the other's in rows 8..15),
+    which issues exactly these products for both; a side-1 step without a partner issues twice its
+    count, and the excess is not counted."""
     return 0.5 * (2 * 8 * 256 * 256 * 2)
 
 
@@ -156,7 +158,7 @@ def walk_roofline(n, h, steps_per_launch, avg_ms, walks, iters):
                                       "reaches the same f through phi-linearity"}}
     mf = mfma_ops_per_step(n) * steps_per_launch / secs
     out["mfma_i8"] = {"achieved": mf / 1e12, "peak": MFMA_I8_PEAK_OPS / 1e12, "unit": "Tops/s",
-                      "frac": mf / MFMA_I8_PEAK_OPS, "counted": "useful products only (zero half of A excluded)"}
+                      "frac": mf / MFMA_I8_PEAK_OPS, "counted": "useful products only"}
     out["hbm"] = None if traffic is None else {
         "achieved": traffic / secs / 1e9, "peak": HBM_PEAK_BYTES / 1e9, "unit": "GB/s", "frac": traffic / secs / HBM_PEAK_BYTES}
     c = measured_counters(walks, iters)

@@ -14,7 +14,8 @@
 // 256 values), so a step reads one row of it and applies the remaining h - 2.  The side-1 product
 // with the fixed chunk matrix S_c = (A + B sqrt2)/sqrt2^e runs on int8 MFMA for n >= 3 (A and B in
 // LDS as B-operand fragments, against signed base-256 digits of u and 2^31 u) and on int8 dot
-// products (v_dot4_i32_i8) against 7-bit limbs of u for n <= 2.  Then (nu + h of Sec. 2):
+// products (v_dot4_i32_i8) against 7-bit limbs of u for n <= 2.  At n = 4 a wavefront runs two
+// walks, and when both next points are on side 1 one pass of the MFMAs serves both steps.  Then (nu + h of Sec. 2):
 //   D_r = min(S_r, p - S_r)   (sign-normalised row: negating a row negates S_r)
 //   H = mix64(sum_r g(D_r))   (mod 2^64: an additive multiset hash, so the order of the rows -- a
 //                               left signed permutation -- drops out), with the element map
@@ -1064,7 +1065,15 @@ __device__ inline void flush_counts(const WalkDev& wd, WalkCounts& c, bool leade
     c = WalkCounts{};
 }
 
-__device__ inline void add_counts(WalkCounts& to, const WalkCounts& c) {
+// The same counts over one slice of one launch, where they stay far below 2^32 (a pair's evaluations
+// per launch are 2 iters).
+struct WalkCounts32 {
+    uint32_t steps = 0, dps = 0, ins = 0, ab = 0, rh = 0, same = 0, red = 0, claw = 0, full = 0, spin = 0,
+             active = 0;
+};
+
+template <typename C>
+__device__ inline void add_counts(WalkCounts& to, const C& c) {
     to.steps += c.steps;
     to.dps += c.dps;
     to.ins += c.ins;
@@ -1107,9 +1116,9 @@ __device__ inline uint64_t step_arg(const WalkState& st) {
 // Walk w's state after one evaluation f(arg) = (nxt, H): distinguished points into the table,
 // backtracking of two trails that met (Sec. 3, Fig. 2), claws recorded, trails restarted.  WHOLE:
 // the walk occupies the whole wavefront (its leader is lane 0).
-template <bool WHOLE>
+template <bool WHOLE, typename C>
 __device__ inline void advance_walk(const SpaceDev& sp, const WalkDev& wd, WalkState& st, int64_t w, uint64_t arg,
-                                    uint64_t nxt, uint64_t H, bool leader, int gbase, WalkCounts& c) {
+                                    uint64_t nxt, uint64_t H, bool leader, int gbase, C& c) {
     const uint32_t mode = st.mode & 0xff;
     const uint32_t which = (st.mode >> 8) & 1;
     bool restart = false;
@@ -1307,7 +1316,7 @@ __device__ void walk_block_pairs(const SpaceDev& sp, const WalkDev& wd, int iter
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool leader = lane == 0;
     uint32_t* limbs = L.limbs[wave];
-    WalkCounts c;
+    WalkCounts32 c;
     const int64_t pairs = (wd.walks + 1) / 2;
     for (int64_t q = block * WAVES + wave; q < pairs; q += nblocks * WAVES) {
         const int64_t w0 = 2 * q, w1 = 2 * q + 1;
@@ -1351,7 +1360,7 @@ __device__ void walk_block_pairs(const SpaceDev& sp, const WalkDev& wd, int iter
                     sa = st;
             }
         }
-        c.steps += (uint64_t)(total - left);
+        c.steps += (uint32_t)(total - left);
         if ((sa.mode & 0xff) != MODE_DONE) c.active++;
         if (has_b && (sb.mode & 0xff) != MODE_DONE) c.active++;
         if (leader) {
@@ -1410,7 +1419,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_walk_queue(const SpaceDev* sps, 
         const int32_t i = __builtin_amdgcn_readfirstlane(s_next);
         if (i >= n_items) break;
         const WorkItem it = items[i];
-        const SpaceDev sp = sps[it.slot];
+        // read through the pointer where used (scalar loads) rather than held in registers for the item
+        const SpaceDev& sp = sps[it.slot];
         if (it.slot != loaded) {
             if (loaded >= 0) flush_counts(wds[loaded], mine, leader);
             load_lds(L, sp);

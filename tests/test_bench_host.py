@@ -19,7 +19,7 @@ def test_work_counts_at_n4k7():
     assert bench.LITERAL_OPS_PER_STEP_N4 > 50 * bench.valu_ops_per_step(4, 3)
     # side 1 (half the steps): two digit sets x 8 digit rows x the 256 x 256 product, multiply and add
     assert bench.mfma_ops_per_step(4) == 0.5 * 2 * 8 * 256 * 256 * 2
-    # which is half of what the 16 N tiles x 8 K steps of 16 x 16 x 64 MFMAs issue (zero half of A)
+    # one pass of the 16 N tiles x 8 K steps of 16 x 16 x 64 MFMAs serves two walks' side-1 steps
     assert 2 * bench.mfma_ops_per_step(4) == 0.5 * 2 * 16 * 16 * 64 * 16 * 8
     with pytest.raises(ValueError):
         bench.valu_ops_per_step(3, 3)
