@@ -313,7 +313,9 @@ def test_walk_session_counters_n2(ctx):
 def test_walk_kernel_full_size_sampled_n4(ctx):
     """n = 4, k = 7 at 2^20 walks, theta = 2^-12, 2^26 slots and 8 steps per walk per launch (the
     benchmark launch): sampled walks still on their first trail hold start = start(w, 0) and
-    cur = f^len(start), len = 8."""
+    cur = f^len(start).  The two walks of a wavefront share the pair's 16 evaluations (side-0 steps
+    alone, side-1 steps together), so when both are still on their first trail their lengths add up
+    to 16."""
     say("walk n4 full size")
     n, k, delta = 4, 7, 12
     tw, u = oracle_target(n, k, 1)
@@ -338,10 +340,14 @@ def test_walk_kernel_full_size_sampled_n4(ctx):
         assert int(s["cur"]) == pt
         checked += 1
     assert checked >= len(sample) // 2  # at theta = 2^-12 almost every walk is still on its first trail
+    for w0 in (0, 65536, 500000, (1 << 20) - 2):
+        a, b = w.read_states(w0, 2)
+        if all(int(x["trail"]) == 0 and int(x["mode"]) == 0 for x in (a, b)):
+            assert int(a["len"]) + int(b["len"]) == 16
     w.end()
 
 
-@pytest.mark.parametrize("n,k,delta,walks,lg", [(2, 4, 3, 64, 10), (3, 6, 4, 256, 14)])
+@pytest.mark.parametrize("n,k,delta,walks,lg", [(2, 4, 3, 64, 10), (3, 6, 4, 256, 14), (4, 6, 3, 64, 12)])
 def test_dp_table_entries(ctx, n, k, delta, walks, lg):
     """The distinguished-point table after a few launches: every key is distinguished, keys are
     unique, and each value (start, length, ready bit) is a trail the oracle walks from that start to
