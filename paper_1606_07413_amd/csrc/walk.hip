@@ -1061,30 +1061,26 @@ __device__ inline void flush_counts(const WalkDev& wd, WalkCounts& c, bool leade
         atomicAdd(&wd.stats[ST_FULL], (unsigned long long)c.full);
         atomicAdd(&wd.stats[ST_SPIN], (unsigned long long)c.spin);
         atomicAdd(&wd.stats[ST_ACTIVE], (unsigned long long)c.active);
+        c = WalkCounts{};
     }
-    c = WalkCounts{};
 }
 
-// The same counts over one slice of one launch, where they stay far below 2^32 (a pair's evaluations
-// per launch are 2 iters).
-struct WalkCounts32 {
-    uint32_t steps = 0, dps = 0, ins = 0, ab = 0, rh = 0, same = 0, red = 0, claw = 0, full = 0, spin = 0,
-             active = 0;
+// Events of one evaluation, as bits: advance_walk returns them and the walk group's leader adds
+// them to the group's counts in LDS, so no count is held in registers through the step.
+enum : uint32_t {
+    EV_DP = 1, EV_INS = 2, EV_AB = 4, EV_RH = 8, EV_SAME = 16, EV_RED = 32, EV_CLAW = 64, EV_FULL = 128, EV_SPIN = 256
 };
 
-template <typename C>
-__device__ inline void add_counts(WalkCounts& to, const C& c) {
-    to.steps += c.steps;
-    to.dps += c.dps;
-    to.ins += c.ins;
-    to.ab += c.ab;
-    to.rh += c.rh;
-    to.same += c.same;
-    to.red += c.red;
-    to.claw += c.claw;
-    to.full += c.full;
-    to.spin += c.spin;
-    to.active += c.active;
+__device__ inline void count_events(WalkCounts& c, uint32_t ev) {
+    if (ev & EV_DP) c.dps++;
+    if (ev & EV_INS) c.ins++;
+    if (ev & EV_AB) c.ab++;
+    if (ev & EV_RH) c.rh++;
+    if (ev & EV_SAME) c.same++;
+    if (ev & EV_RED) c.red++;
+    if (ev & EV_CLAW) c.claw++;
+    if (ev & EV_FULL) c.full++;
+    if (ev & EV_SPIN) c.spin++;
 }
 
 __device__ inline WalkState load_state(const WalkDev& wd, int64_t w, bool uniform) {
@@ -1116,9 +1112,10 @@ __device__ inline uint64_t step_arg(const WalkState& st) {
 // Walk w's state after one evaluation f(arg) = (nxt, H): distinguished points into the table,
 // backtracking of two trails that met (Sec. 3, Fig. 2), claws recorded, trails restarted.  WHOLE:
 // the walk occupies the whole wavefront (its leader is lane 0).
-template <bool WHOLE, typename C>
-__device__ inline void advance_walk(const SpaceDev& sp, const WalkDev& wd, WalkState& st, int64_t w, uint64_t arg,
-                                    uint64_t nxt, uint64_t H, bool leader, int gbase, C& c) {
+template <bool WHOLE>
+__device__ inline uint32_t advance_walk(const SpaceDev& sp, const WalkDev& wd, WalkState& st, int64_t w,
+                                        uint64_t arg, uint64_t nxt, uint64_t H, bool leader, int gbase) {
+    uint32_t ev = 0;
     const uint32_t mode = st.mode & 0xff;
     const uint32_t which = (st.mode >> 8) & 1;
     bool restart = false;
@@ -1128,7 +1125,7 @@ __device__ inline void advance_walk(const SpaceDev& sp, const WalkDev& wd, WalkS
         // 32-bit atomic minimum, so no ordering between writers is needed).  The pairs are read
         // out after the last point (k_enum_pairs): which pairs are reported does not depend on
         // the order in which walks arrive.
-        c.dps++;
+        ev |= EV_DP;
         const uint64_t key = H == EMPTY_KEY ? (H ^ 1) : H;
         int kind = 0;
         if (leader) {
@@ -1144,14 +1141,14 @@ __device__ inline void advance_walk(const SpaceDev& sp, const WalkDev& wd, WalkS
         else
             kind = (int)shfl32((uint32_t)kind, gbase);
         if (kind == 3)
-            c.full++;
+            ev |= EV_FULL;
         else if (kind == 1)
-            c.ins++;
+            ev |= EV_INS;
         restart = true;
     } else if (mode == MODE_WALK) {
         st.len++;
         if (is_dist(sp, nxt)) {
-            c.dps++;
+            ev |= EV_DP;
             int kind = 0;
             uint64_t slot = 0, other = 0;
             if (leader) kind = table_claim(wd, nxt, slot);
@@ -1180,11 +1177,11 @@ __device__ inline void advance_walk(const SpaceDev& sp, const WalkDev& wd, WalkS
             }
             restart = true;
             if (kind == 1) {
-                c.ins++;
+                ev |= EV_INS;
             } else if (kind == 3) {
-                c.full++;
+                ev |= EV_FULL;
             } else if (kind == 4) {
-                c.spin++;
+                ev |= EV_SPIN;
             } else if (kind == 2) {
                 const uint64_t ostart = other & 0x1ffffffffull;
                 const uint32_t olen = (uint32_t)((other >> 33) & 0x3fffffffu);
@@ -1209,7 +1206,7 @@ __device__ inline void advance_walk(const SpaceDev& sp, const WalkDev& wd, WalkS
                 }
             }
         } else if (st.len >= wd.cap) {
-            c.ab++;
+            ev |= EV_AB;
             restart = true;
         } else {
             st.cur = nxt;
@@ -1218,7 +1215,7 @@ __device__ inline void advance_walk(const SpaceDev& sp, const WalkDev& wd, WalkS
         if (which) st.pb = nxt; else st.pa = nxt;
         if (--st.rem == 0) {
             if (st.pa == st.pb) {
-                c.rh++;  // one trail started on the other
+                ev |= EV_RH;  // one trail started on the other
                 restart = true;
             } else {
                 st.mode = MODE_LOCK;
@@ -1235,11 +1232,11 @@ __device__ inline void advance_walk(const SpaceDev& sp, const WalkDev& wd, WalkS
                 // f(pa) = f(pb) with pa != pb: the merge
                 const uint64_t sa = (st.pa >> 32) & 1, sb = (st.pb >> 32) & 1;
                 if (sa == sb) {
-                    c.same++;
+                    ev |= EV_SAME;
                 } else if (st.ha != H) {
-                    c.red++;
+                    ev |= EV_RED;
                 } else {
-                    c.claw++;
+                    ev |= EV_CLAW;
                     if (leader) {
                         const unsigned long long idx = atomicAdd(wd.claw_count, 1ull);
                         if (idx < wd.claw_cap) {
@@ -1273,10 +1270,12 @@ __device__ inline void advance_walk(const SpaceDev& sp, const WalkDev& wd, WalkS
         }
         st.cur = st.start;
     }
+    return ev;
 }
 
 // `iters` evaluations of f for every walk of slice `block` of `nblocks` (walks (block * WAVES + wave)
-// * WPW + group, then every nblocks * WAVES * WPW further); events are added to cnt.
+// * WPW + group, then every nblocks * WAVES * WPW further).  cnt is the walk group's counts in LDS;
+// only the group's leader lane writes it.
 template <int NQ, int WAVES>
 __device__ void walk_block_single(const SpaceDev& sp, const WalkDev& wd, int iters, Lds<NQ, WAVES>& L, int64_t block,
                                   int64_t nblocks, WalkCounts& cnt) {
@@ -1285,7 +1284,7 @@ __device__ void walk_block_single(const SpaceDev& sp, const WalkDev& wd, int ite
     const int gi = lane / Gm::G, gl = lane % Gm::G, gbase = gi * Gm::G;
     const bool leader = gl == 0;
     uint32_t* limbs = L.limbs[wave * Gm::WPW + gi];
-    WalkCounts c;
+    uint32_t steps = 0, active = 0;
     const int64_t stride = nblocks * WAVES * Gm::WPW;
     for (int64_t base = (block * WAVES + wave) * Gm::WPW; base < wd.walks; base += stride) {
         const int64_t w = base + gi;
@@ -1296,18 +1295,22 @@ __device__ void walk_block_single(const SpaceDev& sp, const WalkDev& wd, int ite
             const uint64_t arg = step_arg(st);
             uint64_t nxt, H;
             walk_step<NQ, WAVES>(sp, L, limbs, arg, gl, gbase, nxt, H);
-            c.steps++;
-            advance_walk<Gm::G == 64>(sp, wd, st, w, arg, nxt, H, leader, gbase, c);
+            steps++;
+            const uint32_t ev = advance_walk<Gm::G == 64>(sp, wd, st, w, arg, nxt, H, leader, gbase);
+            if (ev && leader) count_events(cnt, ev);
         }
-        if ((st.mode & 0xff) != MODE_DONE) c.active++;
+        if ((st.mode & 0xff) != MODE_DONE) active++;
         if (leader) wd.states[w] = st;
     }
-    add_counts(cnt, c);
+    if (leader) {
+        cnt.steps += steps;
+        cnt.active += active;
+    }
 }
 
 // n = 4: each wavefront runs two walks, 2q and 2q + 1 for q = block * WAVES + wave, then every
 // nblocks * WAVES further, and gives the pair 2 iters evaluations of f (a walk without a partner
-// gets iters).  A walk whose next point is on side 0 steps alone; when both next points are on side
+// gets iters); cnt as in walk_block_single.  A walk whose next point is on side 0 steps alone; when both next points are on side
 // 1 the two steps share one MFMA product (walk_step_pair4).  So the pair's steps add up to 2 iters
 // while each walk's share varies with its sides: a launch's total is walks x iters as before.
 template <int WAVES>
@@ -1316,7 +1319,7 @@ __device__ void walk_block_pairs(const SpaceDev& sp, const WalkDev& wd, int iter
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool leader = lane == 0;
     uint32_t* limbs = L.limbs[wave];
-    WalkCounts32 c;
+    uint32_t steps = 0, active = 0;
     const int64_t pairs = (wd.walks + 1) / 2;
     for (int64_t q = block * WAVES + wave; q < pairs; q += nblocks * WAVES) {
         const int64_t w0 = 2 * q, w1 = 2 * q + 1;
@@ -1352,23 +1355,27 @@ __device__ void walk_block_pairs(const SpaceDev& sp, const WalkDev& wd, int iter
             for (int k = 0; k < 2; ++k) {
                 if (!(k ? do_b : do_a)) continue;
                 WalkState st = k ? sb : sa;
-                advance_walk<true>(sp, wd, st, k ? w1 : w0, k ? arg_b : arg_a, k ? nb : na, k ? hb : ha, leader, 0,
-                                   c);
+                const uint32_t ev =
+                    advance_walk<true>(sp, wd, st, k ? w1 : w0, k ? arg_b : arg_a, k ? nb : na, k ? hb : ha, leader, 0);
+                if (ev && leader) count_events(cnt, ev);
                 if (k)
                     sb = st;
                 else
                     sa = st;
             }
         }
-        c.steps += (uint32_t)(total - left);
-        if ((sa.mode & 0xff) != MODE_DONE) c.active++;
-        if (has_b && (sb.mode & 0xff) != MODE_DONE) c.active++;
+        steps += (uint32_t)(total - left);
+        if ((sa.mode & 0xff) != MODE_DONE) active++;
+        if (has_b && (sb.mode & 0xff) != MODE_DONE) active++;
         if (leader) {
             wd.states[w0] = sa;
             if (has_b) wd.states[w1] = sb;
         }
     }
-    add_counts(cnt, c);
+    if (leader) {
+        cnt.steps += steps;
+        cnt.active += active;
+    }
 }
 
 // The walks of one slice: paired on side 1 at n = 4, one walk group at a time otherwise.
@@ -1384,11 +1391,16 @@ __device__ void walk_block(const SpaceDev& sp, const WalkDev& wd, int iters, Lds
 template <int NQ, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_walk(SpaceDev sp, WalkDev wd, int iters) {
     __shared__ Lds<NQ, WAVES> L;
+    // one count slot per walk group (raw storage: a __shared__ object cannot have initialisers)
+    __shared__ __attribute__((aligned(8))) unsigned char s_cnt[WAVES * Geo<NQ>::WPW * sizeof(WalkCounts)];
+    const int lane = threadIdx.x & 63;
+    const bool leader = lane % Geo<NQ>::G == 0;
+    WalkCounts& mine = reinterpret_cast<WalkCounts*>(s_cnt)[(threadIdx.x >> 6) * Geo<NQ>::WPW + lane / Geo<NQ>::G];
+    if (leader) mine = WalkCounts{};
     load_lds(L, sp);
     __syncthreads();
-    WalkCounts cnt;
-    walk_block<NQ, WAVES>(sp, wd, iters, L, blockIdx.x, gridDim.x, cnt);
-    flush_counts(wd, cnt, (threadIdx.x & 63) % Geo<NQ>::G == 0);
+    walk_block<NQ, WAVES>(sp, wd, iters, L, blockIdx.x, gridDim.x, mine);
+    flush_counts(wd, mine, leader);
 }
 
 // Many members in one persistent launch per qubit count, fed from a device queue: each block takes
@@ -1397,13 +1409,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_walk(SpaceDev sp, WalkDev wd, in
 // head[0] is the queue position (zeroed by a kernel before the launch); count[0] items are queued.
 // Every block leaves once the position passes the count, so the grid always drains.
 template <int NQ, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void k_walk_queue(const SpaceDev* sps, const WalkDev* wds,
-                                                           const WorkItem* items, const int32_t* count,
+__global__ __launch_bounds__(WAVES * 64) void k_walk_queue(const SpaceDev* __restrict__ sps, const WalkDev* __restrict__ wds,
+                                                           const WorkItem* __restrict__ items, const int32_t* count,
                                                            uint32_t* head) {
     __shared__ Lds<NQ, WAVES> L;
     __shared__ int32_t s_next;
-    // the loaded member's event counts so far, one slot per walk group, owned by the group's leader
-    // (kept in LDS: across items they would hold 22 more VGPRs through the step and spill)
+    // the loaded member's event counts so far, one slot per walk group, written by the group's leader
+    // as events happen (in registers they would hold 22 more VGPRs through the step and spill)
     __shared__ __attribute__((aligned(8))) unsigned char s_cnt[WAVES * Geo<NQ>::WPW * sizeof(WalkCounts)];
     const int32_t n_items = *count;
     const int lane = threadIdx.x & 63;
@@ -1419,7 +1431,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_walk_queue(const SpaceDev* sps, 
         const int32_t i = __builtin_amdgcn_readfirstlane(s_next);
         if (i >= n_items) break;
         const WorkItem it = items[i];
-        // read through the pointer where used (scalar loads) rather than held in registers for the item
+        // read through the pointer where used (scalar loads; the descriptors are never written during
+        // the launch, which __restrict__ tells the compiler, so it may keep or reload them freely)
         const SpaceDev& sp = sps[it.slot];
         if (it.slot != loaded) {
             if (loaded >= 0) flush_counts(wds[loaded], mine, leader);
@@ -1427,21 +1440,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_walk_queue(const SpaceDev* sps, 
             loaded = it.slot;
         }
         __syncthreads();
-        WalkCounts c;
-        walk_block<NQ, WAVES>(sp, wds[it.slot], it.iters, L, it.unit, it.units, c);
-        if (leader) {
-            mine.steps += c.steps;
-            mine.dps += c.dps;
-            mine.ins += c.ins;
-            mine.ab += c.ab;
-            mine.rh += c.rh;
-            mine.same += c.same;
-            mine.red += c.red;
-            mine.claw += c.claw;
-            mine.full += c.full;
-            mine.spin += c.spin;
-            mine.active += c.active;
-        }
+        walk_block<NQ, WAVES>(sp, wds[it.slot], it.iters, L, it.unit, it.units, mine);
         __syncthreads();  // s_next and, for the next member, the LDS are rewritten after this
     }
     if (loaded >= 0) flush_counts(wds[loaded], mine, leader);
@@ -1608,11 +1607,12 @@ int cu_count(int device) {
 
 }  // namespace
 
-int walk_grid_blocks(int n, int device) {
+int walk_grid_blocks(int n, int device, bool queue) {
     // one persistent block per CU for n = 4 (the int8 S_c fills most of the 160 KiB LDS); at n = 3 the
-    // kernel's 96 VGPRs leave room for five 4-wave blocks per CU (measured 8% faster than four)
+    // walk kernel's 71 VGPRs leave room for six 4-wave blocks per CU (measured: six 13.4 ms, seven
+    // 13.5 ms per 3.4e7 steps), the queue kernel's 88 for five
     const int cus = cu_count(device);
-    return n == 4 ? cus : (n == 3 ? cus * 5 : cus * 4);
+    return n == 4 ? cus : (n == 3 ? cus * (queue ? 5 : 6) : cus * 4);
 }
 
 hipError_t keys_fill(int n, uint64_t seed, uint64_t* keys, hipStream_t s) {
