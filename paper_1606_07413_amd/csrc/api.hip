@@ -1239,6 +1239,17 @@ uint64_t version_steps(const tcw_walk_params* p, uint64_t npts, int delta, int64
     return per_version < table_v ? per_version : table_v;
 }
 
+// The least table size, at most 2^lg slots, that keeps the function version as long as 2^lg slots
+// would (version_steps) with the table at most a quarter full when the version ends: the stored
+// distinguished points, and so the walks, are the same, and a larger table would only cost memory,
+// allocation and clears.
+int version_table_log2(const tcw_walk_params* p, uint64_t npts, int delta, int64_t walks, int lg) {
+    const uint64_t dps = version_steps(p, npts, delta, walks, lg) >> delta;
+    int fit = 10;
+    while (fit < lg && (1ull << (fit - 2)) < dps) ++fit;
+    return fit < lg ? fit : lg;
+}
+
 // the tables of one group of concurrently searched chunks stay within 2^35 bytes (32 GiB)
 constexpr int CHUNK_TABLE_POOL_LOG2 = 35;
 
@@ -1344,12 +1355,13 @@ int open_space(tcw_ctx* c, SearchRun& s) {
         uint32_t cap = 0;
         if ((rc = trail_cap_of(c, p, s.delta, &cap))) return rc;
         const int64_t walks = walks_for(p->walks, s.npts);
+        const int lg = version_table_log2(p, s.npts, s.delta, walks, p->log2_table);
         s.budget = (uint64_t)p->budget_beta * s.npts << s.delta;
-        s.per_version = version_steps(p, s.npts, s.delta, walks, p->log2_table);
+        s.per_version = version_steps(p, s.npts, s.delta, walks, lg);
         // a launch must not overrun a function version
         const uint64_t fit = s.per_version / (uint64_t)walks;
         if ((uint64_t)s.iters > fit) s.iters = fit > 0 ? (int)fit : 1;
-        rc = tcw_walk_begin(c, t, &sp, walks, p->log2_table, cap, 0, &s.w);
+        rc = tcw_walk_begin(c, t, &sp, walks, lg, cap, 0, &s.w);
     }
     return rc;
 }
@@ -2053,7 +2065,8 @@ int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStr
                 if ((rc = autotune(c, b.t, b.k, b.chunk, delta, b.p.seed, &cfg))) return rc;
             }
             b.walks = walks_for(b.p.walks > 0 ? b.p.walks : cfg.walks, npts);
-            b.log2 = b.p.log2_table > 0 ? b.p.log2_table : cfg.log2_table;
+            b.log2 = version_table_log2(&b.p, npts, delta, b.walks,
+                                        b.p.log2_table > 0 ? b.p.log2_table : cfg.log2_table);
             b.iters = b.p.iters_per_launch > 0 ? b.p.iters_per_launch : cfg.iters;
         }
         b.space.reset(new Space());
