@@ -156,8 +156,10 @@ int tcw_claw_check(tcw_ctx* ctx, const tcw_target* t, const tcw_space* sp, const
 
 /* ---- walk sessions: many concurrent walks with a device distinguished-point table ----------
  * A session owns `walks` walk states (64 B each) and a table of 2^log2_table slots (16 B each).
- * tcw_walk_run enqueues one launch in which every walk performs `iters` evaluations of f
- * (walking, inserting distinguished points, backtracking merged trails).  Claw candidates (equal
+ * tcw_walk_run enqueues one launch of walks x iters evaluations of f (walking, inserting
+ * distinguished points, backtracking merged trails): every walk performs `iters` of them, except at
+ * n = 4, where the two walks a wavefront runs (2q, 2q + 1) share 2 iters between them (a side-0 step
+ * runs alone, two side-1 steps share one MFMA pass), so each one's share varies with its sides.  Claw candidates (equal
  * matrix hash, opposite sides) are queued on the device.  enumerate != 0 is the exhaustive mode for
  * small spaces: walk w takes the points w, w + walks, w + 2 walks, ... of the space once each and the
  * table is keyed by each point's full 64-bit matrix hash, keeping per side the least x that reached
@@ -231,7 +233,7 @@ typedef struct tcw_walk_params {
     int32_t budget_beta;      /* steps per (k, chunk) = beta * N * 2^delta, N = 2 xi^h (default 16) */
     int32_t version_factor;   /* steps per function version = max(factor * N, 2 walks 2^delta) (default 2) */
     int64_t enum_max;         /* enumerate spaces with N <= enum_max (default 65536) */
-    int32_t iters_per_launch; /* f evaluations per walk per launch (default by n) */
+    int32_t iters_per_launch; /* f evaluations per walk per launch, on average at n = 4 (default by n) */
     int32_t depth_order_kind; /* TCW_ORDER_PLAIN or TCW_ORDER_GIVEN */
     int32_t depth_order_len;
     int32_t depth_order[16];  /* depths to try in this order (GIVEN) */
