@@ -60,6 +60,7 @@ struct tcw_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int* flag = nullptr;          // device scratch flag
+    int32_t* rot_min = nullptr;   // device scratch of exact_rotate1 (the least reduction count)
     void* claw_scratch = nullptr;
     size_t claw_scratch_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -206,20 +207,15 @@ int prepare_space(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, Space& o
     HIP_TRY(c, hipMalloc(&out.keys, (size_t)R * sizeof(uint64_t)));
     if ((rc = clear_flag(c))) return rc;
     // S_c = U R(c)^T for odd k, U for even k
-    DevScope scope;
-    uint16_t* seq = nullptr;
-    uint8_t* tr = nullptr;
-    int nseq = 0;
+    hipError_t e = hipSuccess;
     if (sp->k % 2 == 1) {
-        HIP_TRY(c, scope.alloc(&seq, sizeof(uint16_t)));
-        HIP_TRY(c, scope.alloc(&tr, 1));
-        const uint16_t cc = (uint16_t)sp->chunk;
-        const uint8_t one = 1;
-        HIP_TRY(c, hipMemcpyAsync(seq, &cc, sizeof(cc), hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(c, hipMemcpyAsync(tr, &one, 1, hipMemcpyHostToDevice, c->stream));
-        nseq = 1;
+        e = tcw::exact_rotate1(out.S, t->U, (uint32_t)sp->chunk, 1, c->rot_min, c->flag, c->stream);
+    } else {
+        const size_t bytes = (size_t)out.S.r * out.S.r * out.S.elem;
+        e = hipMemcpyAsync(out.S.a, t->U.a, bytes, hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(out.S.b, t->U.b, bytes, hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(out.S.e, t->U.e, sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream);
     }
-    hipError_t e = tcw::exact_apply(out.S, t->U, seq, tr, nseq, c->flag, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "chunk matrix");
     HIP_TRY(c, tcw::exact_pack_phi(out.S, out.phi, c->flag, c->stream));
     HIP_TRY(c, tcw::keys_fill(n, sp->seed, out.keys, c->stream));
@@ -386,7 +382,8 @@ int tcw_create(tcw_ctx** out, int device, void* stream) {
     c->device = device;
     c->stream = (hipStream_t)stream;
     if (hipSetDevice(device) != hipSuccess || hipMalloc(&c->flag, sizeof(int)) != hipSuccess ||
-        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        hipMalloc(&c->rot_min, sizeof(int32_t)) != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
+        hipEventCreate(&c->ev1) != hipSuccess) {
         delete c;
         return TCW_EDEVICE;
     }
@@ -400,6 +397,7 @@ int tcw_destroy(tcw_ctx* c) {
     if (c->stopped) free_search_run(c->stopped);
     c->stopped = nullptr;
     if (c->flag) (void)hipFree(c->flag);
+    if (c->rot_min) (void)hipFree(c->rot_min);
     if (c->claw_scratch) (void)hipFree(c->claw_scratch);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);

@@ -663,6 +663,75 @@ hipError_t exact_apply(ExactDev& dst, const ExactDev& src, const uint16_t* seq, 
 }
 
 namespace {
+// One rotation on many blocks (the chunk matrix S_c = U R(c)^T), in two passes with no work matrices.
+// Pass 1 writes (A', B') = the rotated columns of (src.A, src.B) into dst and folds into *m_min the
+// number of reduction steps each entry allows: a step (a, b) -> (b, a / 2) needs a even, so from
+// (a, b) the steps alternate the conditions 2 | a, 2 | b, 4 | a, 4 | b, ... and entry (a, b) allows
+// min(2 v2(a), 2 v2(b) + 1) of them (v2 = 2-adic valuation, unbounded for 0).  Pass 2 takes
+// m = min(*m_min, e + 1) steps in closed form, as block_apply's loop would: after 2j steps
+// (a, b) / 2^j, after 2j + 1 steps (b / 2^j, a / 2^(j + 1)).
+template <typename T>
+__device__ inline int v2_of(T v) {
+    if (v == 0) return 1 << 20;
+    return (int)__builtin_ctzll((unsigned long long)v);
+}
+
+template <int NQ, typename T>
+__global__ __launch_bounds__(256) void k_rotate1(T* a, T* b, const T* sa, const T* sb, uint32_t p, int transposed,
+                                                int* flag, int32_t* m_min) {
+    constexpr int R = EGeo<NQ>::R;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    int m = 1 << 30;
+    if (idx < R * R) {
+        const uint32_t q = idx & (R - 1);
+        const int row = idx - (int)q;
+        T va, vb;
+        if (anticommutes<NQ>(p, q)) {
+            int sg = rotation_sign<NQ>(p, q);
+            if (transposed) sg = -sg;
+            const int j = row + (int)(q ^ p);
+            va = sg > 0 ? sa[idx] + sa[j] : sa[idx] - sa[j];
+            vb = sg > 0 ? sb[idx] + sb[j] : sb[idx] - sb[j];
+        } else {
+            va = sb[idx] * 2;
+            vb = sa[idx];
+        }
+        const T lim = lim_of<T>();
+        if (va > lim || va < -lim || vb > lim || vb < -lim) atomicOr(flag, 4);
+        a[idx] = va;
+        b[idx] = vb;
+        const int ma = 2 * v2_of(va), mb = 2 * v2_of(vb) + 1;
+        m = ma < mb ? ma : mb;
+    }
+    // the wavefront's least, then one atomic per wavefront
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int o = __shfl_xor(m, off);
+        m = o < m ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0 && m < (1 << 30)) atomicMin(m_min, m);
+}
+
+template <int NQ, typename T>
+__global__ __launch_bounds__(256) void k_rotate1_reduce(T* a, T* b, int32_t* e_io, const int32_t* se,
+                                                       const int32_t* m_min) {
+    constexpr int R = EGeo<NQ>::R;
+    const int e1 = *se + 1;
+    const int m = *m_min < e1 ? *m_min : e1;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < R * R && m > 0) {
+        const T va = a[idx], vb = b[idx];
+        const int j = m >> 1;
+        if (m & 1) {
+            a[idx] = vb / ((T)1 << j);
+            b[idx] = va / ((T)1 << (j + 1));
+        } else {
+            a[idx] = va / ((T)1 << j);
+            b[idx] = vb / ((T)1 << j);
+        }
+    }
+    if (idx == 0) *e_io = e1 - m;
+}
+
 __global__ void k_seq_one(uint16_t* seq, uint8_t* tr, uint16_t p, uint8_t t) {
     if (threadIdx.x == 0) {
         seq[0] = p;
@@ -673,6 +742,23 @@ __global__ void k_fill_i32(int* dst, int v, int count) {
     for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = v;
 }
 }  // namespace
+
+hipError_t exact_rotate1(ExactDev& dst, const ExactDev& src, uint32_t p, int transposed, int32_t* m_tmp, int* flag,
+                         hipStream_t s) {
+    if (dst.a == src.a || dst.b == src.b) return hipErrorInvalidValue;
+    hipError_t err = fill_i32(m_tmp, 1 << 30, 1, s);
+    if (err != hipSuccess) return err;
+    auto f = [&]<int NQ, typename T>() -> hipError_t {
+        constexpr int R = EGeo<NQ>::R;
+        const int blocks = (R * R + 255) / 256;
+        hipLaunchKernelGGL((k_rotate1<NQ, T>), dim3(blocks), dim3(256), 0, s, (T*)dst.a, (T*)dst.b, (const T*)src.a,
+                           (const T*)src.b, p, transposed, flag, m_tmp);
+        hipLaunchKernelGGL((k_rotate1_reduce<NQ, T>), dim3(blocks), dim3(256), 0, s, (T*)dst.a, (T*)dst.b, dst.e,
+                           src.e, m_tmp);
+        return hipGetLastError();
+    };
+    return dispatch_exact(dst.n, f);
+}
 
 hipError_t exact_seq_one(uint16_t* seq, uint8_t* tr, uint16_t p, uint8_t transpose, hipStream_t s) {
     hipLaunchKernelGGL(k_seq_one, dim3(1), dim3(64), 0, s, seq, tr, p, transpose);

@@ -89,6 +89,11 @@ hipError_t exact_apply(ExactDev& dst, const ExactDev& src, const uint16_t* seq_d
 // synchronisation
 hipError_t exact_apply_ws(ExactDev& dst, const ExactDev& src, const uint16_t* seq, const uint8_t* tr, int nseq,
                           void* ta, void* tb, int* flag, hipStream_t s);
+// dst = src * R(p)^(T if transposed), reduced, for dst distinct from src: the result of exact_apply
+// with a one-rotation word, on many blocks and without work matrices; m_tmp is one device int32 of
+// scratch.  No synchronisation.
+hipError_t exact_rotate1(ExactDev& dst, const ExactDev& src, uint32_t p, int transposed, int32_t* m_tmp, int* flag,
+                         hipStream_t s);
 // seq[0] = p, tr[0] = transpose (a one-rotation word on the device, written by a kernel)
 hipError_t exact_seq_one(uint16_t* seq, uint8_t* tr, uint16_t p, uint8_t transpose, hipStream_t s);
 // dst[0..count) = v by a kernel (no memset node, so it may sit in captured work)
