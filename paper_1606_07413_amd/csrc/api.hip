@@ -202,9 +202,17 @@ int prepare_space(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, Space& o
     out.chunk = sp->chunk;
     out.delta = sp->delta;
     out.seed = sp->seed;
-    HIP_TRY(c, tcw::exact_alloc(out.S, n));
-    HIP_TRY(c, hipMalloc(&out.phi, (size_t)R * R / 2 * sizeof(uint32_t) + 16));
-    HIP_TRY(c, hipMalloc(&out.keys, (size_t)R * sizeof(uint64_t)));
+    // a Space prepared before for the same qubit count keeps its buffers (a batch member's next chunk)
+    if (out.S.a == nullptr || out.S.n != n || !out.phi || !out.keys) {
+        tcw::exact_free(out.S);
+        if (out.phi) (void)hipFree(out.phi);
+        if (out.keys) (void)hipFree(out.keys);
+        out.phi = nullptr;
+        out.keys = nullptr;
+        HIP_TRY(c, tcw::exact_alloc(out.S, n));
+        HIP_TRY(c, hipMalloc(&out.phi, (size_t)R * R / 2 * sizeof(uint32_t) + 16));
+        HIP_TRY(c, hipMalloc(&out.keys, (size_t)R * sizeof(uint64_t)));
+    }
     if ((rc = clear_flag(c))) return rc;
     // S_c = U R(c)^T for odd k, U for even k
     hipError_t e = hipSuccess;
@@ -2067,7 +2075,9 @@ int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStr
                                         b.p.log2_table > 0 ? b.p.log2_table : cfg.log2_table);
             b.iters = b.p.iters_per_launch > 0 ? b.p.iters_per_launch : cfg.iters;
         }
-        b.space.reset(new Space());
+        // the member's previous space is finished (its candidates were checked and the round that
+        // used it has completed), so its buffers serve the next one
+        if (!b.space) b.space.reset(new Space());
         tcw_space sp{b.k, b.chunk, b.p.seed, b.p.version, delta};
         if ((rc = prepare_space(c, b.t, &sp, *b.space))) return rc;
         b.res->spaces++;
