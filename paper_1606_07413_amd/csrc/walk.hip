@@ -732,6 +732,9 @@ __device__ void walk_step_pair4(const SpaceDev& sp, const Lds<4, WAVES>& L, uint
                                 uint64_t pb, int lane, uint64_t& out_a, uint64_t& h_a, uint64_t& out_b,
                                 uint64_t& h_b) {
     constexpr int HMAX = Geo<4>::HMAX;
+    // the points are the same in every lane: decode on the scalar unit (uniform branches below)
+    pa = uniform64(pa);
+    pb = uniform64(pb);
     v4i afr[N4_KK];
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
