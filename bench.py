@@ -104,9 +104,9 @@ def valu_ops_per_step(n: int, h: int) -> float:
     return 64.0 * (rotations + 0.5 * side0 + both + 0.5 * side1)
 
 
-# The survey's count of integer operations per step of the literal method (the 256 x 256 channel
-# representation updated by h sparse butterflies, its 65,536 entries normalised and digested, the
-# rows sorted): about 1.3e6 at n = 4.  The kernel reaches the same f without forming that matrix.
+# Integer operations per step of the literal method (the 256 x 256 channel representation updated
+# by h sparse butterflies, its 65,536 entries normalised and digested, the rows sorted): about 1.3e6
+# at n = 4.  The kernel reaches the same f without forming that matrix.
 LITERAL_OPS_PER_STEP_N4 = 1.3e6
 
 
@@ -142,7 +142,7 @@ def measured_counters(walks: int, iters: int):
 
 
 def walk_roofline(n, h, steps_per_launch, avg_ms, walks, iters):
-    """The walk kernel against the VALU peak (its bound), with the survey's literal-method count, the
+    """The walk kernel against the VALU peak (its bound), with the literal method's count, the
     compiled kernel's issued VALU work and busy share (counters), the int8 MFMA rate and HBM bytes."""
     secs = avg_ms * 1e-3
     ops = valu_ops_per_step(n, h)

@@ -15,7 +15,7 @@ def test_work_counts_at_n4k7():
     assert bench.valu_ops_per_step(4, 3) == 64 * 260 == 16640
     # each further rotation adds 13 operations on each of a lane's four rows
     assert bench.valu_ops_per_step(4, 4) - bench.valu_ops_per_step(4, 3) == 64 * 13 * 4
-    # the survey's literal-method count exceeds the phi-linear step's by far
+    # the literal method's count exceeds the phi-linear step's by far
     assert bench.LITERAL_OPS_PER_STEP_N4 > 50 * bench.valu_ops_per_step(4, 3)
     # side 1 (half the steps): two digit sets x 8 digit rows x the 256 x 256 product, multiply and add
     assert bench.mfma_ops_per_step(4) == 0.5 * 2 * 8 * 256 * 256 * 2
