@@ -53,7 +53,9 @@ typedef struct tcw_walk tcw_walk;
  * tcw_create: bind to HIP device `device`; `hip_stream` (a hipStream_t, may be NULL for the null
  * stream) is borrowed, e.g. torch.cuda.current_stream().cuda_stream.  The context owns the device
  * buffers it allocates; among them, for n = 4, the rotated-key tables of up to 32 search seeds
- * (257 MiB each), kept for later searches with the same seed and released by tcw_destroy.
+ * (257 MiB each), kept for later searches with the same seed and released by tcw_destroy.  It also
+ * keeps the device buffers of finished batch members and concurrently searched chunks (S_c, keys,
+ * walk states, tables; at most 40 GiB) for later members of the same sizes, also until tcw_destroy.
  * tcw_last_error's string is owned by the context and valid until the next call on it. */
 int tcw_create(tcw_ctx** out, int device, void* hip_stream);
 int tcw_destroy(tcw_ctx* ctx);

@@ -68,6 +68,9 @@ struct tcw_ctx {
     hipError_t noalloc_err = hipSuccess;
     std::atomic<int> stop_req{0};   // tcw_search_stop: end the running search at its next launch boundary
     SearchRun* stopped = nullptr;   // the last search that ended on a stop, for tcw_checkpoint
+    // device buffers of finished batch members, by exact size, for later batches (pool_get / pool_put)
+    std::multimap<size_t, void*> pool;
+    size_t pool_bytes = 0;
 };
 
 struct tcw_target {
@@ -89,6 +92,34 @@ int fail(tcw_ctx* c, int code, const std::string& msg) {
 int hip_fail(tcw_ctx* c, hipError_t e, const char* where) {
     std::string m = std::string(where) + ": " + hipGetErrorString(e);
     return fail(c, e == hipErrorOutOfMemory ? TCW_ENOMEM : TCW_EDEVICE, m);
+}
+
+// A search at n = 4 opens hundreds of chunk spaces as batch members, and allocating and freeing
+// their buffers costs more than the kernels that fill them.  A finished batch returns its members'
+// buffers here (after its streams are synchronised, so no work on them is pending) and later members
+// take buffers of exactly the size they need; beyond POOL_MAX bytes they are freed.  tcw_destroy
+// frees the rest.
+constexpr size_t POOL_MAX = (size_t)40 << 30;
+
+hipError_t pool_alloc(tcw_ctx* c, void** p, size_t bytes) {
+    auto it = c->pool.find(bytes);
+    if (it != c->pool.end()) {
+        *p = it->second;
+        c->pool.erase(it);
+        c->pool_bytes -= bytes;
+        return hipSuccess;
+    }
+    return hipMalloc(p, bytes);
+}
+
+void pool_put(tcw_ctx* c, void* p, size_t bytes) {
+    if (!p) return;
+    if (c->pool_bytes + bytes > POOL_MAX) {
+        (void)hipFree(p);
+        return;
+    }
+    c->pool.emplace(bytes, p);
+    c->pool_bytes += bytes;
 }
 
 #define HIP_TRY(ctx, expr)                                   \
@@ -164,12 +195,31 @@ struct Space {
     uint64_t* keys = nullptr;
     std::shared_ptr<tcw::RotKeys> rk;  // n = 4: rotated keys (SpaceDev::rkeys, rkeys2)
     SpaceDev dev{};
+    bool pooled = false;  // a batch member's space: buffers from and back to the context's pool
 
-    ~Space() {
-        tcw::exact_free(S);
-        if (phi) (void)hipFree(phi);
-        if (keys) (void)hipFree(keys);
+    size_t mat_bytes() const { return (size_t)S.r * S.r * S.elem; }
+    size_t phi_bytes() const { return (size_t)S.r * S.r / 2 * sizeof(uint32_t) + 16; }
+    size_t key_bytes() const { return (size_t)S.r * sizeof(uint64_t); }
+
+    void release() {
+        if (pooled && ctx) {
+            pool_put(ctx, S.a, mat_bytes());
+            pool_put(ctx, S.b, mat_bytes());
+            pool_put(ctx, S.e, sizeof(int32_t));
+            pool_put(ctx, phi, phi_bytes());
+            pool_put(ctx, keys, key_bytes());
+            S.a = S.b = nullptr;
+            S.e = nullptr;
+        } else {
+            tcw::exact_free(S);
+            if (phi) (void)hipFree(phi);
+            if (keys) (void)hipFree(keys);
+        }
+        phi = nullptr;
+        keys = nullptr;
     }
+
+    ~Space() { release(); }
 
     void set_version(uint32_t v) {
         version = v;
@@ -204,14 +254,21 @@ int prepare_space(tcw_ctx* c, const tcw_target* t, const tcw_space* sp, Space& o
     out.seed = sp->seed;
     // a Space prepared before for the same qubit count keeps its buffers (a batch member's next chunk)
     if (out.S.a == nullptr || out.S.n != n || !out.phi || !out.keys) {
-        tcw::exact_free(out.S);
-        if (out.phi) (void)hipFree(out.phi);
-        if (out.keys) (void)hipFree(out.keys);
-        out.phi = nullptr;
-        out.keys = nullptr;
-        HIP_TRY(c, tcw::exact_alloc(out.S, n));
-        HIP_TRY(c, hipMalloc(&out.phi, (size_t)R * R / 2 * sizeof(uint32_t) + 16));
-        HIP_TRY(c, hipMalloc(&out.keys, (size_t)R * sizeof(uint64_t)));
+        out.release();
+        if (out.pooled) {
+            out.S.n = n;
+            out.S.r = R;
+            out.S.elem = n <= 2 ? 8 : 4;
+            HIP_TRY(c, pool_alloc(c, &out.S.a, out.mat_bytes()));
+            HIP_TRY(c, pool_alloc(c, &out.S.b, out.mat_bytes()));
+            HIP_TRY(c, pool_alloc(c, reinterpret_cast<void**>(&out.S.e), sizeof(int32_t)));
+            HIP_TRY(c, pool_alloc(c, reinterpret_cast<void**>(&out.phi), out.phi_bytes()));
+            HIP_TRY(c, pool_alloc(c, reinterpret_cast<void**>(&out.keys), out.key_bytes()));
+        } else {
+            HIP_TRY(c, tcw::exact_alloc(out.S, n));
+            HIP_TRY(c, hipMalloc(&out.phi, (size_t)R * R / 2 * sizeof(uint32_t) + 16));
+            HIP_TRY(c, hipMalloc(&out.keys, (size_t)R * sizeof(uint64_t)));
+        }
     }
     if ((rc = clear_flag(c))) return rc;
     // S_c = U R(c)^T for odd k, U for even k
@@ -406,6 +463,8 @@ int tcw_destroy(tcw_ctx* c) {
     c->stopped = nullptr;
     if (c->flag) (void)hipFree(c->flag);
     if (c->rot_min) (void)hipFree(c->rot_min);
+    for (auto& e : c->pool) (void)hipFree(e.second);
+    c->pool.clear();
     if (c->claw_scratch) (void)hipFree(c->claw_scratch);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -1956,9 +2015,10 @@ struct BatchBuffers {
     }
 };
 
-void free_walk_buffers(BatchTarget& b) {
-    if (b.wd.states) (void)hipFree(b.wd.states);
-    if (b.wd.table) (void)hipFree(b.wd.table);
+// back to the context's pool: the caller has synchronised every stream that used them
+void free_walk_buffers(tcw_ctx* c, BatchTarget& b) {
+    pool_put(c, b.wd.states, b.states_cap);
+    if (b.wd.table) pool_put(c, b.wd.table, ((size_t)1 << b.table_cap) * 16);
     b.wd.states = nullptr;
     b.wd.table = nullptr;
     b.states_cap = 0;
@@ -2077,7 +2137,10 @@ int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStr
         }
         // the member's previous space is finished (its candidates were checked and the round that
         // used it has completed), so its buffers serve the next one
-        if (!b.space) b.space.reset(new Space());
+        if (!b.space) {
+            b.space.reset(new Space());
+            b.space->pooled = true;
+        }
         tcw_space sp{b.k, b.chunk, b.p.seed, b.p.version, delta};
         if ((rc = prepare_space(c, b.t, &sp, *b.space))) return rc;
         b.res->spaces++;
@@ -2097,17 +2160,17 @@ int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStr
         // walk buffers (kept across spaces when large enough)
         const size_t sbytes = (size_t)b.walks * sizeof(tcw::WalkState);
         if (b.states_cap < sbytes) {
-            if (b.wd.states) (void)hipFree(b.wd.states);
+            pool_put(c, b.wd.states, b.states_cap);  // no round is in flight here
             b.wd.states = nullptr;
             b.states_cap = 0;
-            HIP_TRY(c, hipMalloc(&b.wd.states, sbytes));
+            HIP_TRY(c, pool_alloc(c, reinterpret_cast<void**>(&b.wd.states), sbytes));
             b.states_cap = sbytes;
         }
         if (b.table_cap < b.log2) {
-            if (b.wd.table) (void)hipFree(b.wd.table);
+            if (b.wd.table) pool_put(c, b.wd.table, ((size_t)1 << b.table_cap) * 16);
             b.wd.table = nullptr;
             b.table_cap = 0;
-            HIP_TRY(c, hipMalloc(&b.wd.table, ((size_t)1 << b.log2) * 16));
+            HIP_TRY(c, pool_alloc(c, reinterpret_cast<void**>(&b.wd.table), ((size_t)1 << b.log2) * 16));
             b.table_cap = b.log2;
         }
         b.wd.walks = b.walks;
@@ -2124,7 +2187,7 @@ int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStr
         return TCW_OK;
     }
     b.walking = false;
-    free_walk_buffers(b);
+    free_walk_buffers(c, b);  // between rounds: its last round has completed
     return TCW_OK;
 }
 
@@ -2210,7 +2273,8 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
         if (bt[i].done) bt[i].res->seconds = now_s() - t0;
     }
     if (rc) {
-        for (auto& b : bt) free_walk_buffers(b);
+        (void)hipStreamSynchronize(c->stream);
+        for (auto& b : bt) free_walk_buffers(c, b);
         return rc;
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -2221,6 +2285,9 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     auto cleanup = [&]() {
+        // nothing may still use the members' buffers when they go back to the pool
+        if (gs[0]) (void)hipStreamSynchronize(gs[0]);
+        (void)hipStreamSynchronize(c->stream);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         for (int n = 0; n <= 4; ++n) {
@@ -2228,7 +2295,7 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
             if (join[n]) (void)hipEventDestroy(join[n]);
         }
         if (fork) (void)hipEventDestroy(fork);
-        for (auto& b : bt) free_walk_buffers(b);
+        for (auto& b : bt) free_walk_buffers(c, b);
     };
 #define BATCH_TRY(expr)                      \
     do {                                     \
@@ -2282,7 +2349,7 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
             }
             if (b.done) {
                 b.res->seconds = now_s() - t0;
-                free_walk_buffers(b);
+                free_walk_buffers(c, b);
             } else {
                 int e = batch_advance(c, b, i, bb, gs[0], t0, !found);
                 if (e) return e;
