@@ -2006,9 +2006,11 @@ struct BatchBuffers {
     int64_t items_cap[5] = {0, 0, 0, 0, 0};
     int32_t* counts = nullptr;             // 5: items queued per qubit count
     int32_t* heads = nullptr;              // 5: queue positions (zeroed by a kernel at the start of a round)
+    int32_t* restart = nullptr;            // count: slots restarted before the next round
+    std::vector<int32_t> pending;          // host: members whose restart waits for the next round
     ~BatchBuffers() {
         for (void* q : {(void*)stats, (void*)claw_count, (void*)claws, (void*)sps, (void*)wds, (void*)counts,
-                        (void*)heads})
+                        (void*)heads, (void*)restart})
             if (q) (void)hipFree(q);
         for (auto* q : items)
             if (q) (void)hipFree(q);
@@ -2025,14 +2027,10 @@ void free_walk_buffers(tcw_ctx* c, BatchTarget& b) {
     b.table_cap = 0;
 }
 
-// (Re)start the walks of a target's current space on stream s: table cleared, counters zeroed.
-int batch_restart(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStream_t s) {
-    HIP_TRY(c, tcw::launch_table_clear(b.wd.table, b.wd.log2_table, b.wd.enumerate ? tcw::ENUM_TABLE_INIT : 0, s));
-    HIP_TRY(c, hipMemsetAsync(bb.stats + (size_t)slot * tcw::ST_COUNT, 0, tcw::ST_COUNT * 8, s));
-    HIP_TRY(c, hipMemsetAsync(bb.claw_count + slot, 0, 8, s));
-    HIP_TRY(c, tcw::launch_walk_init(b.space->dev, b.wd, s));
-    return TCW_OK;
-}
+// (Re)start the walks of a target's current space: table cleared, counters zeroed, walks initialised.
+// Queued and done for every pending member in one launch on the batch stream before the next round
+// (k_member_restart), after that round's descriptors are on the device.
+void batch_restart(BatchBuffers& bb, int slot) { bb.pending.push_back(slot); }
 
 // A verified decomposition of member b (in b.res).  TCW_ORDER_GIVEN then searches the depths below it
 // not yet searched, in increasing order (the first further hit is the lowest); otherwise b is done.
@@ -2053,7 +2051,7 @@ void batch_on_hit(BatchTarget& b) {
 // depth, enumerated when small and walked otherwise, leaves the target `walking`.  prev_done: the
 // current space ran to its budget without a verified decomposition (so its depth is failed once its
 // last chunk is done).
-int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStream_t s, double t0, bool prev_done) {
+int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, double t0, bool prev_done) {
     const int n = b.t->n;
     const uint32_t xi = xi_of(n);
     while (!b.done) {
@@ -2182,7 +2180,7 @@ int batch_advance(tcw_ctx* c, BatchTarget& b, int slot, BatchBuffers& bb, hipStr
         b.wd.claws = bb.claws + (size_t)slot * BATCH_CLAW_CAP * 2;
         b.wd.claw_count = bb.claw_count + slot;
         b.wd.claw_cap = BATCH_CLAW_CAP;
-        if ((rc = batch_restart(c, b, slot, bb, s))) return rc;
+        batch_restart(bb, slot);
         b.walking = true;
         return TCW_OK;
     }
@@ -2254,6 +2252,7 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
     HIP_TRY(c, hipMalloc(&bb.wds, (size_t)count * sizeof(tcw::WalkDev)));
     HIP_TRY(c, hipMalloc(&bb.counts, 5 * 4));
     HIP_TRY(c, hipMalloc(&bb.heads, 5 * 4));
+    HIP_TRY(c, hipMalloc(&bb.restart, (size_t)count * 4));
     HIP_TRY(c, hipMemsetAsync(bb.stats, 0, (size_t)count * tcw::ST_COUNT * 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(bb.claw_count, 0, (size_t)count * 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(bb.counts, 0, 5 * 4, c->stream));
@@ -2269,7 +2268,7 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
     if (int e = ensure_claw_scratch(c, nmax)) return e;
     int rc = TCW_OK;
     for (int i = 0; i < count && !rc; ++i) {
-        rc = batch_advance(c, bt[i], i, bb, c->stream, t0, false);
+        rc = batch_advance(c, bt[i], i, bb, t0, false);
         if (bt[i].done) bt[i].res->seconds = now_s() - t0;
     }
     if (rc) {
@@ -2351,7 +2350,7 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
                 b.res->seconds = now_s() - t0;
                 free_walk_buffers(c, b);
             } else {
-                int e = batch_advance(c, b, i, bb, gs[0], t0, !found);
+                int e = batch_advance(c, b, i, bb, t0, !found);
                 if (e) return e;
                 if (b.done) b.res->seconds = now_s() - t0;
             }
@@ -2364,8 +2363,7 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
             b.seen = 0;
             b.held = false;
             dirty = true;
-            int e = batch_restart(c, b, i, bb, gs[0]);
-            if (e) return e;
+            batch_restart(bb, i);
         }
         return TCW_OK;
     };
@@ -2449,14 +2447,26 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
             h_sps[i] = bt[i].space->dev;
             h_wds[i] = bt[i].wd;
         }
+        for (const int32_t i : bb.pending) {
+            h_sps[i] = bt[i].space->dev;
+            h_wds[i] = bt[i].wd;
+        }
         const double tl = now_s();
-        if (round) {
-            // descriptors for this replay (salts change with versions), then the round itself
+        if (round || !bb.pending.empty()) {
+            // descriptors for this replay (salts change with versions), the restarts of members that
+            // begin a space or a version, then the round itself
             BATCH_TRY(hipMemcpyAsync(bb.sps, h_sps.data(), count * sizeof(tcw::SpaceDev), hipMemcpyHostToDevice,
                                      gs[0]));
             BATCH_TRY(hipMemcpyAsync(bb.wds, h_wds.data(), count * sizeof(tcw::WalkDev), hipMemcpyHostToDevice,
                                      gs[0]));
-            BATCH_TRY(hipGraphLaunch(exec, gs[0]));
+            if (!bb.pending.empty()) {
+                BATCH_TRY(hipMemcpyAsync(bb.restart, bb.pending.data(), bb.pending.size() * 4, hipMemcpyHostToDevice,
+                                         gs[0]));
+                BATCH_TRY(tcw::launch_member_restart(bb.sps, bb.wds, bb.restart, (int)bb.pending.size(), gs[0]));
+                BATCH_TRY(hipStreamSynchronize(gs[0]));  // the host may refill the list before the copy ran
+                bb.pending.clear();
+            }
+            if (round) BATCH_TRY(hipGraphLaunch(exec, gs[0]));
         }
         // the last round's claw candidates, checked exactly while this round runs
         for (int i = 0; i < count; ++i) {

@@ -160,6 +160,10 @@ int walks_per_block(int n);
 // value: what every slot's value word starts at (0 for walk tables: "not ready"; ENUM_TABLE_INIT for
 // enumeration tables: no x on either side)
 hipError_t launch_table_clear(uint64_t* table, int log2_table, uint64_t value, hipStream_t s);
+// restart batch members slots[0..count) in one launch (descriptors already on the device): each
+// member's table cleared, statistics and candidate count zeroed, walk states initialised
+hipError_t launch_member_restart(const SpaceDev* sps, const WalkDev* wds, const int32_t* slots, int count,
+                                 hipStream_t s);
 // enumeration mode, after the last point: one claw candidate per key reached from both sides
 hipError_t launch_enum_pairs(const WalkDev& wd, hipStream_t s);
 int walk_grid_blocks(int n, int device, bool queue);

@@ -1474,6 +1474,48 @@ __global__ void k_walk_init(SpaceDev sp, WalkDev wd) {
     }
 }
 
+// Several batch members restarted in one launch: for member slots[blockIdx.x / RESTART_PER], its
+// table cleared (EMPTY_KEY keys; values 0, or ENUM_TABLE_INIT in enumeration mode), its statistics
+// and candidate count zeroed and its walk states set as k_walk_init sets them; RESTART_PER blocks
+// share each member's work.
+constexpr int RESTART_PER = 32;
+__global__ __launch_bounds__(256) void k_member_restart(const SpaceDev* sps, const WalkDev* wds,
+                                                        const int32_t* slots) {
+    const int32_t slot = slots[blockIdx.x / RESTART_PER];
+    const SpaceDev sp = sps[slot];
+    const WalkDev wd = wds[slot];
+    const uint64_t stride = (uint64_t)RESTART_PER * blockDim.x;
+    const uint64_t first = (uint64_t)(blockIdx.x % RESTART_PER) * blockDim.x + threadIdx.x;
+    const uint64_t value = wd.enumerate ? ENUM_TABLE_INIT : 0;
+    const uint64_t nslots = 1ull << wd.log2_table;
+    for (uint64_t i = first; i < nslots; i += stride) {
+        wd.table[2 * i] = EMPTY_KEY;
+        wd.table[2 * i + 1] = value;
+    }
+    for (uint64_t w = first; w < (uint64_t)wd.walks; w += stride) {
+        WalkState st;
+        st.trail = 0;
+        st.len = 0;
+        st.mode = MODE_WALK;
+        st.rem = 0;
+        st.pa = st.pb = st.na = st.ha = 0;
+        if (wd.enumerate) {
+            if (w >= wd.n_points) {
+                st.mode = MODE_DONE;
+                st.start = 0;
+            } else {
+                st.start = (w % sp.n_half) | ((w / sp.n_half) << 32);
+            }
+        } else {
+            st.start = start_point(sp, w, 0);
+        }
+        st.cur = st.start;
+        wd.states[w] = st;
+    }
+    if (first < ST_COUNT) wd.stats[first] = 0;
+    if (first == 0) *wd.claw_count = 0;
+}
+
 __global__ void k_table_clear(uint64_t* table, uint64_t slots, uint64_t value) {
     for (uint64_t i = threadIdx.x + (uint64_t)blockIdx.x * blockDim.x; i < slots;
          i += (uint64_t)blockDim.x * gridDim.x) {
@@ -1741,6 +1783,13 @@ hipError_t launch_walk_init(const SpaceDev& sp, const WalkDev& wd, hipStream_t s
     int64_t blocks = (wd.walks + 255) / 256;
     if (blocks > 65535) blocks = 65535;
     hipLaunchKernelGGL(k_walk_init, dim3((unsigned)blocks), dim3(256), 0, s, sp, wd);
+    return hipGetLastError();
+}
+
+hipError_t launch_member_restart(const SpaceDev* sps, const WalkDev* wds, const int32_t* slots, int count,
+                                 hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_member_restart, dim3((unsigned)(count * RESTART_PER)), dim3(256), 0, s, sps, wds, slots);
     return hipGetLastError();
 }
 
