@@ -897,7 +897,7 @@ int tcw_walk_run(tcw_walk* w, int iters) {
     HIP_TRY(c, hipMemsetAsync(&w->wd.stats[tcw::ST_ACTIVE], 0, sizeof(unsigned long long), c->stream));
     HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
     HIP_TRY(c, tcw::launch_walk(w->space.n, w->space.dev, w->wd, iters,
-                                tcw::walk_grid_blocks(w->space.n, c->device, false), c->stream));
+                                tcw::walk_grid_blocks(w->space.n, c->device, false, w->wd.walks), c->stream));
     HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
     w->launches++;
     return TCW_OK;
@@ -2319,7 +2319,7 @@ int batch_run(tcw_ctx* c, std::vector<BatchTarget>& bt, bool stop_on_first, doub
     }
     BATCH_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
     int grid[5] = {0, 0, 0, 0, 0};
-    for (int n = 1; n <= 4; ++n) grid[n] = has_n[n] ? tcw::walk_grid_blocks(n, c->device, true) : 0;
+    for (int n = 1; n <= 4; ++n) grid[n] = has_n[n] ? tcw::walk_grid_blocks(n, c->device, true, 0) : 0;
     bool dirty = true, recapture = true;
     int64_t total_steps = 0;
     double walk_seconds = 0;

@@ -166,7 +166,7 @@ hipError_t launch_member_restart(const SpaceDev* sps, const WalkDev* wds, const 
                                  hipStream_t s);
 // enumeration mode, after the last point: one claw candidate per key reached from both sides
 hipError_t launch_enum_pairs(const WalkDev& wd, hipStream_t s);
-int walk_grid_blocks(int n, int device, bool queue);
+int walk_grid_blocks(int n, int device, bool queue, int64_t walks);
 hipError_t pack_phi_i32(int n, const int32_t* a, const int32_t* b, int64_t count, uint32_t* phi_out,
                         int* flag_dev, hipStream_t s);
 

@@ -1287,7 +1287,9 @@ __device__ void walk_block_single(const SpaceDev& sp, const WalkDev& wd, int ite
     const int gi = lane / Gm::G, gl = lane % Gm::G, gbase = gi * Gm::G;
     const bool leader = gl == 0;
     uint32_t* limbs = L.limbs[wave * Gm::WPW + gi];
-    uint32_t steps = 0, active = 0;
+    // the frequent events (every distinguished point, most of them inserts) are counted in registers
+    // and added to cnt once; the rest go to cnt as they happen
+    uint32_t steps = 0, active = 0, dps = 0, ins = 0;
     const int64_t stride = nblocks * WAVES * Gm::WPW;
     for (int64_t base = (block * WAVES + wave) * Gm::WPW; base < wd.walks; base += stride) {
         const int64_t w = base + gi;
@@ -1300,7 +1302,10 @@ __device__ void walk_block_single(const SpaceDev& sp, const WalkDev& wd, int ite
             walk_step<NQ, WAVES>(sp, L, limbs, arg, gl, gbase, nxt, H);
             steps++;
             const uint32_t ev = advance_walk<Gm::G == 64>(sp, wd, st, w, arg, nxt, H, leader, gbase);
-            if (ev && leader) count_events(cnt, ev);
+            dps += ev & EV_DP;
+            ins += (ev >> 1) & 1;
+            const uint32_t rare = ev & ~(uint32_t)(EV_DP | EV_INS);
+            if (rare && leader) count_events(cnt, rare);
         }
         if ((st.mode & 0xff) != MODE_DONE) active++;
         if (leader) wd.states[w] = st;
@@ -1308,6 +1313,8 @@ __device__ void walk_block_single(const SpaceDev& sp, const WalkDev& wd, int ite
     if (leader) {
         cnt.steps += steps;
         cnt.active += active;
+        cnt.dps += dps;
+        cnt.ins += ins;
     }
 }
 
@@ -1322,7 +1329,7 @@ __device__ void walk_block_pairs(const SpaceDev& sp, const WalkDev& wd, int iter
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool leader = lane == 0;
     uint32_t* limbs = L.limbs[wave];
-    uint32_t steps = 0, active = 0;
+    uint32_t steps = 0, active = 0, dps = 0, ins = 0;  // frequent events in registers, as in walk_block_single
     const int64_t pairs = (wd.walks + 1) / 2;
     for (int64_t q = block * WAVES + wave; q < pairs; q += nblocks * WAVES) {
         const int64_t w0 = 2 * q, w1 = 2 * q + 1;
@@ -1360,7 +1367,10 @@ __device__ void walk_block_pairs(const SpaceDev& sp, const WalkDev& wd, int iter
                 WalkState st = k ? sb : sa;
                 const uint32_t ev =
                     advance_walk<true>(sp, wd, st, k ? w1 : w0, k ? arg_b : arg_a, k ? nb : na, k ? hb : ha, leader, 0);
-                if (ev && leader) count_events(cnt, ev);
+                dps += ev & EV_DP;
+                ins += (ev >> 1) & 1;
+                const uint32_t rare = ev & ~(uint32_t)(EV_DP | EV_INS);
+                if (rare && leader) count_events(cnt, rare);
                 if (k)
                     sb = st;
                 else
@@ -1378,6 +1388,8 @@ __device__ void walk_block_pairs(const SpaceDev& sp, const WalkDev& wd, int iter
     if (leader) {
         cnt.steps += steps;
         cnt.active += active;
+        cnt.dps += dps;
+        cnt.ins += ins;
     }
 }
 
@@ -1652,12 +1664,15 @@ int cu_count(int device) {
 
 }  // namespace
 
-int walk_grid_blocks(int n, int device, bool queue) {
+int walk_grid_blocks(int n, int device, bool queue, int64_t walks) {
     // one persistent block per CU for n = 4 (the int8 S_c fills most of the 160 KiB LDS); at n = 3 the
-    // walk kernel's 71 VGPRs leave room for six 4-wave blocks per CU (measured: six 13.4 ms, seven
-    // 13.5 ms per 3.4e7 steps), the queue kernel's 88 for five
+    // walk kernel's 71 VGPRs leave room for six 4-wave blocks per CU, which pays with many walks
+    // (2^20 walks: 13.8 ms per 3.4e7 steps against 14.4 ms with five) but not with a search's usual
+    // 2^16 (the Toffoli search at theta = 1/2: 0.140 s with five, 0.151 s with six); the queue
+    // kernel's 88 VGPRs leave room for five
     const int cus = cu_count(device);
-    return n == 4 ? cus : (n == 3 ? cus * (queue ? 5 : 6) : cus * 4);
+    if (n == 3) return cus * (!queue && walks >= (1 << 19) ? 6 : 5);
+    return n == 4 ? cus : cus * 4;
 }
 
 hipError_t keys_fill(int n, uint64_t seed, uint64_t* keys, hipStream_t s) {
