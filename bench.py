@@ -634,12 +634,32 @@ def network_leg(ctx, batch: int = 4096, reps: int = 10):
     t_step = (time.perf_counter() - t0) / reps
     fwd = 2.0 * batch * (inp * hidden + (depth - 1) * hidden * hidden + hidden * classes)
     net.free()
-    _log(f"network: forward {t_fwd * 1e3:.3f} ms, train step {t_step * 1e3:.3f} ms")
+    # the vendor library on the layer-0 product alone (torch.mm, which calls hipBLASLt: BF16 operands,
+    # FP32 accumulation, batch x inp times inp x hidden), a reference point for the network's own GEMM
+    a = x.to(torch.bfloat16)
+    w = (torch.randn((inp, hidden), device="cuda:0", generator=g) * 0.02).to(torch.bfloat16)
+    for _ in range(3):
+        torch.mm(a, w)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    lib_reps = 20
+    e0.record()
+    for _ in range(lib_reps):
+        torch.mm(a, w)
+    e1.record()
+    torch.cuda.synchronize()
+    t_lib = e0.elapsed_time(e1) / lib_reps * 1e-3
+    lib_flops = 2.0 * batch * inp * hidden
+    del a, w
+    _log(f"network: forward {t_fwd * 1e3:.3f} ms, train step {t_step * 1e3:.3f} ms; "
+         f"torch.mm on the layer-0 product {t_lib * 1e6:.1f} us")
     return {"shape": f"{inp}->{hidden}x{depth}->{classes}", "batch": batch,
             "forward_ms": t_fwd * 1e3, "forward_tflops": fwd / t_fwd / 1e12,
             "train_step_ms": t_step * 1e3, "train_step_tflops": 3 * fwd / t_step / 1e12,
             "train_step_bf16_frac": 3 * fwd / t_step / 2.5e15,
-            "flops_counted": "GEMMs only: 2 b (in h + (d-1) h^2 + h c) forward, 3x that per training step"}
+            "flops_counted": "GEMMs only: 2 b (in h + (d-1) h^2 + h c) forward, 3x that per training step",
+            "library_layer0_mm": {"what": f"torch.mm (hipBLASLt), BF16, {batch} x {hidden} x {inp}",
+                                  "us": t_lib * 1e6, "tflops": lib_flops / t_lib / 1e12,
+                                  "bf16_frac": lib_flops / t_lib / 2.5e15}}
 
 
 LEARNED_ORDERS = ("plain", "learned_first")
