@@ -68,7 +68,7 @@ struct tcw_ctx {
     hipError_t noalloc_err = hipSuccess;
     std::atomic<int> stop_req{0};   // tcw_search_stop: end the running search at its next launch boundary
     SearchRun* stopped = nullptr;   // the last search that ended on a stop, for tcw_checkpoint
-    // device buffers of finished batch members, by exact size, for later batches (pool_get / pool_put)
+    // device buffers of finished batch members, by exact size, for later batches (pool_alloc / pool_put)
     std::multimap<size_t, void*> pool;
     size_t pool_bytes = 0;
 };
@@ -109,7 +109,17 @@ hipError_t pool_alloc(tcw_ctx* c, void** p, size_t bytes) {
         c->pool_bytes -= bytes;
         return hipSuccess;
     }
-    return hipMalloc(p, bytes);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipErrorOutOfMemory && !c->pool.empty()) {
+        // pooled buffers of other sizes hold the memory: free them (nothing is pending on them) and
+        // try once more; the failed call's error is cleared so that later launch checks do not see it
+        (void)hipGetLastError();
+        for (auto& kv : c->pool) (void)hipFree(kv.second);
+        c->pool.clear();
+        c->pool_bytes = 0;
+        e = hipMalloc(p, bytes);
+    }
+    return e;
 }
 
 void pool_put(tcw_ctx* c, void* p, size_t bytes) {
